@@ -1,0 +1,477 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these compare the oracle with itself: they check closed forms,
+theorems of the paper, printed table values, brute force and invariants.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import shortest_path
+
+import gen
+import oracle
+from oracle import amg
+from gen import fields
+from refsel import RefSelector
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_tables_1_2.json")
+
+
+# ----------------------------------------------------------------------------
+# inputs: Nedelec assembly (Section 2)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,size,kw", [("hex", 3, {}), ("hex", 5, {}), ("tri", 3, {}),
+                                          ("tet", 3, dict(jitter=0.2, mesh_seed=4))])
+def test_curl_part_annihilates_gradients(kind, size, kw):
+    """ker A^s = range G (de Rham, Section 2)."""
+    p = gen.make_problem(kind, size, alpha=lambda m: fields.subdomain_log_uniform(m, 2, 7),
+                         parts=True, **kw)
+    assert abs(p.As @ p.G).max() <= 1e-12 * abs(p.As).max()
+    # and the mass part does not: A is SPD, G has full column rank
+    assert abs(p.Am @ p.G).max() > 1e-3 * abs(p.Am).max()
+
+
+def test_dof_counts_closed_forms():
+    # hex, Dirichlet: 3N(N-1)^2 DoFs; natural: 3N(N+1)^2
+    for N in (2, 4, 8):
+        p = gen.make_problem("hex", N)
+        assert p.A.shape[0] == 3 * N * (N - 1) ** 2
+    assert gen.make_problem("hex", 8).A.nnz == 31008
+    assert gen.make_problem("hex", 8, dirichlet=False).A.shape[0] == 1944
+    # uniform triangles, Dirichlet: n = 3 4^L - 2 2^L, nnz = 15 4^L - 18 2^L + 4
+    for L in (2, 3, 4, 5):
+        p = gen.make_problem("tri", L)
+        assert p.A.shape[0] == 3 * 4 ** L - 2 * 2 ** L
+        assert p.A.nnz == 15 * 4 ** L - 18 * 2 ** L + 4
+    # the sizes of Tables 1-2 (Section 5): 736, 3008, 12160 for L = 4, 5, 6
+    assert [3 * 4 ** L - 2 * 2 ** L for L in (4, 5, 6, 7, 8)] == [736, 3008, 12160, 48896, 196096]
+    # Kuhn tets: every edge of the N^3 cubes, face and body diagonals
+    m = gen.kuhn_tet_mesh(3)
+    assert m.edges.shape[0] == 3 * 3 * 16 + 3 * 9 * 4 + 27
+
+
+def _edge_dofs_of_field(mesh, a, b):
+    x0 = mesh.coords[mesh.edges[:, 0]]
+    x1 = mesh.coords[mesh.edges[:, 1]]
+    mid = 0.5 * (x0 + x1)
+    if mesh.dim == 3:
+        u = a[None, :] + np.cross(b[None, :], mid)
+    else:
+        u = a[None, :] + b * np.stack([-mid[:, 1], mid[:, 0]], axis=1)
+    return np.einsum("ed,ed->e", u, x1 - x0)
+
+
+@pytest.mark.parametrize("kind,size", [("hex", 3), ("tri", 3), ("tet", 2)])
+def test_energies_of_rigid_fields(kind, size):
+    """u = a + b x X lies in the lowest-order Nedelec space: curl u = 2b, so
+    u^T A^s u = sum_K alpha_K |2b|^2 |K| and u^T A^m u = int |u|^2."""
+    kw = dict(jitter=0.2, mesh_seed=3) if kind == "tet" else {}
+    p = gen.make_problem(kind, size, alpha=lambda m: fields.subdomain_log_uniform(m, 2, 5, -1, 1),
+                         dirichlet=False, parts=True, **kw)
+    rng = np.random.default_rng(0)
+    dim = p.mesh.dim
+    a = rng.standard_normal(dim)
+    b = rng.standard_normal(3) if dim == 3 else rng.standard_normal()
+    u = _edge_dofs_of_field(p.mesh, a, b)
+    vol = np.abs(amg_volumes(p.mesh))
+    curl2 = 4.0 * (b @ b if dim == 3 else b * b)
+    assert np.isclose(u @ (p.As @ u), np.sum(p.alpha * vol) * curl2, rtol=1e-12)
+    # int |a + b x X|^2 over the unit square/cube, by a tensor Gauss rule (exact for quadratics)
+    g = np.array([0.5 - 0.5 / np.sqrt(3), 0.5 + 0.5 / np.sqrt(3)])
+    pts = np.array(np.meshgrid(*([g] * dim), indexing="ij")).reshape(dim, -1).T
+    if dim == 3:
+        uu = a[None] + np.cross(b[None], pts)
+    else:
+        uu = a[None] + b * np.stack([-pts[:, 1], pts[:, 0]], axis=1)
+    exact = np.mean(np.sum(uu * uu, axis=1))
+    assert np.isclose(u @ (p.Am @ u), exact, rtol=1e-12)
+
+
+def amg_volumes(mesh):
+    if mesh.kind == "hex":
+        return np.full(mesh.elems.shape[0], mesh.h ** 3)
+    X = mesh.coords[mesh.elems]
+    J = np.stack([X[:, a + 1] - X[:, 0] for a in range(mesh.dim)], axis=2)
+    return np.linalg.det(J) / (2.0 if mesh.dim == 2 else 6.0)
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 1
+# ----------------------------------------------------------------------------
+def test_augment_g_hand_example():
+    # 4 edges, 2 nodes: rows with one entry get a new column with the opposite sign
+    G = sp.csr_matrix(np.array([[-1.0, 1.0], [0.0, 1.0], [-1.0, 0.0], [1.0, -1.0]]))
+    Gt, B = amg.augment_g(G)
+    want = np.array([[-1, 1, 0, 0], [0, 1, -1, 0], [-1, 0, 0, 1], [1, -1, 0, 0]], dtype=float)
+    assert np.array_equal(Gt.toarray(), want)
+    assert B.tolist() == [2, 3]
+
+
+def test_augment_g_structure_hex():
+    p = gen.make_problem("hex", 6)
+    Gt, B = amg.augment_g(p.G)
+    cnt = np.diff(Gt.indptr)
+    assert np.all(cnt == 2)
+    assert np.allclose(np.asarray(Gt.sum(axis=1)).ravel(), 0.0)
+    # one artificial node per boundary-touching edge: 6 (N-1)^2
+    assert len(B) == 6 * 25
+
+
+# ----------------------------------------------------------------------------
+# nodal graph, C/F splitting (Algorithm 2)
+# ----------------------------------------------------------------------------
+def test_nodal_graph_is_27_point_on_hex():
+    N = 6
+    p = gen.make_problem("hex", N)
+    Gt, B = amg.augment_g(p.G)
+    S = amg.nodal_graph(p.A, Gt)
+    m = p.G.shape[1]
+    deg = np.diff(S.indptr)[:m]
+    # interior nodes not next to the boundary have the 26 king-move neighbours
+    ijk = np.array(np.unravel_index(np.arange(m), (N - 1,) * 3))  # k, j, i of interior lattice
+    deep = np.all((ijk >= 1) & (ijk <= N - 3), axis=0)
+    assert np.all(deg[deep] == 26)
+
+
+def test_rs_splitting_invariants_and_hex_lattice():
+    for N in (6, 8, 10):
+        p = gen.make_problem("hex", N)
+        Gt, B = amg.augment_g(p.G)
+        S = amg.nodal_graph(p.A, Gt)
+        cG, st = amg.nodal_cf(S, B)
+        isC = st == 1
+        isB = np.zeros(S.shape[0], dtype=bool)
+        isB[B] = True
+        # no chosen C node next to another C node (the prescribed boundary nodes
+        # B may touch each other); every node decided; every F has a C neighbour
+        rows = np.repeat(np.arange(S.shape[0]), np.diff(S.indptr))
+        assert not np.any(isC[rows] & ~isB[rows] & isC[S.indices])
+        assert np.all(st != 0)
+        hasC = np.zeros(S.shape[0], dtype=bool)
+        np.logical_or.at(hasC, rows, isC[S.indices])
+        assert np.all(hasC[st == 2])
+        # closed form: coarse nodes are the even interior lattice ((N/2-1)^3 nodes)
+        m = p.G.shape[1]
+        lat = np.array(np.unravel_index(np.arange(m), (N - 1,) * 3)) + 1
+        even = np.nonzero(np.all(lat % 2 == 0, axis=0))[0]
+        assert np.array_equal(cG, even)
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 3
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,size", [("tri", 3), ("hex", 4), ("hex", 6), ("tet", 3)])
+def test_matching_postconditions_brute_force(kind, size):
+    """Every DoF in at most one R row; every middle node used once; r G~ = -e_i + e_j;
+    R R^T = 2 I; R S_I = 0; and (brute force over all pairs of C') every pair at
+    edge distance exactly two, not both in B, is either matched or blocked
+    because its smallest mutual neighbour is already a middle."""
+    kw = dict(jitter=0.2, mesh_seed=4) if kind == "tet" else {}
+    p = gen.make_problem(kind, size, **kw)
+    Gt, B = amg.augment_g(p.G)
+    S = amg.nodal_graph(p.A, Gt)
+    cG, _ = amg.nodal_cf(S, B)
+    Cp = np.concatenate([cG, B])
+    n = p.A.shape[0]
+    rr, interior = amg.form_r(Gt, Cp, B, n)
+    dofs = np.concatenate([rr.dof1, rr.dof2])
+    assert len(np.unique(dofs)) == len(dofs)
+    assert len(np.unique(rr.k)) == len(rr.k)
+    R = amg.r_transpose(rr, n).T.tocsr()
+    RG = (R @ Gt).toarray()
+    want = np.zeros_like(RG)
+    want[np.arange(len(rr)), rr.i] = -1
+    want[np.arange(len(rr)), rr.j] = 1
+    assert np.array_equal(RG, want)
+    assert np.array_equal((R @ R.T).toarray(), 2 * np.eye(len(rr)))
+    assert abs(R[:, interior]).sum() == 0
+    assert np.array_equal(np.sort(np.concatenate([dofs, interior])), np.arange(n))
+    # brute force over all pairs
+    E, _ = amg.edge_graph(Gt)
+    D = shortest_path(E, unweighted=True, indices=Cp)
+    Cset = np.sort(Cp)
+    isB = np.zeros(Gt.shape[1], dtype=bool)
+    isB[B] = True
+    matched = set(zip(np.minimum(rr.i, rr.j).tolist(), np.maximum(rr.i, rr.j).tolist()))
+    K = set(rr.k.tolist())
+    Ed = E.toarray() > 0
+    pos = {c: t for t, c in enumerate(Cp)}
+    for a in Cset:
+        for b in Cset:
+            if b <= a or (isB[a] and isB[b]) or D[pos[a], b] != 2:
+                continue
+            kmin = int(np.nonzero(Ed[a] & Ed[b])[0][0])
+            assert (a, b) in matched or kmin in K
+    # hex: the pairs are exactly the coarse-mesh edges of the refinement
+    if kind == "hex":
+        N = size
+        assert len(rr) == 3 * (N // 2) * (N // 2 - 1) ** 2
+
+
+# ----------------------------------------------------------------------------
+# Tables 1-2: structural complexities (Section 5)
+# ----------------------------------------------------------------------------
+def _golden():
+    return json.load(open(GOLDEN))
+
+
+@pytest.mark.parametrize("L", [4, 5, 6])
+def test_table1_algebraic_complexities_exact(L):
+    """Alg: the operator and grid complexities and level counts printed in
+    Table 1 (and, identically, Table 2) are reproduced to every digit."""
+    row = _golden()["table1_uniform_isotropic"][str(L)]
+    for alpha in (1.0, lambda m: fields.stripes_2d(m)):
+        p = gen.make_problem("tri", L, beta=0.01, alpha=alpha)
+        H = oracle.setup(p.A, p.G)
+        assert H.nlevels == row["levels_alg"]
+        assert abs(H.oc() - row["oc_alg"]) < 1e-12
+        assert abs(H.gc() - row["gc_alg"]) < 1e-12
+
+
+@pytest.mark.parametrize("L", [4, 5, 6])
+def test_table1_refinement_complexities_exact(L):
+    """Ref (coarse nodes from the geometric hierarchy): Table 1's OC/GC."""
+    row = _golden()["table1_uniform_isotropic"][str(L)]
+    p = gen.make_problem("tri", L, beta=0.01)
+    H = oracle.setup(p.A, p.G, interp="ref", ref_select=RefSelector(p), max_levels=L, min_coarse=0)
+    assert H.nlevels == row["levels_ref"]
+    assert abs(H.oc() - row["oc_ref"]) < 1e-12
+    assert abs(H.gc() - row["gc_ref"]) < 1e-12
+
+
+@pytest.mark.parametrize("L", [4, 5])
+def test_table1_iteration_counts_isotropic(L):
+    """Isotropic Table 1 counts (random x0, b = (1..n)): PCG within 1, stand-alone AMG within 3."""
+    row = _golden()["table1_uniform_isotropic"][str(L)]
+    p = gen.make_problem("tri", L, beta=0.01)
+    n = p.A.shape[0]
+    b = np.arange(1, n + 1, dtype=float)
+    x0 = np.random.default_rng(0).random(n)
+    H = oracle.setup(p.A, p.G)
+    _, it, _ = oracle.pcg(H, p.A, b, x0=x0)
+    _, ita, _ = oracle.amg_solve(H, p.A, b, x0=x0)
+    assert abs(it - row["pcg_alg"]) <= 1
+    assert abs(ita - row["amg_alg"]) <= 3
+    Hr = oracle.setup(p.A, p.G, interp="ref", ref_select=RefSelector(p), max_levels=L, min_coarse=0)
+    _, it, _ = oracle.pcg(Hr, p.A, b, x0=x0)
+    _, ita, _ = oracle.amg_solve(Hr, p.A, b, x0=x0)
+    assert abs(it - row["pcg_ref"]) <= 1
+    assert abs(ita - row["amg_ref"]) <= 6
+
+
+# ----------------------------------------------------------------------------
+# interpolation, theory (Section 3)
+# ----------------------------------------------------------------------------
+def _two_level_2d(L=3, beta=0.01, alpha=1.0, As_only=False):
+    """Refinement-based R and P_app of the finest level (no smoother, so that
+    A = A^s, whose node-star blocks are singular, can be used)."""
+    p = gen.make_problem("tri", L, beta=beta, alpha=alpha, parts=True)
+    A = p.As if As_only else p.A
+    lv = amg.Level(A=sp.csr_matrix(A), G=p.G)
+    lv.Gt, lv.B = amg.augment_g(p.G)
+    cG, Bc = RefSelector(p)(0, lv)
+    Cp = np.concatenate([cG, Bc])
+    n = A.shape[0]
+    lv.rr, lv.interior = amg.form_r(lv.Gt, Cp, lv.B, n, skip_bb=False)
+    lv.blocks, lv.depths, lv.exact_blocks = amg.extension_blocks(
+        lv.A, lv.Gt, lv.interior, np.concatenate([Cp, lv.rr.k]))
+    lv.P = amg.interpolation(lv.A, amg.r_transpose(lv.rr, n), lv.blocks, lv.depths)
+    return p, A, lv
+
+
+def test_block_extension_equals_dense_ideal_formula():
+    """2D: graph(A_II) splits into small components, and P equals
+    R^T - S_I A_II^{-1} S_I^T A R^T computed densely (eq. sparseP)."""
+    for alpha in (1.0, lambda m: fields.stripes_2d(m)):
+        for mode in ("ref", "alg"):
+            p = gen.make_problem("tri", 3, beta=0.01, alpha=alpha)
+            kw = dict(interp="ref", ref_select=RefSelector(p), min_coarse=0) if mode == "ref" else {}
+            H = oracle.setup(p.A, p.G, max_levels=2, **kw)
+            lv = H.levels[0]
+            assert lv.exact_blocks
+            n = p.A.shape[0]
+            Rt = amg.r_transpose(lv.rr, n).toarray()
+            Ad = p.A.toarray()
+            I = lv.interior
+            Pd = Rt.copy()
+            Pd[I] = Rt[I] - np.linalg.solve(Ad[np.ix_(I, I)], Ad[I] @ Rt)
+            assert np.abs(lv.P.toarray() - Pd).max() <= 1e-10 * np.abs(Pd).max()
+
+
+def test_lemma1_and_commuting_theorem_2d():
+    """beta = 0 (A = A^s, A^s_II invertible on the 2D refinement): Lemma 1
+    X_E(A^s) S_E = 0 and X_E(A^s) G_E = 0, and Theorem 2: A^s P G_c = 0."""
+    p, As, lv = _two_level_2d(L=3, alpha=lambda m: fields.stripes_2d(m), As_only=True)
+    n = As.shape[0]
+    Ad = As.toarray()
+    I = lv.interior
+    E = np.setdiff1d(np.arange(n), I)
+    XE = Ad[np.ix_(E, E)] - Ad[np.ix_(E, I)] @ np.linalg.solve(Ad[np.ix_(I, I)], Ad[np.ix_(I, E)])
+    # S_E: one column per R row, the oriented difference of its two DoFs
+    SE = np.zeros((n, len(lv.rr)))
+    SE[lv.rr.dof1, np.arange(len(lv.rr))] = lv.rr.s1
+    SE[lv.rr.dof2, np.arange(len(lv.rr))] = -lv.rr.s2
+    # S_E columns are the restrictions of G's columns at the middle nodes k
+    scale = np.abs(XE).max()
+    assert np.abs(XE @ SE[E]).max() <= 1e-10 * scale
+    assert np.abs(XE @ p.G.toarray()[E]).max() <= 1e-10 * scale
+    Gc, _ = amg.coarse_gradient(p.G, lv.rr)
+    APG = As @ (lv.P @ Gc)
+    assert abs(APG).max() <= 1e-10 * abs(As).max()
+
+
+def test_commuting_defect_is_order_beta():
+    """For beta != 0 the commuting relation holds up to O(beta): slope ~1 in log-log."""
+    defects = []
+    betas = [1e-1, 1e-2, 1e-3, 1e-4]
+    for beta in betas:
+        p, A, lv = _two_level_2d(L=3, beta=beta)
+        Gc, _ = amg.coarse_gradient(p.G, lv.rr)
+        defects.append(abs(p.As @ (lv.P @ Gc)).max())
+    slopes = np.diff(np.log10(defects)) / np.diff(np.log10(betas))
+    assert np.all(np.abs(slopes - 1.0) < 0.1)
+
+
+def _coarse_hat_2d(xs, ys):
+    """P1 hat of the unit '/'-cut square mesh centred at the origin."""
+    return np.maximum.reduce([
+        np.where((xs >= 0) & (ys >= 0) & (xs <= 1) & (ys <= 1), 1 - np.maximum(xs, ys), 0.0),
+        np.where((xs <= 0) & (ys <= 0) & (xs >= -1) & (ys >= -1), 1 + np.minimum(xs, ys), 0.0),
+        np.where((xs >= 0) & (ys <= 0) & (xs - ys <= 1), 1 - (xs - ys), 0.0),
+        np.where((xs <= 0) & (ys >= 0) & (ys - xs <= 1), 1 - (ys - xs), 0.0)])
+
+
+@pytest.mark.parametrize("alpha", [1.0, "stripes"])
+def test_coarse_gradients_map_to_fine_gradients_of_linear_interpolant(alpha):
+    """2D refinement (Section 3.1): P G_c / 2 = G P_n with P_n the piecewise
+    linear interpolation of coarse nodal functions, up to O(beta) (the 1/2
+    comes from the +-1 entries of R).  Checked for beta = 1e-2 and 1e-4."""
+    al = (lambda m: fields.stripes_2d(m)) if alpha == "stripes" else alpha
+    errs = []
+    for beta in (1e-2, 1e-4):
+        p, A, lv = _two_level_2d(L=3, beta=beta, alpha=al)
+        Gc, cols = amg.coarse_gradient(p.G, lv.rr)
+        M = 2 ** 3
+        m = p.G.shape[1]
+        lat = np.array(np.unravel_index(np.arange(m), (M - 1, M - 1)))[::-1] + 1   # (i, j)
+        Pn = np.zeros((m, len(cols)))
+        for c in range(len(cols)):
+            Pn[:, c] = _coarse_hat_2d((lat[0] - lat[0, cols[c]]) / 2.0, (lat[1] - lat[1, cols[c]]) / 2.0)
+        lhs = (lv.P @ Gc).toarray() / 2.0
+        errs.append(np.abs(lhs - p.G.toarray() @ Pn).max())
+    assert errs[1] < 1e-3 and errs[1] < errs[0] / 50
+
+
+# ----------------------------------------------------------------------------
+# Galerkin operator, smoother, cycle
+# ----------------------------------------------------------------------------
+def _small_hier():
+    p = gen.make_problem("hex", 6, beta=1.0, alpha=lambda m: fields.subdomain_log_uniform(m, 3, 11))
+    return p, oracle.setup(p.A, p.G)
+
+
+def test_galerkin_symmetric_positive_definite():
+    p, H = _small_hier()
+    for lv in H.levels[1:]:
+        A = lv.A.toarray()
+        assert np.abs(A - A.T).max() <= 1e-13 * np.abs(A).max()
+        assert np.linalg.eigvalsh(0.5 * (A + A.T)).min() > 0
+
+
+def test_colouring_makes_colour_blocks_uncoupled():
+    p, H = _small_hier()
+    for lv in H.levels:
+        sm = lv.smoother
+        A = lv.A.tocsr()
+        for c in range(sm.ncolors):
+            owner = np.full(A.shape[0], -1)
+            for b in np.nonzero(sm.color == c)[0]:
+                assert np.all(owner[sm.blocks[b]] == -1)
+                owner[sm.blocks[b]] = b
+            for b in np.nonzero(sm.color == c)[0]:
+                for e in sm.blocks[b]:
+                    nb = owner[A.indices[A.indptr[e]:A.indptr[e + 1]]]
+                    assert np.all((nb == -1) | (nb == b))
+
+
+def test_colour_sweep_equals_sequential_block_sweep():
+    """The colour-vectorised sweep equals block-by-block multiplicative Schwarz
+    in colour order (written out directly with dense solves)."""
+    p, H = _small_hier()
+    lv = H.levels[0]
+    sm = lv.smoother
+    A = lv.A.tocsr()
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(A.shape[0])
+    x = np.zeros_like(b)
+    order = [blk for c in range(sm.ncolors) for blk in np.nonzero(sm.color == c)[0]]
+    for blk in order:
+        d = sm.blocks[blk]
+        r = b[d] - A[d] @ x
+        x[d] += np.linalg.solve(A[d][:, d].toarray(), r)
+    mats = amg._cast(H, np.float64)
+    y = amg._schwarz(mats[0], np.zeros_like(b), b, list(range(sm.ncolors)))
+    assert np.abs(x - y).max() <= 1e-9 * np.abs(x).max()   # jumps of 10^8: local kappa ~1e7
+
+
+def test_vcycle_is_symmetric_and_positive():
+    p, H = _small_hier()
+    rng = np.random.default_rng(1)
+    n = p.A.shape[0]
+    r1, r2 = rng.standard_normal(n), rng.standard_normal(n)
+    v1, v2 = oracle.vcycle(H, r1), oracle.vcycle(H, r2)
+    assert abs(v1 @ r2 - r1 @ v2) <= 1e-10 * np.linalg.norm(v1) * np.linalg.norm(r2)
+    assert v1 @ r1 > 0
+
+
+def test_two_grid_gamg_bound():
+    """Section 1: ||E_TG||_A^2 <= 1 - 1/K with K = sup ||(I - P R^)e||^2_Mt / ||e||^2_A,
+    Mt = M (M + M^T - A)^{-1} M^T, for any R^ with R^ P = I (here R^ = R/2).
+    Checked densely on a tiny mesh with the oracle's own smoother."""
+    for alpha in (1.0, lambda m: fields.subdomain_log_uniform(m, 2, 5)):
+        p = gen.make_problem("hex", 4, beta=1.0, alpha=alpha)
+        H = oracle.setup(p.A, p.G, max_levels=2)
+        A = p.A.toarray()
+        n = A.shape[0]
+        lv = H.levels[0]
+        P = lv.P.toarray()
+        Rh = amg.r_transpose(lv.rr, n).toarray().T / 2.0
+        assert np.allclose(Rh @ P, np.eye(P.shape[1]))
+        # pre-smoother error propagation E_pre (columns = images of unit vectors)
+        mats = amg._cast(H, np.float64)
+        nc = lv.smoother.ncolors
+
+        def pre(e):
+            # smoothing A x = 0 from the initial error e gives the new error
+            x = e.copy()
+            b = np.zeros(n)
+            x = amg._schwarz(mats[0], x, b, list(range(nc)))
+            x = amg._schwarz(mats[0], x, b, list(range(nc - 1, -1, -1)))
+            return x + (b - mats[0]["A"] @ x) / mats[0]["l1"]
+        Epre = np.stack([pre(col) for col in np.eye(n)], axis=1)
+        # M from I - M^{-1} A = E_pre
+        M = A @ np.linalg.inv(np.eye(n) - Epre)
+        Mt = M @ np.linalg.solve(M + M.T - A, M.T)
+        Q = np.eye(n) - P @ Rh
+        import scipy.linalg as sl
+        K = sl.eigh(Q.T @ (0.5 * (Mt + Mt.T)) @ Q, A, eigvals_only=True).max()
+        Pi = P @ np.linalg.solve(P.T @ A @ P, P.T @ A)
+        E = Epre @ (np.eye(n) - Pi)
+        # ||E||_A = ||A^{1/2} E A^{-1/2}||_2
+        w, V = np.linalg.eigh(A)
+        Ah = V @ np.diag(np.sqrt(w)) @ V.T
+        Aih = V @ np.diag(1 / np.sqrt(w)) @ V.T
+        nE = np.linalg.norm(Ah @ E @ Aih, 2)
+        assert K >= 1.0
+        assert nE ** 2 <= 1.0 - 1.0 / K + 1e-10
+
+
+def test_pcg_reaches_tolerance_true_residual():
+    p, H = _small_hier()
+    f = fields.rhs_uniform(p.A.shape[0], 1)
+    x, it, hist = oracle.pcg(H, p.A, f)
+    assert np.linalg.norm(f - p.A @ x) <= 1.01e-8 * np.linalg.norm(f)
+    assert it < 100
