@@ -1,0 +1,202 @@
+/*
+ * amg.h -- C ABI of the MI355X H(curl) algebraic multigrid library.
+ *
+ * The library solves A u = f for the lowest-order Nedelec discretisation of
+ * curl(alpha curl u) + beta u = f with u x n = 0 (Section 2 of
+ * arXiv 2602.23613, "Nodal Coarsening and Sparse Ideal Interpolation for
+ * H(curl) Problems in Algebraic Multigrid").  Inputs are the sparse SPD
+ * matrix A (Section 1, eq. (axb)) and the discrete gradient G from nodes to
+ * edges (Section 2, eq. (deRham)).  The preconditioner is the paper's
+ * algebraic multigrid hierarchy:
+ *   - augmentG (Algorithm 1), nodal coarsening of the dual operator
+ *     G~^T A G~ (Algorithm 2), coarse edge variables from length-two paths
+ *     (Algorithm 3) and the coarse gradient G_c = R G I_C (eq. (Gc));
+ *   - the sparse ideal interpolation P_app = (I - S_I A_II^{-1} S_I^T A) R^T
+ *     (eq. (sparseP)) built by batched local harmonic extension on the GPU;
+ *   - Galerkin coarse operators A_c = P^T A P (Section 1) by GPU SpGEMM;
+ *   - V(1,1) cycles with the symmetrised multiplicative Schwarz + l1-Jacobi
+ *     smoother (Section 5), used as a preconditioner for CG.
+ *
+ * Conventions
+ *   - Every function returns amg_status; 0 (AMG_OK) is success.  On a
+ *     negative status the caller's buffers are left untouched and
+ *     amg_last_error() returns a message naming the level and the cause.
+ *   - CSR inputs are borrowed for the duration of the call only: column
+ *     indices sorted and unique within each row, int64 row pointers, int32
+ *     column indices, FP64 values.  `on_device` = 1 means the three arrays
+ *     are HIP device pointers, 0 means host pointers.
+ *   - Vectors passed to amg_vcycle / amg_pcg_solve are caller-owned HIP
+ *     device buffers (e.g. torch tensors' data_ptr()).
+ *   - Streams: `stream` is a hipStream_t (NULL = the default stream).  All
+ *     device work of a call is enqueued in order on that stream.
+ *     amg_vcycle returns without synchronising; amg_setup,
+ *     amg_resetup_numeric and amg_pcg_solve synchronise before returning.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef HCURL_AMG_H
+#define HCURL_AMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AMG_OK = 0,
+  AMG_NOT_CONVERGED = 1,       /* PCG hit maxit; u and stats hold the last iterate */
+  AMG_ERR_ARG = -1,            /* NULL pointer, bad option value */
+  AMG_ERR_SHAPE = -2,          /* inconsistent sizes (A not square, G rows != n, ...) */
+  AMG_ERR_CSR = -3,            /* row pointers not monotone, column out of range, unsorted or duplicate */
+  AMG_ERR_G_NOT_INCIDENCE = -4,/* a row of G is not {}, {+-1} or {+1, -1} */
+  AMG_ERR_NOT_SPD = -5,        /* non-positive pivot in a block or coarse Cholesky factorisation */
+  AMG_ERR_COARSEN = -6,        /* the first coarsening step produced no coarse variables */
+  AMG_ERR_HIP = -7,            /* a HIP runtime call failed (message holds the HIP error string) */
+  AMG_ERR_OOM = -8,            /* device allocation failed */
+  AMG_ERR_LIMIT = -9,          /* a block or row exceeds a kernel's size limit (message names it) */
+  AMG_ERR_NOT_FINITE = -10     /* NaN or Inf in the right-hand side */
+} amg_status;
+
+enum { AMG_INTERP_ALG = 0, AMG_INTERP_REF = 1 };
+
+/* Compressed sparse row view (borrowed). */
+typedef struct {
+  int64_t nrows, ncols, nnz;
+  const int64_t *rowptr;   /* nrows + 1 */
+  const int32_t *colidx;   /* nnz */
+  const double *val;       /* nnz */
+  int on_device;           /* 0: host pointers, 1: HIP device pointers */
+} amg_csr;
+
+/* Setup options; amg_default_options() fills the paper's values (Section 5). */
+typedef struct {
+  int interp;              /* AMG_INTERP_ALG (Algorithms 1-3) or AMG_INTERP_REF */
+  int max_levels;          /* 20: maximum number of levels (Section 5) */
+  int64_t min_coarse;      /* 32: stop coarsening at or below this many DoFs (Section 5) */
+  int vcycle_prec;         /* 64: FP64 V-cycle; 32: FP32 V-cycle (FP64 coarsest solve) */
+  int ext_block_max;       /* 64: largest connected component of graph(A_II) solved as one exact block */
+  double stall_ratio;      /* 0.9: stop when n_{l+1} > stall_ratio * n_l */
+  /* AMG_INTERP_REF only: for levels 0 .. ref_nlevels-1 the coarse nodes come
+     from the geometric refinement instead of Algorithm 2.  Per level l:
+     ref_coarse_nodes[l] (ref_ncoarse[l] entries) lists coarse real nodes
+     (columns of G_l); ref_coarse_bnd[l] (ref_nbnd[l] entries) lists the coarse
+     artificial nodes, as ids in augmentG's numbering (columns m_l, m_l+1, ...
+     of G~_l).  Host pointers, read during amg_setup only. */
+  int ref_nlevels;
+  const int32_t *const *ref_coarse_nodes;
+  const int64_t *ref_ncoarse;
+  const int32_t *const *ref_coarse_bnd;
+  const int64_t *ref_nbnd;
+} amg_options;
+
+typedef struct amg_hier amg_hier;   /* opaque; owns all device memory of the hierarchy */
+
+typedef struct {
+  int iterations;          /* CG iterations performed */
+  double relres;           /* final ||f - A u|| / ||f - A u0|| (recursive residual) */
+  double true_relres;      /* final true residual recomputed with one extra SpMV */
+  double seconds;          /* wall time of the solve on the host clock */
+  double *history;         /* optional caller buffer (maxit + 1 doubles) of residual norms, or NULL */
+} amg_solve_stats;
+
+typedef struct {
+  int64_t n, nnz;          /* DoFs and stored entries of A_l */
+  int64_t p_nnz;           /* stored entries of P_l (0 on the coarsest level) */
+  int64_t nblocks;         /* smoother blocks (node stars) */
+  int ncolors;             /* colours of the multiplicative Schwarz sweep */
+  int exact_blocks;        /* 1 if P_l used exact component blocks of A_II */
+  int64_t star_rows;       /* sum of block sizes: rows visited by one Schwarz sweep */
+  int64_t star_row_nnz;    /* stored entries of A_l in those rows (with repetition) */
+  int64_t fac_entries;     /* packed lower-triangular factor entries of all blocks */
+} amg_level_info;
+
+/* Integer results of one level's setup, for bit-exact comparison.  All
+   arrays are host memory owned by the handle (valid until amg_destroy). */
+typedef struct {
+  int64_t n, m_real, n_art;                 /* DoFs, columns of G_l, artificial nodes of G~_l */
+  const int8_t *cf;                         /* m_real + n_art node states (1 = C, 2 = F), NULL in REF levels */
+  int64_t n_cg; const int32_t *cg;          /* coarse real nodes c_G (ascending) */
+  int64_t nc;                               /* coarse DoFs = rows of R */
+  const int32_t *r_dof1, *r_dof2, *r_i, *r_j, *r_k;
+  const int8_t *r_s1, *r_s2;
+  int64_t n_interior; const int32_t *interior;
+  int64_t nblocks; const int64_t *block_ptr; const int32_t *block_dofs; const int64_t *block_key_depth;
+  int exact_blocks;
+  int64_t nstars; const int64_t *star_ptr; const int32_t *star_dofs; const int32_t *star_color;
+  int ncolors;
+  int64_t gc_nrows, gc_ncols; const int64_t *gc_ptr; const int32_t *gc_col; const int8_t *gc_val;
+  const int32_t *gc_cols;                   /* level-l node id of each column of G_{l+1} */
+} amg_int_export;
+
+/* Fill *opt with the paper's defaults (Section 5). */
+void amg_default_options(amg_options *opt);
+
+/* Build the hierarchy for A (n x n, SPD) and G (n x m discrete gradient).
+   The integer phase runs on the host, every floating-point step on the GPU.
+   On success *out owns a new handle. */
+amg_status amg_setup(const amg_csr *A, const amg_csr *G, const amg_options *opt,
+                     void *stream, amg_hier **out);
+
+/* Recompute every floating-point part of the hierarchy (P, A_c, smoother
+   factors, l1 diagonals, coarsest factor) for a new A with exactly the
+   pattern of the one given to amg_setup (e.g. a new coefficient field on the
+   same mesh); the integer setup is reused unchanged. */
+amg_status amg_resetup_numeric(amg_hier *h, const amg_csr *A, void *stream);
+
+/* z = B r: one V(1,1) cycle with zero initial guess.  r and z are device
+   buffers of n doubles (the FP32 form converts at the boundary).  r and z
+   must not alias.  Asynchronous on `stream`. */
+amg_status amg_vcycle(amg_hier *h, const double *r, double *z, void *stream);
+
+/* Preconditioned CG on A u = f (FP64 vectors, reductions and updates; the
+   V-cycle in the handle's precision, with the flexible Polak-Ribiere beta
+   for the FP32 form).  f, u: device buffers of n doubles; u holds the
+   initial guess on entry and the iterate on exit.  Stops when
+   ||r_k|| <= rtol ||r_0||.  Returns AMG_NOT_CONVERGED after maxit. */
+amg_status amg_pcg_solve(amg_hier *h, const double *f, double *u, double rtol, int maxit,
+                         amg_solve_stats *stats, void *stream);
+
+/* One multiplicative Schwarz sweep of the smoother on level `level`
+   (Section 5): for every colour in ascending order (backward = 0) or
+   descending order (backward = 1), x_B += A_BB^{-1} (b - A x)_B for all
+   node-star blocks B of that colour.  prec = 64: b, x are device doubles
+   and the FP64 factors are used; prec = 32: device floats and the FP32
+   copies (only in a hierarchy built with vcycle_prec = 32).  Asynchronous;
+   used for kernel tests and measurement. */
+amg_status amg_smoother_sweep(amg_hier *h, int level, int prec, const void *b, void *x,
+                              int backward, void *stream);
+
+/* y = A x with the CSR SpMV kernel of the solve phase (device CSR and
+   vectors, FP64).  Used for measurement and kernel tests. */
+amg_status amg_spmv(const amg_csr *A, const double *x, double *y, void *stream);
+
+/* Per-level sizes; writes min(cap, levels) entries and the level count. */
+amg_status amg_hier_info(const amg_hier *h, amg_level_info *lv, int cap, int *nlevels);
+
+/* Integer results of level `level` (0 .. nlevels-2). */
+amg_status amg_export_integers(const amg_hier *h, int level, amg_int_export *out);
+
+/* Copy level `level`'s matrices to caller host buffers: A_l (nnz values,
+   rowptr, colidx) and, unless `level` is the coarsest, P_l.  Any pointer
+   may be NULL to skip it.  Sizes come from amg_hier_info. */
+amg_status amg_export_level(const amg_hier *h, int level,
+                            int64_t *a_ptr, int32_t *a_col, double *a_val,
+                            int64_t *p_ptr, int32_t *p_col, double *p_val);
+
+/* Host-only integer setup of the finest level (no GPU needed): the same
+   code path amg_setup runs for level 0.  *out is owned by *handle; release
+   it with amg_free_integers. */
+amg_status amg_level0_integers(const amg_csr *A, const amg_csr *G, const amg_options *opt,
+                               amg_int_export *out, void **handle);
+void amg_free_integers(void *handle);
+
+/* Release a hierarchy and all its device memory.  NULL is ignored. */
+void amg_destroy(amg_hier *h);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *amg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HCURL_AMG_H */

@@ -1,0 +1,185 @@
+"""MI355X-native H(curl) algebraic multigrid (arXiv 2602.23613).
+
+Python front end of libhcurlamg.so: argument marshalling only.  Inputs are
+scipy CSR matrices (host) or torch CUDA tensors (device); vectors passed to
+the solve phase are torch CUDA tensors of float64.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import AmgError, load  # noqa: F401
+
+__all__ = ["Hierarchy", "level0_integers", "spmv", "load", "AmgError"]
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return None
+
+
+def _csr_arg(M, keep):
+    """amg_csr for a scipy matrix (host) or a (rowptr, colidx, val, nrows, ncols) tuple of tensors."""
+    if isinstance(M, tuple):
+        rp, ci, va, nr, nc = M
+        keep.extend([rp, ci, va])
+        return _lib.make_csr(rp, ci, va, nr, nc)
+    rp, ci, va = _lib.host_csr(M)
+    keep.extend([rp, ci, va])
+    return _lib.make_csr(rp, ci, va, M.shape[0], M.shape[1])
+
+
+def _options(keep, interp="alg", max_levels=20, min_coarse=32, vcycle_prec=64, ext_block_max=64,
+             stall_ratio=0.9, ref=None):
+    o = _lib.default_options()
+    o.interp = _lib.AMG_INTERP_REF if interp == "ref" else _lib.AMG_INTERP_ALG
+    o.max_levels = max_levels
+    o.min_coarse = min_coarse
+    o.vcycle_prec = vcycle_prec
+    o.ext_block_max = ext_block_max
+    o.stall_ratio = stall_ratio
+    if ref:
+        # ref: list of (coarse real nodes, coarse artificial nodes) per level
+        nl = len(ref)
+        cn = [np.ascontiguousarray(r[0], dtype=np.int32) for r in ref]
+        cb = [np.ascontiguousarray(r[1], dtype=np.int32) for r in ref]
+        keep.extend(cn + cb)
+        P32 = C.POINTER(C.c_int32)
+        arr_n = (P32 * nl)(*[a.ctypes.data_as(P32) for a in cn])
+        arr_b = (P32 * nl)(*[a.ctypes.data_as(P32) for a in cb])
+        cnt_n = (C.c_int64 * nl)(*[len(a) for a in cn])
+        cnt_b = (C.c_int64 * nl)(*[len(a) for a in cb])
+        keep.extend([arr_n, arr_b, cnt_n, cnt_b])
+        o.ref_nlevels = nl
+        o.ref_coarse_nodes = C.cast(arr_n, C.POINTER(P32))
+        o.ref_coarse_bnd = C.cast(arr_b, C.POINTER(P32))
+        o.ref_ncoarse = C.cast(cnt_n, C.POINTER(C.c_int64))
+        o.ref_nbnd = C.cast(cnt_b, C.POINTER(C.c_int64))
+    return o
+
+
+class Hierarchy:
+    """AMG hierarchy owned by the library (amg_setup / amg_destroy)."""
+
+    def __init__(self, A, G, stream=None, **opts):
+        lib = load()
+        keep = []
+        a = _csr_arg(A, keep)
+        g = _csr_arg(G, keep)
+        o = _options(keep, **opts)
+        h = C.c_void_p()
+        _lib.check(lib.amg_setup(C.byref(a), C.byref(g), C.byref(o), _stream(stream), C.byref(h)))
+        self._h = h
+        self.prec = opts.get("vcycle_prec", 64)
+        self.n = A[3] if isinstance(A, tuple) else A.shape[0]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().amg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def resetup(self, A, stream=None):
+        keep = []
+        a = _csr_arg(A, keep)
+        _lib.check(load().amg_resetup_numeric(self._h, C.byref(a), _stream(stream)))
+
+    def vcycle(self, r, z, stream=None):
+        """z = B r (device float64 tensors), asynchronous on the stream."""
+        _lib.check(load().amg_vcycle(self._h, r.data_ptr(), z.data_ptr(), _stream(stream)))
+
+    def pcg(self, f, u, rtol=1e-8, maxit=500, history=False, stream=None):
+        st = _lib.amg_solve_stats()
+        hist = None
+        if history:
+            hist = np.zeros(maxit + 1)
+            st.history = hist.ctypes.data_as(C.POINTER(C.c_double))
+        status = _lib.check(load().amg_pcg_solve(self._h, f.data_ptr(), u.data_ptr(), rtol, maxit,
+                                                 C.byref(st), _stream(stream)))
+        out = dict(status=status, iterations=st.iterations, relres=st.relres,
+                   true_relres=st.true_relres, seconds=st.seconds)
+        if history:
+            out["history"] = hist[:st.iterations + 1].copy()
+        return out
+
+    def info(self):
+        cap = 32
+        arr = (_lib.amg_level_info * cap)()
+        nl = C.c_int()
+        _lib.check(load().amg_hier_info(self._h, arr, cap, C.byref(nl)))
+        return [dict(n=x.n, nnz=x.nnz, p_nnz=x.p_nnz, nblocks=x.nblocks, ncolors=x.ncolors,
+                     exact_blocks=bool(x.exact_blocks), star_rows=x.star_rows,
+                     star_row_nnz=x.star_row_nnz, fac_entries=x.fac_entries)
+                for x in arr[:nl.value]]
+
+    def sweep(self, level, b, x, backward=False, stream=None):
+        """One multiplicative Schwarz sweep on `level` (x updated in place)."""
+        import torch
+        prec = 32 if b.dtype == torch.float32 else 64
+        _lib.check(load().amg_smoother_sweep(self._h, level, prec, b.data_ptr(), x.data_ptr(),
+                                             1 if backward else 0, _stream(stream)))
+
+    def integers(self, level):
+        e = _lib.amg_int_export()
+        _lib.check(load().amg_export_integers(self._h, level, C.byref(e)))
+        return _lib.export_to_dict(e)
+
+    def level(self, level):
+        """(A_l, P_l) as scipy CSR matrices copied from the device (P_l None on the coarsest)."""
+        import scipy.sparse as sp
+        info = self.info()
+        li = info[level]
+        n, nnz, pnnz = li["n"], li["nnz"], li["p_nnz"]
+        ap = np.zeros(n + 1, np.int64)
+        ac = np.zeros(max(nnz, 1), np.int32)
+        av = np.zeros(max(nnz, 1), np.float64)
+        coarsest = level == len(info) - 1
+        pp = np.zeros(n + 1, np.int64)
+        pc = np.zeros(max(pnnz, 1), np.int32)
+        pv = np.zeros(max(pnnz, 1), np.float64)
+        _lib.check(load().amg_export_level(self._h, level, ap.ctypes.data, ac.ctypes.data,
+                                           av.ctypes.data, pp.ctypes.data, pc.ctypes.data,
+                                           pv.ctypes.data))
+        A = sp.csr_matrix((av[:nnz], ac[:nnz], ap), shape=(n, n))
+        P = None
+        if not coarsest:
+            P = sp.csr_matrix((pv[:pnnz], pc[:pnnz], pp), shape=(n, info[level + 1]["n"]))
+        return A, P
+
+
+def level0_integers(A, G, **opts):
+    """Host-only integer setup of the finest level (same code as amg_setup's)."""
+    lib = load()
+    keep = []
+    a = _csr_arg(A, keep)
+    g = _csr_arg(G, keep)
+    o = _options(keep, **opts)
+    e = _lib.amg_int_export()
+    h = C.c_void_p()
+    _lib.check(lib.amg_level0_integers(C.byref(a), C.byref(g), C.byref(o), C.byref(e), C.byref(h)))
+    try:
+        return _lib.export_to_dict(e)
+    finally:
+        lib.amg_free_integers(h)
+
+
+def spmv(rowptr, colidx, val, x, y, stream=None):
+    """y = A x with the library's CSR kernel (all device tensors)."""
+    n = rowptr.shape[0] - 1
+    a = _lib.make_csr(rowptr, colidx, val, n, x.shape[0])
+    _lib.check(load().amg_spmv(C.byref(a), x.data_ptr(), y.data_ptr(), _stream(stream)))

@@ -1,0 +1,982 @@
+// C ABI of the H(curl) AMG library: hierarchy construction (host integer
+// phase + GPU numeric phase), V-cycle and PCG drivers.  See include/amg.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/amg.h"
+#include "host_setup.hpp"
+#include "kernels.hpp"
+
+using namespace hamg;
+
+namespace {
+
+thread_local std::string g_err;
+
+// HCURL_AMG_VERBOSE=1: per-phase wall times of the setup on stderr
+bool verbose() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("HCURL_AMG_VERBOSE");
+    v = (e && e[0] && e[0] != '0') ? 1 : 0;
+  }
+  return v == 1;
+}
+
+struct PhaseClock {
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void mark(hipStream_t st, const char* what, int level) {
+    if (!verbose()) return;
+    (void)hipStreamSynchronize(st);
+    auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[amg] level %d %-28s %8.3f s\n", level, what,
+                 std::chrono::duration<double>(now - t).count());
+    std::fflush(stderr);
+    t = now;
+  }
+};
+
+struct Fail {
+  amg_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(amg_status c, const std::string& m) { throw Fail{c, m}; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory) fail(AMG_ERR_OOM, std::string(what) + ": out of device memory");
+    fail(AMG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+#define HIPC(x) hip_check((x), #x)
+
+int lpr_for(int64_t n, int64_t nnz) {
+  double avg = n > 0 ? (double)nnz / (double)n : 1.0;
+  if (avg <= 6) return 4;
+  if (avg <= 40) return 8;
+  if (avg <= 100) return 16;
+  if (avg <= 250) return 32;
+  return 64;
+}
+
+// Device allocations owned by a hierarchy.
+struct Pool {
+  std::vector<void*> ptrs;
+  template <class T>
+  T* get(size_t n) {
+    if (n == 0) n = 1;
+    void* p = nullptr;
+    HIPC(hipMalloc(&p, n * sizeof(T)));
+    ptrs.push_back(p);
+    return (T*)p;
+  }
+  template <class T>
+  T* upload(const std::vector<T>& v, hipStream_t st) {
+    T* d = get<T>(v.size());
+    if (!v.empty()) HIPC(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    return d;
+  }
+  ~Pool() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+struct Stage {
+  int64_t b0, nb;
+  int smax, cmax;
+};
+
+struct Level {
+  // host side
+  Pattern Apat;
+  Incidence G;
+  Pattern S;
+  LevelInts ints;
+  bool coarsest = false;
+  // device: A
+  int64_t n = 0, nnz = 0;
+  int64_t* A_ptr = nullptr;
+  int32_t* A_col = nullptr;
+  double* A_val = nullptr;
+  float* A_val32 = nullptr;
+  int lpr_A = 8;
+  // device: P and P^T
+  int64_t nc = 0, p_nnz = 0;
+  int64_t* P_ptr = nullptr;
+  int32_t* P_col = nullptr;
+  double* P_val = nullptr;
+  float* P_val32 = nullptr;
+  int8_t* P_sign = nullptr;
+  int64_t* PT_ptr = nullptr;
+  int32_t* PT_col = nullptr;
+  double* PT_val = nullptr;
+  float* PT_val32 = nullptr;
+  int64_t* PT_perm = nullptr;
+  int lpr_P = 4, lpr_PT = 8;
+  int32_t* dof_stage = nullptr;
+  int64_t* blk_ptr = nullptr;
+  int32_t* blk_dofs = nullptr;
+  std::vector<Stage> stages;
+  int rap_mmax = 0, ap_mmax = 0;
+  int64_t ap_nnz = 0;
+  int64_t* AP_ptr = nullptr;     // A P (n x nc), kept for numeric re-setup
+  int32_t* AP_col = nullptr;
+  double* AP_val = nullptr;
+  // device: smoother
+  int64_t nstars = 0;
+  int ncolours = 0;
+  std::vector<int> colour_chunk;
+  int32_t* chunk_blk = nullptr;
+  int64_t* sb_ptr = nullptr;
+  int32_t* sb_dofs = nullptr;
+  int64_t* fac_off = nullptr;
+  int64_t fac_total = 0;
+  double* fac = nullptr;
+  float* fac32 = nullptr;
+  double* dinv = nullptr;
+  float* dinv32 = nullptr;
+  int lpr_S = 8;
+  // device: cycle vectors
+  double *x = nullptr, *t = nullptr, *b = nullptr, *r = nullptr;
+  float *x32 = nullptr, *t32 = nullptr, *b32 = nullptr, *r32 = nullptr;
+  // coarsest factor
+  double* Lc = nullptr;
+
+  template <class T>
+  CsrDev<T> A_dev() const {
+    CsrDev<T> m;
+    m.n = n; m.m = n; m.nnz = nnz; m.ptr = A_ptr; m.col = A_col; m.lpr = lpr_A;
+    if constexpr (std::is_same<T, double>::value) m.val = A_val; else m.val = A_val32;
+    return m;
+  }
+  template <class T>
+  CsrDev<T> P_dev() const {
+    CsrDev<T> m;
+    m.n = n; m.m = nc; m.nnz = p_nnz; m.ptr = P_ptr; m.col = P_col; m.lpr = lpr_P;
+    if constexpr (std::is_same<T, double>::value) m.val = P_val; else m.val = P_val32;
+    return m;
+  }
+  template <class T>
+  CsrDev<T> PT_dev() const {
+    CsrDev<T> m;
+    m.n = nc; m.m = n; m.nnz = p_nnz; m.ptr = PT_ptr; m.col = PT_col; m.lpr = lpr_PT;
+    if constexpr (std::is_same<T, double>::value) m.val = PT_val; else m.val = PT_val32;
+    return m;
+  }
+  template <class T>
+  SmootherDev<T> S_dev() const {
+    SmootherDev<T> s;
+    s.ncolours = ncolours; s.colour_chunk = colour_chunk; s.chunk_blk = chunk_blk;
+    s.sb_ptr = sb_ptr; s.sb_dofs = sb_dofs; s.fac_off = fac_off; s.lpr = lpr_S;
+    if constexpr (std::is_same<T, double>::value) s.fac = fac; else s.fac = fac32;
+    return s;
+  }
+};
+
+}  // namespace
+
+struct amg_hier {
+  amg_options opt;
+  std::vector<Level> lv;
+  Pool pool;
+  int prec = 64;
+  int* d_flag = nullptr;        // non-SPD / overflow flags
+  double* d_sc = nullptr;       // CG scalars
+  double* d_partial = nullptr;  // reduction partials
+  int64_t partial_cap = 0;
+  double* h_sc = nullptr;       // pinned host mirror of the scalars
+  double* dense_work = nullptr;
+  // PCG vectors
+  double *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr, *prold = nullptr;
+  ~amg_hier() {
+    if (h_sc) (void)hipHostFree(h_sc);
+  }
+};
+
+namespace {
+
+void check_flag(amg_hier* h, hipStream_t st, amg_status code, const std::string& msg) {
+  int f = 0;
+  HIPC(hipMemcpyAsync(&f, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  if (f) {
+    HIPC(hipMemsetAsync(h->d_flag, 0, sizeof(int), st));
+    HIPC(hipStreamSynchronize(st));
+    fail(code, msg);
+  }
+}
+
+// Host copies of a CSR (pattern, and values if wanted).
+void host_csr(const amg_csr* M, std::vector<int64_t>& ptr, std::vector<int32_t>& col,
+              std::vector<double>* val) {
+  ptr.resize(M->nrows + 1);
+  if (M->on_device) {
+    HIPC(hipMemcpy(ptr.data(), M->rowptr, ptr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(ptr.data(), M->rowptr, ptr.size() * sizeof(int64_t));
+  }
+  int64_t nnz = ptr.back();
+  if (nnz != M->nnz) fail(AMG_ERR_CSR, "rowptr[nrows] != nnz");
+  col.resize(nnz);
+  if (val) val->resize(nnz);
+  if (M->on_device) {
+    HIPC(hipMemcpy(col.data(), M->colidx, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (val) HIPC(hipMemcpy(val->data(), M->val, nnz * sizeof(double), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(col.data(), M->colidx, nnz * sizeof(int32_t));
+    if (val) std::memcpy(val->data(), M->val, nnz * sizeof(double));
+  }
+}
+
+// --- smoother: colour-sorted star blocks, chunks, factors, l1 diagonal ---
+void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
+  const LevelInts& I = L.ints;
+  int64_t ns = (int64_t)I.star_ptr.size() - 1;
+  L.nstars = ns;
+  L.ncolours = I.ncolors;
+  int maxs = 0;
+  for (int64_t b = 0; b < ns; ++b) maxs = std::max<int>(maxs, (int)(I.star_ptr[b + 1] - I.star_ptr[b]));
+  if (maxs > 32) fail(AMG_ERR_LIMIT, "smoother block with more than 32 DoFs");
+  int lpr = L.lpr_A;
+  while (lpr > 4 && 256 / lpr < std::max(maxs, 1)) lpr /= 2;
+  L.lpr_S = lpr;
+  const int rpb = 256 / lpr;
+  // blocks in (colour, id) order
+  std::vector<int64_t> order(ns);
+  {
+    std::vector<int64_t> cnt(I.ncolors + 1, 0);
+    for (int64_t b = 0; b < ns; ++b) cnt[I.star_color[b] + 1]++;
+    for (int c = 0; c < I.ncolors; ++c) cnt[c + 1] += cnt[c];
+    for (int64_t b = 0; b < ns; ++b) order[cnt[I.star_color[b]]++] = b;
+  }
+  std::vector<int64_t> sb_ptr(ns + 1, 0), fac_off(ns + 1, 0);
+  std::vector<int32_t> sb_dofs;
+  sb_dofs.reserve(I.star_dofs.size());
+  for (int64_t t = 0; t < ns; ++t) {
+    int64_t b = order[t];
+    int64_t s = I.star_ptr[b + 1] - I.star_ptr[b];
+    for (int64_t q = I.star_ptr[b]; q < I.star_ptr[b + 1]; ++q) sb_dofs.push_back(I.star_dofs[q]);
+    sb_ptr[t + 1] = sb_ptr[t] + s;
+    fac_off[t + 1] = fac_off[t] + s * (s + 1) / 2;
+  }
+  // chunks: consecutive blocks of one colour with at most rpb rows
+  std::vector<int32_t> chunk_blk;
+  L.colour_chunk.assign(I.ncolors + 1, 0);
+  int64_t t = 0;
+  for (int c = 0; c < I.ncolors; ++c) {
+    L.colour_chunk[c] = (int)chunk_blk.size();
+    while (t < ns && I.star_color[order[t]] == c) {
+      chunk_blk.push_back((int32_t)t);
+      int64_t rows = 0;
+      while (t < ns && I.star_color[order[t]] == c && rows + (sb_ptr[t + 1] - sb_ptr[t]) <= rpb) {
+        rows += sb_ptr[t + 1] - sb_ptr[t];
+        ++t;
+      }
+    }
+  }
+  L.colour_chunk[I.ncolors] = (int)chunk_blk.size();
+  chunk_blk.push_back((int32_t)ns);
+  L.chunk_blk = h->pool.upload(chunk_blk, st);
+  L.sb_ptr = h->pool.upload(sb_ptr, st);
+  L.sb_dofs = h->pool.upload(sb_dofs, st);
+  L.fac_off = h->pool.upload(fac_off, st);
+  L.fac_total = fac_off[ns];
+  L.fac = h->pool.get<double>(L.fac_total);
+  L.dinv = h->pool.get<double>(L.n);
+}
+
+void factor_smoother(amg_hier* h, Level& L, int level, hipStream_t st) {
+  star_chol(L.nstars, L.sb_ptr, L.sb_dofs, L.fac_off, L.A_dev<double>(), L.fac, h->d_flag, st);
+  check_flag(h, st, AMG_ERR_NOT_SPD, "smoother block Cholesky: non-positive pivot on level " +
+                                         std::to_string(level));
+  l1inv(L.A_dev<double>(), L.dinv, st);
+}
+
+// --- interpolation: pattern upload, exterior signs, stage-by-stage blocks ---
+void build_interp_structs(amg_hier* h, Level& L, hipStream_t st) {
+  const LevelInts& I = L.ints;
+  L.nc = (int64_t)I.r_dof1.size();
+  L.p_nnz = I.p.nnz();
+  L.P_ptr = h->pool.upload(I.p.ptr, st);
+  L.P_col = h->pool.upload(I.p.idx, st);
+  L.P_sign = h->pool.upload(I.p_ext_sign, st);
+  L.P_val = h->pool.get<double>(L.p_nnz);
+  L.lpr_P = lpr_for(L.n, L.p_nnz);
+  L.dof_stage = h->pool.upload(I.dof_stage, st);
+  L.blk_ptr = h->pool.upload(I.block_ptr, st);
+  L.blk_dofs = h->pool.upload(I.block_dofs, st);
+  L.stages.clear();
+  int64_t nst = (int64_t)I.stage_ptr.size() - 1;
+  for (int64_t s = 0; s < nst; ++s) {
+    Stage S{I.stage_ptr[s], I.stage_ptr[s + 1] - I.stage_ptr[s], 0, 0};
+    for (int64_t b = I.stage_ptr[s]; b < I.stage_ptr[s + 1]; ++b) {
+      int sz = (int)(I.block_ptr[b + 1] - I.block_ptr[b]);
+      int32_t d0 = I.block_dofs[I.block_ptr[b]];
+      int cc = (int)(I.p.ptr[d0 + 1] - I.p.ptr[d0]);
+      S.smax = std::max(S.smax, sz);
+      S.cmax = std::max(S.cmax, cc);
+    }
+    if (S.smax > 64)
+      fail(AMG_ERR_LIMIT, "extension block with more than 64 DoFs (" + std::to_string(S.smax) + ")");
+    if (ext_block_lds(S.smax, S.cmax) > 65536)
+      fail(AMG_ERR_LIMIT, "extension block of " + std::to_string(S.smax) + " DoFs x " +
+                              std::to_string(S.cmax) + " columns exceeds 64 KiB of LDS");
+    L.stages.push_back(S);
+  }
+  // P^T pattern and the permutation P entry -> P^T entry
+  int64_t n = L.n, nc = L.nc, nnz = L.p_nnz;
+  std::vector<int64_t> tptr(nc + 1, 0), perm(nnz);
+  std::vector<int32_t> tcol(nnz);
+  for (int64_t q = 0; q < nnz; ++q) tptr[I.p.idx[q] + 1]++;
+  for (int64_t c = 0; c < nc; ++c) tptr[c + 1] += tptr[c];
+  std::vector<int64_t> pos(tptr.begin(), tptr.end() - 1);
+  for (int64_t e = 0; e < n; ++e)
+    for (int64_t q = I.p.ptr[e]; q < I.p.ptr[e + 1]; ++q) {
+      int64_t d = pos[I.p.idx[q]]++;
+      tcol[d] = (int32_t)e;
+      perm[q] = d;
+    }
+  L.PT_ptr = h->pool.upload(tptr, st);
+  L.PT_col = h->pool.upload(tcol, st);
+  L.PT_perm = h->pool.upload(perm, st);
+  L.PT_val = h->pool.get<double>(nnz);
+  L.lpr_PT = lpr_for(nc, nnz);
+}
+
+void compute_interp(amg_hier* h, Level& L, int level, hipStream_t st) {
+  sign_to_val(L.p_nnz, L.P_sign, L.P_val, st);
+  for (size_t s = 0; s < L.stages.size(); ++s) {
+    const Stage& S = L.stages[s];
+    ext_blocks(S.b0, S.nb, L.blk_ptr, L.blk_dofs, L.dof_stage, (int)s, L.A_dev<double>(), L.P_ptr,
+               L.P_col, L.P_val, S.smax, S.cmax, h->d_flag, st);
+  }
+  check_flag(h, st, AMG_ERR_NOT_SPD,
+             "local harmonic extension: non-positive pivot in A_BB on level " + std::to_string(level));
+  permute(L.p_nnz, L.PT_perm, L.P_val, L.PT_val, st);
+}
+
+// --- Galerkin product A_c = P^T (A P): symbolic (once) and numeric ---
+// C = X Y symbolic: row counts, host scan, sorted columns; returns the
+// largest row length (the numeric pass's LDS size)
+int64_t mm_symbolic(amg_hier* h, int64_t nrows, const CsrPat& X, const CsrPat& Y,
+                    std::vector<int64_t>& cptr, int64_t*& d_cptr, int32_t*& d_ccol,
+                    const std::string& what, hipStream_t st) {
+  int64_t* d_cnt = h->pool.get<int64_t>(nrows);
+  mm_count(nrows, X, Y, d_cnt, h->d_flag, st);
+  check_flag(h, st, AMG_ERR_LIMIT, what + ": a row has more than " + std::to_string(mm_hash_cap()) +
+                                       " distinct columns");
+  std::vector<int64_t> cnt(nrows);
+  HIPC(hipMemcpyAsync(cnt.data(), d_cnt, nrows * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  cptr.assign(nrows + 1, 0);
+  int64_t mmax = 0;
+  for (int64_t i = 0; i < nrows; ++i) {
+    cptr[i + 1] = cptr[i] + cnt[i];
+    mmax = std::max(mmax, cnt[i]);
+  }
+  if (mmax > mm_hash_cap() / 2)
+    fail(AMG_ERR_LIMIT, what + ": row with " + std::to_string(mmax) +
+                            " entries exceeds the LDS hash capacity");
+  if ((size_t)mmax * (sizeof(double) + sizeof(int32_t)) > 65536)
+    fail(AMG_ERR_LIMIT, what + ": row too long for the numeric pass");
+  d_cptr = h->pool.upload(cptr, st);
+  d_ccol = h->pool.get<int32_t>(std::max<int64_t>(cptr[nrows], 1));
+  mm_fill(nrows, X, Y, d_cptr, d_ccol, h->d_flag, st);
+  check_flag(h, st, AMG_ERR_LIMIT, what + ": column fill overflow");
+  return mmax;
+}
+
+void galerkin_symbolic(amg_hier* h, Level& L, Level& C, int level, hipStream_t st) {
+  int64_t n = L.n, nc = L.nc;
+  std::string lv = " on level " + std::to_string(level);
+  CsrPat A{L.A_ptr, L.A_col}, P{L.P_ptr, L.P_col}, PT{L.PT_ptr, L.PT_col};
+  std::vector<int64_t> apptr;
+  L.ap_mmax = (int)mm_symbolic(h, n, A, P, apptr, L.AP_ptr, L.AP_col, "A P" + lv, st);
+  L.ap_nnz = apptr[n];
+  L.AP_val = h->pool.get<double>(std::max<int64_t>(L.ap_nnz, 1));
+  CsrPat AP{L.AP_ptr, L.AP_col};
+  std::vector<int64_t> cptr;
+  L.rap_mmax = (int)mm_symbolic(h, nc, PT, AP, cptr, C.A_ptr, C.A_col, "P^T (A P)" + lv, st);
+  C.n = nc;
+  C.nnz = cptr[nc];
+  C.A_val = h->pool.get<double>(std::max<int64_t>(C.nnz, 1));
+  C.lpr_A = lpr_for(C.n, C.nnz);
+  C.Apat.n = C.Apat.m = nc;
+  C.Apat.ptr = cptr;
+  C.Apat.idx.resize(C.nnz);
+  HIPC(hipMemcpyAsync(C.Apat.idx.data(), C.A_col, C.nnz * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+}
+
+void galerkin_numeric(amg_hier* h, Level& L, Level& C, hipStream_t st) {
+  CsrPat A{L.A_ptr, L.A_col}, P{L.P_ptr, L.P_col}, PT{L.PT_ptr, L.PT_col}, AP{L.AP_ptr, L.AP_col};
+  mm_vals(L.n, A, L.A_val, P, L.P_val, L.AP_ptr, L.AP_col, L.AP_val, L.ap_mmax, st);
+  mm_vals(L.nc, PT, L.PT_val, AP, L.AP_val, C.A_ptr, C.A_col, C.A_val, L.rap_mmax, st);
+}
+
+void coarsest_factor(amg_hier* h, Level& L, hipStream_t st) {
+  if (L.n > 8192) fail(AMG_ERR_COARSEN, "coarsest level has " + std::to_string(L.n) +
+                                            " DoFs (more than 8192 for the dense solve)");
+  if (!L.Lc) L.Lc = h->pool.get<double>((size_t)L.n * L.n);
+  dense_factor(L.n, L.A_ptr, L.A_col, L.A_val, L.Lc, h->d_flag, st);
+  check_flag(h, st, AMG_ERR_NOT_SPD, "coarsest Cholesky: non-positive pivot");
+}
+
+void cast_level(amg_hier* h, Level& L, hipStream_t st) {
+  if (!L.A_val32) L.A_val32 = h->pool.get<float>(L.nnz);
+  cast<double, float>(L.nnz, L.A_val, L.A_val32, st);
+  if (L.coarsest) return;
+  if (!L.P_val32) {
+    L.P_val32 = h->pool.get<float>(L.p_nnz);
+    L.PT_val32 = h->pool.get<float>(L.p_nnz);
+    L.fac32 = h->pool.get<float>(L.fac_total);
+    L.dinv32 = h->pool.get<float>(L.n);
+  }
+  cast<double, float>(L.p_nnz, L.P_val, L.P_val32, st);
+  cast<double, float>(L.p_nnz, L.PT_val, L.PT_val32, st);
+  cast<double, float>(L.fac_total, L.fac, L.fac32, st);
+  cast<double, float>(L.n, L.dinv, L.dinv32, st);
+}
+
+void numeric_all(amg_hier* h, hipStream_t st, PhaseClock* clk = nullptr) {
+  size_t nl = h->lv.size();
+  for (size_t l = 0; l < nl; ++l) {
+    Level& L = h->lv[l];
+    if (L.coarsest) {
+      coarsest_factor(h, L, st);
+      if (clk) clk->mark(st, "coarsest dense Cholesky (GPU)", (int)l);
+      break;
+    }
+    factor_smoother(h, L, (int)l, st);
+    if (clk) clk->mark(st, "smoother factors + l1 (GPU)", (int)l);
+    compute_interp(h, L, (int)l, st);
+    if (clk) clk->mark(st, "local extension P (GPU)", (int)l);
+    galerkin_numeric(h, L, h->lv[l + 1], st);
+    if (clk) clk->mark(st, "Galerkin numeric (GPU)", (int)l);
+  }
+  if (h->prec == 32)
+    for (auto& L : h->lv) cast_level(h, L, st);
+  HIPC(hipStreamSynchronize(st));
+}
+
+void alloc_vectors(amg_hier* h) {
+  for (size_t l = 0; l < h->lv.size(); ++l) {
+    Level& L = h->lv[l];
+    L.x = h->pool.get<double>(L.n);
+    L.t = h->pool.get<double>(L.n);
+    L.b = h->pool.get<double>(L.n);
+    L.r = h->pool.get<double>(L.n);
+    if (h->prec == 32) {
+      L.x32 = h->pool.get<float>(L.n);
+      L.t32 = h->pool.get<float>(L.n);
+      L.b32 = h->pool.get<float>(L.n);
+      L.r32 = h->pool.get<float>(L.n);
+    }
+  }
+  int64_t n = h->lv[0].n;
+  h->pr = h->pool.get<double>(n);
+  h->pz = h->pool.get<double>(n);
+  h->pp = h->pool.get<double>(n);
+  h->pq = h->pool.get<double>(n);
+  h->prold = h->pool.get<double>(n);
+  h->partial_cap = std::max<int64_t>(2 * red_grid(), spmv_dot_partials(4, n));
+  h->d_partial = h->pool.get<double>(h->partial_cap);
+  h->d_sc = h->pool.get<double>(SC_COUNT);
+  int64_t nL = h->lv.back().n;
+  h->dense_work = h->pool.get<double>(std::max<int64_t>(nL, 1));
+}
+
+// --- the V(1,1) cycle ---
+template <class T>
+struct Vec {
+  static T* x(Level& L) { if constexpr (std::is_same<T, double>::value) return L.x; else return L.x32; }
+  static T* t(Level& L) { if constexpr (std::is_same<T, double>::value) return L.t; else return L.t32; }
+  static T* b(Level& L) { if constexpr (std::is_same<T, double>::value) return L.b; else return L.b32; }
+  static T* r(Level& L) { if constexpr (std::is_same<T, double>::value) return L.r; else return L.r32; }
+  static T* dinv(Level& L) { if constexpr (std::is_same<T, double>::value) return L.dinv; else return L.dinv32; }
+};
+
+template <class T>
+void vcycle_T(amg_hier* h, const T* b0, T* x0, hipStream_t st) {
+  size_t nl = h->lv.size();
+  auto B = [&](size_t l) -> const T* { return l == 0 ? b0 : Vec<T>::b(h->lv[l]); };
+  auto X = [&](size_t l) -> T* { return l == 0 ? x0 : Vec<T>::x(h->lv[l]); };
+  for (size_t l = 0; l + 1 < nl; ++l) {
+    Level& L = h->lv[l];
+    CsrDev<T> A = L.A_dev<T>();
+    SmootherDev<T> S = L.S_dev<T>();
+    T* x = X(l);
+    fill<T>(L.n, (T)0, x, st);
+    for (int c = 0; c < S.ncolours; ++c) schwarz_colour<T>(S, A, c, B(l), x, st);
+    for (int c = S.ncolours - 1; c >= 0; --c) schwarz_colour<T>(S, A, c, B(l), x, st);
+    jacobi<T>(A, x, B(l), Vec<T>::dinv(L), Vec<T>::t(L), st);
+    residual<T>(A, Vec<T>::t(L), B(l), Vec<T>::r(L), st);
+    spmv<T>(L.PT_dev<T>(), Vec<T>::r(L), Vec<T>::b(h->lv[l + 1]), st);
+  }
+  Level& C = h->lv[nl - 1];
+  dense_solve<T>((int)C.n, C.Lc, B(nl - 1), X(nl - 1), h->dense_work, st);
+  for (size_t l = nl - 1; l-- > 0;) {
+    Level& L = h->lv[l];
+    CsrDev<T> A = L.A_dev<T>();
+    SmootherDev<T> S = L.S_dev<T>();
+    spmv_add<T>(L.P_dev<T>(), X(l + 1), Vec<T>::t(L), st);
+    T* x = X(l);
+    jacobi<T>(A, Vec<T>::t(L), B(l), Vec<T>::dinv(L), x, st);
+    for (int c = 0; c < S.ncolours; ++c) schwarz_colour<T>(S, A, c, B(l), x, st);
+    for (int c = S.ncolours - 1; c >= 0; --c) schwarz_colour<T>(S, A, c, B(l), x, st);
+  }
+}
+
+void vcycle_any(amg_hier* h, const double* r, double* z, hipStream_t st) {
+  if (h->prec == 64) {
+    vcycle_T<double>(h, r, z, st);
+  } else {
+    Level& L0 = h->lv[0];
+    cast<double, float>(L0.n, r, L0.b32, st);
+    vcycle_T<float>(h, L0.b32, L0.x32, st);
+    cast<float, double>(L0.n, L0.x32, z, st);
+  }
+}
+
+double read_scalar(amg_hier* h, int slot, hipStream_t st) {
+  HIPC(hipMemcpyAsync(h->h_sc + slot, h->d_sc + slot, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  return h->h_sc[slot];
+}
+
+template <class F>
+amg_status guarded(F&& f) {
+  try {
+    g_err.clear();
+    return f();
+  } catch (const Fail& e) {
+    g_err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return AMG_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return AMG_ERR_ARG;
+  }
+}
+
+void validate_csr_arg(const amg_csr* M, const char* name) {
+  if (!M || !M->rowptr || (M->nnz > 0 && (!M->colidx || !M->val)))
+    fail(AMG_ERR_ARG, std::string(name) + ": NULL pointer");
+  if (M->nrows < 0 || M->ncols < 0 || M->nnz < 0) fail(AMG_ERR_SHAPE, std::string(name) + ": negative size");
+}
+
+// host integer setup of the finest level + everything it needs
+struct Level0Host {
+  Pattern Apat;
+  Incidence G;
+  Pattern S;
+};
+
+void level0_host(const amg_csr* A, const amg_csr* G, Level0Host& out, std::vector<double>* Aval) {
+  validate_csr_arg(A, "A");
+  validate_csr_arg(G, "G");
+  if (A->nrows != A->ncols) fail(AMG_ERR_SHAPE, "A is not square");
+  if (G->nrows != A->nrows) fail(AMG_ERR_SHAPE, "G must have one row per row of A");
+  if (A->nrows > INT32_MAX || G->ncols > INT32_MAX) fail(AMG_ERR_SHAPE, "more than 2^31-1 rows or nodes");
+  std::vector<int64_t> gptr;
+  std::vector<int32_t> gcol;
+  std::vector<double> gval;
+  host_csr(A, out.Apat.ptr, out.Apat.idx, Aval);
+  out.Apat.n = out.Apat.m = A->nrows;
+  HostError err;
+  if (!validate_pattern(A->nrows, A->ncols, out.Apat.ptr.data(), out.Apat.idx.data(), err))
+    fail((amg_status)err.code, "A: " + err.msg);
+  host_csr(G, gptr, gcol, &gval);
+  if (!incidence_from_csr(G->nrows, G->ncols, gptr.data(), gcol.data(), gval.data(), out.G, err))
+    fail((amg_status)err.code, err.msg);
+  Incidence Gt;
+  std::vector<int32_t> B;
+  augment_g(out.G, Gt, B);
+  out.S = nodal_graph_level0(out.Apat, Gt);
+}
+
+void fill_export(const LevelInts& I, amg_int_export* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->n = I.n;
+  o->m_real = I.m_real;
+  o->n_art = I.n_art;
+  o->cf = I.cf.empty() ? nullptr : I.cf.data();
+  o->n_cg = (int64_t)I.cg.size();
+  o->cg = I.cg.data();
+  o->nc = (int64_t)I.r_dof1.size();
+  o->r_dof1 = I.r_dof1.data();
+  o->r_dof2 = I.r_dof2.data();
+  o->r_i = I.r_i.data();
+  o->r_j = I.r_j.data();
+  o->r_k = I.r_k.data();
+  o->r_s1 = I.r_s1.data();
+  o->r_s2 = I.r_s2.data();
+  o->n_interior = (int64_t)I.interior.size();
+  o->interior = I.interior.data();
+  o->nblocks = I.block_ptr.empty() ? 0 : (int64_t)I.block_ptr.size() - 1;
+  o->block_ptr = I.block_ptr.data();
+  o->block_dofs = I.block_dofs.data();
+  o->block_key_depth = I.block_depth.data();
+  o->exact_blocks = I.exact_blocks ? 1 : 0;
+  o->nstars = I.star_ptr.empty() ? 0 : (int64_t)I.star_ptr.size() - 1;
+  o->star_ptr = I.star_ptr.data();
+  o->star_dofs = I.star_dofs.data();
+  o->star_color = I.star_color.data();
+  o->ncolors = I.ncolors;
+  o->gc_nrows = I.gc.n;
+  o->gc_ncols = I.gc.m;
+  o->gc_ptr = I.gc_ptr.data();
+  o->gc_col = I.gc_col.data();
+  o->gc_val = I.gc_val.data();
+  o->gc_cols = I.gc_cols.data();
+}
+
+}  // namespace
+
+extern "C" {
+
+void amg_default_options(amg_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->interp = AMG_INTERP_ALG;
+  opt->max_levels = 20;
+  opt->min_coarse = 32;
+  opt->vcycle_prec = 64;
+  opt->ext_block_max = 64;
+  opt->stall_ratio = 0.9;
+}
+
+const char* amg_last_error(void) { return g_err.c_str(); }
+
+amg_status amg_setup(const amg_csr* A, const amg_csr* G, const amg_options* opt, void* stream,
+                     amg_hier** out) {
+  return guarded([&]() -> amg_status {
+    if (!out) fail(AMG_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    amg_options o;
+    if (opt) o = *opt; else amg_default_options(&o);
+    if (o.vcycle_prec != 64 && o.vcycle_prec != 32) fail(AMG_ERR_ARG, "vcycle_prec must be 64 or 32");
+    if (o.max_levels < 1) fail(AMG_ERR_ARG, "max_levels < 1");
+    if (o.interp == AMG_INTERP_REF && o.ref_nlevels > 0 &&
+        (!o.ref_coarse_nodes || !o.ref_ncoarse || !o.ref_coarse_bnd || !o.ref_nbnd))
+      fail(AMG_ERR_ARG, "refinement mode without coarse node lists");
+    hipStream_t st = (hipStream_t)stream;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(AMG_ERR_HIP, "no HIP device");
+    auto h = std::make_unique<amg_hier>();
+    h->opt = o;
+    h->prec = o.vcycle_prec;
+    h->d_flag = h->pool.get<int>(1);
+    HIPC(hipMemsetAsync(h->d_flag, 0, sizeof(int), st));
+    HIPC(hipHostMalloc((void**)&h->h_sc, SC_COUNT * sizeof(double), hipHostMallocDefault));
+    PhaseClock clk;
+    Level0Host l0;
+    std::vector<double> aval;
+    level0_host(A, G, l0, A->on_device ? nullptr : &aval);
+    clk.mark(st, "input copy + nodal graph", 0);
+    h->lv.emplace_back();
+    {
+      Level& L = h->lv[0];
+      L.Apat = std::move(l0.Apat);
+      L.G = std::move(l0.G);
+      L.S = std::move(l0.S);
+      L.n = A->nrows;
+      L.nnz = A->nnz;
+      L.A_ptr = h->pool.upload(L.Apat.ptr, st);
+      L.A_col = h->pool.upload(L.Apat.idx, st);
+      L.A_val = h->pool.get<double>(L.nnz);
+      if (A->on_device) {
+        HIPC(hipMemcpyAsync(L.A_val, A->val, L.nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
+      } else {
+        HIPC(hipMemcpyAsync(L.A_val, aval.data(), L.nnz * sizeof(double), hipMemcpyHostToDevice, st));
+      }
+      L.lpr_A = lpr_for(L.n, L.nnz);
+    }
+    for (int l = 0;; ++l) {
+      Level& L = h->lv[l];
+      bool stop = (l + 1 >= o.max_levels) || (L.n <= o.min_coarse);
+      if (!stop) {
+        bool use_ref = o.interp == AMG_INTERP_REF && l < o.ref_nlevels;
+        std::vector<int32_t> rc, rb;
+        if (use_ref) {
+          rc.assign(o.ref_coarse_nodes[l], o.ref_coarse_nodes[l] + o.ref_ncoarse[l]);
+          rb.assign(o.ref_coarse_bnd[l], o.ref_coarse_bnd[l] + o.ref_nbnd[l]);
+        }
+        HostError err;
+        if (!setup_level_integers(L.Apat, L.G, L.S, use_ref, rc, rb, o.ext_block_max, L.ints, err))
+          fail((amg_status)err.code, "level " + std::to_string(l) + ": " + err.msg);
+        clk.mark(st, "integer setup (Alg. 1-3, P pattern)", l);
+        int64_t nc = (int64_t)L.ints.r_dof1.size();
+        if (nc == 0 || (double)nc > o.stall_ratio * (double)L.n) stop = true;
+      }
+      if (stop) {
+        L.coarsest = true;
+        if (l == 0 && L.n > 8192) fail(AMG_ERR_COARSEN, "no coarse variables on the finest level");
+        break;
+      }
+      stars_and_colours(L.Apat, L.G, L.ints);
+      build_smoother(h.get(), L, st);
+      clk.mark(st, "smoother stars + colours", l);
+      build_interp_structs(h.get(), L, st);
+      clk.mark(st, "P structures upload", l);
+      h->lv.emplace_back();
+      Level& L2 = h->lv[l + 1];
+      Level& L1 = h->lv[l];   // re-fetch after emplace_back
+      galerkin_symbolic(h.get(), L1, L2, l, st);
+      clk.mark(st, "Galerkin symbolic (GPU)", l);
+      L2.G = L1.ints.gc;
+      L2.S = nodal_graph_coarse(L1.S, L1.ints.fine_of_next);
+      clk.mark(st, "coarse nodal graph", l);
+    }
+    numeric_all(h.get(), st, &clk);
+    alloc_vectors(h.get());
+    HIPC(hipStreamSynchronize(st));
+    *out = h.release();
+    return AMG_OK;
+  });
+}
+
+amg_status amg_resetup_numeric(amg_hier* h, const amg_csr* A, void* stream) {
+  return guarded([&]() -> amg_status {
+    if (!h) fail(AMG_ERR_ARG, "handle is NULL");
+    validate_csr_arg(A, "A");
+    Level& L0 = h->lv[0];
+    if (A->nrows != L0.n || A->nnz != L0.nnz) fail(AMG_ERR_SHAPE, "A's size differs from the setup's");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> col;
+    if (A->on_device) {
+      HIPC(hipMemcpyAsync(L0.A_val, A->val, L0.nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
+    } else {
+      HIPC(hipMemcpyAsync(L0.A_val, A->val, L0.nnz * sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    // the pattern must be the one given to amg_setup
+    host_csr(A, ptr, col, nullptr);
+    if (ptr != L0.Apat.ptr || col != L0.Apat.idx) fail(AMG_ERR_CSR, "A's pattern differs from the setup's");
+    numeric_all(h, st);
+    return AMG_OK;
+  });
+}
+
+amg_status amg_vcycle(amg_hier* h, const double* r, double* z, void* stream) {
+  return guarded([&]() -> amg_status {
+    if (!h || !r || !z) fail(AMG_ERR_ARG, "NULL argument");
+    if (r == z) fail(AMG_ERR_ARG, "r and z alias");
+    vcycle_any(h, r, z, (hipStream_t)stream);
+    HIPC(hipGetLastError());
+    return AMG_OK;
+  });
+}
+
+amg_status amg_pcg_solve(amg_hier* h, const double* f, double* u, double rtol, int maxit,
+                         amg_solve_stats* stats, void* stream) {
+  return guarded([&]() -> amg_status {
+    if (!h || !f || !u) fail(AMG_ERR_ARG, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    Level& L0 = h->lv[0];
+    int64_t n = L0.n;
+    CsrDev<double> A = L0.A_dev<double>();
+    const bool flexible = h->prec != 64;
+    double* r = h->pr;
+    double* z = h->pz;
+    double* p = h->pp;
+    double* q = h->pq;
+    double* rold = flexible ? h->prold : nullptr;
+    residual<double>(A, u, f, r, st);
+    dot2(n, r, r, nullptr, h->d_partial, st);
+    reduce(red_grid(), h->d_partial, h->d_sc, SC_RR, -1, st);
+    double r0 = std::sqrt(read_scalar(h, SC_RR, st));
+    if (!std::isfinite(r0)) fail(AMG_ERR_NOT_FINITE, "initial residual is not finite");
+    int it = 0;
+    double nr = r0;
+    if (stats && stats->history) stats->history[0] = r0;
+    if (r0 > 0.0) {
+      vcycle_any(h, r, z, st);
+      dot2(n, r, z, nullptr, h->d_partial, st);
+      reduce(red_grid(), h->d_partial, h->d_sc, SC_RZ, -1, st);
+      cg_dir(n, h->d_sc, z, p, 1, st);
+      int64_t np = spmv_dot_partials(A.lpr, n);
+      while (it < maxit) {
+        spmv_dot(A, p, q, h->d_partial, st);
+        reduce(np, h->d_partial, h->d_sc, SC_PQ, -1, st);
+        cg_scalar(h->d_sc, 0, flexible, st);
+        cg_update(n, h->d_sc, p, q, u, r, rold, h->d_partial, st);
+        reduce(red_grid(), h->d_partial, h->d_sc, SC_RR, -1, st);
+        ++it;
+        nr = std::sqrt(read_scalar(h, SC_RR, st));
+        if (stats && stats->history) stats->history[it] = nr;
+        if (!std::isfinite(nr)) fail(AMG_ERR_NOT_FINITE, "residual became non-finite");
+        if (verbose() && it % 100 == 0) {
+          std::fprintf(stderr, "[amg] pcg iteration %d relres %.3e\n", it, nr / r0);
+          std::fflush(stderr);
+        }
+        if (nr <= rtol * r0) break;
+        vcycle_any(h, r, z, st);
+        dot2(n, r, z, rold, h->d_partial, st);
+        reduce(red_grid(), h->d_partial, h->d_sc, SC_RZNEW, flexible ? SC_ROLDZ : -1, st);
+        cg_scalar(h->d_sc, 1, flexible, st);
+        cg_dir(n, h->d_sc, z, p, 0, st);
+      }
+    }
+    HIPC(hipStreamSynchronize(st));
+    auto t1 = std::chrono::steady_clock::now();
+    if (stats) {
+      stats->iterations = it;
+      stats->relres = r0 > 0 ? nr / r0 : 0.0;
+      stats->seconds = std::chrono::duration<double>(t1 - t0).count();
+      residual<double>(A, u, f, q, st);
+      dot2(n, q, q, nullptr, h->d_partial, st);
+      reduce(red_grid(), h->d_partial, h->d_sc, SC_RR, -1, st);
+      double tr = std::sqrt(read_scalar(h, SC_RR, st));
+      stats->true_relres = r0 > 0 ? tr / r0 : 0.0;
+    }
+    HIPC(hipGetLastError());
+    return (r0 == 0.0 || nr <= rtol * r0) ? AMG_OK : AMG_NOT_CONVERGED;
+  });
+}
+
+amg_status amg_smoother_sweep(amg_hier* h, int level, int prec, const void* b, void* x,
+                              int backward, void* stream) {
+  return guarded([&]() -> amg_status {
+    if (!h || !b || !x) fail(AMG_ERR_ARG, "NULL argument");
+    if (level < 0 || level + 1 >= (int)h->lv.size()) fail(AMG_ERR_ARG, "level has no smoother");
+    if (prec != 64 && prec != 32) fail(AMG_ERR_ARG, "prec must be 64 or 32");
+    if (prec == 32 && h->prec != 32) fail(AMG_ERR_ARG, "FP32 sweep needs an FP32 hierarchy");
+    Level& L = h->lv[level];
+    hipStream_t st = (hipStream_t)stream;
+    auto run = [&](auto tag) {
+      using T = decltype(tag);
+      CsrDev<T> A = L.A_dev<T>();
+      SmootherDev<T> S = L.S_dev<T>();
+      for (int k = 0; k < S.ncolours; ++k) {
+        int c = backward ? S.ncolours - 1 - k : k;
+        schwarz_colour<T>(S, A, c, (const T*)b, (T*)x, st);
+      }
+    };
+    if (prec == 64) run(double()); else run(float());
+    HIPC(hipGetLastError());
+    return AMG_OK;
+  });
+}
+
+amg_status amg_spmv(const amg_csr* A, const double* x, double* y, void* stream) {
+  return guarded([&]() -> amg_status {
+    validate_csr_arg(A, "A");
+    if (!A->on_device) fail(AMG_ERR_ARG, "amg_spmv needs device CSR arrays");
+    if (!x || !y) fail(AMG_ERR_ARG, "NULL vector");
+    CsrDev<double> M;
+    M.n = A->nrows; M.m = A->ncols; M.nnz = A->nnz;
+    M.ptr = A->rowptr; M.col = A->colidx; M.val = A->val;
+    M.lpr = lpr_for(M.n, M.nnz);
+    spmv<double>(M, x, y, (hipStream_t)stream);
+    HIPC(hipGetLastError());
+    return AMG_OK;
+  });
+}
+
+amg_status amg_hier_info(const amg_hier* h, amg_level_info* lv, int cap, int* nlevels) {
+  return guarded([&]() -> amg_status {
+    if (!h || !nlevels) fail(AMG_ERR_ARG, "NULL argument");
+    *nlevels = (int)h->lv.size();
+    for (int l = 0; l < cap && l < (int)h->lv.size(); ++l) {
+      const Level& L = h->lv[l];
+      lv[l].n = L.n;
+      lv[l].nnz = L.nnz;
+      lv[l].p_nnz = L.coarsest ? 0 : L.p_nnz;
+      lv[l].nblocks = L.coarsest ? 0 : L.nstars;
+      lv[l].ncolors = L.coarsest ? 0 : L.ncolours;
+      lv[l].exact_blocks = L.coarsest ? 0 : (L.ints.exact_blocks ? 1 : 0);
+      int64_t rows = 0, rnnz = 0;
+      if (!L.coarsest) {
+        const auto& sp = L.ints.star_ptr;
+        for (size_t b = 0; b + 1 < sp.size(); ++b)
+          for (int64_t q = sp[b]; q < sp[b + 1]; ++q) {
+            int32_t e = L.ints.star_dofs[q];
+            rnnz += L.Apat.ptr[e + 1] - L.Apat.ptr[e];
+          }
+        rows = sp.empty() ? 0 : sp.back();
+      }
+      lv[l].star_rows = rows;
+      lv[l].star_row_nnz = rnnz;
+      lv[l].fac_entries = L.coarsest ? 0 : L.fac_total;
+    }
+    return AMG_OK;
+  });
+}
+
+amg_status amg_export_integers(const amg_hier* h, int level, amg_int_export* out) {
+  return guarded([&]() -> amg_status {
+    if (!h || !out) fail(AMG_ERR_ARG, "NULL argument");
+    if (level < 0 || level + 1 >= (int)h->lv.size()) fail(AMG_ERR_ARG, "level out of range");
+    fill_export(h->lv[level].ints, out);
+    return AMG_OK;
+  });
+}
+
+amg_status amg_export_level(const amg_hier* h, int level, int64_t* a_ptr, int32_t* a_col,
+                            double* a_val, int64_t* p_ptr, int32_t* p_col, double* p_val) {
+  return guarded([&]() -> amg_status {
+    if (!h) fail(AMG_ERR_ARG, "NULL handle");
+    if (level < 0 || level >= (int)h->lv.size()) fail(AMG_ERR_ARG, "level out of range");
+    const Level& L = h->lv[level];
+    if (a_ptr) HIPC(hipMemcpy(a_ptr, L.A_ptr, (L.n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    if (a_col) HIPC(hipMemcpy(a_col, L.A_col, L.nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (a_val) HIPC(hipMemcpy(a_val, L.A_val, L.nnz * sizeof(double), hipMemcpyDeviceToHost));
+    if (!L.coarsest) {
+      if (p_ptr) HIPC(hipMemcpy(p_ptr, L.P_ptr, (L.n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+      if (p_col) HIPC(hipMemcpy(p_col, L.P_col, L.p_nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+      if (p_val) HIPC(hipMemcpy(p_val, L.P_val, L.p_nnz * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    return AMG_OK;
+  });
+}
+
+struct IntsHandle {
+  LevelInts ints;
+};
+
+amg_status amg_level0_integers(const amg_csr* A, const amg_csr* G, const amg_options* opt,
+                               amg_int_export* out, void** handle) {
+  return guarded([&]() -> amg_status {
+    if (!out || !handle) fail(AMG_ERR_ARG, "NULL argument");
+    if (A && A->on_device) fail(AMG_ERR_ARG, "amg_level0_integers takes host arrays");
+    if (G && G->on_device) fail(AMG_ERR_ARG, "amg_level0_integers takes host arrays");
+    amg_options o;
+    if (opt) o = *opt; else amg_default_options(&o);
+    Level0Host l0;
+    level0_host(A, G, l0, nullptr);
+    auto H = std::make_unique<IntsHandle>();
+    bool use_ref = o.interp == AMG_INTERP_REF && o.ref_nlevels > 0;
+    std::vector<int32_t> rc, rb;
+    if (use_ref) {
+      rc.assign(o.ref_coarse_nodes[0], o.ref_coarse_nodes[0] + o.ref_ncoarse[0]);
+      rb.assign(o.ref_coarse_bnd[0], o.ref_coarse_bnd[0] + o.ref_nbnd[0]);
+    }
+    HostError err;
+    if (!setup_level_integers(l0.Apat, l0.G, l0.S, use_ref, rc, rb, o.ext_block_max, H->ints, err))
+      fail((amg_status)err.code, err.msg);
+    stars_and_colours(l0.Apat, l0.G, H->ints);
+    fill_export(H->ints, out);
+    *handle = H.release();
+    return AMG_OK;
+  });
+}
+
+void amg_free_integers(void* handle) { delete (IntsHandle*)handle; }
+
+void amg_destroy(amg_hier* h) { delete h; }
+
+}  // extern "C"

@@ -1,0 +1,763 @@
+// Host integer phase of the H(curl) AMG setup (see host_setup.hpp).
+#include "host_setup.hpp"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <limits>
+#include <numeric>
+#include <queue>
+#include <thread>
+
+namespace hamg {
+
+namespace {
+
+// Run body(begin, end) over [0, n) split across hardware threads.
+// Host threads of the integer phase: hardware threads, at most 16 (or
+// HCURL_AMG_THREADS when set).
+unsigned host_threads() {
+  unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  hw = std::min(hw, 16u);
+  if (const char* e = std::getenv("HCURL_AMG_THREADS")) {
+    int v = std::atoi(e);
+    if (v > 0) hw = (unsigned)v;
+  }
+  return hw;
+}
+
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& body) {
+  unsigned hw = host_threads();
+  int64_t nt = std::min<int64_t>(hw, std::max<int64_t>(1, n / 4096));
+  if (nt <= 1) {
+    body(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  int64_t chunk = (n + nt - 1) / nt;
+  for (int64_t t = 0; t < nt; ++t) {
+    int64_t b = t * chunk, e = std::min(n, b + chunk);
+    if (b >= e) break;
+    th.emplace_back(body, b, e);
+  }
+  for (auto& x : th) x.join();
+}
+
+// Build a CSR pattern from per-row lists produced in parallel: count(i)
+// returns the row length, fill(i, out) writes the (sorted) row.
+template <class Count, class Fill>
+Pattern build_rows(int64_t n, int64_t m, Count count, Fill fill) {
+  Pattern P;
+  P.n = n;
+  P.m = m;
+  P.ptr.assign(n + 1, 0);
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i) P.ptr[i + 1] = count(i);
+  });
+  for (int64_t i = 0; i < n; ++i) P.ptr[i + 1] += P.ptr[i];
+  P.idx.resize(P.ptr[n]);
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i) fill(i, P.idx.data() + P.ptr[i]);
+  });
+  return P;
+}
+
+// Transpose of an incidence matrix: for each node, the rows containing it.
+Pattern node_to_rows(const Incidence& G) {
+  Pattern T;
+  T.n = G.m;
+  T.m = G.n;
+  T.ptr.assign(G.m + 1, 0);
+  for (int64_t r = 0; r < G.n; ++r) {
+    if (G.a[r] >= 0) T.ptr[G.a[r] + 1]++;
+    if (G.b[r] >= 0) T.ptr[G.b[r] + 1]++;
+  }
+  for (int64_t i = 0; i < G.m; ++i) T.ptr[i + 1] += T.ptr[i];
+  T.idx.resize(T.ptr[G.m]);
+  std::vector<int64_t> pos(T.ptr.begin(), T.ptr.end() - 1);
+  for (int64_t r = 0; r < G.n; ++r) {   // rows visited ascending: lists come out sorted
+    if (G.a[r] >= 0) T.idx[pos[G.a[r]]++] = (int32_t)r;
+    if (G.b[r] >= 0) T.idx[pos[G.b[r]]++] = (int32_t)r;
+  }
+  return T;
+}
+
+// Edge graph of G~: nodes joined by a row with two entries; per neighbour
+// the joining row (the largest row id if several rows join the same pair).
+struct EdgeGraph {
+  std::vector<int64_t> ptr;
+  std::vector<int32_t> nb;
+  std::vector<int32_t> row;
+  int32_t row_of(int32_t u, int32_t v) const {
+    auto b = nb.begin() + ptr[u], e = nb.begin() + ptr[u + 1];
+    auto it = std::lower_bound(b, e, v);
+    return row[it - nb.begin()];
+  }
+};
+
+EdgeGraph edge_graph(const Incidence& Gt) {
+  int64_t nn = Gt.m;
+  std::vector<int64_t> cnt(nn + 1, 0);
+  for (int64_t r = 0; r < Gt.n; ++r)
+    if (Gt.a[r] >= 0 && Gt.b[r] >= 0) {
+      cnt[Gt.a[r] + 1]++;
+      cnt[Gt.b[r] + 1]++;
+    }
+  for (int64_t i = 0; i < nn; ++i) cnt[i + 1] += cnt[i];
+  std::vector<std::pair<int32_t, int32_t>> tmp(cnt[nn]);
+  std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+  for (int64_t r = 0; r < Gt.n; ++r)
+    if (Gt.a[r] >= 0 && Gt.b[r] >= 0) {
+      tmp[pos[Gt.a[r]]++] = {Gt.b[r], (int32_t)r};
+      tmp[pos[Gt.b[r]]++] = {Gt.a[r], (int32_t)r};
+    }
+  EdgeGraph E;
+  E.ptr.assign(nn + 1, 0);
+  for (int64_t u = 0; u < nn; ++u) {
+    auto b = tmp.begin() + cnt[u], e = tmp.begin() + cnt[u + 1];
+    std::sort(b, e);
+    // collapse duplicate neighbours keeping the largest row
+    int64_t w = cnt[u];
+    for (auto it = b; it != e; ++it) {
+      if (w > cnt[u] && tmp[w - 1].first == it->first) {
+        tmp[w - 1].second = std::max(tmp[w - 1].second, it->second);
+      } else {
+        tmp[w++] = *it;
+      }
+    }
+    E.ptr[u + 1] = w - cnt[u];
+  }
+  for (int64_t u = 0; u < nn; ++u) E.ptr[u + 1] += E.ptr[u];
+  E.nb.resize(E.ptr[nn]);
+  E.row.resize(E.ptr[nn]);
+  for (int64_t u = 0; u < nn; ++u)
+    for (int64_t t = 0; t < E.ptr[u + 1] - E.ptr[u]; ++t) {
+      E.nb[E.ptr[u] + t] = tmp[cnt[u] + t].first;
+      E.row[E.ptr[u] + t] = tmp[cnt[u] + t].second;
+    }
+  return E;
+}
+
+int8_t entry(const Incidence& G, int64_t r, int32_t c) {
+  if (G.a[r] == c) return G.sa[r];
+  if (G.b[r] == c) return G.sb[r];
+  return 0;
+}
+
+}  // namespace
+
+bool validate_pattern(int64_t n, int64_t m, const int64_t* ptr, const int32_t* idx,
+                      HostError& err) {
+  if (ptr[0] != 0) {
+    err = {-3, "CSR row pointer does not start at 0"};
+    return false;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    if (ptr[i + 1] < ptr[i]) {
+      err = {-3, "CSR row pointers decrease at row " + std::to_string(i)};
+      return false;
+    }
+    for (int64_t t = ptr[i]; t < ptr[i + 1]; ++t) {
+      if (idx[t] < 0 || idx[t] >= m) {
+        err = {-3, "CSR column out of range in row " + std::to_string(i)};
+        return false;
+      }
+      if (t > ptr[i] && idx[t] <= idx[t - 1]) {
+        err = {-3, "CSR columns unsorted or duplicated in row " + std::to_string(i)};
+        return false;
+      }
+    }
+  }
+  return true;
+}
+
+bool incidence_from_csr(int64_t n, int64_t m, const int64_t* ptr, const int32_t* idx,
+                        const double* val, Incidence& G, HostError& err) {
+  if (!validate_pattern(n, m, ptr, idx, err)) return false;
+  G.n = n;
+  G.m = m;
+  G.a.assign(n, -1);
+  G.b.assign(n, -1);
+  G.sa.assign(n, 0);
+  G.sb.assign(n, 0);
+  for (int64_t r = 0; r < n; ++r) {
+    int64_t k = ptr[r + 1] - ptr[r];
+    if (k > 2) {
+      err = {-4, "G row " + std::to_string(r) + " has more than two entries"};
+      return false;
+    }
+    for (int64_t t = ptr[r]; t < ptr[r + 1]; ++t)
+      if (val[t] != 1.0 && val[t] != -1.0) {
+        err = {-4, "G row " + std::to_string(r) + " has an entry other than +-1"};
+        return false;
+      }
+    if (k >= 1) {
+      G.a[r] = idx[ptr[r]];
+      G.sa[r] = (int8_t)val[ptr[r]];
+    }
+    if (k == 2) {
+      G.b[r] = idx[ptr[r] + 1];
+      G.sb[r] = (int8_t)val[ptr[r] + 1];
+      if (G.sa[r] == G.sb[r]) {
+        err = {-4, "G row " + std::to_string(r) + " has two entries of the same sign"};
+        return false;
+      }
+    }
+  }
+  return true;
+}
+
+// Algorithm 1: every row with a single entry delta gets a new column -delta.
+void augment_g(const Incidence& G, Incidence& Gt, std::vector<int32_t>& B) {
+  Gt = G;
+  B.clear();
+  int64_t k = 0;
+  for (int64_t r = 0; r < G.n; ++r) {
+    if (G.nnz(r) == 1) {
+      Gt.b[r] = (int32_t)(G.m + k);
+      Gt.sb[r] = (int8_t)(-G.sa[r]);
+      B.push_back((int32_t)(G.m + k));
+      ++k;
+    }
+  }
+  Gt.m = G.m + k;
+}
+
+// Off-diagonal pattern of |G~|^T |A| |G~|: u ~ v iff some edge at u is
+// coupled in A to some edge at v.
+Pattern nodal_graph_level0(const Pattern& A, const Incidence& Gt) {
+  Pattern N2R = node_to_rows(Gt);
+  int64_t nn = Gt.m;
+  auto visit = [&](int64_t u, std::vector<int64_t>& stamp, std::vector<int32_t>& out) {
+    out.clear();
+    for (int64_t t = N2R.ptr[u]; t < N2R.ptr[u + 1]; ++t) {
+      int32_t e = N2R.idx[t];
+      for (int64_t q = A.ptr[e]; q < A.ptr[e + 1]; ++q) {
+        int32_t j = A.idx[q];
+        int32_t nodes[2] = {Gt.a[j], Gt.b[j]};
+        for (int32_t v : nodes) {
+          if (v < 0 || v == u || stamp[v] == u) continue;
+          stamp[v] = u;
+          out.push_back(v);
+        }
+      }
+    }
+    std::sort(out.begin(), out.end());
+  };
+  std::vector<std::vector<int32_t>> rows(nn);
+  parallel_for(nn, [&](int64_t b, int64_t e) {
+    std::vector<int64_t> stamp(nn, -1);
+    std::vector<int32_t> out;
+    for (int64_t u = b; u < e; ++u) {
+      visit(u, stamp, out);
+      rows[u] = out;
+    }
+  });
+  Pattern S;
+  S.n = S.m = nn;
+  S.ptr.assign(nn + 1, 0);
+  for (int64_t u = 0; u < nn; ++u) S.ptr[u + 1] = S.ptr[u] + (int64_t)rows[u].size();
+  S.idx.resize(S.ptr[nn]);
+  for (int64_t u = 0; u < nn; ++u) {
+    std::copy(rows[u].begin(), rows[u].end(), S.idx.begin() + S.ptr[u]);
+    std::vector<int32_t>().swap(rows[u]);
+  }
+  return S;
+}
+
+// u ~ v iff the fine counterparts are within distance two in S_fine.
+Pattern nodal_graph_coarse(const Pattern& Sf, const std::vector<int32_t>& fine_of) {
+  int64_t nc = (int64_t)fine_of.size();
+  int64_t nf = Sf.n;
+  // fine node -> coarse nodes standing for it
+  std::vector<int64_t> iptr(nf + 1, 0);
+  for (int64_t u = 0; u < nc; ++u) iptr[fine_of[u] + 1]++;
+  for (int64_t i = 0; i < nf; ++i) iptr[i + 1] += iptr[i];
+  std::vector<int32_t> inv(nc);
+  {
+    std::vector<int64_t> pos(iptr.begin(), iptr.end() - 1);
+    for (int64_t u = 0; u < nc; ++u) inv[pos[fine_of[u]]++] = (int32_t)u;
+  }
+  std::vector<std::vector<int32_t>> rows(nc);
+  parallel_for(nc, [&](int64_t b, int64_t e) {
+    std::vector<int64_t> fstamp(nf, -1), cstamp(nc, -1);
+    std::vector<int32_t> reach, out;
+    for (int64_t u = b; u < e; ++u) {
+      reach.clear();
+      out.clear();
+      int32_t f = fine_of[u];
+      fstamp[f] = u;
+      reach.push_back(f);
+      for (int64_t t = Sf.ptr[f]; t < Sf.ptr[f + 1]; ++t) {
+        int32_t w = Sf.idx[t];
+        if (fstamp[w] != u) { fstamp[w] = u; reach.push_back(w); }
+      }
+      size_t n1 = reach.size();
+      for (size_t q = 1; q < n1; ++q) {
+        int32_t w1 = reach[q];
+        for (int64_t t = Sf.ptr[w1]; t < Sf.ptr[w1 + 1]; ++t) {
+          int32_t w = Sf.idx[t];
+          if (fstamp[w] != u) { fstamp[w] = u; reach.push_back(w); }
+        }
+      }
+      for (int32_t w : reach)
+        for (int64_t t = iptr[w]; t < iptr[w + 1]; ++t) {
+          int32_t v = inv[t];
+          if (v == u || cstamp[v] == u) continue;
+          cstamp[v] = u;
+          out.push_back(v);
+        }
+      std::sort(out.begin(), out.end());
+      rows[u] = out;
+    }
+  });
+  Pattern S;
+  S.n = S.m = nc;
+  S.ptr.assign(nc + 1, 0);
+  for (int64_t u = 0; u < nc; ++u) S.ptr[u + 1] = S.ptr[u] + (int64_t)rows[u].size();
+  S.idx.resize(S.ptr[nc]);
+  for (int64_t u = 0; u < nc; ++u) std::copy(rows[u].begin(), rows[u].end(), S.idx.begin() + S.ptr[u]);
+  return S;
+}
+
+// Ruge-Stueben first pass: measure |N_U| + 2|N_F|; the undecided node of
+// largest measure (smallest id on ties) becomes C, its undecided
+// neighbours F; undecided neighbours of new F nodes gain one.  Buckets of
+// min-heaps with lazy deletion give exactly that selection order.
+std::vector<int8_t> rs_first_pass(const Pattern& S, const std::vector<int32_t>& c_ini,
+                                  const std::vector<int32_t>& f_ini) {
+  const int8_t U = 0, C = 1, F = 2;
+  int64_t n = S.n;
+  std::vector<int8_t> st(n, U);
+  for (int32_t c : c_ini) st[c] = C;
+  for (int32_t f : f_ini) st[f] = F;
+  std::vector<int32_t> lam(n, 0);
+  int64_t maxdeg = 0;
+  for (int64_t i = 0; i < n; ++i) maxdeg = std::max<int64_t>(maxdeg, S.ptr[i + 1] - S.ptr[i]);
+  using MinHeap = std::priority_queue<int32_t, std::vector<int32_t>, std::greater<int32_t>>;
+  std::vector<MinHeap> bucket(2 * maxdeg + 2);
+  int64_t top = -1;
+  for (int64_t i = 0; i < n; ++i) {
+    if (st[i] != U) continue;
+    int32_t l = 0;
+    for (int64_t t = S.ptr[i]; t < S.ptr[i + 1]; ++t) {
+      int8_t s = st[S.idx[t]];
+      l += (s == U) ? 1 : (s == F ? 2 : 0);
+    }
+    lam[i] = l;
+    bucket[l].push((int32_t)i);
+    top = std::max<int64_t>(top, l);
+  }
+  std::vector<int32_t> newf;
+  while (top >= 0) {
+    if (bucket[top].empty()) {
+      --top;
+      continue;
+    }
+    int32_t i = bucket[top].top();
+    bucket[top].pop();
+    if (st[i] != U || lam[i] != top) continue;
+    st[i] = C;
+    newf.clear();
+    for (int64_t t = S.ptr[i]; t < S.ptr[i + 1]; ++t) {
+      int32_t j = S.idx[t];
+      if (st[j] == U) {
+        st[j] = F;
+        newf.push_back(j);
+      }
+    }
+    for (int32_t j : newf)
+      for (int64_t t = S.ptr[j]; t < S.ptr[j + 1]; ++t) {
+        int32_t m = S.idx[t];
+        if (st[m] == U) {
+          ++lam[m];
+          bucket[lam[m]].push(m);
+          if (lam[m] > top) top = lam[m];
+        }
+      }
+  }
+  return st;
+}
+
+namespace {
+
+// Algorithm 3 over the edge graph of G~.
+void form_r(const Incidence& Gt, const EdgeGraph& E, const std::vector<int32_t>& Cp,
+            const std::vector<char>& isB, bool skip_bb, LevelInts& L) {
+  int64_t nn = Gt.m;
+  std::vector<char> inCp(nn, 0), inK(nn, 0), used(Gt.n, 0);
+  for (int32_t c : Cp) inCp[c] = 1;
+  std::vector<int64_t> stamp(nn, -1);
+  std::vector<int32_t> d2;
+  for (int32_t i : Cp) {
+    // nodes at edge distance exactly two from i
+    stamp[i] = i;
+    for (int64_t t = E.ptr[i]; t < E.ptr[i + 1]; ++t) stamp[E.nb[t]] = i;
+    d2.clear();
+    for (int64_t t = E.ptr[i]; t < E.ptr[i + 1]; ++t) {
+      int32_t k = E.nb[t];
+      for (int64_t q = E.ptr[k]; q < E.ptr[k + 1]; ++q) {
+        int32_t j = E.nb[q];
+        if (stamp[j] != i) {
+          stamp[j] = i;
+          d2.push_back(j);
+        }
+      }
+    }
+    std::sort(d2.begin(), d2.end());
+    for (int32_t j : d2) {
+      if (j <= i || !inCp[j]) continue;
+      if (skip_bb && isB[i] && isB[j]) continue;
+      // smallest mutual neighbour (sorted merge of the two lists)
+      int64_t a = E.ptr[i], ae = E.ptr[i + 1], b = E.ptr[j], be = E.ptr[j + 1];
+      int32_t k = -1;
+      while (a < ae && b < be) {
+        if (E.nb[a] == E.nb[b]) { k = E.nb[a]; break; }
+        if (E.nb[a] < E.nb[b]) ++a; else ++b;
+      }
+      if (k < 0 || inK[k]) continue;
+      int32_t dof1 = E.row_of(i, k), dof2 = E.row_of(k, j);
+      used[dof1] = used[dof2] = 1;
+      inK[k] = 1;
+      L.r_dof1.push_back(dof1);
+      L.r_dof2.push_back(dof2);
+      L.r_s1.push_back((int8_t)(-entry(Gt, dof1, i)));
+      L.r_s2.push_back(entry(Gt, dof2, j));
+      L.r_i.push_back(i);
+      L.r_j.push_back(j);
+      L.r_k.push_back(k);
+    }
+  }
+  L.interior.clear();
+  for (int64_t e = 0; e < Gt.n; ++e)
+    if (!used[e]) L.interior.push_back((int32_t)e);
+}
+
+// G_c = R G I_C: row r = s1 G(dof1,:) + s2 G(dof2,:), zero sums dropped;
+// the kept columns are the nonzero ones, ascending.
+void coarse_gradient(const Incidence& G, LevelInts& L) {
+  int64_t nc = (int64_t)L.r_dof1.size();
+  std::vector<std::vector<std::pair<int32_t, int>>> rows(nc);
+  std::vector<char> keep(G.m, 0);
+  for (int64_t r = 0; r < nc; ++r) {
+    std::pair<int32_t, int> ent[4];
+    int ne = 0;
+    auto add = [&](int32_t c, int v) {
+      if (c < 0) return;
+      for (int q = 0; q < ne; ++q)
+        if (ent[q].first == c) { ent[q].second += v; return; }
+      ent[ne++] = {c, v};
+    };
+    int64_t d1 = L.r_dof1[r], d2 = L.r_dof2[r];
+    add(G.a[d1], L.r_s1[r] * G.sa[d1]);
+    add(G.b[d1], L.r_s1[r] * G.sb[d1]);
+    add(G.a[d2], L.r_s2[r] * G.sa[d2]);
+    add(G.b[d2], L.r_s2[r] * G.sb[d2]);
+    for (int q = 0; q < ne; ++q)
+      if (ent[q].second != 0) {
+        rows[r].push_back(ent[q]);
+        keep[ent[q].first] = 1;
+      }
+    std::sort(rows[r].begin(), rows[r].end());
+  }
+  std::vector<int32_t> newid(G.m, -1);
+  L.gc_cols.clear();
+  for (int64_t c = 0; c < G.m; ++c)
+    if (keep[c]) {
+      newid[c] = (int32_t)L.gc_cols.size();
+      L.gc_cols.push_back((int32_t)c);
+    }
+  Incidence& Gc = L.gc;
+  Gc.n = nc;
+  Gc.m = (int64_t)L.gc_cols.size();
+  Gc.a.assign(nc, -1);
+  Gc.b.assign(nc, -1);
+  Gc.sa.assign(nc, 0);
+  Gc.sb.assign(nc, 0);
+  L.gc_ptr.assign(nc + 1, 0);
+  L.gc_col.clear();
+  L.gc_val.clear();
+  for (int64_t r = 0; r < nc; ++r) {
+    auto& rw = rows[r];
+    if (rw.size() >= 1) { Gc.a[r] = newid[rw[0].first]; Gc.sa[r] = (int8_t)rw[0].second; }
+    if (rw.size() >= 2) { Gc.b[r] = newid[rw[1].first]; Gc.sb[r] = (int8_t)rw[1].second; }
+    for (auto& pr : rw) {
+      L.gc_col.push_back(newid[pr.first]);
+      L.gc_val.push_back((int8_t)pr.second);
+    }
+    L.gc_ptr[r + 1] = (int64_t)L.gc_col.size();
+  }
+  // fine counterparts of the next level's nodes (real, then artificial in row order)
+  L.fine_of_next = L.gc_cols;
+  for (int64_t r = 0; r < nc; ++r)
+    if (Gc.nnz(r) == 1) {
+      int32_t bi = L.r_i[r] >= G.m ? L.r_i[r] : L.r_j[r];
+      L.fine_of_next.push_back(bi);
+    }
+}
+
+// Blocks of A_II (component blocks when all are small, otherwise owner
+// groups by BFS depth from the coarse/path nodes), then the structural
+// pattern of P.
+void extension_and_pattern(const Pattern& A, const Incidence& Gt, const EdgeGraph& E,
+                           const std::vector<int32_t>& sources, int ext_block_max, LevelInts& L) {
+  int64_t n = A.n;
+  int64_t nc = (int64_t)L.r_dof1.size();
+  std::vector<char> isint(n, 0);
+  for (int32_t e : L.interior) isint[e] = 1;
+  // --- connected components of graph(A_II) (union-find) ---
+  std::vector<int32_t> par(n);
+  std::iota(par.begin(), par.end(), 0);
+  std::function<int32_t(int32_t)> find = [&](int32_t x) {
+    while (par[x] != x) { par[x] = par[par[x]]; x = par[x]; }
+    return x;
+  };
+  for (int32_t e : L.interior)
+    for (int64_t t = A.ptr[e]; t < A.ptr[e + 1]; ++t) {
+      int32_t j = A.idx[t];
+      if (!isint[j]) continue;
+      int32_t a = find(e), b = find(j);
+      if (a != b) par[std::max(a, b)] = std::min(a, b);
+    }
+  std::vector<int32_t> csize(n, 0);
+  int32_t maxsz = 0;
+  for (int32_t e : L.interior) maxsz = std::max(maxsz, ++csize[find(e)]);
+  L.block_ptr.assign(1, 0);
+  L.block_dofs.clear();
+  L.block_depth.clear();
+  if (L.interior.empty() || maxsz <= ext_block_max) {
+    L.exact_blocks = true;
+    // components ordered by their smallest DoF; root = smallest DoF
+    std::vector<int64_t> start(n, -1);
+    std::vector<int32_t> roots;
+    for (int32_t e : L.interior) {
+      int32_t r = find(e);
+      if (r == e) roots.push_back(e);
+    }
+    std::vector<int64_t> off(n, 0);
+    int64_t acc = 0;
+    for (int32_t r : roots) { off[r] = acc; acc += csize[r]; L.block_ptr.push_back(acc); L.block_depth.push_back(0); }
+    L.block_dofs.resize(acc);
+    std::vector<int64_t> pos(n, 0);
+    for (int32_t r : roots) pos[r] = off[r];
+    for (int32_t e : L.interior) L.block_dofs[pos[find(e)]++] = e;
+  } else {
+    L.exact_blocks = false;
+    const int64_t INF = std::numeric_limits<int64_t>::max();
+    int64_t nn = Gt.m;
+    std::vector<int64_t> depth(nn, INF);
+    std::vector<int32_t> q;
+    q.reserve(nn);
+    for (int32_t s : sources) if (depth[s] == INF) { depth[s] = 0; q.push_back(s); }
+    for (size_t h = 0; h < q.size(); ++h) {
+      int32_t u = q[h];
+      for (int64_t t = E.ptr[u]; t < E.ptr[u + 1]; ++t) {
+        int32_t v = E.nb[t];
+        if (depth[v] == INF) { depth[v] = depth[u] + 1; q.push_back(v); }
+      }
+    }
+    // key = (depth of owner, owner id) or (0, -1-e) for a DoF with no node
+    std::vector<std::pair<std::pair<int64_t, int64_t>, int32_t>> keyed;
+    keyed.reserve(L.interior.size());
+    for (int32_t e : L.interior) {
+      std::pair<int64_t, int64_t> key;
+      if (Gt.a[e] < 0 && Gt.b[e] < 0) {
+        key = {0, -1 - (int64_t)e};
+      } else {
+        bool first = true;
+        int32_t nodes[2] = {Gt.a[e], Gt.b[e]};
+        for (int32_t v : nodes) {
+          if (v < 0) continue;
+          std::pair<int64_t, int64_t> c = {depth[v], v};
+          if (first || c > key) key = c;
+          first = false;
+        }
+      }
+      keyed.push_back({key, e});
+    }
+    std::sort(keyed.begin(), keyed.end());
+    for (size_t t = 0; t < keyed.size(); ++t) {
+      if (t > 0 && keyed[t].first != keyed[t - 1].first) {
+        L.block_ptr.push_back((int64_t)L.block_dofs.size());
+        L.block_depth.push_back(keyed[t - 1].first.first);
+      }
+      L.block_dofs.push_back(keyed[t].second);
+    }
+    if (!keyed.empty()) {
+      L.block_ptr.push_back((int64_t)L.block_dofs.size());
+      L.block_depth.push_back(keyed.back().first.first);
+    }
+  }
+  // --- depth stages (blocks are sorted by depth) ---
+  int64_t nb = (int64_t)L.block_depth.size();
+  L.stage_ptr.assign(1, 0);
+  L.dof_stage.assign(n, -1);
+  for (int64_t b = 0; b < nb; ++b) {
+    if (b > 0 && L.block_depth[b] != L.block_depth[b - 1]) L.stage_ptr.push_back(b);
+  }
+  L.stage_ptr.push_back(nb);
+  int64_t nst = (int64_t)L.stage_ptr.size() - 1;
+  for (int64_t s = 0; s < nst; ++s)
+    for (int64_t b = L.stage_ptr[s]; b < L.stage_ptr[s + 1]; ++b)
+      for (int64_t t = L.block_ptr[b]; t < L.block_ptr[b + 1]; ++t) L.dof_stage[L.block_dofs[t]] = (int32_t)s;
+  // --- structural pattern of P: exterior rows from R^T; a block's rows share
+  //     the union of the done-row patterns reached through A ---
+  std::vector<std::vector<int32_t>> rowcols(n);
+  std::vector<int8_t> extsign(n, 0);
+  for (int64_t r = 0; r < nc; ++r) {
+    rowcols[L.r_dof1[r]] = {(int32_t)r};
+    rowcols[L.r_dof2[r]] = {(int32_t)r};
+    extsign[L.r_dof1[r]] = L.r_s1[r];
+    extsign[L.r_dof2[r]] = L.r_s2[r];
+  }
+  std::vector<int64_t> block_cols_ptr(nb + 1, 0);
+  for (int64_t s = 0; s < nst; ++s) {
+    int64_t b0 = L.stage_ptr[s], b1 = L.stage_ptr[s + 1];
+    std::vector<std::vector<int32_t>> bcols(b1 - b0);
+    parallel_for(b1 - b0, [&](int64_t lo, int64_t hi) {
+      std::vector<int64_t> stamp(nc, -1);
+      for (int64_t bb = lo; bb < hi; ++bb) {
+        int64_t b = b0 + bb;
+        auto& out = bcols[bb];
+        for (int64_t t = L.block_ptr[b]; t < L.block_ptr[b + 1]; ++t) {
+          int32_t e = L.block_dofs[t];
+          for (int64_t q2 = A.ptr[e]; q2 < A.ptr[e + 1]; ++q2) {
+            int32_t j = A.idx[q2];
+            int32_t sj = L.dof_stage[j];
+            if (sj >= 0 && sj >= s) continue;     // not done yet
+            for (int32_t c : rowcols[j])
+              if (stamp[c] != b) { stamp[c] = b; out.push_back(c); }
+          }
+        }
+        std::sort(out.begin(), out.end());
+      }
+    });
+    for (int64_t bb = 0; bb < b1 - b0; ++bb) {
+      int64_t b = b0 + bb;
+      for (int64_t t = L.block_ptr[b]; t < L.block_ptr[b + 1]; ++t) rowcols[L.block_dofs[t]] = bcols[bb];
+    }
+  }
+  Pattern& P = L.p;
+  P.n = n;
+  P.m = nc;
+  P.ptr.assign(n + 1, 0);
+  for (int64_t e = 0; e < n; ++e) P.ptr[e + 1] = P.ptr[e] + (int64_t)rowcols[e].size();
+  P.idx.resize(P.ptr[n]);
+  L.p_ext_sign.assign(P.ptr[n], 0);
+  for (int64_t e = 0; e < n; ++e) {
+    std::copy(rowcols[e].begin(), rowcols[e].end(), P.idx.begin() + P.ptr[e]);
+    if (extsign[e] != 0) L.p_ext_sign[P.ptr[e]] = extsign[e];
+  }
+}
+
+}  // namespace
+
+void stars_and_colours(const Pattern& A, const Incidence& G, LevelInts& L) {
+  Pattern N2R = node_to_rows(G);
+  L.star_ptr.assign(1, 0);
+  L.star_dofs.clear();
+  std::vector<int32_t> star_of_node(G.m, -1);
+  for (int64_t v = 0; v < G.m; ++v) {
+    if (N2R.ptr[v + 1] == N2R.ptr[v]) continue;
+    star_of_node[v] = (int32_t)(L.star_ptr.size() - 1);
+    for (int64_t t = N2R.ptr[v]; t < N2R.ptr[v + 1]; ++t) L.star_dofs.push_back(N2R.idx[t]);
+    L.star_ptr.push_back((int64_t)L.star_dofs.size());
+  }
+  int64_t ns = (int64_t)L.star_ptr.size() - 1;
+  L.star_color.assign(ns, -1);
+  std::vector<int64_t> stamp(A.n, -1);
+  std::vector<int64_t> cstamp(64, -1);
+  int ncol = 0;
+  for (int64_t b = 0; b < ns; ++b) {
+    // colours of earlier blocks that share a DoF with, or are A-coupled to, block b
+    for (int64_t t = L.star_ptr[b]; t < L.star_ptr[b + 1]; ++t) {
+      int32_t e = L.star_dofs[t];
+      for (int64_t q = A.ptr[e]; q <= A.ptr[e + 1]; ++q) {
+        int32_t d = (q == A.ptr[e + 1]) ? e : A.idx[q];
+        if (stamp[d] == b) continue;
+        stamp[d] = b;
+        int32_t nodes[2] = {G.a[d], G.b[d]};
+        for (int32_t v : nodes) {
+          if (v < 0) continue;
+          int32_t c = star_of_node[v];
+          if (c >= 0 && c < b) {
+            int col = L.star_color[c];
+            if (col >= (int)cstamp.size()) cstamp.resize(col + 1, -1);
+            cstamp[col] = b;
+          }
+        }
+      }
+    }
+    int col = 0;
+    while (col < (int)cstamp.size() && cstamp[col] == b) ++col;
+    L.star_color[b] = col;
+    ncol = std::max(ncol, col + 1);
+  }
+  L.ncolors = ncol;
+}
+
+bool setup_level_integers(const Pattern& A, const Incidence& G, const Pattern& S, bool use_ref,
+                          const std::vector<int32_t>& ref_cg, const std::vector<int32_t>& ref_bnd,
+                          int ext_block_max, LevelInts& L, HostError& err) {
+  L.n = A.n;
+  L.m_real = G.m;
+  Incidence Gt;
+  std::vector<int32_t> B;
+  augment_g(G, Gt, B);
+  L.n_art = (int64_t)B.size();
+  if (S.n != Gt.m) {
+    err = {-2, "nodal graph size does not match G~"};
+    return false;
+  }
+  std::vector<char> isB(Gt.m, 0);
+  for (int32_t b : B) isB[b] = 1;
+  std::vector<int32_t> Cp;
+  bool skip_bb = true;
+  if (use_ref) {
+    L.cg = ref_cg;
+    std::sort(L.cg.begin(), L.cg.end());
+    L.cg.erase(std::unique(L.cg.begin(), L.cg.end()), L.cg.end());
+    for (int32_t c : L.cg)
+      if (c < 0 || c >= G.m) { err = {-1, "refinement coarse node out of range"}; return false; }
+    Cp = L.cg;
+    for (int32_t b : ref_bnd) {
+      if (b < G.m || b >= Gt.m) { err = {-1, "refinement boundary node out of range"}; return false; }
+      Cp.push_back(b);
+    }
+    skip_bb = false;
+    L.cf.clear();
+  } else {
+    std::vector<char> mark(Gt.m, 0);
+    std::vector<int32_t> f_ini;
+    for (int32_t b : B)
+      for (int64_t t = S.ptr[b]; t < S.ptr[b + 1]; ++t) {
+        int32_t v = S.idx[t];
+        if (!isB[v] && !mark[v]) { mark[v] = 1; f_ini.push_back(v); }
+      }
+    std::sort(f_ini.begin(), f_ini.end());
+    L.cf = rs_first_pass(S, B, f_ini);
+    L.cg.clear();
+    for (int64_t u = 0; u < G.m; ++u)
+      if (L.cf[u] == 1) L.cg.push_back((int32_t)u);
+    Cp = L.cg;
+    Cp.insert(Cp.end(), B.begin(), B.end());
+  }
+  std::sort(Cp.begin(), Cp.end());
+  Cp.erase(std::unique(Cp.begin(), Cp.end()), Cp.end());
+  EdgeGraph E = edge_graph(Gt);
+  L.r_dof1.clear(); L.r_dof2.clear(); L.r_s1.clear(); L.r_s2.clear();
+  L.r_i.clear(); L.r_j.clear(); L.r_k.clear();
+  form_r(Gt, E, Cp, isB, skip_bb, L);
+  if (L.r_dof1.empty()) return true;
+  std::vector<int32_t> sources = Cp;
+  sources.insert(sources.end(), L.r_k.begin(), L.r_k.end());
+  std::sort(sources.begin(), sources.end());
+  sources.erase(std::unique(sources.begin(), sources.end()), sources.end());
+  extension_and_pattern(A, Gt, E, sources, ext_block_max, L);
+  coarse_gradient(G, L);
+  return true;
+}
+
+}  // namespace hamg

@@ -1,0 +1,802 @@
+// HIP kernels (gfx950) of the H(curl) AMG solver.
+//
+// Solve phase (memory-bound; CSR rows are streamed by groups of LPR lanes of
+// a 64-wide wavefront, reduced with cross-lane shuffles):
+//   k_spmv        y = A x and fused epilogues (residual, l1-Jacobi step,
+//                 prolongation add, dot-product partials)
+//   k_schwarz     one colour of the multiplicative Schwarz sweep over
+//                 node-star blocks (residual rows -> LDS, block Cholesky
+//                 solve, update)
+//   k_dense_solve coarsest-level FP64 Cholesky solve (one workgroup)
+//   PCG helpers   deterministic two-stage reductions and vector updates
+// Setup phase:
+//   k_ext_block   local harmonic extension X_B = -A_BB^{-1} A_B,: P_done
+//                 (one wavefront per block, LDS-resident dense block)
+//   k_mm_*        sparse products by row merge (A P, then P^T (A P)): LDS
+//                 hash symbolic pass, sorted column fill, deterministic
+//                 numeric pass
+//   k_star_chol   Cholesky factors of the smoother's diagonal blocks
+//   k_l1inv, casts, dense coarsest factorisation
+#include "kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+namespace hamg {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+template <int LPR, class T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int off = LPR / 2; off > 0; off >>= 1) v += __shfl_down(v, off, LPR);
+  return v;
+}
+
+__device__ __forceinline__ int lower_bound_i32(const int32_t* a, int n, int32_t key) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+template <class T> void fill(int64_t n, T v, T* x, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// SpMV family
+// ---------------------------------------------------------------------------
+enum { EPI_Y = 0, EPI_RES = 1, EPI_JAC = 2, EPI_ADD = 3, EPI_DOT = 4 };
+
+template <class T, int LPR, int EPI>
+__global__ __launch_bounds__(256) void k_spmv(int64_t n, const int64_t* __restrict__ ptr,
+                                              const int32_t* __restrict__ col,
+                                              const T* __restrict__ val, const T* __restrict__ x,
+                                              const T* __restrict__ b, const T* __restrict__ dinv,
+                                              T* __restrict__ y, double* __restrict__ partial) {
+  constexpr int RPB = 256 / LPR;
+  const int lane = threadIdx.x % LPR;
+  const int grp = threadIdx.x / LPR;
+  const int64_t row = (int64_t)blockIdx.x * RPB + grp;
+  T s = 0;
+  if (row < n) {
+    const int64_t e = ptr[row + 1];
+    for (int64_t q = ptr[row] + lane; q < e; q += LPR) s += val[q] * x[col[q]];
+  }
+  s = group_sum<LPR>(s);
+  double d = 0.0;
+  if (row < n && lane == 0) {
+    if (EPI == EPI_Y) y[row] = s;
+    if (EPI == EPI_RES) y[row] = b[row] - s;
+    if (EPI == EPI_JAC) y[row] = x[row] + (b[row] - s) * dinv[row];
+    if (EPI == EPI_ADD) y[row] += s;
+    if (EPI == EPI_DOT) {
+      y[row] = s;
+      d = (double)s * (double)x[row];
+    }
+  }
+  if (EPI == EPI_DOT) {
+    __shared__ double red[RPB];
+    if (lane == 0) red[grp] = d;
+    __syncthreads();
+    for (int w = RPB / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  }
+}
+
+template <class T, int EPI>
+static void spmv_lpr(int lpr, hipStream_t st, int64_t n, const int64_t* ptr, const int32_t* col,
+                     const T* val, const T* x, const T* b, const T* dinv, T* y, double* partial) {
+  if (n <= 0) return;
+#define LAUNCH_SPMV(L)                                                                        \
+  {                                                                                           \
+    int64_t grid = (n + (256 / L) - 1) / (256 / L);                                           \
+    hipLaunchKernelGGL((k_spmv<T, L, EPI>), dim3((unsigned)grid), dim3(256), 0, st, n, ptr, col, \
+                       val, x, b, dinv, y, partial);                                          \
+  }
+  switch (lpr) {
+    case 4: LAUNCH_SPMV(4); break;
+    case 8: LAUNCH_SPMV(8); break;
+    case 16: LAUNCH_SPMV(16); break;
+    case 32: LAUNCH_SPMV(32); break;
+    default: LAUNCH_SPMV(64); break;
+  }
+#undef LAUNCH_SPMV
+}
+
+int64_t spmv_dot_partials(int lpr, int64_t n) {
+  int64_t rpb = 256 / lpr;
+  return (n + rpb - 1) / rpb;
+}
+
+template <class T>
+void spmv(const CsrDev<T>& A, const T* x, T* y, hipStream_t st) {
+  spmv_lpr<T, EPI_Y>(A.lpr, st, A.n, A.ptr, A.col, A.val, x, nullptr, nullptr, y, nullptr);
+}
+template <class T>
+void residual(const CsrDev<T>& A, const T* x, const T* b, T* r, hipStream_t st) {
+  spmv_lpr<T, EPI_RES>(A.lpr, st, A.n, A.ptr, A.col, A.val, x, b, nullptr, r, nullptr);
+}
+template <class T>
+void jacobi(const CsrDev<T>& A, const T* x, const T* b, const T* dinv, T* xn, hipStream_t st) {
+  spmv_lpr<T, EPI_JAC>(A.lpr, st, A.n, A.ptr, A.col, A.val, x, b, dinv, xn, nullptr);
+}
+template <class T>
+void spmv_add(const CsrDev<T>& A, const T* x, T* y, hipStream_t st) {
+  spmv_lpr<T, EPI_ADD>(A.lpr, st, A.n, A.ptr, A.col, A.val, x, nullptr, nullptr, y, nullptr);
+}
+void spmv_dot(const CsrDev<double>& A, const double* x, double* y, double* partial,
+              hipStream_t st) {
+  spmv_lpr<double, EPI_DOT>(A.lpr, st, A.n, A.ptr, A.col, A.val, x, nullptr, nullptr, y, partial);
+}
+
+// ---------------------------------------------------------------------------
+// multiplicative Schwarz: one colour
+// ---------------------------------------------------------------------------
+// chunk c covers blocks [chunk_blk[c], chunk_blk[c+1]); their rows are
+// contiguous in sb_dofs and number at most 256/LPR.  Blocks of one colour
+// share no DoF and no coupling, so chunks update x independently.
+template <class T, int LPR>
+__global__ __launch_bounds__(256) void k_schwarz(
+    const int32_t* __restrict__ chunk_blk, int chunk0, const int64_t* __restrict__ sb_ptr,
+    const int32_t* __restrict__ sb_dofs, const int64_t* __restrict__ fac_off,
+    const T* __restrict__ fac, const int64_t* __restrict__ Aptr, const int32_t* __restrict__ Acol,
+    const T* __restrict__ Aval, const T* __restrict__ b, T* __restrict__ x) {
+  constexpr int RPB = 256 / LPR;
+  __shared__ T res[RPB];
+  const int c = chunk0 + blockIdx.x;
+  const int blk0 = chunk_blk[c], blk1 = chunk_blk[c + 1];
+  const int64_t r0 = sb_ptr[blk0];
+  const int nrows = (int)(sb_ptr[blk1] - r0);
+  const int grp = threadIdx.x / LPR, lane = threadIdx.x % LPR;
+  if (grp < nrows) {
+    const int32_t dof = sb_dofs[r0 + grp];
+    T s = 0;
+    const int64_t e = Aptr[dof + 1];
+    for (int64_t q = Aptr[dof] + lane; q < e; q += LPR) s += Aval[q] * x[Acol[q]];
+    s = group_sum<LPR>(s);
+    if (lane == 0) res[grp] = b[dof] - s;
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < blk1 - blk0) {
+    const int blk = blk0 + t;
+    const int off = (int)(sb_ptr[blk] - r0);
+    const int sz = (int)(sb_ptr[blk + 1] - sb_ptr[blk]);
+    const T* L = fac + fac_off[blk];
+    T* v = res + off;
+    for (int i = 0; i < sz; ++i) {
+      T a = v[i];
+      const T* Li = L + i * (i + 1) / 2;
+      for (int j = 0; j < i; ++j) a -= Li[j] * v[j];
+      v[i] = a / Li[i];
+    }
+    for (int i = sz - 1; i >= 0; --i) {
+      T a = v[i];
+      for (int j = i + 1; j < sz; ++j) a -= L[j * (j + 1) / 2 + i] * v[j];
+      v[i] = a / L[i * (i + 1) / 2 + i];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < nrows) x[sb_dofs[r0 + threadIdx.x]] += res[threadIdx.x];
+}
+
+template <class T>
+void schwarz_colour(const SmootherDev<T>& S, const CsrDev<T>& A, int colour, const T* b, T* x,
+                    hipStream_t st) {
+  int c0 = S.colour_chunk[colour], c1 = S.colour_chunk[colour + 1];
+  if (c1 <= c0) return;
+#define LAUNCH_SW(L)                                                                          \
+  hipLaunchKernelGGL((k_schwarz<T, L>), dim3(c1 - c0), dim3(256), 0, st, S.chunk_blk, c0,      \
+                     S.sb_ptr, S.sb_dofs, S.fac_off, S.fac, A.ptr, A.col, A.val, b, x);
+  switch (S.lpr) {
+    case 4: LAUNCH_SW(4); break;
+    case 8: LAUNCH_SW(8); break;
+    case 16: LAUNCH_SW(16); break;
+    case 32: LAUNCH_SW(32); break;
+    default: LAUNCH_SW(64); break;
+  }
+#undef LAUNCH_SW
+}
+
+// ---------------------------------------------------------------------------
+// coarsest level: x = (L L^T)^{-1} b with a dense FP64 factor, one workgroup
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void k_dense_solve(int n, const double* __restrict__ L,
+                                                     const T* __restrict__ b, T* __restrict__ x,
+                                                     double* __restrict__ work) {
+  // work: n doubles (global scratch for the running right-hand side)
+  for (int i = threadIdx.x; i < n; i += blockDim.x) work[i] = (double)b[i];
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    double yk = work[k] / L[(int64_t)k * n + k];
+    __syncthreads();
+    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) work[i] -= L[(int64_t)i * n + k] * yk;
+    if (threadIdx.x == 0) work[k] = yk;
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    double xk = work[k] / L[(int64_t)k * n + k];
+    __syncthreads();
+    for (int i = threadIdx.x; i < k; i += blockDim.x) work[i] -= L[(int64_t)k * n + i] * xk;
+    if (threadIdx.x == 0) work[k] = xk;
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = (T)work[i];
+}
+
+template <class T>
+void dense_solve(int n, const double* L, const T* b, T* x, double* work, hipStream_t st) {
+  hipLaunchKernelGGL((k_dense_solve<T>), dim3(1), dim3(256), 0, st, n, L, b, x, work);
+}
+
+// dense gather of a (small) CSR matrix into row-major n x n
+__global__ void k_csr_to_dense(int64_t n, const int64_t* __restrict__ ptr,
+                               const int32_t* __restrict__ col, const double* __restrict__ val,
+                               double* __restrict__ D) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q) D[i * n + col[q]] = val[q];
+}
+
+// right-looking dense Cholesky (lower, row-major; upper part left as is)
+__global__ __launch_bounds__(256) void k_dense_chol(int n, double* __restrict__ D,
+                                                    int* __restrict__ flag) {
+  for (int k = 0; k < n; ++k) {
+    __shared__ double dk;
+    if (threadIdx.x == 0) {
+      double a = D[(int64_t)k * n + k];
+      if (!(a > 0.0)) {
+        *flag = 1;
+        a = 1.0;
+      }
+      dk = sqrt(a);
+      D[(int64_t)k * n + k] = dk;
+    }
+    __syncthreads();
+    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) D[(int64_t)i * n + k] /= dk;
+    __syncthreads();
+    // trailing update of the lower triangle: rows i > k, cols k < j <= i
+    int64_t m = n - k - 1;
+    for (int64_t t = threadIdx.x; t < m * m; t += blockDim.x) {
+      int64_t i = k + 1 + t / m, j = k + 1 + t % m;
+      if (j <= i) D[i * n + j] -= D[i * n + k] * D[j * n + k];
+    }
+    __syncthreads();
+  }
+}
+
+void dense_factor(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, double* D,
+                  int* flag, hipStream_t st) {
+  fill<double>(n * n, 0.0, D, st);
+  hipLaunchKernelGGL(k_csr_to_dense, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, ptr,
+                     col, val, D);
+  hipLaunchKernelGGL(k_dense_chol, dim3(1), dim3(256), 0, st, (int)n, D, flag);
+}
+
+// ---------------------------------------------------------------------------
+// vector kernels (FP64 PCG, casts, fills)
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_fill(int64_t n, T v, T* __restrict__ x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+template <class A, class B>
+__global__ void k_cast(int64_t n, const A* __restrict__ a, B* __restrict__ b) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = (B)a[i];
+}
+
+static unsigned grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+template <class T>
+void fill(int64_t n, T v, T* x, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(n)), dim3(256), 0, st, n, v, x);
+}
+template <class A, class B>
+void cast(int64_t n, const A* a, B* b, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL((k_cast<A, B>), dim3(grid_for(n)), dim3(256), 0, st, n, a, b);
+}
+
+// Deterministic reductions: a fixed grid of RED_GRID blocks, each summing a
+// fixed strided subset in a fixed order, then one block summing the partials.
+constexpr int RED_GRID = 1024;
+
+__device__ __forceinline__ double block_sum256(double v) {
+  __shared__ double red[256];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// x += alpha p; r -= alpha q; partial[b] = sum r.r
+__global__ __launch_bounds__(256) void k_cg_update(int64_t n, const double* __restrict__ sc,
+                                                   const double* __restrict__ p,
+                                                   const double* __restrict__ q,
+                                                   double* __restrict__ x, double* __restrict__ r,
+                                                   double* __restrict__ r_old,
+                                                   double* __restrict__ partial) {
+  const double alpha = sc[SC_ALPHA];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)RED_GRID * 256) {
+    x[i] += alpha * p[i];
+    double ri = r[i];
+    if (r_old) r_old[i] = ri;
+    ri -= alpha * q[i];
+    r[i] = ri;
+    acc += ri * ri;
+  }
+  acc = block_sum256(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// partial sums of a.b (and, if c != NULL, of c.b)
+__global__ __launch_bounds__(256) void k_dot2(int64_t n, const double* __restrict__ a,
+                                              const double* __restrict__ b,
+                                              const double* __restrict__ c,
+                                              double* __restrict__ partial) {
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)RED_GRID * 256) {
+    s0 += a[i] * b[i];
+    if (c) s1 += c[i] * b[i];
+  }
+  s0 = block_sum256(s0);
+  s1 = block_sum256(s1);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = s0;
+    partial[RED_GRID + blockIdx.x] = s1;
+  }
+}
+
+// sum `count` partials into sc[slot] (and a second set into sc[slot2])
+__global__ __launch_bounds__(256) void k_reduce(int64_t count, const double* __restrict__ partial,
+                                                double* __restrict__ sc, int slot, int slot2) {
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += 256) s += partial[i];
+  s = block_sum256(s);
+  double s2 = 0.0;
+  if (slot2 >= 0) {
+    for (int64_t i = threadIdx.x; i < count; i += 256) s2 += partial[RED_GRID + i];
+    s2 = block_sum256(s2);
+  }
+  if (threadIdx.x == 0) {
+    sc[slot] = s;
+    if (slot2 >= 0) sc[slot2] = s2;
+  }
+}
+
+// scalar step of CG: mode 0: alpha = rz / pq; mode 1: beta (FR or PR), rz = rz_new
+__global__ void k_cg_scalar(double* sc, int mode, int flexible) {
+  if (threadIdx.x != 0) return;
+  if (mode == 0) {
+    sc[SC_ALPHA] = sc[SC_RZ] / sc[SC_PQ];
+  } else {
+    double beta = flexible ? (sc[SC_RZNEW] - sc[SC_ROLDZ]) / sc[SC_RZ] : sc[SC_RZNEW] / sc[SC_RZ];
+    sc[SC_BETA] = beta;
+    sc[SC_RZ] = sc[SC_RZNEW];
+  }
+}
+
+// p = z + beta p; on the first iteration p = z (p is not read: it may hold
+// anything, and 0 * NaN would poison the direction)
+__global__ __launch_bounds__(256) void k_cg_dir(int64_t n, const double* __restrict__ sc,
+                                                const double* __restrict__ z,
+                                                double* __restrict__ p, int first) {
+  if (first) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+      p[i] = z[i];
+    return;
+  }
+  const double beta = sc[SC_BETA];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = z[i] + beta * p[i];
+}
+
+void cg_update(int64_t n, const double* sc, const double* p, const double* q, double* x, double* r,
+               double* r_old, double* partial, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_update, dim3(RED_GRID), dim3(256), 0, st, n, sc, p, q, x, r, r_old,
+                     partial);
+}
+void dot2(int64_t n, const double* a, const double* b, const double* c, double* partial,
+          hipStream_t st) {
+  hipLaunchKernelGGL(k_dot2, dim3(RED_GRID), dim3(256), 0, st, n, a, b, c, partial);
+}
+void reduce(int64_t count, const double* partial, double* sc, int slot, int slot2, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, count, partial, sc, slot, slot2);
+}
+void cg_scalar(double* sc, int mode, int flexible, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(64), 0, st, sc, mode, flexible);
+}
+void cg_dir(int64_t n, const double* sc, const double* z, double* p, int first, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_dir, dim3(grid_for(n)), dim3(256), 0, st, n, sc, z, p, first);
+}
+int red_grid() { return RED_GRID; }
+
+// ---------------------------------------------------------------------------
+// setup: local harmonic extension (eq. (sparseP))
+// ---------------------------------------------------------------------------
+// One 64-lane workgroup per block B (|B| <= 64): lane a gathers row a of
+// A_BB and of the right-hand side A_B,: P_done (sequentially, so the sum
+// order is fixed), the block is Cholesky-factored in LDS and every
+// right-hand-side column is solved by one lane; P rows get -X.
+__global__ __launch_bounds__(64) void k_ext_block(
+    int64_t b0, const int64_t* __restrict__ bptr, const int32_t* __restrict__ bdofs,
+    const int32_t* __restrict__ dof_stage, int stage, const int64_t* __restrict__ Aptr,
+    const int32_t* __restrict__ Acol, const double* __restrict__ Aval,
+    const int64_t* __restrict__ Pptr, const int32_t* __restrict__ Pcol, double* __restrict__ Pval,
+    int smax, int cmax, int* __restrict__ flag) {
+  extern __shared__ unsigned char lds_raw[];
+  double* Abb = (double*)lds_raw;                 // smax * smax
+  double* R = Abb + smax * smax;                   // smax * cmax
+  int32_t* cols = (int32_t*)(R + smax * cmax);     // cmax
+  int32_t* dofs = cols + cmax;                     // smax
+  const int64_t blk = b0 + blockIdx.x;
+  const int64_t d0 = bptr[blk];
+  const int s = (int)(bptr[blk + 1] - d0);
+  const int32_t first = bdofs[d0];
+  const int64_t c0 = Pptr[first];
+  const int c = (int)(Pptr[first + 1] - c0);
+  const int lane = threadIdx.x;
+  for (int t = lane; t < c; t += 64) cols[t] = Pcol[c0 + t];
+  for (int t = lane; t < s; t += 64) dofs[t] = bdofs[d0 + t];
+  for (int t = lane; t < s * s; t += 64) Abb[t] = 0.0;
+  for (int t = lane; t < s * c; t += 64) R[t] = 0.0;
+  __syncthreads();
+  if (lane < s) {
+    const int32_t e = dofs[lane];
+    double* Rr = R + lane * c;
+    for (int64_t q = Aptr[e]; q < Aptr[e + 1]; ++q) {
+      const int32_t j = Acol[q];
+      const double a = Aval[q];
+      const int pos = lower_bound_i32(dofs, s, j);
+      if (pos < s && dofs[pos] == j) {
+        Abb[lane * s + pos] = a;
+        continue;
+      }
+      const int sj = dof_stage[j];
+      if (sj >= 0 && sj >= stage) continue;  // not extended yet
+      for (int64_t u = Pptr[j]; u < Pptr[j + 1]; ++u) {
+        const int cp = lower_bound_i32(cols, c, Pcol[u]);
+        if (cp < c && cols[cp] == Pcol[u]) {
+          Rr[cp] += a * Pval[u];
+        } else {
+          atomicExch(flag, 2);   // pattern mismatch (cannot happen for host-built patterns)
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // Cholesky (lower) of Abb in place, lane i owns row i
+  for (int k = 0; k < s; ++k) {
+    if (lane == 0) {
+      double a = Abb[k * s + k];
+      if (!(a > 0.0)) {
+        atomicExch(flag, 1);
+        a = 1.0;
+      }
+      Abb[k * s + k] = sqrt(a);
+    }
+    __syncthreads();
+    const double dk = Abb[k * s + k];
+    if (lane > k && lane < s) Abb[lane * s + k] /= dk;
+    __syncthreads();
+    if (lane > k && lane < s)
+      for (int j = k + 1; j <= lane; ++j) Abb[lane * s + j] -= Abb[lane * s + k] * Abb[j * s + k];
+    __syncthreads();
+  }
+  // solve L L^T X = R column by column; write P = -X
+  for (int t = lane; t < c; t += 64) {
+    for (int i = 0; i < s; ++i) {
+      double v = R[i * c + t];
+      for (int j = 0; j < i; ++j) v -= Abb[i * s + j] * R[j * c + t];
+      R[i * c + t] = v / Abb[i * s + i];
+    }
+    for (int i = s - 1; i >= 0; --i) {
+      double v = R[i * c + t];
+      for (int j = i + 1; j < s; ++j) v -= Abb[j * s + i] * R[j * c + t];
+      R[i * c + t] = v / Abb[i * s + i];
+    }
+    for (int i = 0; i < s; ++i) Pval[Pptr[dofs[i]] + t] = -R[i * c + t];
+  }
+}
+
+size_t ext_block_lds(int smax, int cmax) {
+  return sizeof(double) * ((size_t)smax * smax + (size_t)smax * cmax) +
+         sizeof(int32_t) * ((size_t)cmax + (size_t)smax);
+}
+
+void ext_blocks(int64_t b0, int64_t nb, const int64_t* bptr, const int32_t* bdofs,
+                const int32_t* dof_stage, int stage, const CsrDev<double>& A,
+                const int64_t* Pptr, const int32_t* Pcol, double* Pval, int smax, int cmax,
+                int* flag, hipStream_t st) {
+  if (nb <= 0) return;
+  size_t lds = ext_block_lds(smax, cmax);
+  hipLaunchKernelGGL(k_ext_block, dim3((unsigned)nb), dim3(64), lds, st, b0, bptr, bdofs,
+                     dof_stage, stage, A.ptr, A.col, A.val, Pptr, Pcol, Pval, smax, cmax, flag);
+}
+
+// P values from the exterior signs (interior entries start at 0)
+__global__ void k_sign_to_val(int64_t n, const int8_t* __restrict__ s, double* __restrict__ v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = (double)s[i];
+}
+void sign_to_val(int64_t n, const int8_t* s, double* v, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_sign_to_val, dim3(grid_for(n)), dim3(256), 0, st, n, s, v);
+}
+
+// PT values by a precomputed permutation
+__global__ void k_permute(int64_t n, const int64_t* __restrict__ perm, const double* __restrict__ a,
+                          double* __restrict__ b) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    b[perm[i]] = a[i];
+}
+void permute(int64_t n, const int64_t* perm, const double* a, double* b, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_permute, dim3(grid_for(n)), dim3(256), 0, st, n, perm, a, b);
+}
+
+// ---------------------------------------------------------------------------
+// setup: sparse products C = X Y (row merge), used for A P and P^T (A P)
+// ---------------------------------------------------------------------------
+constexpr int HCAP = 8192;   // LDS hash slots of the symbolic passes (32 KiB)
+
+// insert the columns of row i of X Y into an LDS hash; the 256 threads take
+// the entries of X's row in turn and walk the matching rows of Y
+__device__ void mm_insert(int64_t i, const int64_t* Xptr, const int32_t* Xcol, const int64_t* Yptr,
+                          const int32_t* Ycol, int32_t* hash, int* count, int* overflow) {
+  for (int64_t t = Xptr[i] + threadIdx.x; t < Xptr[i + 1]; t += blockDim.x) {
+    const int32_t k = Xcol[t];
+    for (int64_t u = Yptr[k]; u < Yptr[k + 1]; ++u) {
+      const int32_t J = Ycol[u];
+      uint32_t h = ((uint32_t)J * 2654435761u) & (HCAP - 1);
+      int probes = 0;
+      while (true) {
+        int32_t old = atomicCAS(&hash[h], -1, J);
+        if (old == -1) {
+          atomicAdd(count, 1);
+          break;
+        }
+        if (old == J) break;
+        h = (h + 1) & (HCAP - 1);
+        if (++probes >= HCAP) {
+          atomicExch(overflow, 1);
+          break;
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mm_count(int64_t nrows, const int64_t* __restrict__ Xptr,
+                                                  const int32_t* __restrict__ Xcol,
+                                                  const int64_t* __restrict__ Yptr,
+                                                  const int32_t* __restrict__ Ycol,
+                                                  int64_t* __restrict__ cnt,
+                                                  int* __restrict__ overflow) {
+  __shared__ int32_t hash[HCAP];
+  __shared__ int count;
+  const int64_t i = blockIdx.x;
+  for (int t = threadIdx.x; t < HCAP; t += blockDim.x) hash[t] = -1;
+  if (threadIdx.x == 0) count = 0;
+  __syncthreads();
+  mm_insert(i, Xptr, Xcol, Yptr, Ycol, hash, &count, overflow);
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[i] = count;
+}
+
+// sorted columns of row i (its length, from k_mm_count, is at most HCAP / 2)
+__global__ __launch_bounds__(256) void k_mm_fill(int64_t nrows, const int64_t* __restrict__ Xptr,
+                                                 const int32_t* __restrict__ Xcol,
+                                                 const int64_t* __restrict__ Yptr,
+                                                 const int32_t* __restrict__ Ycol,
+                                                 const int64_t* __restrict__ Cptr,
+                                                 int32_t* __restrict__ Ccol,
+                                                 int* __restrict__ overflow) {
+  __shared__ int32_t hash[HCAP];
+  __shared__ int count;
+  __shared__ int nfill;
+  const int64_t i = blockIdx.x;
+  for (int t = threadIdx.x; t < HCAP; t += blockDim.x) hash[t] = -1;
+  if (threadIdx.x == 0) {
+    count = 0;
+    nfill = 0;
+  }
+  __syncthreads();
+  mm_insert(i, Xptr, Xcol, Yptr, Ycol, hash, &count, overflow);
+  __syncthreads();
+  // gather the keys into registers, then compact them to the front
+  int32_t keys[HCAP / 256];
+  int nk = 0;
+  for (int t = threadIdx.x; t < HCAP; t += blockDim.x)
+    if (hash[t] >= 0) keys[nk++] = hash[t];
+  __syncthreads();
+  for (int t = threadIdx.x; t < HCAP; t += blockDim.x) hash[t] = 0x7fffffff;
+  __syncthreads();
+  for (int t = 0; t < nk; ++t) hash[atomicAdd(&nfill, 1)] = keys[t];
+  __syncthreads();
+  const int m = nfill;
+  int P2 = 1;
+  while (P2 < m) P2 <<= 1;
+  // bitonic sort of hash[0 .. P2) (padding holds INT_MAX)
+  for (int k = 2; k <= P2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int q = threadIdx.x; q < P2; q += blockDim.x) {
+        int qj = q ^ j;
+        if (qj > q) {
+          int32_t a = hash[q], b = hash[qj];
+          bool up = (q & k) == 0;
+          if ((a > b) == up) {
+            hash[q] = b;
+            hash[qj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const int64_t o = Cptr[i];
+  for (int t = threadIdx.x; t < m; t += blockDim.x) Ccol[o + t] = hash[t];
+}
+
+// numeric pass of row i: C[i,:] = sum_t X[i,t] Y[t,:] in the stored order of
+// X's row; lanes own distinct columns of one Y row at a time, so every
+// accumulator slot is updated in a fixed order (deterministic)
+__global__ __launch_bounds__(64) void k_mm_vals(
+    int64_t nrows, const int64_t* __restrict__ Xptr, const int32_t* __restrict__ Xcol,
+    const double* __restrict__ Xval, const int64_t* __restrict__ Yptr,
+    const int32_t* __restrict__ Ycol, const double* __restrict__ Yval,
+    const int64_t* __restrict__ Cptr, const int32_t* __restrict__ Ccol, double* __restrict__ Cval,
+    int mmax) {
+  extern __shared__ unsigned char lds_raw[];
+  double* acc = (double*)lds_raw;          // mmax
+  int32_t* cols = (int32_t*)(acc + mmax);  // mmax
+  const int64_t i = blockIdx.x;
+  const int64_t o = Cptr[i];
+  const int m = (int)(Cptr[i + 1] - o);
+  const int lane = threadIdx.x;
+  for (int t = lane; t < m; t += 64) {
+    cols[t] = Ccol[o + t];
+    acc[t] = 0.0;
+  }
+  __syncthreads();
+  for (int64_t t = Xptr[i]; t < Xptr[i + 1]; ++t) {
+    const int32_t k = Xcol[t];
+    const double x = Xval[t];
+    for (int64_t u = Yptr[k] + lane; u < Yptr[k + 1]; u += 64) {
+      const int pos = lower_bound_i32(cols, m, Ycol[u]);
+      if (pos < m && cols[pos] == Ycol[u]) acc[pos] += x * Yval[u];
+    }
+    __syncthreads();
+  }
+  for (int t = lane; t < m; t += 64) Cval[o + t] = acc[t];
+}
+
+void mm_count(int64_t nrows, const CsrPat& X, const CsrPat& Y, int64_t* cnt, int* overflow,
+              hipStream_t st) {
+  if (nrows > 0)
+    hipLaunchKernelGGL(k_mm_count, dim3((unsigned)nrows), dim3(256), 0, st, nrows, X.ptr, X.col,
+                       Y.ptr, Y.col, cnt, overflow);
+}
+void mm_fill(int64_t nrows, const CsrPat& X, const CsrPat& Y, const int64_t* Cptr, int32_t* Ccol,
+             int* overflow, hipStream_t st) {
+  if (nrows > 0)
+    hipLaunchKernelGGL(k_mm_fill, dim3((unsigned)nrows), dim3(256), 0, st, nrows, X.ptr, X.col,
+                       Y.ptr, Y.col, Cptr, Ccol, overflow);
+}
+void mm_vals(int64_t nrows, const CsrPat& X, const double* Xval, const CsrPat& Y,
+             const double* Yval, const int64_t* Cptr, const int32_t* Ccol, double* Cval, int mmax,
+             hipStream_t st) {
+  if (nrows <= 0) return;
+  size_t lds = (size_t)std::max(mmax, 1) * (sizeof(double) + sizeof(int32_t));
+  hipLaunchKernelGGL(k_mm_vals, dim3((unsigned)nrows), dim3(64), lds, st, nrows, X.ptr, X.col,
+                     Xval, Y.ptr, Y.col, Yval, Cptr, Ccol, Cval, mmax);
+}
+int mm_hash_cap() { return HCAP; }
+
+// ---------------------------------------------------------------------------
+// setup: smoother factors and l1 diagonal
+// ---------------------------------------------------------------------------
+constexpr int MAXS = 32;
+
+// one thread per block: gather the lower triangle of A_BB, factor, store packed
+__global__ void k_star_chol(int64_t nb, const int64_t* __restrict__ sb_ptr,
+                            const int32_t* __restrict__ sb_dofs, const int64_t* __restrict__ fac_off,
+                            const int64_t* __restrict__ Aptr, const int32_t* __restrict__ Acol,
+                            const double* __restrict__ Aval, double* __restrict__ fac,
+                            int* __restrict__ flag) {
+  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const int64_t d0 = sb_ptr[b];
+  const int s = (int)(sb_ptr[b + 1] - d0);
+  double* L = fac + fac_off[b];
+  for (int i = 0; i < s; ++i) {
+    const int32_t e = sb_dofs[d0 + i];
+    const int64_t q0 = Aptr[e];
+    const int len = (int)(Aptr[e + 1] - q0);
+    for (int j = 0; j <= i; ++j) {
+      const int32_t d = sb_dofs[d0 + j];
+      const int pos = lower_bound_i32(Acol + q0, len, d);
+      L[i * (i + 1) / 2 + j] = (pos < len && Acol[q0 + pos] == d) ? Aval[q0 + pos] : 0.0;
+    }
+  }
+  for (int j = 0; j < s; ++j) {
+    double a = L[j * (j + 1) / 2 + j];
+    for (int k = 0; k < j; ++k) a -= L[j * (j + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+    if (!(a > 0.0)) {
+      atomicExch(flag, 1);
+      a = 1.0;
+    }
+    const double d = sqrt(a);
+    L[j * (j + 1) / 2 + j] = d;
+    for (int i = j + 1; i < s; ++i) {
+      double v = L[i * (i + 1) / 2 + j];
+      for (int k = 0; k < j; ++k) v -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+      L[i * (i + 1) / 2 + j] = v / d;
+    }
+  }
+}
+
+void star_chol(int64_t nb, const int64_t* sb_ptr, const int32_t* sb_dofs, const int64_t* fac_off,
+               const CsrDev<double>& A, double* fac, int* flag, hipStream_t st) {
+  if (nb > 0)
+    hipLaunchKernelGGL(k_star_chol, dim3((unsigned)((nb + 127) / 128)), dim3(128), 0, st, nb,
+                       sb_ptr, sb_dofs, fac_off, A.ptr, A.col, A.val, fac, flag);
+}
+
+__global__ void k_l1inv(int64_t n, const int64_t* __restrict__ ptr, const double* __restrict__ val,
+                        double* __restrict__ dinv) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q) s += fabs(val[q]);
+    dinv[i] = 1.0 / s;
+  }
+}
+void l1inv(const CsrDev<double>& A, double* dinv, hipStream_t st) {
+  if (A.n > 0)
+    hipLaunchKernelGGL(k_l1inv, dim3(grid_for(A.n)), dim3(256), 0, st, A.n, A.ptr, A.val, dinv);
+}
+
+// ---------------------------------------------------------------------------
+// explicit instantiations
+// ---------------------------------------------------------------------------
+template void spmv<double>(const CsrDev<double>&, const double*, double*, hipStream_t);
+template void spmv<float>(const CsrDev<float>&, const float*, float*, hipStream_t);
+template void residual<double>(const CsrDev<double>&, const double*, const double*, double*, hipStream_t);
+template void residual<float>(const CsrDev<float>&, const float*, const float*, float*, hipStream_t);
+template void jacobi<double>(const CsrDev<double>&, const double*, const double*, const double*, double*, hipStream_t);
+template void jacobi<float>(const CsrDev<float>&, const float*, const float*, const float*, float*, hipStream_t);
+template void spmv_add<double>(const CsrDev<double>&, const double*, double*, hipStream_t);
+template void spmv_add<float>(const CsrDev<float>&, const float*, float*, hipStream_t);
+template void schwarz_colour<double>(const SmootherDev<double>&, const CsrDev<double>&, int, const double*, double*, hipStream_t);
+template void schwarz_colour<float>(const SmootherDev<float>&, const CsrDev<float>&, int, const float*, float*, hipStream_t);
+template void dense_solve<double>(int, const double*, const double*, double*, double*, hipStream_t);
+template void dense_solve<float>(int, const double*, const float*, float*, double*, hipStream_t);
+template void fill<double>(int64_t, double, double*, hipStream_t);
+template void fill<float>(int64_t, float, float*, hipStream_t);
+template void cast<double, float>(int64_t, const double*, float*, hipStream_t);
+template void cast<float, double>(int64_t, const float*, double*, hipStream_t);
+
+}  // namespace hamg

@@ -1,0 +1,93 @@
+// Device data structures and kernel launchers of the H(curl) AMG solver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+namespace hamg {
+
+// Device CSR matrix (values of type T); lpr = lanes per row of the row kernels.
+template <class T>
+struct CsrDev {
+  int64_t n = 0, m = 0, nnz = 0;
+  const int64_t* ptr = nullptr;
+  const int32_t* col = nullptr;
+  const T* val = nullptr;
+  int lpr = 8;
+};
+
+// Device pattern only.
+struct CsrPat {
+  const int64_t* ptr = nullptr;
+  const int32_t* col = nullptr;
+};
+
+// Smoother blocks sorted by colour and packed into chunks for k_schwarz.
+template <class T>
+struct SmootherDev {
+  int ncolours = 0;
+  std::vector<int> colour_chunk;        // host: chunk range of each colour
+  const int32_t* chunk_blk = nullptr;   // first block of each chunk (+ sentinel)
+  const int64_t* sb_ptr = nullptr;      // rows of each block (colour order)
+  const int32_t* sb_dofs = nullptr;
+  const int64_t* fac_off = nullptr;     // packed lower factor offset of each block
+  const T* fac = nullptr;
+  int lpr = 8;
+};
+
+// scalar slots of the CG state vector
+enum { SC_RZ = 0, SC_PQ = 1, SC_ALPHA = 2, SC_BETA = 3, SC_RR = 4, SC_RZNEW = 5, SC_ROLDZ = 6,
+       SC_COUNT = 8 };
+
+template <class T> void spmv(const CsrDev<T>& A, const T* x, T* y, hipStream_t st);
+template <class T> void residual(const CsrDev<T>& A, const T* x, const T* b, T* r, hipStream_t st);
+template <class T>
+void jacobi(const CsrDev<T>& A, const T* x, const T* b, const T* dinv, T* xn, hipStream_t st);
+template <class T> void spmv_add(const CsrDev<T>& A, const T* x, T* y, hipStream_t st);
+void spmv_dot(const CsrDev<double>& A, const double* x, double* y, double* partial, hipStream_t st);
+int64_t spmv_dot_partials(int lpr, int64_t n);
+
+template <class T>
+void schwarz_colour(const SmootherDev<T>& S, const CsrDev<T>& A, int colour, const T* b, T* x,
+                    hipStream_t st);
+template <class T>
+void dense_solve(int n, const double* L, const T* b, T* x, double* work, hipStream_t st);
+void dense_factor(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, double* D,
+                  int* flag, hipStream_t st);
+
+template <class T> void fill(int64_t n, T v, T* x, hipStream_t st);
+template <class A, class B> void cast(int64_t n, const A* a, B* b, hipStream_t st);
+
+void cg_update(int64_t n, const double* sc, const double* p, const double* q, double* x, double* r,
+               double* r_old, double* partial, hipStream_t st);
+void dot2(int64_t n, const double* a, const double* b, const double* c, double* partial,
+          hipStream_t st);
+void reduce(int64_t count, const double* partial, double* sc, int slot, int slot2, hipStream_t st);
+void cg_scalar(double* sc, int mode, int flexible, hipStream_t st);
+void cg_dir(int64_t n, const double* sc, const double* z, double* p, int first, hipStream_t st);
+int red_grid();
+
+size_t ext_block_lds(int smax, int cmax);
+void ext_blocks(int64_t b0, int64_t nb, const int64_t* bptr, const int32_t* bdofs,
+                const int32_t* dof_stage, int stage, const CsrDev<double>& A,
+                const int64_t* Pptr, const int32_t* Pcol, double* Pval, int smax, int cmax,
+                int* flag, hipStream_t st);
+void sign_to_val(int64_t n, const int8_t* s, double* v, hipStream_t st);
+void permute(int64_t n, const int64_t* perm, const double* a, double* b, hipStream_t st);
+
+void mm_count(int64_t nrows, const CsrPat& X, const CsrPat& Y, int64_t* cnt, int* overflow,
+              hipStream_t st);
+void mm_fill(int64_t nrows, const CsrPat& X, const CsrPat& Y, const int64_t* Cptr, int32_t* Ccol,
+             int* overflow, hipStream_t st);
+void mm_vals(int64_t nrows, const CsrPat& X, const double* Xval, const CsrPat& Y,
+             const double* Yval, const int64_t* Cptr, const int32_t* Ccol, double* Cval, int mmax,
+             hipStream_t st);
+int mm_hash_cap();
+
+void star_chol(int64_t nb, const int64_t* sb_ptr, const int32_t* sb_dofs, const int64_t* fac_off,
+               const CsrDev<double>& A, double* fac, int* flag, hipStream_t st);
+void l1inv(const CsrDev<double>& A, double* dinv, hipStream_t st);
+
+}  // namespace hamg

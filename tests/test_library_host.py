@@ -1,0 +1,122 @@
+"""Host-side checks of the compiled library (no GPU needed): it loads, it
+exports every function include/amg.h declares, and its integer setup of the
+finest level is bit-exact with the oracle (Algorithms 1-3, G_c, extension
+blocks, smoother stars and colours)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import gen
+from gen import fields
+import paper_2602_23613_amd as amglib
+from paper_2602_23613_amd import _lib
+from oracle import amg
+from refsel import RefSelector
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_function():
+    lib = _lib.load()
+    hdr = open(os.path.join(ROOT, "include", "amg.h")).read()
+    names = set(re.findall(r"\b(amg_[a-z0-9_]+)\s*\(", hdr))
+    assert names, "no declarations found"
+    for nm in sorted(names):
+        assert hasattr(lib, nm), nm
+    assert set(_lib.EXPORTED) <= names
+
+
+def oracle_level0(p, ref=None):
+    lv = amg.Level(A=p.A, G=p.G)
+    lv.Gt, lv.B = amg.augment_g(p.G)
+    lv.S = amg.nodal_graph(p.A, lv.Gt)
+    if ref is not None:
+        cg, bc = ref
+        lv.cG, lv.cf = np.sort(cg), None
+        Cp = np.concatenate([lv.cG, bc])
+    else:
+        lv.cG, lv.cf = amg.nodal_cf(lv.S, lv.B)
+        Cp = np.concatenate([lv.cG, lv.B])
+    n = p.A.shape[0]
+    lv.rr, lv.interior = amg.form_r(lv.Gt, Cp, lv.B, n, skip_bb=ref is None)
+    lv.blocks, lv.depths, lv.exact_blocks = amg.extension_blocks(
+        p.A, lv.Gt, lv.interior, np.concatenate([Cp, lv.rr.k]))
+    Gc, cols = amg.coarse_gradient(p.G, lv.rr)
+    lv.smoother = amg.smoother_setup(p.A, p.G)
+    return lv, Gc, cols
+
+
+def compare_integers(d, lv, Gc, cols):
+    """Assert the library's exported integers equal the oracle level's."""
+    if lv.cf is not None:
+        assert np.array_equal(d["cf"], lv.cf)
+    assert np.array_equal(d["cg"], lv.cG)
+    for f in ("dof1", "dof2", "i", "j", "k", "s1", "s2"):
+        assert np.array_equal(d["r_" + f], getattr(lv.rr, f)), f
+    assert np.array_equal(d["interior"], lv.interior)
+    ob = np.concatenate([[0], np.cumsum([len(b) for b in lv.blocks])]).astype(np.int64)
+    assert np.array_equal(d["block_ptr"], ob)
+    if len(lv.blocks):
+        assert np.array_equal(d["block_dofs"], np.concatenate(lv.blocks))
+    assert np.array_equal(d["block_depth"], lv.depths)
+    assert d["exact_blocks"] == lv.exact_blocks
+    sm = lv.smoother
+    sp_ = np.concatenate([[0], np.cumsum([len(b) for b in sm.blocks])]).astype(np.int64)
+    assert np.array_equal(d["star_ptr"], sp_)
+    assert np.array_equal(d["star_dofs"], np.concatenate(sm.blocks))
+    assert np.array_equal(d["star_color"], sm.color)
+    assert d["ncolors"] == sm.ncolors
+    assert np.array_equal(d["gc_ptr"], Gc.indptr)
+    assert np.array_equal(d["gc_col"], Gc.indices)
+    assert np.array_equal(d["gc_val"], Gc.data.astype(np.int64))
+    assert np.array_equal(d["gc_cols"], cols)
+
+
+CASES = [("tri", 4, {}, 1.0), ("tri", 5, {}, "stripes"), ("hex", 6, {}, 1.0),
+         ("hex", 9, {}, "jump"), ("tet", 4, dict(jitter=0.2, mesh_seed=4), "checker"),
+         ("tet", 5, dict(jitter=0.2, mesh_seed=7), 1.0)]
+
+
+def alpha_of(name):
+    return {1.0: 1.0, "stripes": lambda m: fields.stripes_2d(m),
+            "jump": lambda m: fields.subdomain_log_uniform(m, 3, 2),
+            "checker": lambda m: fields.checkerboard(m, 2)}[name]
+
+
+@pytest.mark.parametrize("kind,size,kw,alpha", CASES)
+def test_level0_integers_bit_exact(kind, size, kw, alpha):
+    p = gen.make_problem(kind, size, alpha=alpha_of(alpha), **kw)
+    d = amglib.level0_integers(p.A, p.G)
+    lv, Gc, cols = oracle_level0(p)
+    compare_integers(d, lv, Gc, cols)
+
+
+def test_level0_integers_refinement_mode_bit_exact():
+    p = gen.make_problem("tri", 4, beta=0.01)
+    lv0 = amg.Level(A=p.A, G=p.G)
+    lv0.Gt, lv0.B = amg.augment_g(p.G)
+    cg, bc = RefSelector(p)(0, lv0)
+    d = amglib.level0_integers(p.A, p.G, interp="ref", ref=[(cg, bc)])
+    lv, Gc, cols = oracle_level0(p, ref=(cg, bc))
+    compare_integers(d, lv, Gc, cols)
+
+
+def test_bad_gradient_is_rejected():
+    p = gen.make_problem("hex", 3)
+    G = p.G.tolil()
+    G[0, 5] = 1.0
+    G[0, 6] = -1.0   # now three entries in row 0
+    with pytest.raises(amglib.AmgError) as e:
+        amglib.level0_integers(p.A, G.tocsr())
+    assert e.value.status == -4
+
+
+def test_unsorted_csr_is_rejected():
+    p = gen.make_problem("hex", 3)
+    A = p.A.copy()
+    A.indices[[0, 1]] = A.indices[[1, 0]]
+    with pytest.raises(amglib.AmgError) as e:
+        amglib.level0_integers(A, p.G)
+    assert e.value.status == -3
