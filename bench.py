@@ -96,10 +96,10 @@ def vcycle_bytes(info, w):
     return tot
 
 
-def one_step(amg, Ad, Gd, f, torch, prec, maxit):
+def one_step(amg, Ad, Gd, f, torch, prec, maxit, p_trunc=0.0):
     log(f"fp{prec}: setup + solve")
     t0 = time.perf_counter()
-    H = amg.Hierarchy(Ad, Gd, vcycle_prec=prec)
+    H = amg.Hierarchy(Ad, Gd, vcycle_prec=prec, p_trunc=p_trunc)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     u = torch.zeros_like(f)
@@ -186,6 +186,9 @@ def main():
     ap.add_argument("--size", type=int, default=64)
     ap.add_argument("--beta", type=float, default=1.0)
     ap.add_argument("--maxit", type=int, default=5000)
+    ap.add_argument("--p-trunc", type=float, default=0.0,
+                    help="drop interior P entries below this fraction of the row max "
+                         "(an option outside the paper; 0 = the paper's P)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--kernels-only", action="store_true",
@@ -212,7 +215,7 @@ def main():
     del p
     torch.cuda.synchronize()
     if a.kernels_only:
-        H = amg.Hierarchy(Ad, Gd, vcycle_prec=64)
+        H = amg.Hierarchy(Ad, Gd, vcycle_prec=64, p_trunc=a.p_trunc)
         log("levels", [(l["n"], l["nnz"], l["ncolors"]) for l in H.info()])
         kt = time_kernels(amg, H, f, torch)
         log(f"kernels: {kt}")
@@ -223,7 +226,7 @@ def main():
     headline = None
     for prec in ([64] if a.no_fp32 else [64, 32]):
         for w in range(a.warmup):
-            H, r = one_step(amg, Ad, Gd, f, torch, prec, a.maxit)
+            H, r = one_step(amg, Ad, Gd, f, torch, prec, a.maxit, a.p_trunc)
             H.close()
             log(f"fp{prec} warmup {w}: {r}")
         torch.cuda.synchronize()
@@ -233,7 +236,7 @@ def main():
         for k in range(a.steps):
             if H is not None:
                 H.close()
-            H, r = one_step(amg, Ad, Gd, f, torch, prec, a.maxit)
+            H, r = one_step(amg, Ad, Gd, f, torch, prec, a.maxit, a.p_trunc)
             runs.append(r)
             log(f"fp{prec} step {k}: {r}")
         torch.cuda.synchronize()

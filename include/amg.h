@@ -76,6 +76,9 @@ typedef struct {
   int vcycle_prec;         /* 64: FP64 V-cycle; 32: FP32 V-cycle (FP64 coarsest solve) */
   int ext_block_max;       /* 64: largest connected component of graph(A_II) solved as one exact block */
   double stall_ratio;      /* 0.9: stop when n_{l+1} > stall_ratio * n_l */
+  double p_trunc;          /* 0: the paper's P.  > 0: after the local solves, drop interior-row
+                              entries of P below p_trunc * (row max |p|) (an option outside the
+                              paper that bounds the growth of the coarse operators) */
   /* AMG_INTERP_REF only: for levels 0 .. ref_nlevels-1 the coarse nodes come
      from the geometric refinement instead of Algorithm 2.  Per level l:
      ref_coarse_nodes[l] (ref_ncoarse[l] entries) lists coarse real nodes

@@ -429,6 +429,21 @@ def _csr_union(M, r, c, v, n, nc):
     return sp.csr_matrix((vv, cc, indptr), shape=(n, nc))
 
 
+def truncate_interior(P, interior, tau):
+    """Optional sparsification (not in the paper): on interior rows drop the
+    entries with |p_ij| < tau * max_j |p_ij|; exterior rows (R^T) are kept."""
+    if tau <= 0.0:
+        return P
+    P = sp.csr_matrix(P, copy=True)
+    rowmax = np.asarray(abs(P).max(axis=1).todense()).ravel()
+    rows = np.repeat(np.arange(P.shape[0]), np.diff(P.indptr))
+    isint = np.zeros(P.shape[0], dtype=bool)
+    isint[np.asarray(interior, dtype=np.int64)] = True
+    keep = ~isint[rows] | (np.abs(P.data) >= tau * rowmax[rows])
+    indptr = np.concatenate([[0], np.cumsum(np.bincount(rows[keep], minlength=P.shape[0]))])
+    return sp.csr_matrix((P.data[keep], P.indices[keep], indptr), shape=P.shape)
+
+
 def galerkin(A, P):
     """A_c = P^T (A P), keeping every structural nonzero."""
     AP = structural_product(A, P)
@@ -532,7 +547,7 @@ class Hierarchy:
 
 
 DEFAULTS = dict(interp="alg", max_levels=20, min_coarse=32, ext_block_max=64,
-                ref_select=None, stall_ratio=0.9)
+                ref_select=None, stall_ratio=0.9, p_trunc=0.0)
 
 
 def setup(A, G, **opts):
@@ -543,7 +558,8 @@ def setup(A, G, **opts):
     (coarse real nodes, coarse artificial nodes)); R and S_I by Algorithm 3;
     P by local harmonic extension; A_{l+1} = P^T A_l P; G_{l+1} = R G_l I_C.
     Coarsening stops at max_levels, when n <= min_coarse, when R is empty or
-    when n_{l+1} > stall_ratio * n_l.  The coarsest level is solved by a dense
+    when n_{l+1} > stall_ratio * n_l.  p_trunc > 0 drops small interior
+    entries of P (an option outside the paper, off by default).  The coarsest level is solved by a dense
     Cholesky factorisation."""
     o = dict(DEFAULTS)
     o.update(opts)
@@ -586,6 +602,7 @@ def setup(A, G, **opts):
         lv.blocks, lv.depths, lv.exact_blocks = extension_blocks(
             lv.A, lv.Gt, lv.interior, sources, o["ext_block_max"])
         lv.P = interpolation(lv.A, Rt, lv.blocks, lv.depths)
+        lv.P = truncate_interior(lv.P, lv.interior, o["p_trunc"])
         Ac = galerkin(lv.A, lv.P)
         Gc, cols = coarse_gradient(lv.G, lv.rr)
         lv.Gc_cols = cols

@@ -40,7 +40,7 @@ def _csr_arg(M, keep):
 
 
 def _options(keep, interp="alg", max_levels=20, min_coarse=32, vcycle_prec=64, ext_block_max=64,
-             stall_ratio=0.9, ref=None):
+             stall_ratio=0.9, p_trunc=0.0, ref=None):
     o = _lib.default_options()
     o.interp = _lib.AMG_INTERP_REF if interp == "ref" else _lib.AMG_INTERP_ALG
     o.max_levels = max_levels
@@ -48,6 +48,7 @@ def _options(keep, interp="alg", max_levels=20, min_coarse=32, vcycle_prec=64, e
     o.vcycle_prec = vcycle_prec
     o.ext_block_max = ext_block_max
     o.stall_ratio = stall_ratio
+    o.p_trunc = p_trunc
     if ref:
         # ref: list of (coarse real nodes, coarse artificial nodes) per level
         nl = len(ref)

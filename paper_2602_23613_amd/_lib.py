@@ -45,6 +45,7 @@ class amg_csr(C.Structure):
 class amg_options(C.Structure):
     _fields_ = [("interp", C.c_int), ("max_levels", C.c_int), ("min_coarse", C.c_int64),
                 ("vcycle_prec", C.c_int), ("ext_block_max", C.c_int), ("stall_ratio", C.c_double),
+                ("p_trunc", C.c_double),
                 ("ref_nlevels", C.c_int),
                 ("ref_coarse_nodes", C.POINTER(C.POINTER(C.c_int32))),
                 ("ref_ncoarse", C.POINTER(C.c_int64)),

@@ -123,6 +123,8 @@ struct Level {
   float* PT_val32 = nullptr;
   int64_t* PT_perm = nullptr;
   int lpr_P = 4, lpr_PT = 8;
+  std::vector<int64_t> p_ptr_h;   // host copy of P's current pattern
+  std::vector<int32_t> p_col_h;
   int32_t* dof_stage = nullptr;
   int64_t* blk_ptr = nullptr;
   int32_t* blk_dofs = nullptr;
@@ -136,6 +138,8 @@ struct Level {
   int64_t nstars = 0;
   int ncolours = 0;
   std::vector<int> colour_chunk;
+  int32_t* colour_chunk_dev = nullptr;
+  bool one_launch = false;
   int32_t* chunk_blk = nullptr;
   int64_t* sb_ptr = nullptr;
   int32_t* sb_dofs = nullptr;
@@ -177,6 +181,7 @@ struct Level {
   SmootherDev<T> S_dev() const {
     SmootherDev<T> s;
     s.ncolours = ncolours; s.colour_chunk = colour_chunk; s.chunk_blk = chunk_blk;
+    s.colour_chunk_dev = colour_chunk_dev; s.one_launch = one_launch;
     s.sb_ptr = sb_ptr; s.sb_dofs = sb_dofs; s.fac_off = fac_off; s.lpr = lpr_S;
     if constexpr (std::is_same<T, double>::value) s.fac = fac; else s.fac = fac32;
     return s;
@@ -287,6 +292,9 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   L.colour_chunk[I.ncolors] = (int)chunk_blk.size();
   chunk_blk.push_back((int32_t)ns);
   L.chunk_blk = h->pool.upload(chunk_blk, st);
+  L.colour_chunk_dev = h->pool.upload(std::vector<int32_t>(L.colour_chunk.begin(), L.colour_chunk.end()), st);
+  // small levels: the whole sweep in one launch (colours are many, chunks few)
+  L.one_launch = L.nnz <= 200000;
   L.sb_ptr = h->pool.upload(sb_ptr, st);
   L.sb_dofs = h->pool.upload(sb_dofs, st);
   L.fac_off = h->pool.upload(fac_off, st);
@@ -333,28 +341,66 @@ void build_interp_structs(amg_hier* h, Level& L, hipStream_t st) {
                               std::to_string(S.cmax) + " columns exceeds 64 KiB of LDS");
     L.stages.push_back(S);
   }
-  // P^T pattern and the permutation P entry -> P^T entry
+  L.p_ptr_h = I.p.ptr;
+  L.p_col_h = I.p.idx;
+}
+
+// P^T pattern and the permutation P entry -> P^T entry, from the host copy of
+// P's (possibly truncated) pattern
+void build_transpose(amg_hier* h, Level& L, hipStream_t st) {
   int64_t n = L.n, nc = L.nc, nnz = L.p_nnz;
   std::vector<int64_t> tptr(nc + 1, 0), perm(nnz);
   std::vector<int32_t> tcol(nnz);
-  for (int64_t q = 0; q < nnz; ++q) tptr[I.p.idx[q] + 1]++;
+  for (int64_t q = 0; q < nnz; ++q) tptr[L.p_col_h[q] + 1]++;
   for (int64_t c = 0; c < nc; ++c) tptr[c + 1] += tptr[c];
   std::vector<int64_t> pos(tptr.begin(), tptr.end() - 1);
   for (int64_t e = 0; e < n; ++e)
-    for (int64_t q = I.p.ptr[e]; q < I.p.ptr[e + 1]; ++q) {
-      int64_t d = pos[I.p.idx[q]]++;
+    for (int64_t q = L.p_ptr_h[e]; q < L.p_ptr_h[e + 1]; ++q) {
+      int64_t d = pos[L.p_col_h[q]]++;
       tcol[d] = (int32_t)e;
       perm[q] = d;
     }
   L.PT_ptr = h->pool.upload(tptr, st);
   L.PT_col = h->pool.upload(tcol, st);
   L.PT_perm = h->pool.upload(perm, st);
-  L.PT_val = h->pool.get<double>(nnz);
+  L.PT_val = h->pool.get<double>(std::max<int64_t>(nnz, 1));
   L.lpr_PT = lpr_for(nc, nnz);
 }
 
+// Optional sparsification (not in the paper): drop interior-row entries of
+// P with |p| < tau * (row max |p|); exterior rows are kept.  Same rule as the
+// oracle's truncate_interior.
+void truncate_interp(amg_hier* h, Level& L, double tau, hipStream_t st) {
+  std::vector<double> val(L.p_nnz);
+  HIPC(hipMemcpyAsync(val.data(), L.P_val, L.p_nnz * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  std::vector<int64_t> nptr(L.n + 1, 0);
+  std::vector<int32_t> ncol;
+  std::vector<double> nval;
+  ncol.reserve(L.p_nnz);
+  nval.reserve(L.p_nnz);
+  for (int64_t e = 0; e < L.n; ++e) {
+    const bool interior = L.ints.dof_stage[e] >= 0;
+    double mx = 0.0;
+    for (int64_t q = L.p_ptr_h[e]; q < L.p_ptr_h[e + 1]; ++q) mx = std::max(mx, std::fabs(val[q]));
+    for (int64_t q = L.p_ptr_h[e]; q < L.p_ptr_h[e + 1]; ++q)
+      if (!interior || std::fabs(val[q]) >= tau * mx) {
+        ncol.push_back(L.p_col_h[q]);
+        nval.push_back(val[q]);
+      }
+    nptr[e + 1] = (int64_t)ncol.size();
+  }
+  L.p_ptr_h = std::move(nptr);
+  L.p_col_h = std::move(ncol);
+  L.p_nnz = (int64_t)nval.size();
+  L.P_ptr = h->pool.upload(L.p_ptr_h, st);
+  L.P_col = h->pool.upload(L.p_col_h, st);
+  L.P_val = h->pool.upload(nval, st);
+  L.lpr_P = lpr_for(L.n, L.p_nnz);
+}
+
 void compute_interp(amg_hier* h, Level& L, int level, hipStream_t st) {
-  sign_to_val(L.p_nnz, L.P_sign, L.P_val, st);
+  sign_to_val(L.p_nnz, L.P_sign, L.P_val, st);   // untruncated pattern (p_trunc = 0 here)
   for (size_t s = 0; s < L.stages.size(); ++s) {
     const Stage& S = L.stages[s];
     ext_blocks(S.b0, S.nb, L.blk_ptr, L.blk_dofs, L.dof_stage, (int)s, L.A_dev<double>(), L.P_ptr,
@@ -362,7 +408,6 @@ void compute_interp(amg_hier* h, Level& L, int level, hipStream_t st) {
   }
   check_flag(h, st, AMG_ERR_NOT_SPD,
              "local harmonic extension: non-positive pivot in A_BB on level " + std::to_string(level));
-  permute(L.p_nnz, L.PT_perm, L.P_val, L.PT_val, st);
 }
 
 // --- Galerkin product A_c = P^T (A P): symbolic (once) and numeric ---
@@ -460,6 +505,7 @@ void numeric_all(amg_hier* h, hipStream_t st, PhaseClock* clk = nullptr) {
     factor_smoother(h, L, (int)l, st);
     if (clk) clk->mark(st, "smoother factors + l1 (GPU)", (int)l);
     compute_interp(h, L, (int)l, st);
+    permute(L.p_nnz, L.PT_perm, L.P_val, L.PT_val, st);
     if (clk) clk->mark(st, "local extension P (GPU)", (int)l);
     galerkin_numeric(h, L, h->lv[l + 1], st);
     if (clk) clk->mark(st, "Galerkin numeric (GPU)", (int)l);
@@ -517,8 +563,8 @@ void vcycle_T(amg_hier* h, const T* b0, T* x0, hipStream_t st) {
     SmootherDev<T> S = L.S_dev<T>();
     T* x = X(l);
     fill<T>(L.n, (T)0, x, st);
-    for (int c = 0; c < S.ncolours; ++c) schwarz_colour<T>(S, A, c, B(l), x, st);
-    for (int c = S.ncolours - 1; c >= 0; --c) schwarz_colour<T>(S, A, c, B(l), x, st);
+    schwarz_sweep<T>(S, A, 0, B(l), x, st);
+    schwarz_sweep<T>(S, A, 1, B(l), x, st);
     jacobi<T>(A, x, B(l), Vec<T>::dinv(L), Vec<T>::t(L), st);
     residual<T>(A, Vec<T>::t(L), B(l), Vec<T>::r(L), st);
     spmv<T>(L.PT_dev<T>(), Vec<T>::r(L), Vec<T>::b(h->lv[l + 1]), st);
@@ -532,8 +578,8 @@ void vcycle_T(amg_hier* h, const T* b0, T* x0, hipStream_t st) {
     spmv_add<T>(L.P_dev<T>(), X(l + 1), Vec<T>::t(L), st);
     T* x = X(l);
     jacobi<T>(A, Vec<T>::t(L), B(l), Vec<T>::dinv(L), x, st);
-    for (int c = 0; c < S.ncolours; ++c) schwarz_colour<T>(S, A, c, B(l), x, st);
-    for (int c = S.ncolours - 1; c >= 0; --c) schwarz_colour<T>(S, A, c, B(l), x, st);
+    schwarz_sweep<T>(S, A, 0, B(l), x, st);
+    schwarz_sweep<T>(S, A, 1, B(l), x, st);
   }
 }
 
@@ -656,6 +702,7 @@ void amg_default_options(amg_options* opt) {
   opt->vcycle_prec = 64;
   opt->ext_block_max = 64;
   opt->stall_ratio = 0.9;
+  opt->p_trunc = 0.0;
 }
 
 const char* amg_last_error(void) { return g_err.c_str(); }
@@ -729,18 +776,31 @@ amg_status amg_setup(const amg_csr* A, const amg_csr* G, const amg_options* opt,
       stars_and_colours(L.Apat, L.G, L.ints);
       build_smoother(h.get(), L, st);
       clk.mark(st, "smoother stars + colours", l);
+      factor_smoother(h.get(), L, l, st);
+      clk.mark(st, "smoother factors + l1 (GPU)", l);
       build_interp_structs(h.get(), L, st);
-      clk.mark(st, "P structures upload", l);
+      compute_interp(h.get(), L, l, st);
+      if (o.p_trunc > 0.0) truncate_interp(h.get(), L, o.p_trunc, st);
+      build_transpose(h.get(), L, st);
+      permute(L.p_nnz, L.PT_perm, L.P_val, L.PT_val, st);
+      clk.mark(st, "local extension P (GPU)", l);
       h->lv.emplace_back();
       Level& L2 = h->lv[l + 1];
       Level& L1 = h->lv[l];   // re-fetch after emplace_back
       galerkin_symbolic(h.get(), L1, L2, l, st);
-      clk.mark(st, "Galerkin symbolic (GPU)", l);
+      galerkin_numeric(h.get(), L1, L2, st);
+      clk.mark(st, "Galerkin A P, P^T (A P) (GPU)", l);
       L2.G = L1.ints.gc;
       L2.S = nodal_graph_coarse(L1.S, L1.ints.fine_of_next);
       clk.mark(st, "coarse nodal graph", l);
     }
-    numeric_all(h.get(), st, &clk);
+    {
+      Level& C = h->lv.back();
+      coarsest_factor(h.get(), C, st);
+      clk.mark(st, "coarsest dense Cholesky (GPU)", (int)h->lv.size() - 1);
+      if (h->prec == 32)
+        for (auto& L : h->lv) cast_level(h.get(), L, st);
+    }
     alloc_vectors(h.get());
     HIPC(hipStreamSynchronize(st));
     *out = h.release();
@@ -754,6 +814,8 @@ amg_status amg_resetup_numeric(amg_hier* h, const amg_csr* A, void* stream) {
     validate_csr_arg(A, "A");
     Level& L0 = h->lv[0];
     if (A->nrows != L0.n || A->nnz != L0.nnz) fail(AMG_ERR_SHAPE, "A's size differs from the setup's");
+    if (h->opt.p_trunc > 0.0)
+      fail(AMG_ERR_ARG, "amg_resetup_numeric needs p_trunc = 0 (a truncated P's pattern depends on the values)");
     hipStream_t st = (hipStream_t)stream;
     std::vector<int64_t> ptr;
     std::vector<int32_t> col;
@@ -859,12 +921,7 @@ amg_status amg_smoother_sweep(amg_hier* h, int level, int prec, const void* b, v
     hipStream_t st = (hipStream_t)stream;
     auto run = [&](auto tag) {
       using T = decltype(tag);
-      CsrDev<T> A = L.A_dev<T>();
-      SmootherDev<T> S = L.S_dev<T>();
-      for (int k = 0; k < S.ncolours; ++k) {
-        int c = backward ? S.ncolours - 1 - k : k;
-        schwarz_colour<T>(S, A, c, (const T*)b, (T*)x, st);
-      }
+      schwarz_sweep<T>(L.S_dev<T>(), L.A_dev<T>(), backward, (const T*)b, (T*)x, st);
     };
     if (prec == 64) run(double()); else run(float());
     HIPC(hipGetLastError());

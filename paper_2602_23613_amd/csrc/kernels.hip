@@ -187,6 +187,88 @@ __global__ __launch_bounds__(256) void k_schwarz(
   if (threadIdx.x < nrows) x[sb_dofs[r0 + threadIdx.x]] += res[threadIdx.x];
 }
 
+// Whole sweep of a small level in one launch: a 1024-thread workgroup walks
+// the colours in order; its four 256-thread groups take chunks of the current
+// colour in turn.  __syncthreads after each round makes the x updates of one
+// colour visible before the next colour reads x.
+template <class T, int LPR>
+__global__ __launch_bounds__(1024) void k_schwarz_sweep1(
+    int ncolours, const int32_t* __restrict__ colour_chunk, int backward,
+    const int32_t* __restrict__ chunk_blk, const int64_t* __restrict__ sb_ptr,
+    const int32_t* __restrict__ sb_dofs, const int64_t* __restrict__ fac_off,
+    const T* __restrict__ fac, const int64_t* __restrict__ Aptr, const int32_t* __restrict__ Acol,
+    const T* __restrict__ Aval, const T* __restrict__ b, T* __restrict__ x) {
+  constexpr int RPB = 256 / LPR;
+  __shared__ T res_all[4][RPB];
+  const int sub = threadIdx.x / 256;
+  const int tid = threadIdx.x % 256;
+  T* res = res_all[sub];
+  const int grp = tid / LPR, lane = tid % LPR;
+  for (int ci = 0; ci < ncolours; ++ci) {
+    const int col = backward ? ncolours - 1 - ci : ci;
+    const int c0 = colour_chunk[col], c1 = colour_chunk[col + 1];
+    for (int base = c0; base < c1; base += 4) {
+      const int c = base + sub;
+      const bool act = c < c1;
+      int blk0 = 0, blk1 = 0, nrows = 0;
+      int64_t r0 = 0;
+      if (act) {
+        blk0 = chunk_blk[c];
+        blk1 = chunk_blk[c + 1];
+        r0 = sb_ptr[blk0];
+        nrows = (int)(sb_ptr[blk1] - r0);
+      }
+      if (act && grp < nrows) {
+        const int32_t dof = sb_dofs[r0 + grp];
+        T s = 0;
+        const int64_t e = Aptr[dof + 1];
+        for (int64_t q = Aptr[dof] + lane; q < e; q += LPR) s += Aval[q] * x[Acol[q]];
+        s = group_sum<LPR>(s);
+        if (lane == 0) res[grp] = b[dof] - s;
+      }
+      __syncthreads();
+      if (act && tid < blk1 - blk0) {
+        const int blk = blk0 + tid;
+        const int off = (int)(sb_ptr[blk] - r0);
+        const int sz = (int)(sb_ptr[blk + 1] - sb_ptr[blk]);
+        const T* L = fac + fac_off[blk];
+        T* v = res + off;
+        for (int i = 0; i < sz; ++i) {
+          T a = v[i];
+          const T* Li = L + i * (i + 1) / 2;
+          for (int j = 0; j < i; ++j) a -= Li[j] * v[j];
+          v[i] = a / Li[i];
+        }
+        for (int i = sz - 1; i >= 0; --i) {
+          T a = v[i];
+          for (int j = i + 1; j < sz; ++j) a -= L[j * (j + 1) / 2 + i] * v[j];
+          v[i] = a / L[i * (i + 1) / 2 + i];
+        }
+      }
+      __syncthreads();
+      if (act && tid < nrows) x[sb_dofs[r0 + tid]] += res[tid];
+      __syncthreads();
+    }
+  }
+}
+
+template <class T>
+void schwarz_sweep_small(const SmootherDev<T>& S, const CsrDev<T>& A, int backward, const T* b,
+                         T* x, hipStream_t st) {
+#define LAUNCH_SW1(L)                                                                         \
+  hipLaunchKernelGGL((k_schwarz_sweep1<T, L>), dim3(1), dim3(1024), 0, st, S.ncolours,        \
+                     S.colour_chunk_dev, backward, S.chunk_blk, S.sb_ptr, S.sb_dofs, S.fac_off,  \
+                     S.fac, A.ptr, A.col, A.val, b, x);
+  switch (S.lpr) {
+    case 4: LAUNCH_SW1(4); break;
+    case 8: LAUNCH_SW1(8); break;
+    case 16: LAUNCH_SW1(16); break;
+    case 32: LAUNCH_SW1(32); break;
+    default: LAUNCH_SW1(64); break;
+  }
+#undef LAUNCH_SW1
+}
+
 template <class T>
 void schwarz_colour(const SmootherDev<T>& S, const CsrDev<T>& A, int colour, const T* b, T* x,
                     hipStream_t st) {
@@ -792,6 +874,8 @@ template void spmv_add<double>(const CsrDev<double>&, const double*, double*, hi
 template void spmv_add<float>(const CsrDev<float>&, const float*, float*, hipStream_t);
 template void schwarz_colour<double>(const SmootherDev<double>&, const CsrDev<double>&, int, const double*, double*, hipStream_t);
 template void schwarz_colour<float>(const SmootherDev<float>&, const CsrDev<float>&, int, const float*, float*, hipStream_t);
+template void schwarz_sweep_small<double>(const SmootherDev<double>&, const CsrDev<double>&, int, const double*, double*, hipStream_t);
+template void schwarz_sweep_small<float>(const SmootherDev<float>&, const CsrDev<float>&, int, const float*, float*, hipStream_t);
 template void dense_solve<double>(int, const double*, const double*, double*, double*, hipStream_t);
 template void dense_solve<float>(int, const double*, const float*, float*, double*, hipStream_t);
 template void fill<double>(int64_t, double, double*, hipStream_t);

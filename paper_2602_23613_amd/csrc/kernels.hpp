@@ -29,6 +29,8 @@ template <class T>
 struct SmootherDev {
   int ncolours = 0;
   std::vector<int> colour_chunk;        // host: chunk range of each colour
+  const int32_t* colour_chunk_dev = nullptr;   // the same on the device
+  bool one_launch = false;              // small level: whole sweep in one workgroup
   const int32_t* chunk_blk = nullptr;   // first block of each chunk (+ sentinel)
   const int64_t* sb_ptr = nullptr;      // rows of each block (colour order)
   const int32_t* sb_dofs = nullptr;
@@ -52,6 +54,20 @@ int64_t spmv_dot_partials(int lpr, int64_t n);
 template <class T>
 void schwarz_colour(const SmootherDev<T>& S, const CsrDev<T>& A, int colour, const T* b, T* x,
                     hipStream_t st);
+template <class T>
+void schwarz_sweep_small(const SmootherDev<T>& S, const CsrDev<T>& A, int backward, const T* b,
+                         T* x, hipStream_t st);
+// one multiplicative Schwarz sweep (all colours) with the launch shape the level uses
+template <class T>
+void schwarz_sweep(const SmootherDev<T>& S, const CsrDev<T>& A, int backward, const T* b, T* x,
+                   hipStream_t st) {
+  if (S.one_launch) {
+    schwarz_sweep_small<T>(S, A, backward, b, x, st);
+    return;
+  }
+  for (int k = 0; k < S.ncolours; ++k)
+    schwarz_colour<T>(S, A, backward ? S.ncolours - 1 - k : k, b, x, st);
+}
 template <class T>
 void dense_solve(int n, const double* L, const T* b, T* x, double* work, hipStream_t st);
 void dense_factor(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, double* D,

@@ -265,3 +265,61 @@ def test_vcycle_deterministic():
     torch.cuda.synchronize()
     assert torch.equal(z1, z2)
     H.close()
+
+
+@pytest.mark.parametrize("N", [12, 24])
+def test_smoother_sweep_matches_oracle(N):
+    """One forward and one backward multiplicative Schwarz sweep on level 0
+    against the oracle's colour sweep (N=12 runs the one-launch small-level
+    kernel, N=24 (38,088 DoFs) the per-colour launches)."""
+    d = dev()
+    p = gen.make_problem("hex", N, beta=1.0, alpha=lambda m: fields.subdomain_log_uniform(m, 3, 5, -2, 2))
+    Ho = oracle.setup(p.A, p.G, max_levels=2)
+    H = amglib.Hierarchy(p.A, p.G, max_levels=2)
+    b = np.random.default_rng(N).standard_normal(p.A.shape[0])
+    mats = amg._cast(Ho, np.float64)
+    nc = Ho.levels[0].smoother.ncolors
+    xo = amg._schwarz(mats[0], np.zeros_like(b), b, list(range(nc)))
+    xo = amg._schwarz(mats[0], xo, b, list(range(nc - 1, -1, -1)))
+    bt = torch.tensor(b, device=d)
+    xt = torch.zeros_like(bt)
+    H.sweep(0, bt, xt)
+    H.sweep(0, bt, xt, backward=True)
+    torch.cuda.synchronize()
+    err = np.linalg.norm(xt.cpu().numpy() - xo) / np.linalg.norm(xo)
+    tol = max(1e-12, 16 * kappas(Ho)[1] * EPS)
+    print(f"sweep N={N}: rel err {err:.2e} (tol {tol:.1e})")
+    assert err <= tol
+    H.close()
+
+
+@pytest.mark.parametrize("name", ["hex12_jump", "tet5_checker"])
+def test_truncated_interpolation_option(name):
+    """p_trunc > 0 (an option outside the paper): same truncated P patterns and
+    coarse operators as the oracle's truncate_interior, V-cycle parity and PCG
+    convergence."""
+    d = dev()
+    p, _ = case(name)
+    Ho = oracle.setup(p.A, p.G, p_trunc=0.1)
+    H = amglib.Hierarchy(p.A, p.G, p_trunc=0.1)
+    assert [l["n"] for l in H.info()] == [l.A.shape[0] for l in Ho.levels]
+    for l in range(len(Ho.levels) - 1):
+        _, P_l = H.level(l)
+        Po = Ho.levels[l].P
+        assert np.array_equal(P_l.indptr, Po.indptr) and np.array_equal(P_l.indices, Po.indices)
+        compare_integers(H.integers(l), Ho.levels[l], Ho.levels[l + 1].G, Ho.levels[l].Gc_cols)
+    r = np.random.default_rng(8).standard_normal(p.A.shape[0])
+    rt = torch.tensor(r, device=d)
+    zt = torch.zeros_like(rt)
+    H.vcycle(rt, zt)
+    torch.cuda.synchronize()
+    zo = oracle.vcycle(Ho, r)
+    err = np.linalg.norm(zt.cpu().numpy() - zo) / np.linalg.norm(zo)
+    assert err <= max(1e-10, 16 * kappas(Ho)[1] * EPS)
+    f = torch.tensor(p.f, device=d)
+    u = torch.zeros_like(f)
+    st = H.pcg(f, u)
+    _, it_o, _ = oracle.pcg(Ho, p.A, p.f)
+    print(f"truncated P: PCG {st['iterations']} (oracle {it_o})")
+    assert abs(st["iterations"] - it_o) <= 1 and st["relres"] <= 1e-8
+    H.close()
