@@ -140,6 +140,7 @@ struct Level {
   std::vector<int> colour_chunk;
   int32_t* colour_chunk_dev = nullptr;
   bool one_launch = false;
+  int wg_S = 256;
   int32_t* chunk_blk = nullptr;
   int64_t* sb_ptr = nullptr;
   int32_t* sb_dofs = nullptr;
@@ -182,6 +183,7 @@ struct Level {
     SmootherDev<T> s;
     s.ncolours = ncolours; s.colour_chunk = colour_chunk; s.chunk_blk = chunk_blk;
     s.colour_chunk_dev = colour_chunk_dev; s.one_launch = one_launch;
+    s.wg = wg_S;
     s.sb_ptr = sb_ptr; s.sb_dofs = sb_dofs; s.fac_off = fac_off; s.lpr = lpr_S;
     if constexpr (std::is_same<T, double>::value) s.fac = fac; else s.fac = fac32;
     return s;
@@ -203,7 +205,22 @@ struct amg_hier {
   double* dense_work = nullptr;
   // PCG vectors
   double *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr, *prold = nullptr;
+  // V-cycles captured as HIP graphs, one per (r, z) buffer pair, replayed on
+  // a library stream ordered after / before the caller's stream by events
+  struct Graph {
+    const double* r;
+    double* z;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  bool use_graphs = true;
   ~amg_hier() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (gstream) (void)hipStreamDestroy(gstream);
     if (h_sc) (void)hipHostFree(h_sc);
   }
 };
@@ -252,10 +269,19 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   int maxs = 0;
   for (int64_t b = 0; b < ns; ++b) maxs = std::max<int>(maxs, (int)(I.star_ptr[b + 1] - I.star_ptr[b]));
   if (maxs > 32) fail(AMG_ERR_LIMIT, "smoother block with more than 32 DoFs");
+  // lanes per row from the row length; the workgroup must hold a whole block
+  // (rows per chunk = wg / lpr >= largest block), up to 1024 threads
   int lpr = L.lpr_A;
-  while (lpr > 4 && 256 / lpr < std::max(maxs, 1)) lpr /= 2;
+  int wg = 256;
+  while (wg / lpr < std::max(maxs, 1) && wg < 1024) wg *= 2;
+  while (wg / lpr < std::max(maxs, 1) && lpr > 4) lpr /= 2;
+  if (wg > 256 && lpr < 16) {   // wide workgroups only pay off with wide rows
+    wg = 256;
+    while (256 / lpr < std::max(maxs, 1)) lpr /= 2;
+  }
   L.lpr_S = lpr;
-  const int rpb = 256 / lpr;
+  L.wg_S = wg;
+  const int rpb = wg / lpr;
   // blocks in (colour, id) order
   std::vector<int64_t> order(ns);
   {
@@ -293,8 +319,9 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   chunk_blk.push_back((int32_t)ns);
   L.chunk_blk = h->pool.upload(chunk_blk, st);
   L.colour_chunk_dev = h->pool.upload(std::vector<int32_t>(L.colour_chunk.begin(), L.colour_chunk.end()), st);
-  // small levels: the whole sweep in one launch (colours are many, chunks few)
-  L.one_launch = L.nnz <= 200000;
+  // launch shape of a sweep: tiny levels in one workgroup, the rest one
+  // launch per colour
+  L.one_launch = L.nnz <= 200000 && wg == 256;
   L.sb_ptr = h->pool.upload(sb_ptr, st);
   L.sb_dofs = h->pool.upload(sb_dofs, st);
   L.fac_off = h->pool.upload(fac_off, st);
@@ -594,6 +621,42 @@ void vcycle_any(amg_hier* h, const double* r, double* z, hipStream_t st) {
   }
 }
 
+// V-cycle through a cached HIP graph (captured on first use for this buffer
+// pair); the graph runs on the library stream, which waits for the caller's
+// stream and is waited for by it, so ordering on `st` is preserved.
+void vcycle_graph(amg_hier* h, const double* r, double* z, hipStream_t st) {
+  if (!h->use_graphs) {
+    vcycle_any(h, r, z, st);
+    return;
+  }
+  if (!h->gstream) {
+    HIPC(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+    HIPC(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
+    HIPC(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
+  }
+  hipGraphExec_t exec = nullptr;
+  for (auto& g : h->graphs)
+    if (g.r == r && g.z == z) exec = g.exec;
+  if (!exec) {
+    hipGraph_t graph = nullptr;
+    HIPC(hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
+    vcycle_any(h, r, z, h->gstream);
+    HIPC(hipStreamEndCapture(h->gstream, &graph));
+    HIPC(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(graph);
+    if (h->graphs.size() >= 8) {   // bounded cache
+      (void)hipGraphExecDestroy(h->graphs.front().exec);
+      h->graphs.erase(h->graphs.begin());
+    }
+    h->graphs.push_back({r, z, exec});
+  }
+  HIPC(hipEventRecord(h->ev_in, st));
+  HIPC(hipStreamWaitEvent(h->gstream, h->ev_in, 0));
+  HIPC(hipGraphLaunch(exec, h->gstream));
+  HIPC(hipEventRecord(h->ev_out, h->gstream));
+  HIPC(hipStreamWaitEvent(st, h->ev_out, 0));
+}
+
 double read_scalar(amg_hier* h, int slot, hipStream_t st) {
   HIPC(hipMemcpyAsync(h->h_sc + slot, h->d_sc + slot, sizeof(double), hipMemcpyDeviceToHost, st));
   HIPC(hipStreamSynchronize(st));
@@ -724,6 +787,9 @@ amg_status amg_setup(const amg_csr* A, const amg_csr* G, const amg_options* opt,
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(AMG_ERR_HIP, "no HIP device");
     auto h = std::make_unique<amg_hier>();
     h->opt = o;
+    if (const char* e = std::getenv("HCURL_AMG_NO_GRAPH"))
+      if (e[0] && e[0] != '0') h->use_graphs = false;
+
     h->prec = o.vcycle_prec;
     h->d_flag = h->pool.get<int>(1);
     HIPC(hipMemsetAsync(h->d_flag, 0, sizeof(int), st));
@@ -836,7 +902,7 @@ amg_status amg_vcycle(amg_hier* h, const double* r, double* z, void* stream) {
   return guarded([&]() -> amg_status {
     if (!h || !r || !z) fail(AMG_ERR_ARG, "NULL argument");
     if (r == z) fail(AMG_ERR_ARG, "r and z alias");
-    vcycle_any(h, r, z, (hipStream_t)stream);
+    vcycle_graph(h, r, z, (hipStream_t)stream);
     HIPC(hipGetLastError());
     return AMG_OK;
   });
@@ -866,7 +932,7 @@ amg_status amg_pcg_solve(amg_hier* h, const double* f, double* u, double rtol, i
     double nr = r0;
     if (stats && stats->history) stats->history[0] = r0;
     if (r0 > 0.0) {
-      vcycle_any(h, r, z, st);
+      vcycle_graph(h, r, z, st);
       dot2(n, r, z, nullptr, h->d_partial, st);
       reduce(red_grid(), h->d_partial, h->d_sc, SC_RZ, -1, st);
       cg_dir(n, h->d_sc, z, p, 1, st);
@@ -886,7 +952,7 @@ amg_status amg_pcg_solve(amg_hier* h, const double* f, double* u, double rtol, i
           std::fflush(stderr);
         }
         if (nr <= rtol * r0) break;
-        vcycle_any(h, r, z, st);
+        vcycle_graph(h, r, z, st);
         dot2(n, r, z, rold, h->d_partial, st);
         reduce(red_grid(), h->d_partial, h->d_sc, SC_RZNEW, flexible ? SC_ROLDZ : -1, st);
         cg_scalar(h->d_sc, 1, flexible, st);

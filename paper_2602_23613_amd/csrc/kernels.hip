@@ -35,6 +35,27 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
+// sum_q val[q] x[col[q]] over q = b + lane, b + lane + LPR, ... < e, in that
+// order; the loads of four consecutive terms are issued before their sums so
+// that several gathers are in flight per lane
+template <int LPR, class T>
+__device__ __forceinline__ T row_dot(int64_t b, int64_t e, int lane, const int32_t* __restrict__ col,
+                                     const T* __restrict__ val, const T* __restrict__ x) {
+  T s = 0;
+  int64_t q = b + lane;
+  for (; q + 3 * LPR < e; q += 4 * LPR) {
+    const int32_t c0 = col[q], c1 = col[q + LPR], c2 = col[q + 2 * LPR], c3 = col[q + 3 * LPR];
+    const T v0 = val[q], v1 = val[q + LPR], v2 = val[q + 2 * LPR], v3 = val[q + 3 * LPR];
+    const T x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
+    s += v0 * x0;
+    s += v1 * x1;
+    s += v2 * x2;
+    s += v3 * x3;
+  }
+  for (; q < e; q += LPR) s += val[q] * x[col[q]];
+  return s;
+}
+
 __device__ __forceinline__ int lower_bound_i32(const int32_t* a, int n, int32_t key) {
   int lo = 0, hi = n;
   while (lo < hi) {
@@ -62,10 +83,7 @@ __global__ __launch_bounds__(256) void k_spmv(int64_t n, const int64_t* __restri
   const int grp = threadIdx.x / LPR;
   const int64_t row = (int64_t)blockIdx.x * RPB + grp;
   T s = 0;
-  if (row < n) {
-    const int64_t e = ptr[row + 1];
-    for (int64_t q = ptr[row] + lane; q < e; q += LPR) s += val[q] * x[col[q]];
-  }
+  if (row < n) s = row_dot<LPR, T>(ptr[row], ptr[row + 1], lane, col, val, x);
   s = group_sum<LPR>(s);
   double d = 0.0;
   if (row < n && lane == 0) {
@@ -142,13 +160,13 @@ void spmv_dot(const CsrDev<double>& A, const double* x, double* y, double* parti
 // chunk c covers blocks [chunk_blk[c], chunk_blk[c+1]); their rows are
 // contiguous in sb_dofs and number at most 256/LPR.  Blocks of one colour
 // share no DoF and no coupling, so chunks update x independently.
-template <class T, int LPR>
-__global__ __launch_bounds__(256) void k_schwarz(
+template <class T, int LPR, int WG>
+__global__ __launch_bounds__(WG) void k_schwarz(
     const int32_t* __restrict__ chunk_blk, int chunk0, const int64_t* __restrict__ sb_ptr,
     const int32_t* __restrict__ sb_dofs, const int64_t* __restrict__ fac_off,
     const T* __restrict__ fac, const int64_t* __restrict__ Aptr, const int32_t* __restrict__ Acol,
     const T* __restrict__ Aval, const T* __restrict__ b, T* __restrict__ x) {
-  constexpr int RPB = 256 / LPR;
+  constexpr int RPB = WG / LPR;
   __shared__ T res[RPB];
   const int c = chunk0 + blockIdx.x;
   const int blk0 = chunk_blk[c], blk1 = chunk_blk[c + 1];
@@ -157,9 +175,7 @@ __global__ __launch_bounds__(256) void k_schwarz(
   const int grp = threadIdx.x / LPR, lane = threadIdx.x % LPR;
   if (grp < nrows) {
     const int32_t dof = sb_dofs[r0 + grp];
-    T s = 0;
-    const int64_t e = Aptr[dof + 1];
-    for (int64_t q = Aptr[dof] + lane; q < e; q += LPR) s += Aval[q] * x[Acol[q]];
+    T s = row_dot<LPR, T>(Aptr[dof], Aptr[dof + 1], lane, Acol, Aval, x);
     s = group_sum<LPR>(s);
     if (lane == 0) res[grp] = b[dof] - s;
   }
@@ -220,9 +236,7 @@ __global__ __launch_bounds__(1024) void k_schwarz_sweep1(
       }
       if (act && grp < nrows) {
         const int32_t dof = sb_dofs[r0 + grp];
-        T s = 0;
-        const int64_t e = Aptr[dof + 1];
-        for (int64_t q = Aptr[dof] + lane; q < e; q += LPR) s += Aval[q] * x[Acol[q]];
+        T s = row_dot<LPR, T>(Aptr[dof], Aptr[dof + 1], lane, Acol, Aval, x);
         s = group_sum<LPR>(s);
         if (lane == 0) res[grp] = b[dof] - s;
       }
@@ -274,15 +288,28 @@ void schwarz_colour(const SmootherDev<T>& S, const CsrDev<T>& A, int colour, con
                     hipStream_t st) {
   int c0 = S.colour_chunk[colour], c1 = S.colour_chunk[colour + 1];
   if (c1 <= c0) return;
-#define LAUNCH_SW(L)                                                                          \
-  hipLaunchKernelGGL((k_schwarz<T, L>), dim3(c1 - c0), dim3(256), 0, st, S.chunk_blk, c0,      \
+#define LAUNCH_SW(L, W)                                                                        \
+  hipLaunchKernelGGL((k_schwarz<T, L, W>), dim3(c1 - c0), dim3(W), 0, st, S.chunk_blk, c0,      \
                      S.sb_ptr, S.sb_dofs, S.fac_off, S.fac, A.ptr, A.col, A.val, b, x);
-  switch (S.lpr) {
-    case 4: LAUNCH_SW(4); break;
-    case 8: LAUNCH_SW(8); break;
-    case 16: LAUNCH_SW(16); break;
-    case 32: LAUNCH_SW(32); break;
-    default: LAUNCH_SW(64); break;
+  if (S.wg == 1024) {
+    switch (S.lpr) {
+      case 32: LAUNCH_SW(32, 1024); break;
+      default: LAUNCH_SW(64, 1024); break;
+    }
+  } else if (S.wg == 512) {
+    switch (S.lpr) {
+      case 16: LAUNCH_SW(16, 512); break;
+      case 32: LAUNCH_SW(32, 512); break;
+      default: LAUNCH_SW(64, 512); break;
+    }
+  } else {
+    switch (S.lpr) {
+      case 4: LAUNCH_SW(4, 256); break;
+      case 8: LAUNCH_SW(8, 256); break;
+      case 16: LAUNCH_SW(16, 256); break;
+      case 32: LAUNCH_SW(32, 256); break;
+      default: LAUNCH_SW(64, 256); break;
+    }
   }
 #undef LAUNCH_SW
 }

@@ -30,7 +30,8 @@ struct SmootherDev {
   int ncolours = 0;
   std::vector<int> colour_chunk;        // host: chunk range of each colour
   const int32_t* colour_chunk_dev = nullptr;   // the same on the device
-  bool one_launch = false;              // small level: whole sweep in one workgroup
+  bool one_launch = false;              // tiny level: whole sweep in one workgroup
+  int wg = 256;                         // workgroup size of k_schwarz (rows per chunk = wg / lpr)
   const int32_t* chunk_blk = nullptr;   // first block of each chunk (+ sentinel)
   const int64_t* sb_ptr = nullptr;      // rows of each block (colour order)
   const int32_t* sb_dofs = nullptr;
@@ -57,6 +58,7 @@ void schwarz_colour(const SmootherDev<T>& S, const CsrDev<T>& A, int colour, con
 template <class T>
 void schwarz_sweep_small(const SmootherDev<T>& S, const CsrDev<T>& A, int backward, const T* b,
                          T* x, hipStream_t st);
+
 // one multiplicative Schwarz sweep (all colours) with the launch shape the level uses
 template <class T>
 void schwarz_sweep(const SmootherDev<T>& S, const CsrDev<T>& A, int backward, const T* b, T* x,

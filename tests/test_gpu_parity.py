@@ -323,3 +323,63 @@ def test_truncated_interpolation_option(name):
     print(f"truncated P: PCG {st['iterations']} (oracle {it_o})")
     assert abs(st["iterations"] - it_o) <= 1 and st["relres"] <= 1e-8
     H.close()
+
+
+
+def test_wide_row_level_sweep_matches_oracle():
+    """Level 1 of a 24^3 problem (rows of ~110 entries) runs k_schwarz with
+    wide lane groups; one forward, backward, forward sweep against the
+    oracle's level-1 sweep."""
+    d = dev()
+    p = gen.make_problem("hex", 24, beta=1.0, alpha=lambda m: fields.subdomain_log_uniform(m, 3, 6, -2, 2))
+    H = amglib.Hierarchy(p.A, p.G, max_levels=3)
+    Ho = oracle.setup(p.A, p.G, max_levels=3)
+    n1 = H.info()[1]["n"]
+    b = torch.tensor(np.random.default_rng(1).standard_normal(n1), device=d)
+    x = torch.zeros_like(b)
+    for bw in (False, True, False):
+        H.sweep(1, b, x, backward=bw)
+    torch.cuda.synchronize()
+    mats = amg._cast(Ho, np.float64)
+    nc = Ho.levels[1].smoother.ncolors
+    bo = b.cpu().numpy()
+    xo = np.zeros_like(bo)
+    for order in (range(nc), range(nc - 1, -1, -1), range(nc)):
+        xo = amg._schwarz(mats[1], xo, bo, list(order))
+    err = np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo)
+    tol = max(1e-10, 16 * kappas(Ho)[1] * EPS)
+    print(f"level-1 sweep: rel err vs oracle {err:.2e} (tol {tol:.1e})")
+    assert err <= tol
+    H.close()
+
+
+def test_graph_replays_equal_eager_vcycle():
+    """V-cycles are captured once per (r, z) pair as a HIP graph and replayed.
+    Every replay (with eager work and synchronisations in between, and the
+    inputs changed between replays) must equal the eager V-cycle bit for bit."""
+    import os
+    d = dev()
+    p, _ = case("hex12_jump")
+    Hg = amglib.Hierarchy(p.A, p.G)
+    os.environ["HCURL_AMG_NO_GRAPH"] = "1"
+    try:
+        He = amglib.Hierarchy(p.A, p.G)
+    finally:
+        del os.environ["HCURL_AMG_NO_GRAPH"]
+    rng = np.random.default_rng(12)
+    r = torch.zeros(p.A.shape[0], dtype=torch.float64, device=d)
+    zg, ze = torch.zeros_like(r), torch.zeros_like(r)
+    for rep in range(4):
+        r.copy_(torch.tensor(rng.standard_normal(p.A.shape[0]), device=d))
+        _ = (r * 2.0).sum().item()          # eager work + synchronisation between replays
+        Hg.vcycle(r, zg)
+        He.vcycle(r, ze)
+        torch.cuda.synchronize()
+        assert torch.equal(zg, ze), rep
+    f = torch.tensor(p.f, device=d)
+    ug, ue = torch.zeros_like(f), torch.zeros_like(f)
+    sg = Hg.pcg(f, ug)
+    se = He.pcg(f, ue)
+    assert sg["iterations"] == se["iterations"] and torch.equal(ug, ue)
+    Hg.close()
+    He.close()
