@@ -175,7 +175,7 @@ def cpu_baseline_worker(N, beta, its):
     print(json.dumps(dict(n=p.A.shape[0], setup_s=t1 - t0, solve_s=t2 - t1, its=it)))
 
 
-def cpu_baseline(n_full, its_full, N=24, beta=1.0, its=20):
+def cpu_baseline(n_full, its_full, N=32, beta=1.0, its=30):
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker", str(N), str(beta),
            str(its)]

@@ -193,6 +193,76 @@ amg_status amg_level0_integers(const amg_csr *A, const amg_csr *G, const amg_opt
                                amg_int_export *out, void **handle);
 void amg_free_integers(void *handle);
 
+/* ---------------------------------------------------------------------------
+   Learned setup (an addition outside the paper).  A small network
+   (64 -> 128 -> 128 -> 64, ReLU, BF16 weights with FP32 master copies and
+   FP32 accumulation on MFMA) maps each finest-level extension block of at
+   most 8 DoFs, normalised as D^{-1/2} A_BB D^{-1/2}, to that matrix's
+   inverse, i.e. to the weights of the local harmonic extension
+   X_B = -A_BB^{-1} A_B,: P (eq. (sparseP)).  It is trained on the exact local
+   solves of the current hierarchy.  When enabled, amg_resetup_numeric
+   predicts the eligible finest-level blocks, refines each prediction by
+   Newton-Schulz steps in FP64 and accepts it only if
+   ||Ahat W - I||_F <= accept_tol; every other block is solved exactly.  A
+   global check then compares the stand-alone V-cycle convergence factor with
+   the one measured on the exact hierarchy at training time and redoes the
+   whole numeric setup exactly if it is worse by more than global_slack.
+   --------------------------------------------------------------------------- */
+typedef struct {
+  int epochs;              /* passes over the eligible blocks */
+  int batch;               /* rows per optimisation step (multiple of 16) */
+  double lr;               /* Adam step size */
+  uint64_t seed;           /* order of the samples */
+  double eligible_max;     /* blocks whose normalised inverse has an entry above this are not learned */
+  const float *init;       /* host array of amg_mlp_nparams() initial parameters, or NULL to
+                              continue from the current ones (required on first use) */
+  int global_iters;        /* stand-alone cycles used to measure the reference convergence factor */
+} amg_mlp_train_cfg;
+
+typedef struct {
+  int refine_steps;        /* Newton-Schulz steps after each prediction */
+  double accept_tol;       /* per-block bound on ||Ahat W - I||_F */
+  int global_iters;        /* stand-alone cycles of the global check (0 = no global check) */
+  double global_slack;     /* the learned hierarchy passes if rho <= rho_reference + slack */
+} amg_mlp_use_cfg;
+
+typedef struct {
+  int64_t blocks, eligible, accepted;   /* finest-level extension blocks in the last learned setup */
+  double loss_first, loss_last;         /* training MSE of the first and last epoch */
+  double train_seconds;                 /* last amg_mlp_train */
+  double infer_seconds;                 /* features + network + refinement + learned extension */
+  double exact_seconds;                 /* finest-level extension with exact solves (last exact setup) */
+  double rho_reference, rho_learned;    /* global check (stand-alone V-cycle convergence factors) */
+  int global_fallback;                  /* 1 if the global check rejected the learned setup */
+} amg_mlp_stats;
+
+/* Number of network parameters (FP32, layout W1, b1, W2, b2, W3, b3 row-major). */
+int64_t amg_mlp_nparams(void);
+
+/* Train on the exact finest-level local solves of the hierarchy's current A
+   (the blocks' exact inverses are the targets).  Synchronises. */
+amg_status amg_mlp_train(amg_hier *h, const amg_mlp_train_cfg *cfg, amg_mlp_stats *stats,
+                         void *stream);
+
+/* Enable (cfg != NULL) or disable (cfg == NULL) the learned setup in later
+   amg_resetup_numeric calls. */
+amg_status amg_mlp_use(amg_hier *h, const amg_mlp_use_cfg *cfg);
+
+/* Statistics of the last training and learned setup. */
+amg_status amg_mlp_stats_get(const amg_hier *h, amg_mlp_stats *stats);
+
+/* Read (get != NULL) and/or overwrite (set != NULL) the FP32 master
+   parameters (host arrays of amg_mlp_nparams() floats). */
+amg_status amg_mlp_params(amg_hier *h, float *get, const float *set);
+
+/* Raw network passes for checking the kernels: x = n rows (n a multiple of
+   16) of 64 BF16 features (device, raw 16-bit patterns); y = n x 64 FP32
+   outputs (device).  amg_mlp_backward takes dy = dL/dy (device, n x 64) and
+   writes the gradient of all parameters (device, amg_mlp_nparams() floats). */
+amg_status amg_mlp_forward(amg_hier *h, const uint16_t *x, int64_t n, float *y, void *stream);
+amg_status amg_mlp_backward(amg_hier *h, const uint16_t *x, int64_t n, const float *dy, float *grad,
+                            void *stream);
+
 /* Release a hierarchy and all its device memory.  NULL is ignored. */
 void amg_destroy(amg_hier *h);
 

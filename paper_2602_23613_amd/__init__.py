@@ -135,6 +135,53 @@ class Hierarchy:
         _lib.check(load().amg_smoother_sweep(self._h, level, prec, b.data_ptr(), x.data_ptr(),
                                              1 if backward else 0, _stream(stream)))
 
+    # --- learned setup ---------------------------------------------------
+    def mlp_train(self, epochs=4, batch=1024, lr=1e-3, seed=0, eligible_max=50.0, init=None,
+                  global_iters=0, stream=None):
+        """Train the surrogate on the exact finest-level local solves of the
+        current A.  init: initial parameters (float32 array) or None to continue."""
+        cfg = _lib.amg_mlp_train_cfg(epochs, batch, lr, seed, eligible_max, None, global_iters)
+        keep = None
+        if init is not None:
+            keep = np.ascontiguousarray(init, dtype=np.float32)
+            cfg.init = keep.ctypes.data_as(C.POINTER(C.c_float))
+        st = _lib.amg_mlp_stats()
+        _lib.check(load().amg_mlp_train(self._h, C.byref(cfg), C.byref(st), _stream(stream)))
+        return _stats_dict(st)
+
+    def mlp_use(self, refine_steps=3, accept_tol=1e-10, global_iters=0, global_slack=0.02,
+                enable=True):
+        if not enable:
+            _lib.check(load().amg_mlp_use(self._h, None))
+            return
+        cfg = _lib.amg_mlp_use_cfg(refine_steps, accept_tol, global_iters, global_slack)
+        _lib.check(load().amg_mlp_use(self._h, C.byref(cfg)))
+
+    def mlp_stats(self):
+        st = _lib.amg_mlp_stats()
+        _lib.check(load().amg_mlp_stats_get(self._h, C.byref(st)))
+        return _stats_dict(st)
+
+    def mlp_params(self, set=None):
+        n = load().amg_mlp_nparams()
+        if set is not None:
+            arr = np.ascontiguousarray(set, dtype=np.float32)
+            assert arr.size == n
+            _lib.check(load().amg_mlp_params(self._h, None, arr.ctypes.data))
+            return None
+        out = np.zeros(n, dtype=np.float32)
+        _lib.check(load().amg_mlp_params(self._h, out.ctypes.data, None))
+        return out
+
+    def mlp_forward(self, x_bf16, y, stream=None):
+        n = x_bf16.shape[0]
+        _lib.check(load().amg_mlp_forward(self._h, x_bf16.data_ptr(), n, y.data_ptr(), _stream(stream)))
+
+    def mlp_backward(self, x_bf16, dy, grad, stream=None):
+        n = x_bf16.shape[0]
+        _lib.check(load().amg_mlp_backward(self._h, x_bf16.data_ptr(), n, dy.data_ptr(),
+                                           grad.data_ptr(), _stream(stream)))
+
     def integers(self, level):
         e = _lib.amg_int_export()
         _lib.check(load().amg_export_integers(self._h, level, C.byref(e)))
@@ -161,6 +208,10 @@ class Hierarchy:
         if not coarsest:
             P = sp.csr_matrix((pv[:pnnz], pc[:pnnz], pp), shape=(n, info[level + 1]["n"]))
         return A, P
+
+
+def _stats_dict(st):
+    return {k: getattr(st, k) for k, _ in st._fields_}
 
 
 def level0_integers(A, G, **opts):

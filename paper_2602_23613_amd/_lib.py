@@ -27,7 +27,8 @@ STATUS = {0: "AMG_OK", 1: "AMG_NOT_CONVERGED", -1: "AMG_ERR_ARG", -2: "AMG_ERR_S
 EXPORTED = ["amg_default_options", "amg_setup", "amg_resetup_numeric", "amg_vcycle",
             "amg_pcg_solve", "amg_smoother_sweep", "amg_spmv", "amg_hier_info", "amg_export_integers",
             "amg_export_level", "amg_level0_integers", "amg_free_integers", "amg_destroy",
-            "amg_last_error"]
+            "amg_last_error", "amg_mlp_nparams", "amg_mlp_train", "amg_mlp_use", "amg_mlp_stats_get",
+            "amg_mlp_params", "amg_mlp_forward", "amg_mlp_backward"]
 
 
 class AmgError(RuntimeError):
@@ -85,6 +86,25 @@ class amg_int_export(C.Structure):
                 ("gc_val", C.POINTER(C.c_int8)), ("gc_cols", C.POINTER(C.c_int32))]
 
 
+class amg_mlp_train_cfg(C.Structure):
+    _fields_ = [("epochs", C.c_int), ("batch", C.c_int), ("lr", C.c_double), ("seed", C.c_uint64),
+                ("eligible_max", C.c_double), ("init", C.POINTER(C.c_float)),
+                ("global_iters", C.c_int)]
+
+
+class amg_mlp_use_cfg(C.Structure):
+    _fields_ = [("refine_steps", C.c_int), ("accept_tol", C.c_double), ("global_iters", C.c_int),
+                ("global_slack", C.c_double)]
+
+
+class amg_mlp_stats(C.Structure):
+    _fields_ = [("blocks", C.c_int64), ("eligible", C.c_int64), ("accepted", C.c_int64),
+                ("loss_first", C.c_double), ("loss_last", C.c_double),
+                ("train_seconds", C.c_double), ("infer_seconds", C.c_double),
+                ("exact_seconds", C.c_double), ("rho_reference", C.c_double),
+                ("rho_learned", C.c_double), ("global_fallback", C.c_int)]
+
+
 _lib = None
 
 
@@ -118,10 +138,19 @@ def load():
     lib.amg_destroy.argtypes = [P]
     lib.amg_destroy.restype = None
     lib.amg_last_error.restype = C.c_char_p
+    lib.amg_mlp_nparams.restype = C.c_int64
+    lib.amg_mlp_nparams.argtypes = []
+    lib.amg_mlp_train.argtypes = [P, C.POINTER(amg_mlp_train_cfg), C.POINTER(amg_mlp_stats), P]
+    lib.amg_mlp_use.argtypes = [P, C.POINTER(amg_mlp_use_cfg)]
+    lib.amg_mlp_stats_get.argtypes = [P, C.POINTER(amg_mlp_stats)]
+    lib.amg_mlp_params.argtypes = [P, P, P]
+    lib.amg_mlp_forward.argtypes = [P, P, C.c_int64, P, P]
+    lib.amg_mlp_backward.argtypes = [P, P, C.c_int64, P, P, P]
     for name in ("amg_setup", "amg_resetup_numeric", "amg_vcycle", "amg_pcg_solve", "amg_spmv",
                  "amg_smoother_sweep",
                  "amg_hier_info", "amg_export_integers", "amg_export_level",
-                 "amg_level0_integers"):
+                 "amg_level0_integers", "amg_mlp_train", "amg_mlp_use", "amg_mlp_stats_get",
+                 "amg_mlp_params", "amg_mlp_forward", "amg_mlp_backward"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

@@ -15,6 +15,7 @@
 #include "../../include/amg.h"
 #include "host_setup.hpp"
 #include "kernels.hpp"
+#include "mlp.hpp"
 
 using namespace hamg;
 
@@ -213,6 +214,26 @@ struct amg_hier {
     hipGraphExec_t exec;
   };
   std::vector<Graph> graphs;
+  // learned setup (finest-level extension blocks)
+  MlpDev mlp;
+  MlpWork work;
+  int64_t mlp_nb = 0, mlp_rows = 0;     // blocks, rows padded to a multiple of 16
+  uint16_t* fX = nullptr;                // features (mlp_rows x 64, BF16)
+  float* fT = nullptr;                   // exact targets (mlp_rows x 64)
+  float* fY = nullptr;                   // predictions
+  double* fAhat = nullptr;               // normalised blocks (36 packed)
+  double* fdsq = nullptr;                // sqrt of the block diagonals (8)
+  double* fW = nullptr;                  // refined accepted inverses (36 packed)
+  int8_t* fel = nullptr;                 // eligible
+  int8_t* facc = nullptr;                // accepted
+  float* fres = nullptr;                 // refinement residual
+  uint16_t* bX = nullptr;                // batch buffers
+  float *bT = nullptr, *bY = nullptr, *bdY = nullptr, *bloss = nullptr;
+  int32_t* bidx = nullptr;
+  int64_t batch_cap = 0;
+  bool learned = false;
+  amg_mlp_use_cfg use_cfg{};
+  amg_mlp_stats mstats{};
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   bool use_graphs = true;
@@ -426,12 +447,13 @@ void truncate_interp(amg_hier* h, Level& L, double tau, hipStream_t st) {
   L.lpr_P = lpr_for(L.n, L.p_nnz);
 }
 
-void compute_interp(amg_hier* h, Level& L, int level, hipStream_t st) {
+void compute_interp(amg_hier* h, Level& L, int level, hipStream_t st, bool learned = false) {
   sign_to_val(L.p_nnz, L.P_sign, L.P_val, st);   // untruncated pattern (p_trunc = 0 here)
   for (size_t s = 0; s < L.stages.size(); ++s) {
     const Stage& S = L.stages[s];
     ext_blocks(S.b0, S.nb, L.blk_ptr, L.blk_dofs, L.dof_stage, (int)s, L.A_dev<double>(), L.P_ptr,
-               L.P_col, L.P_val, S.smax, S.cmax, h->d_flag, st);
+               L.P_col, L.P_val, S.smax, S.cmax, h->d_flag, st, learned ? h->fW : nullptr,
+               learned ? h->facc : nullptr, learned ? h->fdsq : nullptr);
   }
   check_flag(h, st, AMG_ERR_NOT_SPD,
              "local harmonic extension: non-positive pivot in A_BB on level " + std::to_string(level));
@@ -520,6 +542,86 @@ void cast_level(amg_hier* h, Level& L, hipStream_t st) {
   cast<double, float>(L.n, L.dinv, L.dinv32, st);
 }
 
+// --- learned setup ---
+void ensure_mlp(amg_hier* h, hipStream_t st) {
+  if (h->mlp.master) return;
+  MlpDev& m = h->mlp;
+  m.master = h->pool.get<float>(MLP_NPARAM);
+  m.grad = h->pool.get<float>(MLP_NPARAM);
+  m.adam_m = h->pool.get<float>(MLP_NPARAM);
+  m.adam_v = h->pool.get<float>(MLP_NPARAM);
+  m.Wb1 = h->pool.get<uint16_t>((size_t)MLP_IN * MLP_HID);
+  m.Wb2 = h->pool.get<uint16_t>((size_t)MLP_HID * MLP_HID);
+  m.Wb3 = h->pool.get<uint16_t>((size_t)MLP_HID * MLP_OUT);
+  m.b1 = m.master + MLP_OFF_B1;
+  m.b2 = m.master + MLP_OFF_B2;
+  m.b3 = m.master + MLP_OFF_B3;
+  fill<float>(MLP_NPARAM, 0.f, m.adam_m, st);
+  fill<float>(MLP_NPARAM, 0.f, m.adam_v, st);
+}
+
+void ensure_work(amg_hier* h, int64_t rows) {
+  if (h->work.rows >= rows) return;
+  MlpWork& w = h->work;
+  w.rows = rows;
+  w.Z1 = h->pool.get<float>((size_t)rows * MLP_HID);
+  w.Z2 = h->pool.get<float>((size_t)rows * MLP_HID);
+  w.dH = h->pool.get<float>((size_t)rows * MLP_HID);
+  w.H1 = h->pool.get<uint16_t>((size_t)rows * MLP_HID);
+  w.H2 = h->pool.get<uint16_t>((size_t)rows * MLP_HID);
+  w.dHb = h->pool.get<uint16_t>((size_t)rows * MLP_HID);
+  w.dYb = h->pool.get<uint16_t>((size_t)rows * MLP_OUT);
+}
+
+constexpr int64_t INFER_ROWS = 16384;   // rows per inference pass
+
+// features, exact targets and eligibility of every finest-level extension block
+void learned_features(amg_hier* h, double eligible_max, hipStream_t st) {
+  Level& L = h->lv[0];
+  int64_t nb = L.ints.block_ptr.empty() ? 0 : (int64_t)L.ints.block_ptr.size() - 1;
+  if (!h->fX) {
+    h->mlp_nb = nb;
+    h->mlp_rows = (nb + 15) / 16 * 16;
+    int64_t r = std::max<int64_t>(h->mlp_rows, 16);
+    h->fX = h->pool.get<uint16_t>((size_t)r * MLP_IN);
+    h->fT = h->pool.get<float>((size_t)r * MLP_OUT);
+    h->fY = h->pool.get<float>((size_t)r * MLP_OUT);
+    h->fAhat = h->pool.get<double>((size_t)std::max<int64_t>(nb, 1) * 36);
+    h->fdsq = h->pool.get<double>((size_t)std::max<int64_t>(nb, 1) * 8);
+    h->fW = h->pool.get<double>((size_t)std::max<int64_t>(nb, 1) * 36);
+    h->fel = h->pool.get<int8_t>(std::max<int64_t>(nb, 1));
+    h->facc = h->pool.get<int8_t>(std::max<int64_t>(nb, 1));
+    h->fres = h->pool.get<float>(std::max<int64_t>(nb, 1));
+    // padding rows stay zero
+    HIPC(hipMemsetAsync(h->fX, 0, (size_t)r * MLP_IN * sizeof(uint16_t), st));
+  }
+  block_features(nb, L.blk_ptr, L.blk_dofs, L.A_ptr, L.A_col, L.A_val, eligible_max, h->fX, h->fT,
+                 h->fAhat, h->fdsq, h->fel, st);
+}
+
+// network prediction + refinement + check for every finest-level block
+void learned_predict(amg_hier* h, hipStream_t st) {
+  learned_features(h, 1e300, st);   // eligibility here only needs a valid exact factorisation
+  ensure_work(h, INFER_ROWS);
+  for (int64_t r0 = 0; r0 < h->mlp_rows; r0 += INFER_ROWS) {
+    int64_t nr = std::min<int64_t>(INFER_ROWS, h->mlp_rows - r0);
+    mlp_forward(h->mlp, h->fX + r0 * MLP_IN, nr, h->work, h->fY + r0 * MLP_OUT, st);
+  }
+  refine_check(h->mlp_nb, h->lv[0].blk_ptr, h->fel, h->fY, h->fAhat, h->use_cfg.refine_steps,
+               h->use_cfg.accept_tol, h->fW, h->facc, h->fres, st);
+  std::vector<int8_t> el(h->mlp_nb), acc(h->mlp_nb);
+  HIPC(hipMemcpyAsync(el.data(), h->fel, h->mlp_nb, hipMemcpyDeviceToHost, st));
+  HIPC(hipMemcpyAsync(acc.data(), h->facc, h->mlp_nb, hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  h->mstats.blocks = h->mlp_nb;
+  h->mstats.eligible = 0;
+  h->mstats.accepted = 0;
+  for (int64_t b = 0; b < h->mlp_nb; ++b) {
+    h->mstats.eligible += el[b] != 0;
+    h->mstats.accepted += acc[b] != 0;
+  }
+}
+
 void numeric_all(amg_hier* h, hipStream_t st, PhaseClock* clk = nullptr) {
   size_t nl = h->lv.size();
   for (size_t l = 0; l < nl; ++l) {
@@ -531,7 +633,15 @@ void numeric_all(amg_hier* h, hipStream_t st, PhaseClock* clk = nullptr) {
     }
     factor_smoother(h, L, (int)l, st);
     if (clk) clk->mark(st, "smoother factors + l1 (GPU)", (int)l);
-    compute_interp(h, L, (int)l, st);
+    auto t0 = std::chrono::steady_clock::now();
+    const bool use_mlp = l == 0 && h->learned;
+    if (use_mlp) learned_predict(h, st);
+    compute_interp(h, L, (int)l, st, use_mlp);
+    if (l == 0) {
+      HIPC(hipStreamSynchronize(st));
+      double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (use_mlp) h->mstats.infer_seconds = sec; else h->mstats.exact_seconds = sec;
+    }
     permute(L.p_nnz, L.PT_perm, L.P_val, L.PT_val, st);
     if (clk) clk->mark(st, "local extension P (GPU)", (int)l);
     galerkin_numeric(h, L, h->lv[l + 1], st);
@@ -655,6 +765,33 @@ void vcycle_graph(amg_hier* h, const double* r, double* z, hipStream_t st) {
   HIPC(hipGraphLaunch(exec, h->gstream));
   HIPC(hipEventRecord(h->ev_out, h->gstream));
   HIPC(hipStreamWaitEvent(st, h->ev_out, 0));
+}
+
+double read_scalar(amg_hier* h, int slot, hipStream_t st);
+
+// Asymptotic convergence factor of the stand-alone cycle e <- e - B A e,
+// estimated as ||e_k||_A / ||e_{k-1}||_A after `iters` cycles from a fixed
+// pseudo-random start (used by the learned setup's global check).
+double convergence_factor(amg_hier* h, int iters, hipStream_t st) {
+  Level& L0 = h->lv[0];
+  int64_t n = L0.n;
+  CsrDev<double> A = L0.A_dev<double>();
+  double* e = h->prold;
+  double* t = h->pq;
+  double* z = h->pz;
+  hash_fill(n, 0x5eed1234ull, e, st);
+  double prev = 0.0, cur = 0.0;
+  for (int k = 0; k <= iters; ++k) {
+    spmv<double>(A, e, t, st);
+    dot2(n, e, t, nullptr, h->d_partial, st);
+    reduce(red_grid(), h->d_partial, h->d_sc, SC_RR, -1, st);
+    prev = cur;
+    cur = std::sqrt(std::max(read_scalar(h, SC_RR, st), 0.0));
+    if (k == iters) break;
+    vcycle_any(h, t, z, st);
+    axpy(n, -1.0, z, e, st);
+  }
+  return prev > 0.0 ? cur / prev : 0.0;
 }
 
 double read_scalar(amg_hier* h, int slot, hipStream_t st) {
@@ -894,6 +1031,24 @@ amg_status amg_resetup_numeric(amg_hier* h, const amg_csr* A, void* stream) {
     host_csr(A, ptr, col, nullptr);
     if (ptr != L0.Apat.ptr || col != L0.Apat.idx) fail(AMG_ERR_CSR, "A's pattern differs from the setup's");
     numeric_all(h, st);
+    h->mstats.global_fallback = 0;
+    if (h->learned && h->use_cfg.global_iters > 0) {
+      double rho = convergence_factor(h, h->use_cfg.global_iters, st);
+      h->mstats.rho_learned = rho;
+      if (!(rho <= h->mstats.rho_reference + h->use_cfg.global_slack)) {
+        // global check failed: redo the numeric setup with exact local solves
+        h->learned = false;
+        try {
+          numeric_all(h, st);
+        } catch (...) {
+          h->learned = true;
+          throw;
+        }
+        h->learned = true;
+        h->mstats.global_fallback = 1;
+        h->mstats.accepted = 0;
+      }
+    }
     return AMG_OK;
   });
 }
@@ -1099,6 +1254,159 @@ amg_status amg_level0_integers(const amg_csr* A, const amg_csr* G, const amg_opt
 }
 
 void amg_free_integers(void* handle) { delete (IntsHandle*)handle; }
+
+int64_t amg_mlp_nparams(void) { return MLP_NPARAM; }
+
+amg_status amg_mlp_params(amg_hier* h, float* get, const float* set) {
+  return guarded([&]() -> amg_status {
+    if (!h) fail(AMG_ERR_ARG, "NULL handle");
+    ensure_mlp(h, nullptr);
+    if (get) {
+      if (!h->mlp.ready) fail(AMG_ERR_ARG, "the network has no parameters yet");
+      HIPC(hipMemcpy(get, h->mlp.master, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost));
+    }
+    if (set) {
+      HIPC(hipMemcpy(h->mlp.master, set, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice));
+      fill<float>(MLP_NPARAM, 0.f, h->mlp.adam_m, nullptr);
+      fill<float>(MLP_NPARAM, 0.f, h->mlp.adam_v, nullptr);
+      h->mlp.step = 0;
+      mlp_refresh_bf16(h->mlp, nullptr);
+      HIPC(hipDeviceSynchronize());
+      h->mlp.ready = true;
+    }
+    return AMG_OK;
+  });
+}
+
+amg_status amg_mlp_forward(amg_hier* h, const uint16_t* x, int64_t n, float* y, void* stream) {
+  return guarded([&]() -> amg_status {
+    if (!h || !x || !y) fail(AMG_ERR_ARG, "NULL argument");
+    if (n <= 0 || n % 16) fail(AMG_ERR_ARG, "n must be a positive multiple of 16");
+    if (!h->mlp.ready) fail(AMG_ERR_ARG, "the network has no parameters yet");
+    ensure_work(h, n);
+    mlp_forward(h->mlp, x, n, h->work, y, (hipStream_t)stream);
+    HIPC(hipGetLastError());
+    return AMG_OK;
+  });
+}
+
+amg_status amg_mlp_backward(amg_hier* h, const uint16_t* x, int64_t n, const float* dy, float* grad,
+                            void* stream) {
+  return guarded([&]() -> amg_status {
+    if (!h || !x || !dy || !grad) fail(AMG_ERR_ARG, "NULL argument");
+    if (n <= 0 || n % 16) fail(AMG_ERR_ARG, "n must be a positive multiple of 16");
+    if (!h->mlp.ready) fail(AMG_ERR_ARG, "the network has no parameters yet");
+    if (h->work.rows < n) fail(AMG_ERR_ARG, "call amg_mlp_forward on the same rows first");
+    mlp_backward(h->mlp, x, n, h->work, dy, grad, (hipStream_t)stream);
+    HIPC(hipGetLastError());
+    return AMG_OK;
+  });
+}
+
+amg_status amg_mlp_train(amg_hier* h, const amg_mlp_train_cfg* cfg, amg_mlp_stats* stats,
+                         void* stream) {
+  return guarded([&]() -> amg_status {
+    if (!h || !cfg) fail(AMG_ERR_ARG, "NULL argument");
+    if (cfg->batch <= 0 || cfg->batch % 16) fail(AMG_ERR_ARG, "batch must be a positive multiple of 16");
+    if (cfg->epochs < 0) fail(AMG_ERR_ARG, "epochs < 0");
+    hipStream_t st = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    ensure_mlp(h, st);
+    if (cfg->init) {
+      HIPC(hipMemcpyAsync(h->mlp.master, cfg->init, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice, st));
+      fill<float>(MLP_NPARAM, 0.f, h->mlp.adam_m, st);
+      fill<float>(MLP_NPARAM, 0.f, h->mlp.adam_v, st);
+      h->mlp.step = 0;
+      mlp_refresh_bf16(h->mlp, st);
+      h->mlp.ready = true;
+    }
+    if (!h->mlp.ready) fail(AMG_ERR_ARG, "first training needs initial parameters (cfg->init)");
+    learned_features(h, cfg->eligible_max, st);
+    std::vector<int8_t> el(h->mlp_nb);
+    HIPC(hipMemcpyAsync(el.data(), h->fel, h->mlp_nb, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    std::vector<int32_t> ids;
+    for (int64_t b = 0; b < h->mlp_nb; ++b)
+      if (el[b]) ids.push_back((int32_t)b);
+    const int64_t B = cfg->batch;
+    if (h->batch_cap < B) {
+      h->bX = h->pool.get<uint16_t>((size_t)B * MLP_IN);
+      h->bT = h->pool.get<float>((size_t)B * MLP_OUT);
+      h->bY = h->pool.get<float>((size_t)B * MLP_OUT);
+      h->bdY = h->pool.get<float>((size_t)B * MLP_OUT);
+      h->bloss = h->pool.get<float>(B);
+      h->batch_cap = B;
+    }
+    ensure_work(h, B);
+    int32_t* d_ids = h->pool.get<int32_t>(std::max<size_t>(ids.size(), 1));
+    uint64_t state = cfg->seed ^ 0x9E3779B97F4A7C15ull;
+    auto next = [&]() {   // SplitMix64
+      uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+      z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+      z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+      return z ^ (z >> 31);
+    };
+    std::vector<float> loss_h(B);
+    double first = 0.0, last = 0.0;
+    const int64_t nids = (int64_t)ids.size();
+    for (int ep = 0; ep < cfg->epochs && nids > 0; ++ep) {
+      for (int64_t i = nids - 1; i > 0; --i) std::swap(ids[i], ids[next() % (uint64_t)(i + 1)]);
+      HIPC(hipMemcpyAsync(d_ids, ids.data(), nids * sizeof(int32_t), hipMemcpyHostToDevice, st));
+      double ep_loss = 0.0;
+      const bool track = ep == 0 || ep == cfg->epochs - 1;
+      for (int64_t o = 0; o < nids; o += B) {
+        const int64_t nb = std::min<int64_t>(B, nids - o);
+        const int64_t npad = (nb + 15) / 16 * 16;
+        mlp_gather(nb, npad, d_ids + o, h->fX, h->fT, h->bX, h->bT, st);
+        mlp_forward(h->mlp, h->bX, npad, h->work, h->bY, st);
+        mlp_mse(npad, h->bY, h->bT, h->bdY, h->bloss, nb, st);
+        mlp_backward(h->mlp, h->bX, npad, h->work, h->bdY, h->mlp.grad, st);
+        mlp_adam(h->mlp, (float)cfg->lr, st);
+        if (track) {
+          HIPC(hipMemcpyAsync(loss_h.data(), h->bloss, nb * sizeof(float), hipMemcpyDeviceToHost, st));
+          HIPC(hipStreamSynchronize(st));
+          for (int64_t r = 0; r < nb; ++r) ep_loss += loss_h[r];
+        }
+      }
+      if (ep == 0) first = ep_loss / nids;
+      if (ep == cfg->epochs - 1) last = ep_loss / nids;
+    }
+    HIPC(hipStreamSynchronize(st));
+    h->mstats.loss_first = first;
+    h->mstats.loss_last = last;
+    h->mstats.eligible = nids;
+    h->mstats.blocks = h->mlp_nb;
+    h->mstats.train_seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (cfg->global_iters > 0)
+      h->mstats.rho_reference = convergence_factor(h, cfg->global_iters, st);
+    if (stats) *stats = h->mstats;
+    return AMG_OK;
+  });
+}
+
+amg_status amg_mlp_use(amg_hier* h, const amg_mlp_use_cfg* cfg) {
+  return guarded([&]() -> amg_status {
+    if (!h) fail(AMG_ERR_ARG, "NULL handle");
+    if (!cfg) {
+      h->learned = false;
+      return AMG_OK;
+    }
+    if (!h->mlp.ready) fail(AMG_ERR_ARG, "train the network (or set its parameters) first");
+    if (cfg->refine_steps < 0 || !(cfg->accept_tol >= 0.0)) fail(AMG_ERR_ARG, "bad use configuration");
+    h->use_cfg = *cfg;
+    h->learned = true;
+    return AMG_OK;
+  });
+}
+
+amg_status amg_mlp_stats_get(const amg_hier* h, amg_mlp_stats* stats) {
+  return guarded([&]() -> amg_status {
+    if (!h || !stats) fail(AMG_ERR_ARG, "NULL argument");
+    *stats = h->mstats;
+    return AMG_OK;
+  });
+}
 
 void amg_destroy(amg_hier* h) { delete h; }
 

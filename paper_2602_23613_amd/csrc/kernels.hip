@@ -554,7 +554,8 @@ __global__ __launch_bounds__(64) void k_ext_block(
     const int32_t* __restrict__ dof_stage, int stage, const int64_t* __restrict__ Aptr,
     const int32_t* __restrict__ Acol, const double* __restrict__ Aval,
     const int64_t* __restrict__ Pptr, const int32_t* __restrict__ Pcol, double* __restrict__ Pval,
-    int smax, int cmax, int* __restrict__ flag) {
+    int smax, int cmax, int* __restrict__ flag, const double* __restrict__ Wl,
+    const int8_t* __restrict__ accepted, const double* __restrict__ dsq) {
   extern __shared__ unsigned char lds_raw[];
   double* Abb = (double*)lds_raw;                 // smax * smax
   double* R = Abb + smax * smax;                   // smax * cmax
@@ -596,6 +597,25 @@ __global__ __launch_bounds__(64) void k_ext_block(
     }
   }
   __syncthreads();
+  if (Wl && accepted[blk]) {
+    // learned block: X = -D^{-1/2} W D^{-1/2} R with the accepted, refined
+    // normalised inverse W (packed lower triangle)
+    const double* w = Wl + blk * 36;
+    const double* dq = dsq + blk * 8;
+    for (int t = lane; t < c; t += 64) {
+      double y[8];
+      for (int i = 0; i < s; ++i) {
+        double v = 0.0;
+        for (int j = 0; j < s; ++j) {
+          const double wij = i >= j ? w[i * (i + 1) / 2 + j] : w[j * (j + 1) / 2 + i];
+          v += wij / dq[j] * R[j * c + t];
+        }
+        y[i] = v / dq[i];
+      }
+      for (int i = 0; i < s; ++i) Pval[Pptr[dofs[i]] + t] = -y[i];
+    }
+    return;
+  }
   // Cholesky (lower) of Abb in place, lane i owns row i
   for (int k = 0; k < s; ++k) {
     if (lane == 0) {
@@ -638,11 +658,37 @@ size_t ext_block_lds(int smax, int cmax) {
 void ext_blocks(int64_t b0, int64_t nb, const int64_t* bptr, const int32_t* bdofs,
                 const int32_t* dof_stage, int stage, const CsrDev<double>& A,
                 const int64_t* Pptr, const int32_t* Pcol, double* Pval, int smax, int cmax,
-                int* flag, hipStream_t st) {
+                int* flag, hipStream_t st, const double* Wl, const int8_t* accepted,
+                const double* dsq) {
   if (nb <= 0) return;
   size_t lds = ext_block_lds(smax, cmax);
   hipLaunchKernelGGL(k_ext_block, dim3((unsigned)nb), dim3(64), lds, st, b0, bptr, bdofs,
-                     dof_stage, stage, A.ptr, A.col, A.val, Pptr, Pcol, Pval, smax, cmax, flag);
+                     dof_stage, stage, A.ptr, A.col, A.val, Pptr, Pcol, Pval, smax, cmax, flag,
+                     Wl, accepted, dsq);
+}
+
+// x_i = a pseudo-random value in [-1, 1) from a counter-based hash (SplitMix64)
+__global__ void k_hash_fill(int64_t n, uint64_t seed, double* __restrict__ x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  }
+}
+// y += a x
+__global__ void k_axpy(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+void hash_fill(int64_t n, uint64_t seed, double* x, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_hash_fill, dim3(grid_for(n)), dim3(256), 0, st, n, seed, x);
+}
+void axpy(int64_t n, double a, const double* x, double* y, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(256), 0, st, n, a, x, y);
 }
 
 // P values from the exterior signs (interior entries start at 0)
