@@ -162,6 +162,54 @@ def time_kernels(amg, H, f, torch, reps=20):
                 ncolors=ncol)
 
 
+def learned_form(amg, Ad, Gd, f, torch, a):
+    """Re-setup on a new coefficient field of the same law: exact local solves
+    against the learned surrogate.  The network is trained on the GPU on the
+    exact local solves of the headline field, then both re-setups run on a
+    field drawn with another seed (same mesh, same pattern)."""
+    from gen.mlp_init import init_params, flatten
+    seed_alpha = (2 if a.size <= 64 else 3) + 10
+    p2 = make_workload(a.size, a.beta, seed_alpha=seed_alpha, seed_f=0)
+    A2 = (Ad[0], Ad[1], torch.from_numpy(p2.A.data.astype(np.float64)).to(f.device), Ad[3], Ad[4])
+    del p2
+    H = amg.Hierarchy(Ad, Gd, vcycle_prec=64)
+    st = H.mlp_train(epochs=a.learn_epochs, batch=1024, lr=1e-3, seed=0,
+                     init=flatten(init_params(0)), global_iters=a.learn_check_iters)
+    log(f"learned: trained {st}")
+    out = dict(field_seed=seed_alpha, train=dict(
+        epochs=a.learn_epochs, batch=1024, blocks=st["blocks"], eligible=st["eligible"],
+        loss_first=st["loss_first"], loss_last=st["loss_last"], train_s=st["train_seconds"],
+        rho_reference=st["rho_reference"]))
+    for name, use in (("exact", False), ("learned", True)):
+        if use:
+            H.mlp_use(refine_steps=6, accept_tol=1e-10, global_iters=a.learn_check_iters,
+                      global_slack=0.02)
+        else:
+            H.mlp_use(enable=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H.resetup(A2)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        u = torch.zeros_like(f)
+        r = H.pcg(f, u, rtol=1e-8, maxit=a.maxit)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ms = H.mlp_stats()
+        out[name] = dict(resetup_s=t1 - t0, solve_s=t2 - t1, total_s=t2 - t0,
+                         iterations=r["iterations"], true_relres=r["true_relres"],
+                         converged=r["status"] == 0)
+        if use:
+            out[name].update(level0_extension_s=ms["infer_seconds"], accepted=ms["accepted"],
+                             predicted=ms["eligible"], rho_learned=ms["rho_learned"],
+                             global_fallback=ms["global_fallback"])
+        else:
+            out[name].update(level0_extension_s=ms["exact_seconds"])
+        log(f"learned form, {name} re-setup: {out[name]}")
+    H.close()
+    return out
+
+
 def cpu_baseline_worker(N, beta, its):
     """Run the oracle on a bounded sample: the same field law on an N^3 mesh,
     full setup plus `its` PCG iterations (test infrastructure timed here only)."""
@@ -206,6 +254,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-trunc-forms", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learn-epochs", type=int, default=30)
+    ap.add_argument("--learn-check-iters", type=int, default=10,
+                    help="stand-alone V-cycles of the learned setup's global check")
     ap.add_argument("--kernels-only", action="store_true",
                     help="setup once and time the V-cycle / level-0 sweep only (for profiling)")
     ap.add_argument("--cpu-baseline-worker", nargs=3, default=None)
@@ -287,6 +339,8 @@ def main():
         if is_head:
             headline = (t1 - t0) / steps, runs, kt
         H.close()
+    if not a.no_learned and a.p_trunc == 0.0:
+        forms["learned_resetup"] = learned_form(amg, Ad, Gd, f, torch, a)
     value, runs, kt = headline
     out = {
         "metric": "s to 1e-8 rel. residual + V-cycle HBM GB/s; FP32/learned vs FP64 on GPU",

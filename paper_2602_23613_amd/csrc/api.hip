@@ -294,12 +294,23 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   // (rows per chunk = wg / lpr >= largest block), up to 1024 threads
   int lpr = L.lpr_A;
   int wg = 256;
-  while (wg / lpr < std::max(maxs, 1) && wg < 1024) wg *= 2;
-  while (wg / lpr < std::max(maxs, 1) && lpr > 4) lpr /= 2;
-  if (wg > 256 && lpr < 16) {   // wide workgroups only pay off with wide rows
-    wg = 256;
-    while (256 / lpr < std::max(maxs, 1)) lpr /= 2;
+  const double avg_row = L.n > 0 ? (double)L.nnz / (double)L.n : 0.0;
+  const char* wide_env = std::getenv("HCURL_AMG_WIDE_ROWS");
+  const bool wide_ok = !(wide_env && wide_env[0] == '0');
+  if (wide_ok && avg_row > 600.0 && maxs <= 8) {
+    // very wide rows (dense coarse operators): two wavefronts per row
+    lpr = 128;
+    wg = 1024;
+  } else {
+    while (wg / lpr < std::max(maxs, 1) && wg < 1024) wg *= 2;
+    while (wg / lpr < std::max(maxs, 1) && lpr > 4) lpr /= 2;
+    if (wg > 256 && lpr < 16) {   // wide workgroups only pay off with wide rows
+      wg = 256;
+      while (256 / lpr < std::max(maxs, 1)) lpr /= 2;
+    }
   }
+  if (!schwarz_shape_ok(lpr, wg) || wg / lpr < std::max(maxs, 1))
+    fail(AMG_ERR_LIMIT, "no smoother launch shape for this level");
   L.lpr_S = lpr;
   L.wg_S = wg;
   const int rpb = wg / lpr;
@@ -340,9 +351,14 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   chunk_blk.push_back((int32_t)ns);
   L.chunk_blk = h->pool.upload(chunk_blk, st);
   L.colour_chunk_dev = h->pool.upload(std::vector<int32_t>(L.colour_chunk.begin(), L.colour_chunk.end()), st);
-  // launch shape of a sweep: tiny levels in one workgroup, the rest one
-  // launch per colour
-  L.one_launch = L.nnz <= 200000 && wg == 256;
+  // launch shape of a sweep: one workgroup for the whole sweep where the rows
+  // it streams are few for the number of colours (one launch per colour costs
+  // a few microseconds, about what one CU streams of 40k row entries), else
+  // one launch per colour
+  int64_t star_row_nnz = 0;
+  for (int32_t d : sb_dofs) star_row_nnz += L.Apat.ptr[d + 1] - L.Apat.ptr[d];
+  L.one_launch = L.nnz <= 200000 || star_row_nnz <= 40000 * (int64_t)I.ncolors;
+  if (const char* e = std::getenv("HCURL_AMG_ONE_LAUNCH")) L.one_launch = e[0] == '1' ? true : e[0] == '0' ? false : L.one_launch;
   L.sb_ptr = h->pool.upload(sb_ptr, st);
   L.sb_dofs = h->pool.upload(sb_dofs, st);
   L.fac_off = h->pool.upload(fac_off, st);

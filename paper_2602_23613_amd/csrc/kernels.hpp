@@ -30,8 +30,8 @@ struct SmootherDev {
   int ncolours = 0;
   std::vector<int> colour_chunk;        // host: chunk range of each colour
   const int32_t* colour_chunk_dev = nullptr;   // the same on the device
-  bool one_launch = false;              // tiny level: whole sweep in one workgroup
-  int wg = 256;                         // workgroup size of k_schwarz (rows per chunk = wg / lpr)
+  bool one_launch = false;              // small level: whole sweep in one workgroup
+  int wg = 256;                         // threads per chunk (rows per chunk = wg / lpr)
   const int32_t* chunk_blk = nullptr;   // first block of each chunk (+ sentinel)
   const int64_t* sb_ptr = nullptr;      // rows of each block (colour order)
   const int32_t* sb_dofs = nullptr;
@@ -52,6 +52,7 @@ template <class T> void spmv_add(const CsrDev<T>& A, const T* x, T* y, hipStream
 void spmv_dot(const CsrDev<double>& A, const double* x, double* y, double* partial, hipStream_t st);
 int64_t spmv_dot_partials(int lpr, int64_t n);
 
+bool schwarz_shape_ok(int lpr, int wg);
 template <class T>
 void schwarz_colour(const SmootherDev<T>& S, const CsrDev<T>& A, int colour, const T* b, T* x,
                     hipStream_t st);

@@ -383,3 +383,47 @@ def test_graph_replays_equal_eager_vcycle():
     assert sg["iterations"] == se["iterations"] and torch.equal(ug, ue)
     Hg.close()
     He.close()
+
+
+def _with_env(env, fn):
+    import os
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        return fn()
+    finally:
+        for k, v in old.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
+
+
+def test_sweep_launch_shapes_agree():
+    """The 16^3 jump case has a dense level (1176 rows of 1176 entries), which
+    takes the two-wavefront rows and the one-launch sweep.  Forcing one launch
+    per colour runs the same chunks with the same per-row summation order, so
+    the V-cycle must not change by a bit; narrower rows (one wavefront) only
+    change the rounding, and stay within the oracle tolerance."""
+    d = dev()
+    p, Ho = case("hex16_jump_b1e-3")
+    rng = np.random.default_rng(21)
+    r = torch.tensor(rng.standard_normal(p.A.shape[0]), device=d)
+    out = {}
+    for name, env in [("default", {}), ("per_colour", {"HCURL_AMG_ONE_LAUNCH": "0"}),
+                      ("one_launch", {"HCURL_AMG_ONE_LAUNCH": "1"}),
+                      ("narrow", {"HCURL_AMG_WIDE_ROWS": "0"})]:
+        H = _with_env(env, lambda: amglib.Hierarchy(p.A, p.G))
+        z = torch.zeros_like(r)
+        H.vcycle(r, z)
+        torch.cuda.synchronize()
+        out[name] = z.cpu().numpy()
+        H.close()
+    assert np.array_equal(out["default"], out["per_colour"])
+    assert np.array_equal(out["default"], out["one_launch"])
+    zo = oracle.vcycle(Ho, r.cpu().numpy())
+    tol = max(1e-10, 16 * kappas(Ho)[1] * EPS)
+    for name in ("default", "narrow"):
+        err = np.linalg.norm(out[name] - zo) / np.linalg.norm(zo)
+        print(f"{name}: V-cycle rel err vs oracle {err:.2e} (tol {tol:.1e})")
+        assert err <= tol
