@@ -13,8 +13,6 @@
 
 namespace hamg {
 
-namespace {
-
 // Run body(begin, end) over [0, n) split across hardware threads.
 // Host threads of the integer phase: hardware threads, at most 16 (or
 // HCURL_AMG_THREADS when set).
@@ -44,6 +42,8 @@ void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& body) 
   }
   for (auto& x : th) x.join();
 }
+
+namespace {
 
 // Build a CSR pattern from per-row lists produced in parallel: count(i)
 // returns the row length, fill(i, out) writes the (sorted) row.

@@ -11,9 +11,15 @@
 
 #include <cstdint>
 #include <string>
+#include <functional>
 #include <vector>
 
 namespace hamg {
+
+// Host threads of the integer phase (at most 16, or HCURL_AMG_THREADS), and
+// body(begin, end) run over [0, n) split across them.
+unsigned host_threads();
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& body);
 
 // CSR pattern (values, where present, live elsewhere).
 struct Pattern {

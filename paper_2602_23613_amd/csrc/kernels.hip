@@ -202,50 +202,84 @@ struct ChunkLds {
 // all) of the multiplicative Schwarz step x_B += A_BB^{-1} (b - A x)_B, by a
 // group of WGS threads (tid = 0..WGS-1).  Called uniformly by every thread
 // of the workgroup (it synchronises); act = false for groups without a chunk.
+// The rows come from the smoother's own copy of A in chunk order (srow_ptr,
+// scol, sval), so one chunk streams one contiguous range; everything the
+// solve and update phases need is fetched up front, which leaves four
+// dependent memory accesses per chunk (chunk bounds, row bounds, row
+// entries, x gathers).
 template <class T, int LPR, int WGS, int U>
 __device__ __forceinline__ void schwarz_chunk(
-    bool act, int c, int tid, ChunkLds<T, LPR, WGS>& S, const int32_t* __restrict__ chunk_blk,
-    const int64_t* __restrict__ sb_ptr, const int32_t* __restrict__ sb_dofs,
-    const int64_t* __restrict__ fac_off, const T* __restrict__ fac,
-    const int64_t* __restrict__ Aptr, const int32_t* __restrict__ Acol,
-    const T* __restrict__ Aval, const T* __restrict__ b, T* __restrict__ x) {
+    bool act, int c, int tid, ChunkLds<T, LPR, WGS>& S, const SmootherArgs<T>& D,
+    const T* __restrict__ b, T* __restrict__ x) {
   constexpr int WPR = ChunkLds<T, LPR, WGS>::WPR;
-  int blk0 = 0, blk1 = 0, nrows = 0, nf = 0;
-  int64_t r0 = 0, f0 = 0;
+  constexpr int FL = (int)(sizeof(S.fl) / sizeof(T));
+  constexpr int FPT = (FL + WGS - 1) / WGS;   // factor entries staged per thread
+  // 1. chunk bounds
+  int blk0 = 0, nblk = 0, r0 = 0, nrows = 0, nf = 0;
+  int64_t f0 = 0;
   if (act) {
-    blk0 = chunk_blk[c];
-    blk1 = chunk_blk[c + 1];
-    r0 = sb_ptr[blk0];
-    nrows = (int)(sb_ptr[blk1] - r0);
-    f0 = fac_off[blk0];
-    nf = (int)(fac_off[blk1] - f0);
+    blk0 = D.chunk_blk[c];
+    nblk = D.chunk_blk[c + 1] - blk0;
+    r0 = D.ck_row0[c];
+    nrows = D.ck_row0[c + 1] - r0;
+    f0 = D.ck_fac0[c];
+    nf = (int)(D.ck_fac0[c + 1] - f0);
   }
-  // the chunk's factors are contiguous: stage them in LDS while rows stream
-  for (int t = tid; t < nf; t += WGS) S.fl[t] = fac[f0 + t];
+  // 2. everything that depends on the bounds only, issued together
   const int grp = tid / LPR, lane = tid % LPR;
-  if (grp < nrows) {
-    const int32_t dof = sb_dofs[r0 + grp];
-    T s = row_dot_batched<LPR, U, T>(Aptr[dof], Aptr[dof + 1], lane, Acol, Aval, x);
+  const bool row_act = grp < nrows;
+  const int64_t r = (int64_t)r0 + grp;
+  int64_t q0 = 0, q1 = 0;
+  int32_t rdof = 0, mydof = 0;
+  if (row_act) {
+    q0 = D.srow_ptr[r];
+    q1 = D.srow_ptr[r + 1];
+    if (lane == 0) rdof = D.sb_dofs[r];
+  }
+  if (tid < nrows) mydof = D.sb_dofs[r0 + tid];
+  int64_t p0 = 0, p1 = 0, fo = 0;
+  if (tid < nblk) {
+    p0 = D.sb_ptr[blk0 + tid];
+    p1 = D.sb_ptr[blk0 + tid + 1];
+    fo = D.fac_off[blk0 + tid];
+  }
+  T fv[FPT];
+#pragma unroll
+  for (int k = 0; k < FPT; ++k) {
+    const int t = tid + k * WGS;
+    fv[k] = t < nf ? D.fac[f0 + t] : T(0);
+  }
+  // 3. second-level loads: right-hand side, own x entries, the row sums
+  T bv = 0, myx = 0;
+  if (row_act && lane == 0) bv = b[rdof];
+  if (tid < nrows) myx = x[mydof];   // only this chunk changes these entries during the colour
+  T s = 0;
+  if (row_act) s = row_dot_batched<LPR, U, T>(q0, q1, lane, D.scol, D.sval, x);
+#pragma unroll
+  for (int k = 0; k < FPT; ++k) {
+    const int t = tid + k * WGS;
+    if (t < nf) S.fl[t] = fv[k];
+  }
+  if (row_act) {
     if constexpr (LPR <= 64) {
       s = group_sum<LPR>(s);
-      if (lane == 0) S.res[grp] = b[dof] - s;
+      if (lane == 0) S.res[grp] = bv - s;
     } else {
       s = group_sum<64>(s);
       if (lane % 64 == 0) S.part[grp * WPR + lane / 64] = s;
-      if (lane == 0) S.res[grp] = b[dof];
+      if (lane == 0) S.res[grp] = bv;
     }
   }
   __syncthreads();
-  if (tid < blk1 - blk0) {
-    const int blk = blk0 + tid;
-    const int off = (int)(sb_ptr[blk] - r0);
-    const int sz = (int)(sb_ptr[blk + 1] - sb_ptr[blk]);
-    const T* L = S.fl + (fac_off[blk] - f0);
-    T* v = S.res + off;
+  // 4. block solves from LDS, one thread per block
+  if (tid < nblk) {
+    const int boff = (int)(p0 - r0), sz = (int)(p1 - p0);
+    const T* L = S.fl + (fo - f0);
+    T* v = S.res + boff;
     if constexpr (WPR > 1) {
       for (int i = 0; i < sz; ++i) {
         T p = 0;
-        for (int w = 0; w < WPR; ++w) p += S.part[(off + i) * WPR + w];
+        for (int w = 0; w < WPR; ++w) p += S.part[(boff + i) * WPR + w];
         v[i] -= p;
       }
     }
@@ -262,20 +296,16 @@ __device__ __forceinline__ void schwarz_chunk(
     }
   }
   __syncthreads();
-  if (tid < nrows) x[sb_dofs[r0 + tid]] += S.res[tid];
+  if (tid < nrows) x[mydof] = myx + S.res[tid];
 }
 
 // one colour: chunk chunk0 + blockIdx.x per workgroup.  Blocks of one colour
 // share no DoF and no coupling, so chunks update x independently.
 template <class T, int LPR, int WG, int U>
-__global__ __launch_bounds__(WG) void k_schwarz(
-    const int32_t* __restrict__ chunk_blk, int chunk0, const int64_t* __restrict__ sb_ptr,
-    const int32_t* __restrict__ sb_dofs, const int64_t* __restrict__ fac_off,
-    const T* __restrict__ fac, const int64_t* __restrict__ Aptr, const int32_t* __restrict__ Acol,
-    const T* __restrict__ Aval, const T* __restrict__ b, T* __restrict__ x) {
+__global__ __launch_bounds__(WG) void k_schwarz(SmootherArgs<T> D, int chunk0, const T* __restrict__ b,
+                                                T* __restrict__ x) {
   __shared__ ChunkLds<T, LPR, WG> S;
-  schwarz_chunk<T, LPR, WG, U>(true, chunk0 + blockIdx.x, threadIdx.x, S, chunk_blk, sb_ptr,
-                               sb_dofs, fac_off, fac, Aptr, Acol, Aval, b, x);
+  schwarz_chunk<T, LPR, WG, U>(true, chunk0 + blockIdx.x, threadIdx.x, S, D, b, x);
 }
 
 // Whole sweep in one launch: a 1024-thread workgroup walks the colours in
@@ -283,23 +313,18 @@ __global__ __launch_bounds__(WG) void k_schwarz(
 // turn.  The barriers inside schwarz_chunk and the one after each round make
 // the x updates of a colour visible before the next colour reads x.
 template <class T, int LPR, int WGS, int U>
-__global__ __launch_bounds__(1024) void k_schwarz_sweep1(
-    int ncolours, const int32_t* __restrict__ colour_chunk, int backward,
-    const int32_t* __restrict__ chunk_blk, const int64_t* __restrict__ sb_ptr,
-    const int32_t* __restrict__ sb_dofs, const int64_t* __restrict__ fac_off,
-    const T* __restrict__ fac, const int64_t* __restrict__ Aptr, const int32_t* __restrict__ Acol,
-    const T* __restrict__ Aval, const T* __restrict__ b, T* __restrict__ x) {
+__global__ __launch_bounds__(1024) void k_schwarz_sweep1(SmootherArgs<T> D, int backward,
+                                                         const T* __restrict__ b, T* __restrict__ x) {
   constexpr int NSUB = 1024 / WGS;
   __shared__ ChunkLds<T, LPR, WGS> S_all[NSUB];
   const int sub = threadIdx.x / WGS;
   const int tid = threadIdx.x % WGS;
-  for (int ci = 0; ci < ncolours; ++ci) {
-    const int colour = backward ? ncolours - 1 - ci : ci;
-    const int c0 = colour_chunk[colour], c1 = colour_chunk[colour + 1];
+  for (int ci = 0; ci < D.ncolours; ++ci) {
+    const int colour = backward ? D.ncolours - 1 - ci : ci;
+    const int c0 = D.colour_chunk_dev[colour], c1 = D.colour_chunk_dev[colour + 1];
     for (int base = c0; base < c1; base += NSUB) {
       const int c = base + sub;
-      schwarz_chunk<T, LPR, WGS, U>(c < c1, c, tid, S_all[sub], chunk_blk, sb_ptr, sb_dofs,
-                                    fac_off, fac, Aptr, Acol, Aval, b, x);
+      schwarz_chunk<T, LPR, WGS, U>(c < c1, c, tid, S_all[sub], D, b, x);
       __syncthreads();
     }
   }
@@ -321,13 +346,12 @@ bool schwarz_shape_ok(int lpr, int wg) {
   X(128, 512) X(32, 1024) X(64, 1024) X(128, 1024) X(256, 1024)
 
 template <class T>
-void schwarz_sweep_small(const SmootherDev<T>& S, const CsrDev<T>& A, int backward, const T* b,
-                         T* x, hipStream_t st) {
+void schwarz_sweep_small(const SmootherDev<T>& S, int backward, const T* b, T* x, hipStream_t st) {
+  const SmootherArgs<T> D = S;
 #define LAUNCH_SW1(L, W)                                                                         \
   if (S.lpr == L && S.wg == W) {                                                                 \
     hipLaunchKernelGGL((k_schwarz_sweep1<T, L, W, unroll_for<L>()>), dim3(1), dim3(1024), 0, st,  \
-                       S.ncolours, S.colour_chunk_dev, backward, S.chunk_blk, S.sb_ptr,          \
-                       S.sb_dofs, S.fac_off, S.fac, A.ptr, A.col, A.val, b, x);                  \
+                       D, backward, b, x);                                                       \
     return;                                                                                      \
   }
   SCHWARZ_SHAPES(LAUNCH_SW1)
@@ -335,19 +359,36 @@ void schwarz_sweep_small(const SmootherDev<T>& S, const CsrDev<T>& A, int backwa
 }
 
 template <class T>
-void schwarz_colour(const SmootherDev<T>& S, const CsrDev<T>& A, int colour, const T* b, T* x,
-                    hipStream_t st) {
+void schwarz_colour(const SmootherDev<T>& S, int colour, const T* b, T* x, hipStream_t st) {
   int c0 = S.colour_chunk[colour], c1 = S.colour_chunk[colour + 1];
   if (c1 <= c0) return;
+  const SmootherArgs<T> D = S;
 #define LAUNCH_SW(L, W)                                                                          \
   if (S.lpr == L && S.wg == W) {                                                                 \
-    hipLaunchKernelGGL((k_schwarz<T, L, W, unroll_for<L>()>), dim3(c1 - c0), dim3(W), 0, st,      \
-                       S.chunk_blk, c0, S.sb_ptr, S.sb_dofs, S.fac_off, S.fac, A.ptr, A.col,     \
-                       A.val, b, x);                                                             \
+    hipLaunchKernelGGL((k_schwarz<T, L, W, unroll_for<L>()>), dim3(c1 - c0), dim3(W), 0, st, D,   \
+                       c0, b, x);                                                                \
     return;                                                                                      \
   }
   SCHWARZ_SHAPES(LAUNCH_SW)
 #undef LAUNCH_SW
+}
+
+// values of the smoother's row copy: star row r is row sb_dofs[r] of A
+__global__ void k_star_rows(int64_t nrows, const int32_t* __restrict__ sb_dofs,
+                            const int64_t* __restrict__ Aptr, const double* __restrict__ Aval,
+                            const int64_t* __restrict__ srow_ptr, double* __restrict__ sval) {
+  const int64_t r = (int64_t)blockIdx.x * 8 + threadIdx.x / 32;
+  const int lane = threadIdx.x % 32;
+  if (r >= nrows) return;
+  const int64_t a0 = Aptr[sb_dofs[r]];
+  const int64_t s0 = srow_ptr[r], len = srow_ptr[r + 1] - s0;
+  for (int64_t q = lane; q < len; q += 32) sval[s0 + q] = Aval[a0 + q];
+}
+void star_rows(int64_t nrows, const int32_t* sb_dofs, const int64_t* Aptr, const double* Aval,
+               const int64_t* srow_ptr, double* sval, hipStream_t st) {
+  if (nrows > 0)
+    hipLaunchKernelGGL(k_star_rows, dim3((unsigned)((nrows + 7) / 8)), dim3(256), 0, st, nrows,
+                       sb_dofs, Aptr, Aval, srow_ptr, sval);
 }
 
 // ---------------------------------------------------------------------------
@@ -981,10 +1022,10 @@ template void jacobi<double>(const CsrDev<double>&, const double*, const double*
 template void jacobi<float>(const CsrDev<float>&, const float*, const float*, const float*, float*, hipStream_t);
 template void spmv_add<double>(const CsrDev<double>&, const double*, double*, hipStream_t);
 template void spmv_add<float>(const CsrDev<float>&, const float*, float*, hipStream_t);
-template void schwarz_colour<double>(const SmootherDev<double>&, const CsrDev<double>&, int, const double*, double*, hipStream_t);
-template void schwarz_colour<float>(const SmootherDev<float>&, const CsrDev<float>&, int, const float*, float*, hipStream_t);
-template void schwarz_sweep_small<double>(const SmootherDev<double>&, const CsrDev<double>&, int, const double*, double*, hipStream_t);
-template void schwarz_sweep_small<float>(const SmootherDev<float>&, const CsrDev<float>&, int, const float*, float*, hipStream_t);
+template void schwarz_colour<double>(const SmootherDev<double>&, int, const double*, double*, hipStream_t);
+template void schwarz_colour<float>(const SmootherDev<float>&, int, const float*, float*, hipStream_t);
+template void schwarz_sweep_small<double>(const SmootherDev<double>&, int, const double*, double*, hipStream_t);
+template void schwarz_sweep_small<float>(const SmootherDev<float>&, int, const float*, float*, hipStream_t);
 template void dense_solve<double>(int, const double*, const double*, double*, double*, hipStream_t);
 template void dense_solve<float>(int, const double*, const float*, float*, double*, hipStream_t);
 template void fill<double>(int64_t, double, double*, hipStream_t);
