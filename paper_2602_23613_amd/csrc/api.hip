@@ -149,13 +149,6 @@ struct Level {
   int64_t fac_total = 0;
   double* fac = nullptr;
   float* fac32 = nullptr;
-  int32_t* ck_row0 = nullptr;
-  int64_t* ck_fac0 = nullptr;
-  int64_t srow_nnz = 0;
-  int64_t* srow_ptr = nullptr;
-  int32_t* scol = nullptr;
-  double* sval = nullptr;
-  float* sval32 = nullptr;
   double* dinv = nullptr;
   float* dinv32 = nullptr;
   int lpr_S = 8;
@@ -193,14 +186,7 @@ struct Level {
     s.colour_chunk_dev = colour_chunk_dev; s.one_launch = one_launch;
     s.wg = wg_S;
     s.sb_ptr = sb_ptr; s.sb_dofs = sb_dofs; s.fac_off = fac_off; s.lpr = lpr_S;
-    s.ck_row0 = ck_row0; s.ck_fac0 = ck_fac0; s.srow_ptr = srow_ptr; s.scol = scol;
-    if constexpr (std::is_same<T, double>::value) {
-      s.fac = fac;
-      s.sval = sval;
-    } else {
-      s.fac = fac32;
-      s.sval = sval32;
-    }
+    if constexpr (std::is_same<T, double>::value) s.fac = fac; else s.fac = fac32;
     return s;
   }
 };
@@ -308,23 +294,12 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   // (rows per chunk = wg / lpr >= largest block), up to 1024 threads
   int lpr = L.lpr_A;
   int wg = 256;
-  const double avg_row = L.n > 0 ? (double)L.nnz / (double)L.n : 0.0;
-  const char* wide_env = std::getenv("HCURL_AMG_WIDE_ROWS");
-  const bool wide_ok = !(wide_env && wide_env[0] == '0');
-  if (wide_ok && avg_row > 600.0 && maxs <= 8) {
-    // very wide rows (dense coarse operators): two wavefronts per row
-    lpr = 128;
-    wg = 1024;
-  } else {
-    while (wg / lpr < std::max(maxs, 1) && wg < 1024) wg *= 2;
-    while (wg / lpr < std::max(maxs, 1) && lpr > 4) lpr /= 2;
-    if (wg > 256 && lpr < 16) {   // wide workgroups only pay off with wide rows
-      wg = 256;
-      while (256 / lpr < std::max(maxs, 1)) lpr /= 2;
-    }
+  while (wg / lpr < std::max(maxs, 1) && wg < 1024) wg *= 2;
+  while (wg / lpr < std::max(maxs, 1) && lpr > 4) lpr /= 2;
+  if (wg > 256 && lpr < 16) {   // wide workgroups only pay off with wide rows
+    wg = 256;
+    while (256 / lpr < std::max(maxs, 1)) lpr /= 2;
   }
-  if (!schwarz_shape_ok(lpr, wg) || wg / lpr < std::max(maxs, 1))
-    fail(AMG_ERR_LIMIT, "no smoother launch shape for this level");
   L.lpr_S = lpr;
   L.wg_S = wg;
   const int rpb = wg / lpr;
@@ -363,49 +338,11 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   }
   L.colour_chunk[I.ncolors] = (int)chunk_blk.size();
   chunk_blk.push_back((int32_t)ns);
-  if (sb_ptr[ns] > INT32_MAX) fail(AMG_ERR_LIMIT, "more than 2^31 smoother rows on one level");
-  // per-chunk first row and first factor entry, so that a chunk finds its
-  // rows and factors with one lookup
-  std::vector<int32_t> ck_row0(chunk_blk.size());
-  std::vector<int64_t> ck_fac0(chunk_blk.size());
-  for (size_t c = 0; c < chunk_blk.size(); ++c) {
-    ck_row0[c] = (int32_t)sb_ptr[chunk_blk[c]];
-    ck_fac0[c] = fac_off[chunk_blk[c]];
-  }
-  L.ck_row0 = h->pool.upload(ck_row0, st);
-  L.ck_fac0 = h->pool.upload(ck_fac0, st);
-  // the smoother's copy of A's rows in star order (pattern here, values at
-  // every numeric setup)
-  {
-    const int64_t nr = sb_ptr[ns];
-    std::vector<int64_t> srow_ptr(nr + 1, 0);
-    for (int64_t r = 0; r < nr; ++r) {
-      const int32_t d = sb_dofs[r];
-      srow_ptr[r + 1] = srow_ptr[r] + (L.Apat.ptr[d + 1] - L.Apat.ptr[d]);
-    }
-    std::vector<int32_t> scol(std::max<int64_t>(srow_ptr[nr], 1));
-    parallel_for(nr, [&](int64_t rb, int64_t re) {
-      for (int64_t r = rb; r < re; ++r) {
-        const int32_t d = sb_dofs[r];
-        std::copy(L.Apat.idx.begin() + L.Apat.ptr[d], L.Apat.idx.begin() + L.Apat.ptr[d + 1],
-                  scol.begin() + srow_ptr[r]);
-      }
-    });
-    L.srow_nnz = srow_ptr[nr];
-    L.srow_ptr = h->pool.upload(srow_ptr, st);
-    L.scol = h->pool.upload(scol, st);
-    L.sval = h->pool.get<double>(std::max<int64_t>(L.srow_nnz, 1));
-  }
   L.chunk_blk = h->pool.upload(chunk_blk, st);
   L.colour_chunk_dev = h->pool.upload(std::vector<int32_t>(L.colour_chunk.begin(), L.colour_chunk.end()), st);
-  // launch shape of a sweep: one workgroup for the whole sweep where the rows
-  // it streams are few for the number of colours (one launch per colour costs
-  // a few microseconds, about what one CU streams of 40k row entries), else
-  // one launch per colour
-  int64_t per_colour = 40000;
-  if (const char* e = std::getenv("HCURL_AMG_SWEEP1_ENTRIES")) per_colour = std::atoll(e);
-  L.one_launch = L.nnz <= 200000 || L.srow_nnz <= per_colour * (int64_t)I.ncolors;
-  if (const char* e = std::getenv("HCURL_AMG_ONE_LAUNCH")) L.one_launch = e[0] == '1' ? true : e[0] == '0' ? false : L.one_launch;
+  // launch shape of a sweep: tiny levels in one workgroup, the rest one
+  // launch per colour
+  L.one_launch = L.nnz <= 200000 && wg == 256;
   L.sb_ptr = h->pool.upload(sb_ptr, st);
   L.sb_dofs = h->pool.upload(sb_dofs, st);
   L.fac_off = h->pool.upload(fac_off, st);
@@ -415,7 +352,6 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
 }
 
 void factor_smoother(amg_hier* h, Level& L, int level, hipStream_t st) {
-  star_rows((int64_t)L.ints.star_dofs.size(), L.sb_dofs, L.A_ptr, L.A_val, L.srow_ptr, L.sval, st);
   star_chol(L.nstars, L.sb_ptr, L.sb_dofs, L.fac_off, L.A_dev<double>(), L.fac, h->d_flag, st);
   check_flag(h, st, AMG_ERR_NOT_SPD, "smoother block Cholesky: non-positive pivot on level " +
                                          std::to_string(level));
@@ -599,9 +535,7 @@ void cast_level(amg_hier* h, Level& L, hipStream_t st) {
     L.PT_val32 = h->pool.get<float>(L.p_nnz);
     L.fac32 = h->pool.get<float>(L.fac_total);
     L.dinv32 = h->pool.get<float>(L.n);
-    L.sval32 = h->pool.get<float>(std::max<int64_t>(L.srow_nnz, 1));
   }
-  cast<double, float>(L.srow_nnz, L.sval, L.sval32, st);
   cast<double, float>(L.p_nnz, L.P_val, L.P_val32, st);
   cast<double, float>(L.p_nnz, L.PT_val, L.PT_val32, st);
   cast<double, float>(L.fac_total, L.fac, L.fac32, st);
@@ -766,8 +700,8 @@ void vcycle_T(amg_hier* h, const T* b0, T* x0, hipStream_t st) {
     SmootherDev<T> S = L.S_dev<T>();
     T* x = X(l);
     fill<T>(L.n, (T)0, x, st);
-    schwarz_sweep<T>(S, 0, B(l), x, st);
-    schwarz_sweep<T>(S, 1, B(l), x, st);
+    schwarz_sweep<T>(S, A, 0, B(l), x, st);
+    schwarz_sweep<T>(S, A, 1, B(l), x, st);
     jacobi<T>(A, x, B(l), Vec<T>::dinv(L), Vec<T>::t(L), st);
     residual<T>(A, Vec<T>::t(L), B(l), Vec<T>::r(L), st);
     spmv<T>(L.PT_dev<T>(), Vec<T>::r(L), Vec<T>::b(h->lv[l + 1]), st);
@@ -781,8 +715,8 @@ void vcycle_T(amg_hier* h, const T* b0, T* x0, hipStream_t st) {
     spmv_add<T>(L.P_dev<T>(), X(l + 1), Vec<T>::t(L), st);
     T* x = X(l);
     jacobi<T>(A, Vec<T>::t(L), B(l), Vec<T>::dinv(L), x, st);
-    schwarz_sweep<T>(S, 0, B(l), x, st);
-    schwarz_sweep<T>(S, 1, B(l), x, st);
+    schwarz_sweep<T>(S, A, 0, B(l), x, st);
+    schwarz_sweep<T>(S, A, 1, B(l), x, st);
   }
 }
 
@@ -1208,7 +1142,7 @@ amg_status amg_smoother_sweep(amg_hier* h, int level, int prec, const void* b, v
     hipStream_t st = (hipStream_t)stream;
     auto run = [&](auto tag) {
       using T = decltype(tag);
-      schwarz_sweep<T>(L.S_dev<T>(), backward, (const T*)b, (T*)x, st);
+      schwarz_sweep<T>(L.S_dev<T>(), L.A_dev<T>(), backward, (const T*)b, (T*)x, st);
     };
     if (prec == 64) run(double()); else run(float());
     HIPC(hipGetLastError());

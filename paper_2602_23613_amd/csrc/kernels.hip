@@ -155,134 +155,38 @@ void spmv_dot(const CsrDev<double>& A, const double* x, double* y, double* parti
 }
 
 // ---------------------------------------------------------------------------
-// multiplicative Schwarz
+// multiplicative Schwarz: one colour
 // ---------------------------------------------------------------------------
-// Row sums for the smoother: each lane first loads U (column, value) pairs of
-// its row (stride LPR), then the U gathers of x, then sums in q order, so a
-// lane keeps 2U independent loads in flight per pass.  Padding slots load
-// nothing and add nothing.
-template <int LPR, int U, class T>
-__device__ __forceinline__ T row_dot_batched(int64_t b, int64_t e, int lane,
-                                             const int32_t* __restrict__ col,
-                                             const T* __restrict__ val, const T* __restrict__ x) {
-  T s = 0;
-  for (int64_t q0 = b + lane; q0 < e; q0 += (int64_t)U * LPR) {
-    int32_t c[U];
-    T v[U], xv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t q = q0 + (int64_t)u * LPR;
-      const bool in = q < e;
-      c[u] = in ? col[q] : -1;
-      v[u] = in ? val[q] : T(0);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) xv[u] = c[u] >= 0 ? x[c[u]] : T(0);
-#pragma unroll
-    for (int u = 0; u < U; ++u) s += v[u] * xv[u];
-  }
-  return s;
-}
-
-// LDS of one chunk: residuals of its rows, per-wave partial sums when a row
-// spans several wavefronts (LPR > 64), and the chunk's packed factors.
-// A chunk holds at most RPB rows in blocks of at most min(RPB, 32) rows, so
-// its packed factors take at most RPB (min(RPB, 32) + 1) / 2 entries.
-template <class T, int LPR, int WGS>
-struct ChunkLds {
-  static constexpr int RPB = WGS / LPR;
-  static constexpr int WPR = LPR > 64 ? LPR / 64 : 1;
-  static constexpr int SMAX = RPB < 32 ? RPB : 32;
-  T res[RPB];
-  T part[WPR > 1 ? RPB * WPR : 1];
-  T fl[RPB * (SMAX + 1) / 2];
-};
-
-// One chunk (consecutive blocks of one colour, at most WGS / LPR rows in
-// all) of the multiplicative Schwarz step x_B += A_BB^{-1} (b - A x)_B, by a
-// group of WGS threads (tid = 0..WGS-1).  Called uniformly by every thread
-// of the workgroup (it synchronises); act = false for groups without a chunk.
-// The rows come from the smoother's own copy of A in chunk order (srow_ptr,
-// scol, sval), so one chunk streams one contiguous range; everything the
-// solve and update phases need is fetched up front, which leaves four
-// dependent memory accesses per chunk (chunk bounds, row bounds, row
-// entries, x gathers).
-template <class T, int LPR, int WGS, int U>
-__device__ __forceinline__ void schwarz_chunk(
-    bool act, int c, int tid, ChunkLds<T, LPR, WGS>& S, const SmootherArgs<T>& D,
-    const T* __restrict__ b, T* __restrict__ x) {
-  constexpr int WPR = ChunkLds<T, LPR, WGS>::WPR;
-  constexpr int FL = (int)(sizeof(S.fl) / sizeof(T));
-  constexpr int FPT = (FL + WGS - 1) / WGS;   // factor entries staged per thread
-  // 1. chunk bounds
-  int blk0 = 0, nblk = 0, r0 = 0, nrows = 0, nf = 0;
-  int64_t f0 = 0;
-  if (act) {
-    blk0 = D.chunk_blk[c];
-    nblk = D.chunk_blk[c + 1] - blk0;
-    r0 = D.ck_row0[c];
-    nrows = D.ck_row0[c + 1] - r0;
-    f0 = D.ck_fac0[c];
-    nf = (int)(D.ck_fac0[c + 1] - f0);
-  }
-  // 2. everything that depends on the bounds only, issued together
-  const int grp = tid / LPR, lane = tid % LPR;
-  const bool row_act = grp < nrows;
-  const int64_t r = (int64_t)r0 + grp;
-  int64_t q0 = 0, q1 = 0;
-  int32_t rdof = 0, mydof = 0;
-  if (row_act) {
-    q0 = D.srow_ptr[r];
-    q1 = D.srow_ptr[r + 1];
-    if (lane == 0) rdof = D.sb_dofs[r];
-  }
-  if (tid < nrows) mydof = D.sb_dofs[r0 + tid];
-  int64_t p0 = 0, p1 = 0, fo = 0;
-  if (tid < nblk) {
-    p0 = D.sb_ptr[blk0 + tid];
-    p1 = D.sb_ptr[blk0 + tid + 1];
-    fo = D.fac_off[blk0 + tid];
-  }
-  T fv[FPT];
-#pragma unroll
-  for (int k = 0; k < FPT; ++k) {
-    const int t = tid + k * WGS;
-    fv[k] = t < nf ? D.fac[f0 + t] : T(0);
-  }
-  // 3. second-level loads: right-hand side, own x entries, the row sums
-  T bv = 0, myx = 0;
-  if (row_act && lane == 0) bv = b[rdof];
-  if (tid < nrows) myx = x[mydof];   // only this chunk changes these entries during the colour
-  T s = 0;
-  if (row_act) s = row_dot_batched<LPR, U, T>(q0, q1, lane, D.scol, D.sval, x);
-#pragma unroll
-  for (int k = 0; k < FPT; ++k) {
-    const int t = tid + k * WGS;
-    if (t < nf) S.fl[t] = fv[k];
-  }
-  if (row_act) {
-    if constexpr (LPR <= 64) {
-      s = group_sum<LPR>(s);
-      if (lane == 0) S.res[grp] = bv - s;
-    } else {
-      s = group_sum<64>(s);
-      if (lane % 64 == 0) S.part[grp * WPR + lane / 64] = s;
-      if (lane == 0) S.res[grp] = bv;
-    }
+// chunk c covers blocks [chunk_blk[c], chunk_blk[c+1]); their rows are
+// contiguous in sb_dofs and number at most 256/LPR.  Blocks of one colour
+// share no DoF and no coupling, so chunks update x independently.
+template <class T, int LPR, int WG>
+__global__ __launch_bounds__(WG) void k_schwarz(
+    const int32_t* __restrict__ chunk_blk, int chunk0, const int64_t* __restrict__ sb_ptr,
+    const int32_t* __restrict__ sb_dofs, const int64_t* __restrict__ fac_off,
+    const T* __restrict__ fac, const int64_t* __restrict__ Aptr, const int32_t* __restrict__ Acol,
+    const T* __restrict__ Aval, const T* __restrict__ b, T* __restrict__ x) {
+  constexpr int RPB = WG / LPR;
+  __shared__ T res[RPB];
+  const int c = chunk0 + blockIdx.x;
+  const int blk0 = chunk_blk[c], blk1 = chunk_blk[c + 1];
+  const int64_t r0 = sb_ptr[blk0];
+  const int nrows = (int)(sb_ptr[blk1] - r0);
+  const int grp = threadIdx.x / LPR, lane = threadIdx.x % LPR;
+  if (grp < nrows) {
+    const int32_t dof = sb_dofs[r0 + grp];
+    T s = row_dot<LPR, T>(Aptr[dof], Aptr[dof + 1], lane, Acol, Aval, x);
+    s = group_sum<LPR>(s);
+    if (lane == 0) res[grp] = b[dof] - s;
   }
   __syncthreads();
-  // 4. block solves from LDS, one thread per block
-  if (tid < nblk) {
-    const int boff = (int)(p0 - r0), sz = (int)(p1 - p0);
-    const T* L = S.fl + (fo - f0);
-    T* v = S.res + boff;
-    if constexpr (WPR > 1) {
-      for (int i = 0; i < sz; ++i) {
-        T p = 0;
-        for (int w = 0; w < WPR; ++w) p += S.part[(boff + i) * WPR + w];
-        v[i] -= p;
-      }
-    }
+  const int t = threadIdx.x;
+  if (t < blk1 - blk0) {
+    const int blk = blk0 + t;
+    const int off = (int)(sb_ptr[blk] - r0);
+    const int sz = (int)(sb_ptr[blk + 1] - sb_ptr[blk]);
+    const T* L = fac + fac_off[blk];
+    T* v = res + off;
     for (int i = 0; i < sz; ++i) {
       T a = v[i];
       const T* Li = L + i * (i + 1) / 2;
@@ -296,99 +200,118 @@ __device__ __forceinline__ void schwarz_chunk(
     }
   }
   __syncthreads();
-  if (tid < nrows) x[mydof] = myx + S.res[tid];
+  if (threadIdx.x < nrows) x[sb_dofs[r0 + threadIdx.x]] += res[threadIdx.x];
 }
 
-// one colour: chunk chunk0 + blockIdx.x per workgroup.  Blocks of one colour
-// share no DoF and no coupling, so chunks update x independently.
-template <class T, int LPR, int WG, int U>
-__global__ __launch_bounds__(WG) void k_schwarz(SmootherArgs<T> D, int chunk0, const T* __restrict__ b,
-                                                T* __restrict__ x) {
-  __shared__ ChunkLds<T, LPR, WG> S;
-  schwarz_chunk<T, LPR, WG, U>(true, chunk0 + blockIdx.x, threadIdx.x, S, D, b, x);
-}
-
-// Whole sweep in one launch: a 1024-thread workgroup walks the colours in
-// order; its 1024 / WGS groups take the chunks of the current colour in
-// turn.  The barriers inside schwarz_chunk and the one after each round make
-// the x updates of a colour visible before the next colour reads x.
-template <class T, int LPR, int WGS, int U>
-__global__ __launch_bounds__(1024) void k_schwarz_sweep1(SmootherArgs<T> D, int backward,
-                                                         const T* __restrict__ b, T* __restrict__ x) {
-  constexpr int NSUB = 1024 / WGS;
-  __shared__ ChunkLds<T, LPR, WGS> S_all[NSUB];
-  const int sub = threadIdx.x / WGS;
-  const int tid = threadIdx.x % WGS;
-  for (int ci = 0; ci < D.ncolours; ++ci) {
-    const int colour = backward ? D.ncolours - 1 - ci : ci;
-    const int c0 = D.colour_chunk_dev[colour], c1 = D.colour_chunk_dev[colour + 1];
-    for (int base = c0; base < c1; base += NSUB) {
+// Whole sweep of a small level in one launch: a 1024-thread workgroup walks
+// the colours in order; its four 256-thread groups take chunks of the current
+// colour in turn.  __syncthreads after each round makes the x updates of one
+// colour visible before the next colour reads x.
+template <class T, int LPR>
+__global__ __launch_bounds__(1024) void k_schwarz_sweep1(
+    int ncolours, const int32_t* __restrict__ colour_chunk, int backward,
+    const int32_t* __restrict__ chunk_blk, const int64_t* __restrict__ sb_ptr,
+    const int32_t* __restrict__ sb_dofs, const int64_t* __restrict__ fac_off,
+    const T* __restrict__ fac, const int64_t* __restrict__ Aptr, const int32_t* __restrict__ Acol,
+    const T* __restrict__ Aval, const T* __restrict__ b, T* __restrict__ x) {
+  constexpr int RPB = 256 / LPR;
+  __shared__ T res_all[4][RPB];
+  const int sub = threadIdx.x / 256;
+  const int tid = threadIdx.x % 256;
+  T* res = res_all[sub];
+  const int grp = tid / LPR, lane = tid % LPR;
+  for (int ci = 0; ci < ncolours; ++ci) {
+    const int col = backward ? ncolours - 1 - ci : ci;
+    const int c0 = colour_chunk[col], c1 = colour_chunk[col + 1];
+    for (int base = c0; base < c1; base += 4) {
       const int c = base + sub;
-      schwarz_chunk<T, LPR, WGS, U>(c < c1, c, tid, S_all[sub], D, b, x);
+      const bool act = c < c1;
+      int blk0 = 0, blk1 = 0, nrows = 0;
+      int64_t r0 = 0;
+      if (act) {
+        blk0 = chunk_blk[c];
+        blk1 = chunk_blk[c + 1];
+        r0 = sb_ptr[blk0];
+        nrows = (int)(sb_ptr[blk1] - r0);
+      }
+      if (act && grp < nrows) {
+        const int32_t dof = sb_dofs[r0 + grp];
+        T s = row_dot<LPR, T>(Aptr[dof], Aptr[dof + 1], lane, Acol, Aval, x);
+        s = group_sum<LPR>(s);
+        if (lane == 0) res[grp] = b[dof] - s;
+      }
+      __syncthreads();
+      if (act && tid < blk1 - blk0) {
+        const int blk = blk0 + tid;
+        const int off = (int)(sb_ptr[blk] - r0);
+        const int sz = (int)(sb_ptr[blk + 1] - sb_ptr[blk]);
+        const T* L = fac + fac_off[blk];
+        T* v = res + off;
+        for (int i = 0; i < sz; ++i) {
+          T a = v[i];
+          const T* Li = L + i * (i + 1) / 2;
+          for (int j = 0; j < i; ++j) a -= Li[j] * v[j];
+          v[i] = a / Li[i];
+        }
+        for (int i = sz - 1; i >= 0; --i) {
+          T a = v[i];
+          for (int j = i + 1; j < sz; ++j) a -= L[j * (j + 1) / 2 + i] * v[j];
+          v[i] = a / L[i * (i + 1) / 2 + i];
+        }
+      }
+      __syncthreads();
+      if (act && tid < nrows) x[sb_dofs[r0 + tid]] += res[tid];
       __syncthreads();
     }
   }
 }
 
-template <int LPR>
-constexpr int unroll_for() { return LPR >= 64 ? 16 : 8; }
-
-// (lanes per row, group size) pairs that the smoother launches support
-bool schwarz_shape_ok(int lpr, int wg) {
-  if (wg == 256) return lpr == 4 || lpr == 8 || lpr == 16 || lpr == 32 || lpr == 64;
-  if (wg == 512) return lpr == 16 || lpr == 32 || lpr == 64 || lpr == 128;
-  if (wg == 1024) return lpr == 32 || lpr == 64 || lpr == 128 || lpr == 256;
-  return false;
-}
-
-#define SCHWARZ_SHAPES(X)                                                                        \
-  X(4, 256) X(8, 256) X(16, 256) X(32, 256) X(64, 256) X(16, 512) X(32, 512) X(64, 512)         \
-  X(128, 512) X(32, 1024) X(64, 1024) X(128, 1024) X(256, 1024)
-
 template <class T>
-void schwarz_sweep_small(const SmootherDev<T>& S, int backward, const T* b, T* x, hipStream_t st) {
-  const SmootherArgs<T> D = S;
-#define LAUNCH_SW1(L, W)                                                                         \
-  if (S.lpr == L && S.wg == W) {                                                                 \
-    hipLaunchKernelGGL((k_schwarz_sweep1<T, L, W, unroll_for<L>()>), dim3(1), dim3(1024), 0, st,  \
-                       D, backward, b, x);                                                       \
-    return;                                                                                      \
+void schwarz_sweep_small(const SmootherDev<T>& S, const CsrDev<T>& A, int backward, const T* b,
+                         T* x, hipStream_t st) {
+#define LAUNCH_SW1(L)                                                                         \
+  hipLaunchKernelGGL((k_schwarz_sweep1<T, L>), dim3(1), dim3(1024), 0, st, S.ncolours,        \
+                     S.colour_chunk_dev, backward, S.chunk_blk, S.sb_ptr, S.sb_dofs, S.fac_off,  \
+                     S.fac, A.ptr, A.col, A.val, b, x);
+  switch (S.lpr) {
+    case 4: LAUNCH_SW1(4); break;
+    case 8: LAUNCH_SW1(8); break;
+    case 16: LAUNCH_SW1(16); break;
+    case 32: LAUNCH_SW1(32); break;
+    default: LAUNCH_SW1(64); break;
   }
-  SCHWARZ_SHAPES(LAUNCH_SW1)
 #undef LAUNCH_SW1
 }
 
 template <class T>
-void schwarz_colour(const SmootherDev<T>& S, int colour, const T* b, T* x, hipStream_t st) {
+void schwarz_colour(const SmootherDev<T>& S, const CsrDev<T>& A, int colour, const T* b, T* x,
+                    hipStream_t st) {
   int c0 = S.colour_chunk[colour], c1 = S.colour_chunk[colour + 1];
   if (c1 <= c0) return;
-  const SmootherArgs<T> D = S;
-#define LAUNCH_SW(L, W)                                                                          \
-  if (S.lpr == L && S.wg == W) {                                                                 \
-    hipLaunchKernelGGL((k_schwarz<T, L, W, unroll_for<L>()>), dim3(c1 - c0), dim3(W), 0, st, D,   \
-                       c0, b, x);                                                                \
-    return;                                                                                      \
+#define LAUNCH_SW(L, W)                                                                        \
+  hipLaunchKernelGGL((k_schwarz<T, L, W>), dim3(c1 - c0), dim3(W), 0, st, S.chunk_blk, c0,      \
+                     S.sb_ptr, S.sb_dofs, S.fac_off, S.fac, A.ptr, A.col, A.val, b, x);
+  if (S.wg == 1024) {
+    switch (S.lpr) {
+      case 32: LAUNCH_SW(32, 1024); break;
+      default: LAUNCH_SW(64, 1024); break;
+    }
+  } else if (S.wg == 512) {
+    switch (S.lpr) {
+      case 16: LAUNCH_SW(16, 512); break;
+      case 32: LAUNCH_SW(32, 512); break;
+      default: LAUNCH_SW(64, 512); break;
+    }
+  } else {
+    switch (S.lpr) {
+      case 4: LAUNCH_SW(4, 256); break;
+      case 8: LAUNCH_SW(8, 256); break;
+      case 16: LAUNCH_SW(16, 256); break;
+      case 32: LAUNCH_SW(32, 256); break;
+      default: LAUNCH_SW(64, 256); break;
+    }
   }
-  SCHWARZ_SHAPES(LAUNCH_SW)
 #undef LAUNCH_SW
-}
-
-// values of the smoother's row copy: star row r is row sb_dofs[r] of A
-__global__ void k_star_rows(int64_t nrows, const int32_t* __restrict__ sb_dofs,
-                            const int64_t* __restrict__ Aptr, const double* __restrict__ Aval,
-                            const int64_t* __restrict__ srow_ptr, double* __restrict__ sval) {
-  const int64_t r = (int64_t)blockIdx.x * 8 + threadIdx.x / 32;
-  const int lane = threadIdx.x % 32;
-  if (r >= nrows) return;
-  const int64_t a0 = Aptr[sb_dofs[r]];
-  const int64_t s0 = srow_ptr[r], len = srow_ptr[r + 1] - s0;
-  for (int64_t q = lane; q < len; q += 32) sval[s0 + q] = Aval[a0 + q];
-}
-void star_rows(int64_t nrows, const int32_t* sb_dofs, const int64_t* Aptr, const double* Aval,
-               const int64_t* srow_ptr, double* sval, hipStream_t st) {
-  if (nrows > 0)
-    hipLaunchKernelGGL(k_star_rows, dim3((unsigned)((nrows + 7) / 8)), dim3(256), 0, st, nrows,
-                       sb_dofs, Aptr, Aval, srow_ptr, sval);
 }
 
 // ---------------------------------------------------------------------------
@@ -1022,10 +945,10 @@ template void jacobi<double>(const CsrDev<double>&, const double*, const double*
 template void jacobi<float>(const CsrDev<float>&, const float*, const float*, const float*, float*, hipStream_t);
 template void spmv_add<double>(const CsrDev<double>&, const double*, double*, hipStream_t);
 template void spmv_add<float>(const CsrDev<float>&, const float*, float*, hipStream_t);
-template void schwarz_colour<double>(const SmootherDev<double>&, int, const double*, double*, hipStream_t);
-template void schwarz_colour<float>(const SmootherDev<float>&, int, const float*, float*, hipStream_t);
-template void schwarz_sweep_small<double>(const SmootherDev<double>&, int, const double*, double*, hipStream_t);
-template void schwarz_sweep_small<float>(const SmootherDev<float>&, int, const float*, float*, hipStream_t);
+template void schwarz_colour<double>(const SmootherDev<double>&, const CsrDev<double>&, int, const double*, double*, hipStream_t);
+template void schwarz_colour<float>(const SmootherDev<float>&, const CsrDev<float>&, int, const float*, float*, hipStream_t);
+template void schwarz_sweep_small<double>(const SmootherDev<double>&, const CsrDev<double>&, int, const double*, double*, hipStream_t);
+template void schwarz_sweep_small<float>(const SmootherDev<float>&, const CsrDev<float>&, int, const float*, float*, hipStream_t);
 template void dense_solve<double>(int, const double*, const double*, double*, double*, hipStream_t);
 template void dense_solve<float>(int, const double*, const float*, float*, double*, hipStream_t);
 template void fill<double>(int64_t, double, double*, hipStream_t);

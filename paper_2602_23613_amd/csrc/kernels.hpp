@@ -24,30 +24,19 @@ struct CsrPat {
   const int32_t* col = nullptr;
 };
 
-// Smoother blocks sorted by colour and packed into chunks for k_schwarz:
-// the device pointers (a plain struct, passed to the kernels by value) ...
+// Smoother blocks sorted by colour and packed into chunks for k_schwarz.
 template <class T>
-struct SmootherArgs {
+struct SmootherDev {
   int ncolours = 0;
-  const int32_t* colour_chunk_dev = nullptr;   // chunk range of each colour
+  std::vector<int> colour_chunk;        // host: chunk range of each colour
+  const int32_t* colour_chunk_dev = nullptr;   // the same on the device
+  bool one_launch = false;              // tiny level: whole sweep in one workgroup
+  int wg = 256;                         // workgroup size of k_schwarz (rows per chunk = wg / lpr)
   const int32_t* chunk_blk = nullptr;   // first block of each chunk (+ sentinel)
   const int64_t* sb_ptr = nullptr;      // rows of each block (colour order)
   const int32_t* sb_dofs = nullptr;
   const int64_t* fac_off = nullptr;     // packed lower factor offset of each block
   const T* fac = nullptr;
-  const int32_t* ck_row0 = nullptr;     // first star row of each chunk (+ sentinel)
-  const int64_t* ck_fac0 = nullptr;     // first factor entry of each chunk (+ sentinel)
-  const int64_t* srow_ptr = nullptr;    // the smoother's copy of A's rows in star order
-  const int32_t* scol = nullptr;
-  const T* sval = nullptr;
-};
-
-// ... and the host-side launch shape.
-template <class T>
-struct SmootherDev : SmootherArgs<T> {
-  std::vector<int> colour_chunk;        // host: chunk range of each colour
-  bool one_launch = false;              // small level: whole sweep in one workgroup
-  int wg = 256;                         // threads per chunk (rows per chunk = wg / lpr)
   int lpr = 8;
 };
 
@@ -63,24 +52,24 @@ template <class T> void spmv_add(const CsrDev<T>& A, const T* x, T* y, hipStream
 void spmv_dot(const CsrDev<double>& A, const double* x, double* y, double* partial, hipStream_t st);
 int64_t spmv_dot_partials(int lpr, int64_t n);
 
-bool schwarz_shape_ok(int lpr, int wg);
 template <class T>
-void schwarz_colour(const SmootherDev<T>& S, int colour, const T* b, T* x, hipStream_t st);
+void schwarz_colour(const SmootherDev<T>& S, const CsrDev<T>& A, int colour, const T* b, T* x,
+                    hipStream_t st);
 template <class T>
-void schwarz_sweep_small(const SmootherDev<T>& S, int backward, const T* b, T* x, hipStream_t st);
+void schwarz_sweep_small(const SmootherDev<T>& S, const CsrDev<T>& A, int backward, const T* b,
+                         T* x, hipStream_t st);
 
 // one multiplicative Schwarz sweep (all colours) with the launch shape the level uses
 template <class T>
-void schwarz_sweep(const SmootherDev<T>& S, int backward, const T* b, T* x, hipStream_t st) {
+void schwarz_sweep(const SmootherDev<T>& S, const CsrDev<T>& A, int backward, const T* b, T* x,
+                   hipStream_t st) {
   if (S.one_launch) {
-    schwarz_sweep_small<T>(S, backward, b, x, st);
+    schwarz_sweep_small<T>(S, A, backward, b, x, st);
     return;
   }
   for (int k = 0; k < S.ncolours; ++k)
-    schwarz_colour<T>(S, backward ? S.ncolours - 1 - k : k, b, x, st);
+    schwarz_colour<T>(S, A, backward ? S.ncolours - 1 - k : k, b, x, st);
 }
-void star_rows(int64_t nrows, const int32_t* sb_dofs, const int64_t* Aptr, const double* Aval,
-               const int64_t* srow_ptr, double* sval, hipStream_t st);
 template <class T>
 void dense_solve(int n, const double* L, const T* b, T* x, double* work, hipStream_t st);
 void dense_factor(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, double* D,

@@ -399,6 +399,9 @@ def _with_env(env, fn):
                 os.environ[k] = v
 
 
+@pytest.mark.skip(reason="the two-wavefront-row / generalised one-launch smoother variant it covers "
+                         "is switched off: a 64^3 PCG run with it ended in a GPU memory fault whose "
+                         "cause is not yet shown")
 def test_sweep_launch_shapes_agree():
     """The 16^3 jump case has a dense level (1176 rows of 1176 entries), which
     takes the two-wavefront rows and the one-launch sweep.  Forcing one launch
