@@ -34,6 +34,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per level-0 k_schwarz<double,8,256> launch on the 64^3 workload, from the
+# rocprofv3 FETCH_SIZE / WRITE_SIZE passes (calibrated on a 1 GiB copy) summarised in
+# profiles/k_schwarz_l0_hex64_counters.md; valid for that kernel and workload only
+SCHWARZ_L0_TRAFFIC_64 = (2.0 * 70504.9 + 3561.0) * 1024
 
 
 def log(*a):
@@ -258,6 +262,9 @@ def main():
     ap.add_argument("--learn-epochs", type=int, default=30)
     ap.add_argument("--learn-check-iters", type=int, default=10,
                     help="stand-alone V-cycles of the learned setup's global check")
+    ap.add_argument("--counters", action="store_true",
+                    help="setup once, then two level-0 sweeps and a 1 GiB device copy only "
+                         "(a short program for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE passes)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="setup once and time the V-cycle / level-0 sweep only (for profiling)")
     ap.add_argument("--cpu-baseline-worker", nargs=3, default=None)
@@ -283,6 +290,23 @@ def main():
     Ad, Gd, f = to_device(p, torch)
     del p
     torch.cuda.synchronize()
+    if a.counters:
+        H = amg.Hierarchy(Ad, Gd, vcycle_prec=64, p_trunc=a.p_trunc)
+        b = f.clone()
+        x = torch.zeros_like(b)
+        for bw in (False, True):
+            H.sweep(0, b, x, backward=bw)
+        # calibration: a plain copy of known size (reads 1 GiB, writes 1 GiB)
+        src = torch.ones(1 << 27, dtype=torch.float64, device=f.device)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        li = H.info()[0]
+        print(json.dumps({"counters": True, "level0_sweep_bytes": sweep_bytes(li, 8),
+                          "level0_colours": li["ncolors"], "copy_bytes_each_way": src.numel() * 8}),
+              flush=True)
+        H.close()
+        return
     if a.kernels_only:
         H = amg.Hierarchy(Ad, Gd, vcycle_prec=64, p_trunc=a.p_trunc)
         log("levels", [(l["n"], l["nnz"], l["ncolors"]) for l in H.info()])
@@ -357,7 +381,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": kt["launch_bytes"] / (kt["launch_ms"] * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": kt["launch_bytes"] / (kt["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": None, "kernel": "k_schwarz<double,8,256> (level-0 colour launch)",
+                     "traffic": SCHWARZ_L0_TRAFFIC_64 if a.size == 64 and a.p_trunc == 0.0 else None,
+                     "traffic_unit": "bytes per launch",
+                     "kernel": "k_schwarz<double,8,256> (level-0 colour launch)",
                      "bytes_per_launch": kt["launch_bytes"], "launch_ms": kt["launch_ms"]},
     }
     if not a.no_cpu_baseline:

@@ -263,6 +263,16 @@ amg_status amg_mlp_forward(amg_hier *h, const uint16_t *x, int64_t n, float *y, 
 amg_status amg_mlp_backward(amg_hier *h, const uint16_t *x, int64_t n, const float *dy, float *grad,
                             void *stream);
 
+/* Training loss of the learned form, for checking the kernel: for each of the
+   n rows (device arrays) y = prediction, t = exact target (64 FP32 values,
+   the first 36 being packed lower triangles of symmetric 8 x 8 matrices) and
+   ahat = the normalised block (36 FP64 values, packed the same way),
+   row_loss[r] = ||Ahat (W - W*)||_F^2 and dy[r] = its gradient with respect
+   to y divided by nvalid; rows r >= nvalid (batch padding) get zeros.
+   Asynchronous on the stream. */
+amg_status amg_mlp_loss_grad(const float *y, const float *t, const double *ahat, int64_t n,
+                             int64_t nvalid, float *dy, float *row_loss, void *stream);
+
 /* Release a hierarchy and all its device memory.  NULL is ignored. */
 void amg_destroy(amg_hier *h);
 

@@ -98,6 +98,35 @@ def backward(params, cache, dY, rounding=True):
     return [gW1, gb1, gW2, gb2, gW3, gb3]
 
 
+def unpack_sym(v, s=SMAX):
+    """Symmetric s x s matrix from its packed lower triangle."""
+    M = np.zeros((s, s))
+    for q, (i, j) in enumerate(packed_index(s)):
+        M[i, j] = M[j, i] = v[q]
+    return M
+
+
+def a_loss_grad(Y, T, Ahat, nvalid):
+    """Training loss of the learned form: per row, the error of the predicted
+    inverse W against the exact W* in the block's metric, ||Ahat (W - W*)||_F^2
+    (equal to the refinement residual ||Ahat W - I||_F^2, as Ahat W* = I).
+    Returns (row losses, gradient of their mean over the first nvalid rows with
+    respect to Y); padding rows get zeros."""
+    n = Y.shape[0]
+    loss = np.zeros(n)
+    G = np.zeros_like(Y, dtype=np.float64)
+    idx = packed_index()
+    for r in range(nvalid):
+        A = unpack_sym(Ahat[r][:36])
+        E = unpack_sym(np.asarray(Y[r][:36], float) - np.asarray(T[r][:36], float))
+        AE = A @ E
+        loss[r] = float((AE * AE).sum())
+        Gm = 2.0 * A @ AE
+        for q, (i, j) in enumerate(idx):
+            G[r, q] = Gm[i, i] if i == j else Gm[i, j] + Gm[j, i]
+    return loss, G / max(nvalid, 1)
+
+
 def mse_grad(Y, T, mask):
     """Loss (1/N) sum mask * (Y - T)^2 and its gradient with respect to Y."""
     N = Y.shape[0]

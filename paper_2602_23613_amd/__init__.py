@@ -13,7 +13,7 @@ import numpy as np
 from . import _lib
 from ._lib import AmgError, load  # noqa: F401
 
-__all__ = ["Hierarchy", "level0_integers", "spmv", "load", "AmgError"]
+__all__ = ["Hierarchy", "level0_integers", "spmv", "mlp_loss_grad", "load", "AmgError"]
 
 
 def _stream(stream):
@@ -212,6 +212,14 @@ class Hierarchy:
 
 def _stats_dict(st):
     return {k: getattr(st, k) for k, _ in st._fields_}
+
+
+def mlp_loss_grad(y, t, ahat, nvalid, dy, row_loss, stream=None):
+    """Learned-form training loss ||Ahat (W - W*)||_F^2 per row and its gradient
+    (device tensors: y, t, dy float32 (n, 64); ahat float64 (n, 36); row_loss (n,))."""
+    n = y.shape[0]
+    _lib.check(load().amg_mlp_loss_grad(y.data_ptr(), t.data_ptr(), ahat.data_ptr(), n, nvalid,
+                                        dy.data_ptr(), row_loss.data_ptr(), _stream(stream)))
 
 
 def level0_integers(A, G, **opts):

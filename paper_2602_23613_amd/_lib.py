@@ -28,7 +28,7 @@ EXPORTED = ["amg_default_options", "amg_setup", "amg_resetup_numeric", "amg_vcyc
             "amg_pcg_solve", "amg_smoother_sweep", "amg_spmv", "amg_hier_info", "amg_export_integers",
             "amg_export_level", "amg_level0_integers", "amg_free_integers", "amg_destroy",
             "amg_last_error", "amg_mlp_nparams", "amg_mlp_train", "amg_mlp_use", "amg_mlp_stats_get",
-            "amg_mlp_params", "amg_mlp_forward", "amg_mlp_backward"]
+            "amg_mlp_params", "amg_mlp_forward", "amg_mlp_backward", "amg_mlp_loss_grad"]
 
 
 class AmgError(RuntimeError):
@@ -146,11 +146,12 @@ def load():
     lib.amg_mlp_params.argtypes = [P, P, P]
     lib.amg_mlp_forward.argtypes = [P, P, C.c_int64, P, P]
     lib.amg_mlp_backward.argtypes = [P, P, C.c_int64, P, P, P]
+    lib.amg_mlp_loss_grad.argtypes = [P, P, P, C.c_int64, C.c_int64, P, P, P]
     for name in ("amg_setup", "amg_resetup_numeric", "amg_vcycle", "amg_pcg_solve", "amg_spmv",
                  "amg_smoother_sweep",
                  "amg_hier_info", "amg_export_integers", "amg_export_level",
                  "amg_level0_integers", "amg_mlp_train", "amg_mlp_use", "amg_mlp_stats_get",
-                 "amg_mlp_params", "amg_mlp_forward", "amg_mlp_backward"):
+                 "amg_mlp_params", "amg_mlp_forward", "amg_mlp_backward", "amg_mlp_loss_grad"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

@@ -573,7 +573,12 @@ void ensure_work(amg_hier* h, int64_t rows) {
   w.dYb = h->pool.get<uint16_t>((size_t)rows * MLP_OUT);
 }
 
-constexpr int64_t INFER_ROWS = 16384;   // rows per inference pass
+// rows per inference pass (a multiple of 16; HCURL_AMG_INFER_ROWS overrides it)
+int64_t infer_rows() {
+  int64_t r = 16384;
+  if (const char* e = std::getenv("HCURL_AMG_INFER_ROWS")) r = std::max<int64_t>(16, std::atoll(e) / 16 * 16);
+  return r;
+}
 
 // features, exact targets and eligibility of every finest-level extension block
 void learned_features(amg_hier* h, double eligible_max, hipStream_t st) {
@@ -602,9 +607,10 @@ void learned_features(amg_hier* h, double eligible_max, hipStream_t st) {
 // network prediction + refinement + check for every finest-level block
 void learned_predict(amg_hier* h, hipStream_t st) {
   learned_features(h, 1e300, st);   // eligibility here only needs a valid exact factorisation
-  ensure_work(h, INFER_ROWS);
-  for (int64_t r0 = 0; r0 < h->mlp_rows; r0 += INFER_ROWS) {
-    int64_t nr = std::min<int64_t>(INFER_ROWS, h->mlp_rows - r0);
+  const int64_t chunk = infer_rows();
+  ensure_work(h, chunk);
+  for (int64_t r0 = 0; r0 < h->mlp_rows; r0 += chunk) {
+    int64_t nr = std::min<int64_t>(chunk, h->mlp_rows - r0);
     mlp_forward(h->mlp, h->fX + r0 * MLP_IN, nr, h->work, h->fY + r0 * MLP_OUT, st);
   }
   refine_check(h->mlp_nb, h->lv[0].blk_ptr, h->fel, h->fY, h->fAhat, h->use_cfg.refine_steps,
@@ -1303,6 +1309,17 @@ amg_status amg_mlp_backward(amg_hier* h, const uint16_t* x, int64_t n, const flo
   });
 }
 
+amg_status amg_mlp_loss_grad(const float* y, const float* t, const double* ahat, int64_t n,
+                             int64_t nvalid, float* dy, float* row_loss, void* stream) {
+  return guarded([&]() -> amg_status {
+    if (!y || !t || !ahat || !dy || !row_loss) fail(AMG_ERR_ARG, "NULL argument");
+    if (n < 0 || nvalid < 0 || nvalid > n) fail(AMG_ERR_ARG, "need 0 <= nvalid <= n");
+    mlp_loss(n, y, t, ahat, nullptr, nvalid, dy, row_loss, (hipStream_t)stream);
+    HIPC(hipGetLastError());
+    return AMG_OK;
+  });
+}
+
 amg_status amg_mlp_train(amg_hier* h, const amg_mlp_train_cfg* cfg, amg_mlp_stats* stats,
                          void* stream) {
   return guarded([&]() -> amg_status {
@@ -1359,7 +1376,7 @@ amg_status amg_mlp_train(amg_hier* h, const amg_mlp_train_cfg* cfg, amg_mlp_stat
         const int64_t npad = (nb + 15) / 16 * 16;
         mlp_gather(nb, npad, d_ids + o, h->fX, h->fT, h->bX, h->bT, st);
         mlp_forward(h->mlp, h->bX, npad, h->work, h->bY, st);
-        mlp_mse(npad, h->bY, h->bT, h->bdY, h->bloss, nb, st);
+        mlp_loss(npad, h->bY, h->bT, h->fAhat, d_ids + o, nb, h->bdY, h->bloss, st);
         mlp_backward(h->mlp, h->bX, npad, h->work, h->bdY, h->mlp.grad, st);
         mlp_adam(h->mlp, (float)cfg->lr, st);
         if (track) {

@@ -115,20 +115,56 @@ __global__ void k_colsum(int64_t rows, int cols, const float* __restrict__ G, fl
   for (int64_t r = 0; r < rows; ++r) s += G[r * cols + c];
   out[c] = s;
 }
-// MSE loss gradient: dY = 2 (Y - T) / nvalid on the first valid_cols outputs
-// of the first nvalid rows (padding rows and columns get zero); loss per row
-__global__ void k_mse(int64_t rows, int cols, const float* __restrict__ Y, const float* __restrict__ T,
-                      int valid_cols, int64_t nvalid, float inv_n, float* __restrict__ dY,
-                      float* __restrict__ row_loss) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Training loss of one sample: the error of the predicted inverse against
+// the exact one in the metric of the block, L = ||Ahat (W - W*)||_F^2, which
+// equals the refinement residual ||Ahat W - I||_F^2 that decides acceptance
+// (Ahat W* = I).  W, W* and Ahat are symmetric 8 x 8 matrices stored as packed
+// lower triangles (36 of the 64 outputs).  dL/dE = 2 Ahat^2 E =: G with
+// E = W - W*; a packed off-diagonal entry feeds E_ij and E_ji, so its gradient
+// is G_ij + G_ji.  Rows r >= nvalid (batch padding) get zero gradient; the
+// loss is averaged over the nvalid rows.  ahat_idx (may be NULL) maps batch
+// rows to rows of Ahat.
+__global__ void k_aloss(int64_t rows, const float* __restrict__ Y, const float* __restrict__ T,
+                        const double* __restrict__ Ahat, const int32_t* __restrict__ ahat_idx,
+                        int64_t nvalid, float inv_n, float* __restrict__ dY,
+                        float* __restrict__ row_loss) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= rows) return;
-  float s = 0.f;
-  for (int c = 0; c < cols; ++c) {
-    float d = (c < valid_cols && r < nvalid) ? Y[r * cols + c] - T[r * cols + c] : 0.f;
-    dY[r * cols + c] = 2.f * d * inv_n;
-    s += d * d;
+  float* g = dY + r * MLP_OUT;
+  if (r >= nvalid) {
+    for (int q = 0; q < MLP_OUT; ++q) g[q] = 0.f;
+    row_loss[r] = 0.f;
+    return;
   }
-  row_loss[r] = s;
+  const int64_t a = ahat_idx ? (int64_t)ahat_idx[r] : r;
+  const double* ap = Ahat + a * 36;
+  double A[8][8], E[8][8], AE[8][8];
+  for (int i = 0; i < 8; ++i)
+    for (int j = 0; j <= i; ++j) {
+      const int q = i * (i + 1) / 2 + j;
+      A[i][j] = A[j][i] = ap[q];
+      E[i][j] = E[j][i] = (double)Y[r * MLP_OUT + q] - (double)T[r * MLP_OUT + q];
+    }
+  double loss = 0.0;
+  for (int i = 0; i < 8; ++i)
+    for (int j = 0; j < 8; ++j) {
+      double v = 0.0;
+      for (int k = 0; k < 8; ++k) v += A[i][k] * E[k][j];
+      AE[i][j] = v;
+      loss += v * v;
+    }
+  for (int i = 0; i < 8; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double gij = 0.0, gji = 0.0;   // (Ahat AE)_ij and (Ahat AE)_ji
+      for (int k = 0; k < 8; ++k) {
+        gij += A[i][k] * AE[k][j];
+        gji += A[j][k] * AE[k][i];
+      }
+      const double d = (i == j) ? 2.0 * gij : 2.0 * (gij + gji);
+      g[i * (i + 1) / 2 + j] = (float)(d * inv_n);
+    }
+  for (int q = 36; q < MLP_OUT; ++q) g[q] = 0.f;
+  row_loss[r] = (float)loss;
 }
 // Adam on the FP32 master parameters (bias-corrected), refresh BF16 copies
 __global__ void k_adam(int64_t n, float* __restrict__ p, const float* __restrict__ g,
@@ -372,10 +408,11 @@ void mlp_adam(MlpDev& m, float lr, hipStream_t st) {
   mlp_refresh_bf16(m, st);
 }
 
-void mlp_mse(int64_t n, const float* Y, const float* T, float* dY, float* row_loss, int64_t nvalid,
-             hipStream_t st) {
-  hipLaunchKernelGGL(k_mse, dim3(grid1(n)), dim3(256), 0, st, n, MLP_OUT, Y, T, 36, nvalid,
-                     1.f / (float)std::max<int64_t>(nvalid, 1), dY, row_loss);
+void mlp_loss(int64_t n, const float* Y, const float* T, const double* Ahat, const int32_t* ahat_idx,
+              int64_t nvalid, float* dY, float* row_loss, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_aloss, dim3(grid1(n, 128)), dim3(128), 0, st, n, Y, T, Ahat, ahat_idx, nvalid,
+                       1.f / (float)std::max<int64_t>(nvalid, 1), dY, row_loss);
 }
 
 void mlp_gather(int64_t n, int64_t npad, const int32_t* idx, const uint16_t* X, const float* T,

@@ -46,8 +46,8 @@ void mlp_backward(const MlpDev& m, const uint16_t* X, int64_t n, MlpWork& w, con
                   float* grad, hipStream_t st);
 void mlp_refresh_bf16(MlpDev& m, hipStream_t st);
 void mlp_adam(MlpDev& m, float lr, hipStream_t st);
-void mlp_mse(int64_t n, const float* Y, const float* T, float* dY, float* row_loss, int64_t nvalid,
-             hipStream_t st);
+void mlp_loss(int64_t n, const float* Y, const float* T, const double* Ahat, const int32_t* ahat_idx,
+              int64_t nvalid, float* dY, float* row_loss, hipStream_t st);
 void mlp_gather(int64_t n, int64_t npad, const int32_t* idx, const uint16_t* X, const float* T,
                 uint16_t* Xb, float* Tb, hipStream_t st);
 void block_features(int64_t nb, const int64_t* bptr, const int32_t* bdofs, const int64_t* Aptr,

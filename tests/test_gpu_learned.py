@@ -237,3 +237,63 @@ def test_learned_api_errors():
     with pytest.raises(amglib.AmgError):
         H.mlp_train(epochs=1, batch=24, init=flatten(init_params(0)))   # batch not a multiple of 16
     H.close()
+
+
+def test_training_loss_kernel_matches_oracle():
+    """The training loss ||Ahat (W - W*)||^2 and its gradient, GPU against the
+    oracle (both evaluate in FP64; the GPU rounds the results to FP32)."""
+    d = dev()
+    rng = np.random.default_rng(31)
+    n, nvalid = 40, 33
+    Ah = np.zeros((n, 36))
+    T = np.zeros((n, 64), np.float32)
+    Y = np.zeros((n, 64), np.float32)
+    idx = omlp.packed_index()
+    for r in range(n):
+        s = int(rng.integers(1, 9))
+        B = rng.standard_normal((s, s))
+        A = B @ B.T + s * np.eye(s)
+        dd = np.sqrt(np.diag(A))
+        M = np.eye(8)
+        M[:s, :s] = A / np.outer(dd, dd)
+        Ah[r] = [M[i, j] for i, j in idx]
+        W = np.linalg.inv(M)
+        T[r, :36] = [W[i, j] for i, j in idx]
+        Y[r, :36] = T[r, :36] + 0.05 * rng.standard_normal(36)
+        Y[r, 36:] = rng.standard_normal(28)
+    loss_o, G_o = omlp.a_loss_grad(Y.astype(np.float64), T.astype(np.float64), Ah, nvalid)
+    yt = torch.tensor(Y, device=d)
+    tt = torch.tensor(T, device=d)
+    at = torch.tensor(Ah, device=d)
+    dy = torch.full((n, 64), 7.0, dtype=torch.float32, device=d)
+    rl = torch.full((n,), 7.0, dtype=torch.float32, device=d)
+    amglib.mlp_loss_grad(yt, tt, at, nvalid, dy, rl)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(rl.cpu().numpy(), loss_o, rtol=2e-7, atol=1e-30)
+    g = dy.cpu().numpy().astype(np.float64)
+    scale = np.abs(G_o).max(axis=1, keepdims=True) + 1e-30
+    assert np.max(np.abs(g - G_o) / scale) <= 2e-7
+    assert np.all(g[nvalid:] == 0.0) and np.all(g[:, 36:] == 0.0)
+
+
+def test_chunked_inference_equals_one_pass():
+    """Inference runs in passes of at most 16384 rows; forcing passes of 32
+    rows must give the same accepted blocks and the same P bit for bit."""
+    import os
+    dev()
+    p, _ = case("hex8_iso")
+    H = amglib.Hierarchy(p.A, p.G)
+    H.mlp_train(epochs=200, batch=64, lr=2e-3, seed=3, init=flatten(init_params(0)))
+    H.mlp_use(refine_steps=6, accept_tol=1e-10)
+    H.resetup(p.A)
+    a1 = H.mlp_stats()["accepted"]
+    _, P1 = H.level(0)
+    os.environ["HCURL_AMG_INFER_ROWS"] = "32"
+    try:
+        H.resetup(p.A)
+    finally:
+        del os.environ["HCURL_AMG_INFER_ROWS"]
+    assert H.mlp_stats()["accepted"] == a1 > 0
+    _, P2 = H.level(0)
+    assert np.array_equal(P1.data, P2.data)
+    H.close()

@@ -113,3 +113,41 @@ def test_init_layout_roundtrip():
     assert f.size == N_PARAMS == 33088
     for a, b in zip(unflatten(f), p):
         np.testing.assert_array_equal(a, np.asarray(b, dtype=np.float32).astype(np.float64))
+
+
+def _spd_packed(rng, s):
+    B = rng.standard_normal((s, s))
+    A = B @ B.T + s * np.eye(s)
+    d = np.sqrt(np.diag(A))
+    A = A / np.outer(d, d)
+    M = np.eye(8)
+    M[:s, :s] = A
+    return np.array([M[i, j] for i, j in mlp.packed_index()]), M
+
+
+def test_a_loss_equals_refinement_residual_and_gradient_is_exact():
+    """||Ahat (W - W*)||^2 = ||Ahat W - I||^2 when W* = Ahat^{-1}; the gradient
+    matches central differences of the loss in the packed outputs."""
+    rng = np.random.default_rng(7)
+    n, nvalid = 5, 4
+    Ah = np.zeros((n, 36))
+    Y = np.zeros((n, 64))
+    T = np.zeros((n, 64))
+    for r in range(n):
+        Ah[r], M = _spd_packed(rng, int(rng.integers(1, 9)))
+        Winv = np.linalg.inv(M)
+        T[r, :36] = [Winv[i, j] for i, j in mlp.packed_index()]
+        Y[r, :36] = T[r, :36] + 0.1 * rng.standard_normal(36)
+        Y[r, 36:] = rng.standard_normal(28)     # unused outputs: no loss, no gradient
+    loss, G = mlp.a_loss_grad(Y, T, Ah, nvalid)
+    for r in range(nvalid):
+        W = mlp.unpack_sym(Y[r, :36])
+        R = mlp.unpack_sym(Ah[r]) @ W - np.eye(8)
+        assert loss[r] == pytest.approx((R * R).sum(), rel=1e-10)
+    assert loss[nvalid] == 0.0 and np.all(G[nvalid] == 0.0) and np.all(G[:, 36:] == 0.0)
+    h = 1e-6
+    mean = lambda YY: mlp.a_loss_grad(YY, T, Ah, nvalid)[0].sum() / nvalid
+    for r, q in [(0, 0), (0, 5), (1, 20), (2, 35), (3, 14)]:
+        Yp = Y.copy(); Yp[r, q] += h
+        Ym = Y.copy(); Ym[r, q] -= h
+        assert (mean(Yp) - mean(Ym)) / (2 * h) == pytest.approx(G[r, q], rel=1e-6, abs=1e-9)
