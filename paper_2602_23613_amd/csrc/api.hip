@@ -131,6 +131,9 @@ struct Level {
   int32_t* blk_dofs = nullptr;
   std::vector<Stage> stages;
   int rap_mmax = 0, ap_mmax = 0;
+  int32_t* ap_wide = nullptr;    // rows of A P / P^T (A P) too long for the LDS numeric pass
+  int32_t* rap_wide = nullptr;
+  int64_t ap_nwide = 0, rap_nwide = 0;
   int64_t ap_nnz = 0;
   int64_t* AP_ptr = nullptr;     // A P (n x nc), kept for numeric re-setup
   int32_t* AP_col = nullptr;
@@ -152,6 +155,10 @@ struct Level {
   double* dinv = nullptr;
   float* dinv32 = nullptr;
   int lpr_S = 8;
+  int max_block = 0;
+  bool dense_S = false;          // dense level: residual-update sweep on a dense copy of A
+  double* Acm = nullptr;         // column-major dense A (dense levels only)
+  float* Acm32 = nullptr;
   // device: cycle vectors
   double *x = nullptr, *t = nullptr, *b = nullptr, *r = nullptr;
   float *x32 = nullptr, *t32 = nullptr, *b32 = nullptr, *r32 = nullptr;
@@ -187,6 +194,17 @@ struct Level {
     s.wg = wg_S;
     s.sb_ptr = sb_ptr; s.sb_dofs = sb_dofs; s.fac_off = fac_off; s.lpr = lpr_S;
     if constexpr (std::is_same<T, double>::value) s.fac = fac; else s.fac = fac32;
+    s.dense = dense_S;
+    s.n = (int)n;
+    s.nblocks = (int)nstars;
+    s.max_block = max_block;
+    if constexpr (std::is_same<T, double>::value) {
+      s.Acm = Acm;
+      s.rtmp = r;
+    } else {
+      s.Acm = Acm32;
+      s.rtmp = r32;
+    }
     return s;
   }
 };
@@ -343,6 +361,16 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   // launch shape of a sweep: tiny levels in one workgroup, the rest one
   // launch per colour
   L.one_launch = L.nnz <= 200000 && wg == 256;
+  // small, nearly sequential level (at most 1.5 blocks per colour, at most
+  // 2048 rows: the bottom of the hierarchy, where the Galerkin operators are
+  // dense or nearly so): swept block by block in one workgroup with the
+  // residual kept in LDS, from a dense copy of A (HCURL_AMG_DENSE_SWEEP=0
+  // turns this off)
+  L.max_block = maxs;
+  const char* dense_env = std::getenv("HCURL_AMG_DENSE_SWEEP");
+  L.dense_S = !(dense_env && dense_env[0] == '0') && 2 * ns <= 3 * (int64_t)I.ncolors &&
+              dense_sweep_ok<double>((int)L.n, maxs);
+  if (L.dense_S) L.Acm = h->pool.get<double>((size_t)L.n * L.n);
   L.sb_ptr = h->pool.upload(sb_ptr, st);
   L.sb_dofs = h->pool.upload(sb_dofs, st);
   L.fac_off = h->pool.upload(fac_off, st);
@@ -352,6 +380,7 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
 }
 
 void factor_smoother(amg_hier* h, Level& L, int level, hipStream_t st) {
+  if (L.dense_S) csr_to_dense_cm(L.n, L.A_ptr, L.A_col, L.A_val, L.Acm, st);
   star_chol(L.nstars, L.sb_ptr, L.sb_dofs, L.fac_off, L.A_dev<double>(), L.fac, h->d_flag, st);
   check_flag(h, st, AMG_ERR_NOT_SPD, "smoother block Cholesky: non-positive pivot on level " +
                                          std::to_string(level));
@@ -384,9 +413,10 @@ void build_interp_structs(amg_hier* h, Level& L, hipStream_t st) {
     }
     if (S.smax > 64)
       fail(AMG_ERR_LIMIT, "extension block with more than 64 DoFs (" + std::to_string(S.smax) + ")");
-    if (ext_block_lds(S.smax, S.cmax) > 65536)
-      fail(AMG_ERR_LIMIT, "extension block of " + std::to_string(S.smax) + " DoFs x " +
-                              std::to_string(S.cmax) + " columns exceeds 64 KiB of LDS");
+    if (ext_block_tile(S.smax) < 1)
+      fail(AMG_ERR_LIMIT, "extension block of " + std::to_string(S.smax) + " DoFs does not fit LDS");
+    if ((S.cmax + ext_block_tile(S.smax) - 1) / ext_block_tile(S.smax) > 65535)
+      fail(AMG_ERR_LIMIT, "extension block with too many P columns (" + std::to_string(S.cmax) + ")");
     L.stages.push_back(S);
   }
   L.p_ptr_h = I.p.ptr;
@@ -460,34 +490,52 @@ void compute_interp(amg_hier* h, Level& L, int level, hipStream_t st, bool learn
 }
 
 // --- Galerkin product A_c = P^T (A P): symbolic (once) and numeric ---
-// C = X Y symbolic: row counts, host scan, sorted columns; returns the
-// largest row length (the numeric pass's LDS size)
-int64_t mm_symbolic(amg_hier* h, int64_t nrows, const CsrPat& X, const CsrPat& Y,
+// C = X Y symbolic: row counts, host scan, sorted columns.  Rows with more
+// distinct columns than the LDS hash holds take the bitset passes.  Returns
+// the numeric pass's LDS row capacity; rows longer than that are listed in
+// `wide` (device) for the numeric pass's wide kernel.
+constexpr int64_t MM_LDS_ROW = 65536 / (sizeof(double) + sizeof(int32_t));
+
+int64_t mm_symbolic(amg_hier* h, int64_t nrows, int64_t ncols, const CsrPat& X, const CsrPat& Y,
                     std::vector<int64_t>& cptr, int64_t*& d_cptr, int32_t*& d_ccol,
-                    const std::string& what, hipStream_t st) {
+                    int32_t*& d_wide, int64_t& nwide, const std::string& what, hipStream_t st) {
   int64_t* d_cnt = h->pool.get<int64_t>(nrows);
   mm_count(nrows, X, Y, d_cnt, h->d_flag, st);
-  check_flag(h, st, AMG_ERR_LIMIT, what + ": a row has more than " + std::to_string(mm_hash_cap()) +
-                                       " distinct columns");
   std::vector<int64_t> cnt(nrows);
   HIPC(hipMemcpyAsync(cnt.data(), d_cnt, nrows * sizeof(int64_t), hipMemcpyDeviceToHost, st));
   HIPC(hipStreamSynchronize(st));
+  std::vector<int32_t> hw;   // rows too wide for the hash passes
+  for (int64_t i = 0; i < nrows; ++i)
+    if (cnt[i] < 0) hw.push_back((int32_t)i);
+  int32_t* d_hw = nullptr;
+  if (!hw.empty()) {
+    if (mm_wide_lds(ncols) > 65536)
+      fail(AMG_ERR_LIMIT, what + ": a row has more than " + std::to_string(mm_hash_cap() / 2) +
+                              " columns and the product has too many columns for the wide passes");
+    d_hw = h->pool.upload(hw, st);
+    HIPC(hipStreamSynchronize(st));
+    mm_count_wide((int64_t)hw.size(), d_hw, X, Y, ncols, d_cnt, st);
+    HIPC(hipMemcpyAsync(cnt.data(), d_cnt, nrows * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+  }
   cptr.assign(nrows + 1, 0);
   int64_t mmax = 0;
+  std::vector<int32_t> nw;   // rows too long for the numeric pass's LDS
+  const int64_t lds_row = std::min<int64_t>(MM_LDS_ROW, std::getenv("HCURL_AMG_MM_WIDE") ? mm_wide_at() : MM_LDS_ROW);
   for (int64_t i = 0; i < nrows; ++i) {
     cptr[i + 1] = cptr[i] + cnt[i];
     mmax = std::max(mmax, cnt[i]);
+    if (cnt[i] > lds_row) nw.push_back((int32_t)i);
   }
-  if (mmax > mm_hash_cap() / 2)
-    fail(AMG_ERR_LIMIT, what + ": row with " + std::to_string(mmax) +
-                            " entries exceeds the LDS hash capacity");
-  if ((size_t)mmax * (sizeof(double) + sizeof(int32_t)) > 65536)
-    fail(AMG_ERR_LIMIT, what + ": row too long for the numeric pass");
   d_cptr = h->pool.upload(cptr, st);
   d_ccol = h->pool.get<int32_t>(std::max<int64_t>(cptr[nrows], 1));
   mm_fill(nrows, X, Y, d_cptr, d_ccol, h->d_flag, st);
+  mm_fill_wide((int64_t)hw.size(), d_hw, X, Y, ncols, d_cptr, d_ccol, st);
   check_flag(h, st, AMG_ERR_LIMIT, what + ": column fill overflow");
-  return mmax;
+  nwide = (int64_t)nw.size();
+  d_wide = nw.empty() ? nullptr : h->pool.upload(nw, st);
+  HIPC(hipStreamSynchronize(st));
+  return std::min(mmax, lds_row);
 }
 
 void galerkin_symbolic(amg_hier* h, Level& L, Level& C, int level, hipStream_t st) {
@@ -495,12 +543,14 @@ void galerkin_symbolic(amg_hier* h, Level& L, Level& C, int level, hipStream_t s
   std::string lv = " on level " + std::to_string(level);
   CsrPat A{L.A_ptr, L.A_col}, P{L.P_ptr, L.P_col}, PT{L.PT_ptr, L.PT_col};
   std::vector<int64_t> apptr;
-  L.ap_mmax = (int)mm_symbolic(h, n, A, P, apptr, L.AP_ptr, L.AP_col, "A P" + lv, st);
+  L.ap_mmax = (int)mm_symbolic(h, n, nc, A, P, apptr, L.AP_ptr, L.AP_col, L.ap_wide, L.ap_nwide,
+                               "A P" + lv, st);
   L.ap_nnz = apptr[n];
   L.AP_val = h->pool.get<double>(std::max<int64_t>(L.ap_nnz, 1));
   CsrPat AP{L.AP_ptr, L.AP_col};
   std::vector<int64_t> cptr;
-  L.rap_mmax = (int)mm_symbolic(h, nc, PT, AP, cptr, C.A_ptr, C.A_col, "P^T (A P)" + lv, st);
+  L.rap_mmax = (int)mm_symbolic(h, nc, nc, PT, AP, cptr, C.A_ptr, C.A_col, L.rap_wide,
+                                L.rap_nwide, "P^T (A P)" + lv, st);
   C.n = nc;
   C.nnz = cptr[nc];
   C.A_val = h->pool.get<double>(std::max<int64_t>(C.nnz, 1));
@@ -515,7 +565,10 @@ void galerkin_symbolic(amg_hier* h, Level& L, Level& C, int level, hipStream_t s
 void galerkin_numeric(amg_hier* h, Level& L, Level& C, hipStream_t st) {
   CsrPat A{L.A_ptr, L.A_col}, P{L.P_ptr, L.P_col}, PT{L.PT_ptr, L.PT_col}, AP{L.AP_ptr, L.AP_col};
   mm_vals(L.n, A, L.A_val, P, L.P_val, L.AP_ptr, L.AP_col, L.AP_val, L.ap_mmax, st);
+  mm_vals_wide(L.ap_nwide, L.ap_wide, A, L.A_val, P, L.P_val, L.nc, L.AP_ptr, L.AP_col, L.AP_val, st);
   mm_vals(L.nc, PT, L.PT_val, AP, L.AP_val, C.A_ptr, C.A_col, C.A_val, L.rap_mmax, st);
+  mm_vals_wide(L.rap_nwide, L.rap_wide, PT, L.PT_val, AP, L.AP_val, L.nc, C.A_ptr, C.A_col, C.A_val,
+               st);
 }
 
 void coarsest_factor(amg_hier* h, Level& L, hipStream_t st) {
@@ -540,6 +593,10 @@ void cast_level(amg_hier* h, Level& L, hipStream_t st) {
   cast<double, float>(L.p_nnz, L.PT_val, L.PT_val32, st);
   cast<double, float>(L.fac_total, L.fac, L.fac32, st);
   cast<double, float>(L.n, L.dinv, L.dinv32, st);
+  if (L.dense_S) {
+    if (!L.Acm32) L.Acm32 = h->pool.get<float>((size_t)L.n * L.n);
+    cast<double, float>(L.n * L.n, L.Acm, L.Acm32, st);
+  }
 }
 
 // --- learned setup ---

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 namespace hamg {
 
@@ -315,6 +316,151 @@ void schwarz_colour(const SmootherDev<T>& S, const CsrDev<T>& A, int colour, con
 }
 
 // ---------------------------------------------------------------------------
+// multiplicative Schwarz on a dense level
+// ---------------------------------------------------------------------------
+// At the bottom of the hierarchy the Galerkin operators are dense or nearly
+// so: almost every pair of blocks conflicts, each colour holds about one
+// block, and a sweep is a sequential chain over the blocks.  One 1024-thread
+// workgroup keeps r = b - A x and x in LDS; for each block B in colour order
+// (blocks of one colour in any order: they are uncoupled, so their updates
+// commute exactly) it solves d = A_BB^{-1} r_B from the packed Cholesky
+// factor, sets x_B += d and updates r -= A_{:,B} d from a column-major dense
+// copy of A.  This is the sweep of the row form; only the rounding differs,
+// because r is updated instead of recomputed.  Everything a block needs from
+// global memory (its DoFs, factor and the columns A_{:,B}) is fetched one
+// block ahead, so the chain between blocks stays in LDS and registers.
+// Limits (checked by the caller): n <= 1024 * RPT, blocks of at most SM <= 16 DoFs.
+constexpr int DENSE_SMAX = 16;
+constexpr int DENSE_FMAX = DENSE_SMAX * (DENSE_SMAX + 1) / 2;
+
+size_t dense_sweep_lds(int n, size_t tsize) {
+  return tsize * (2 * (size_t)n + DENSE_SMAX + DENSE_FMAX) + sizeof(int32_t) * DENSE_SMAX;
+}
+
+template <class T, int RPT, int SM>
+__global__ __launch_bounds__(1024) void k_dense_sweep(int n, int nblocks, int backward,
+                                                      const int64_t* __restrict__ sb_ptr,
+                                                      const int32_t* __restrict__ sb_dofs,
+                                                      const int64_t* __restrict__ fac_off,
+                                                      const T* __restrict__ fac,
+                                                      const T* __restrict__ Acm,
+                                                      const T* __restrict__ r_in, T* __restrict__ x) {
+  extern __shared__ unsigned char lds_raw[];
+  T* r = (T*)lds_raw;                 // n
+  T* xs = r + n;                      // n
+  T* d = xs + n;                      // DENSE_SMAX
+  T* fl = d + DENSE_SMAX;             // DENSE_FMAX
+  int32_t* dofs = (int32_t*)(fl + DENSE_FMAX);   // DENSE_SMAX
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += 1024) {
+    r[i] = r_in[i];
+    xs[i] = x[i];
+  }
+  // one block ahead: its size, this thread's DoF and factor entry, and the
+  // thread's rows of the block's columns
+  int nx_s = 0;
+  int32_t nx_dof = 0;
+  T nx_f = 0;
+  T nx_col[RPT][SM];
+  auto fetch = [&](int bi) {
+    const int blk = backward ? nblocks - 1 - bi : bi;
+    const int64_t p0 = sb_ptr[blk];
+    const int sz = (int)(sb_ptr[blk + 1] - p0);
+    const int64_t f0 = fac_off[blk];
+    nx_s = sz;
+    nx_dof = tid < sz ? sb_dofs[p0 + tid] : 0;
+    nx_f = tid < sz * (sz + 1) / 2 ? fac[f0 + tid] : T(0);
+#pragma unroll
+    for (int k = 0; k < SM; ++k) {
+      const int32_t dk = k < sz ? sb_dofs[p0 + k] : 0;
+#pragma unroll
+      for (int rr = 0; rr < RPT; ++rr) {
+        const int i = tid + rr * 1024;
+        nx_col[rr][k] = (k < sz && i < n) ? Acm[(int64_t)dk * n + i] : T(0);
+      }
+    }
+  };
+  if (nblocks > 0) fetch(0);
+  for (int bi = 0; bi < nblocks; ++bi) {
+    const int sz = nx_s;
+    T col[RPT][SM];
+#pragma unroll
+    for (int rr = 0; rr < RPT; ++rr)
+#pragma unroll
+      for (int k = 0; k < SM; ++k) col[rr][k] = nx_col[rr][k];
+    if (tid < sz) dofs[tid] = nx_dof;
+    if (tid < sz * (sz + 1) / 2) fl[tid] = nx_f;
+    __syncthreads();   // dofs, factor (and, on the first block, r and xs) in LDS
+    if (bi + 1 < nblocks) fetch(bi + 1);
+    if (tid == 0) {
+      for (int i = 0; i < sz; ++i) {
+        T a = r[dofs[i]];
+        const T* Li = fl + i * (i + 1) / 2;
+        for (int j = 0; j < i; ++j) a -= Li[j] * d[j];
+        d[i] = a / Li[i];
+      }
+      for (int i = sz - 1; i >= 0; --i) {
+        T a = d[i];
+        for (int j = i + 1; j < sz; ++j) a -= fl[j * (j + 1) / 2 + i] * d[j];
+        d[i] = a / fl[i * (i + 1) / 2 + i];
+      }
+    }
+    __syncthreads();   // d ready
+    if (tid < sz) xs[dofs[tid]] += d[tid];
+#pragma unroll
+    for (int rr = 0; rr < RPT; ++rr) {
+      const int i = tid + rr * 1024;
+      if (i < n) {
+        T acc = 0;
+#pragma unroll
+        for (int k = 0; k < SM; ++k)
+          if (k < sz) acc += col[rr][k] * d[k];
+        r[i] -= acc;
+      }
+    }
+    __syncthreads();   // r, xs updated; dofs, fl and d free for the next block
+  }
+  for (int i = tid; i < n; i += 1024) x[i] = xs[i];
+}
+
+template <class T>
+bool dense_sweep_ok(int n, int max_block) {
+  return n > 0 && n <= 2048 && max_block <= DENSE_SMAX &&
+         dense_sweep_lds(n, sizeof(T)) <= 64 * 1024;
+}
+
+template <class T>
+void dense_sweep(int n, int nblocks, int max_block, int backward, const int64_t* sb_ptr,
+                 const int32_t* sb_dofs, const int64_t* fac_off, const T* fac, const T* Acm,
+                 const T* r_in, T* x, hipStream_t st) {
+  const size_t lds = dense_sweep_lds(n, sizeof(T));
+#define LAUNCH_DS(R, M)                                                                          \
+  hipLaunchKernelGGL((k_dense_sweep<T, R, M>), dim3(1), dim3(1024), lds, st, n, nblocks, backward, \
+                     sb_ptr, sb_dofs, fac_off, fac, Acm, r_in, x)
+  if (n <= 1024) {
+    if (max_block <= 8) LAUNCH_DS(1, 8); else LAUNCH_DS(1, 16);
+  } else {
+    if (max_block <= 8) LAUNCH_DS(2, 8); else LAUNCH_DS(2, 16);
+  }
+#undef LAUNCH_DS
+}
+
+// column-major dense copy of a CSR matrix (D(i, j) at D[j n + i])
+__global__ void k_csr_to_dense_cm(int64_t n, const int64_t* __restrict__ ptr,
+                                  const int32_t* __restrict__ col, const double* __restrict__ val,
+                                  double* __restrict__ D) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q) D[(int64_t)col[q] * n + i] = val[q];
+}
+void csr_to_dense_cm(int64_t n, const int64_t* ptr, const int32_t* col, const double* val,
+                     double* D, hipStream_t st) {
+  fill<double>(n * n, 0.0, D, st);
+  hipLaunchKernelGGL(k_csr_to_dense_cm, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, ptr,
+                     col, val, D);
+}
+
+// ---------------------------------------------------------------------------
 // coarsest level: x = (L L^T)^{-1} b with a dense FP64 factor, one workgroup
 // ---------------------------------------------------------------------------
 template <class T>
@@ -554,25 +700,31 @@ __global__ __launch_bounds__(64) void k_ext_block(
     const int32_t* __restrict__ dof_stage, int stage, const int64_t* __restrict__ Aptr,
     const int32_t* __restrict__ Acol, const double* __restrict__ Aval,
     const int64_t* __restrict__ Pptr, const int32_t* __restrict__ Pcol, double* __restrict__ Pval,
-    int smax, int cmax, int* __restrict__ flag, const double* __restrict__ Wl,
+    int smax, int ctile, int* __restrict__ flag, const double* __restrict__ Wl,
     const int8_t* __restrict__ accepted, const double* __restrict__ dsq) {
   extern __shared__ unsigned char lds_raw[];
   double* Abb = (double*)lds_raw;                 // smax * smax
-  double* R = Abb + smax * smax;                   // smax * cmax
-  int32_t* cols = (int32_t*)(R + smax * cmax);     // cmax
-  int32_t* dofs = cols + cmax;                     // smax
+  double* R = Abb + smax * smax;                   // smax * ctile
+  int32_t* cols = (int32_t*)(R + smax * ctile);    // ctile
+  int32_t* dofs = cols + ctile;                    // smax
   const int64_t blk = b0 + blockIdx.x;
   const int64_t d0 = bptr[blk];
   const int s = (int)(bptr[blk + 1] - d0);
   const int32_t first = bdofs[d0];
-  const int64_t c0 = Pptr[first];
-  const int c = (int)(Pptr[first + 1] - c0);
+  const int64_t cbeg = Pptr[first];
+  const int ctot = (int)(Pptr[first + 1] - cbeg);
+  // this workgroup's tile of the block's P columns: [t0, t0 + c)
+  const int t0 = (int)blockIdx.y * ctile;
+  if (t0 >= ctot) return;   // the whole workgroup: this block has fewer tiles
+  const int c = min(ctile, ctot - t0);
+  const int64_t c0 = cbeg + t0;
   const int lane = threadIdx.x;
   for (int t = lane; t < c; t += 64) cols[t] = Pcol[c0 + t];
   for (int t = lane; t < s; t += 64) dofs[t] = bdofs[d0 + t];
   for (int t = lane; t < s * s; t += 64) Abb[t] = 0.0;
   for (int t = lane; t < s * c; t += 64) R[t] = 0.0;
   __syncthreads();
+  const int32_t clo = cols[0], chi = cols[c - 1];
   if (lane < s) {
     const int32_t e = dofs[lane];
     double* Rr = R + lane * c;
@@ -587,8 +739,10 @@ __global__ __launch_bounds__(64) void k_ext_block(
       const int sj = dof_stage[j];
       if (sj >= 0 && sj >= stage) continue;  // not extended yet
       for (int64_t u = Pptr[j]; u < Pptr[j + 1]; ++u) {
-        const int cp = lower_bound_i32(cols, c, Pcol[u]);
-        if (cp < c && cols[cp] == Pcol[u]) {
+        const int32_t pc = Pcol[u];
+        if (pc < clo || pc > chi) continue;   // another tile's column
+        const int cp = lower_bound_i32(cols, c, pc);
+        if (cp < c && cols[cp] == pc) {
           Rr[cp] += a * Pval[u];
         } else {
           atomicExch(flag, 2);   // pattern mismatch (cannot happen for host-built patterns)
@@ -612,7 +766,7 @@ __global__ __launch_bounds__(64) void k_ext_block(
         }
         y[i] = v / dq[i];
       }
-      for (int i = 0; i < s; ++i) Pval[Pptr[dofs[i]] + t] = -y[i];
+      for (int i = 0; i < s; ++i) Pval[Pptr[dofs[i]] + t0 + t] = -y[i];
     }
     return;
   }
@@ -646,13 +800,20 @@ __global__ __launch_bounds__(64) void k_ext_block(
       for (int j = i + 1; j < s; ++j) v -= Abb[j * s + i] * R[j * c + t];
       R[i * c + t] = v / Abb[i * s + i];
     }
-    for (int i = 0; i < s; ++i) Pval[Pptr[dofs[i]] + t] = -R[i * c + t];
+    for (int i = 0; i < s; ++i) Pval[Pptr[dofs[i]] + t0 + t] = -R[i * c + t];
   }
 }
 
-size_t ext_block_lds(int smax, int cmax) {
-  return sizeof(double) * ((size_t)smax * smax + (size_t)smax * cmax) +
-         sizeof(int32_t) * ((size_t)cmax + (size_t)smax);
+size_t ext_block_lds(int smax, int ctile) {
+  return sizeof(double) * ((size_t)smax * smax + (size_t)smax * ctile) +
+         sizeof(int32_t) * ((size_t)ctile + (size_t)smax);
+}
+
+// the widest column tile whose block fits 64 KiB of LDS (0 if none does)
+int ext_block_tile(int smax) {
+  const int64_t room = 65536 - (int64_t)sizeof(double) * smax * smax - (int64_t)sizeof(int32_t) * smax;
+  const int64_t per = (int64_t)sizeof(double) * smax + (int64_t)sizeof(int32_t);
+  return room > 0 ? (int)(room / per) : 0;
 }
 
 void ext_blocks(int64_t b0, int64_t nb, const int64_t* bptr, const int32_t* bdofs,
@@ -660,11 +821,16 @@ void ext_blocks(int64_t b0, int64_t nb, const int64_t* bptr, const int32_t* bdof
                 const int64_t* Pptr, const int32_t* Pcol, double* Pval, int smax, int cmax,
                 int* flag, hipStream_t st, const double* Wl, const int8_t* accepted,
                 const double* dsq) {
-  if (nb <= 0) return;
-  size_t lds = ext_block_lds(smax, cmax);
-  hipLaunchKernelGGL(k_ext_block, dim3((unsigned)nb), dim3(64), lds, st, b0, bptr, bdofs,
-                     dof_stage, stage, A.ptr, A.col, A.val, Pptr, Pcol, Pval, smax, cmax, flag,
-                     Wl, accepted, dsq);
+  if (nb <= 0 || cmax <= 0) return;
+  // columns in tiles of ctile (one tile when the widest block fits LDS whole;
+  // HCURL_AMG_EXT_TILE caps the tile width)
+  int ctile = std::min(cmax, ext_block_tile(smax));
+  if (const char* e = std::getenv("HCURL_AMG_EXT_TILE")) ctile = std::max(1, std::min(ctile, std::atoi(e)));
+  const int ntiles = (cmax + ctile - 1) / ctile;
+  size_t lds = ext_block_lds(smax, ctile);
+  hipLaunchKernelGGL(k_ext_block, dim3((unsigned)nb, (unsigned)ntiles), dim3(64), lds, st, b0, bptr,
+                     bdofs, dof_stage, stage, A.ptr, A.col, A.val, Pptr, Pcol, Pval, smax, ctile,
+                     flag, Wl, accepted, dsq);
 }
 
 // x_i = a pseudo-random value in [-1, 1) from a counter-based hash (SplitMix64)
@@ -724,6 +890,7 @@ __device__ void mm_insert(int64_t i, const int64_t* Xptr, const int32_t* Xcol, c
   for (int64_t t = Xptr[i] + threadIdx.x; t < Xptr[i + 1]; t += blockDim.x) {
     const int32_t k = Xcol[t];
     for (int64_t u = Yptr[k]; u < Yptr[k + 1]; ++u) {
+      if (*(volatile int*)overflow) return;   // the row goes to the wide passes anyway
       const int32_t J = Ycol[u];
       uint32_t h = ((uint32_t)J * 2654435761u) & (HCAP - 1);
       int probes = 0;
@@ -749,16 +916,22 @@ __global__ __launch_bounds__(256) void k_mm_count(int64_t nrows, const int64_t* 
                                                   const int64_t* __restrict__ Yptr,
                                                   const int32_t* __restrict__ Ycol,
                                                   int64_t* __restrict__ cnt,
-                                                  int* __restrict__ overflow) {
+                                                  int* __restrict__ overflow, int wide_at) {
   __shared__ int32_t hash[HCAP];
   __shared__ int count;
+  __shared__ int full;
   const int64_t i = blockIdx.x;
   for (int t = threadIdx.x; t < HCAP; t += blockDim.x) hash[t] = -1;
-  if (threadIdx.x == 0) count = 0;
+  if (threadIdx.x == 0) {
+    count = 0;
+    full = 0;
+  }
   __syncthreads();
-  mm_insert(i, Xptr, Xcol, Yptr, Ycol, hash, &count, overflow);
+  mm_insert(i, Xptr, Xcol, Yptr, Ycol, hash, &count, &full);
   __syncthreads();
-  if (threadIdx.x == 0) cnt[i] = count;
+  // a row too wide for the hash passes (more than wide_at <= HCAP / 2
+  // columns) is marked -1 and counted again by k_mm_count_wide
+  if (threadIdx.x == 0) cnt[i] = (full || count > wide_at) ? -1 : count;
 }
 
 // sorted columns of row i (its length, from k_mm_count, is at most HCAP / 2)
@@ -768,19 +941,26 @@ __global__ __launch_bounds__(256) void k_mm_fill(int64_t nrows, const int64_t* _
                                                  const int32_t* __restrict__ Ycol,
                                                  const int64_t* __restrict__ Cptr,
                                                  int32_t* __restrict__ Ccol,
-                                                 int* __restrict__ overflow) {
+                                                 int* __restrict__ overflow, int wide_at) {
   __shared__ int32_t hash[HCAP];
   __shared__ int count;
   __shared__ int nfill;
+  __shared__ int full;
   const int64_t i = blockIdx.x;
+  if (Cptr[i + 1] - Cptr[i] > wide_at) return;   // wide row: k_mm_fill_wide
   for (int t = threadIdx.x; t < HCAP; t += blockDim.x) hash[t] = -1;
   if (threadIdx.x == 0) {
     count = 0;
     nfill = 0;
+    full = 0;
   }
   __syncthreads();
-  mm_insert(i, Xptr, Xcol, Yptr, Ycol, hash, &count, overflow);
+  mm_insert(i, Xptr, Xcol, Yptr, Ycol, hash, &count, &full);
   __syncthreads();
+  if (full) {   // cannot happen: the row was counted to fit
+    if (threadIdx.x == 0) atomicExch(overflow, 1);
+    return;
+  }
   // gather the keys into registers, then compact them to the front
   int32_t keys[HCAP / 256];
   int nk = 0;
@@ -830,6 +1010,7 @@ __global__ __launch_bounds__(64) void k_mm_vals(
   const int64_t i = blockIdx.x;
   const int64_t o = Cptr[i];
   const int m = (int)(Cptr[i + 1] - o);
+  if (m > mmax) return;   // wide row: k_mm_vals_wide
   const int lane = threadIdx.x;
   for (int t = lane; t < m; t += 64) {
     cols[t] = Ccol[o + t];
@@ -848,17 +1029,177 @@ __global__ __launch_bounds__(64) void k_mm_vals(
   for (int t = lane; t < m; t += 64) Cval[o + t] = acc[t];
 }
 
+// Wide rows (more distinct columns than the LDS hash holds): the row's
+// column set is a bitset over the ncols columns of Y in LDS (set bits are
+// order-free, so the result is deterministic), counted by popcount,
+// listed in order by a scan, and addressed in the numeric pass by rank
+// (prefix popcount), with the sums accumulated in place in C's row.
+__device__ void mm_mark_wide(int64_t i, const int64_t* Xptr, const int32_t* Xcol,
+                             const int64_t* Yptr, const int32_t* Ycol, uint32_t* bits) {
+  for (int64_t t = Xptr[i] + threadIdx.x; t < Xptr[i + 1]; t += blockDim.x) {
+    const int32_t k = Xcol[t];
+    for (int64_t u = Yptr[k]; u < Yptr[k + 1]; ++u) {
+      const int32_t J = Ycol[u];
+      atomicOr(&bits[J >> 5], 1u << (J & 31));
+    }
+  }
+}
+
+__device__ int block_exclusive_scan256(int v, int* tmp, int* total) {
+  // Hillis-Steele over 256 threads in LDS
+  tmp[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    int a = threadIdx.x >= off ? tmp[threadIdx.x - off] : 0;
+    __syncthreads();
+    tmp[threadIdx.x] += a;
+    __syncthreads();
+  }
+  const int incl = tmp[threadIdx.x];
+  if (total) *total = tmp[255];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_mm_count_wide(const int32_t* __restrict__ rows,
+                                                       const int64_t* __restrict__ Xptr,
+                                                       const int32_t* __restrict__ Xcol,
+                                                       const int64_t* __restrict__ Yptr,
+                                                       const int32_t* __restrict__ Ycol, int nwords,
+                                                       int64_t* __restrict__ cnt) {
+  extern __shared__ uint32_t bits[];   // nwords
+  __shared__ int tmp[256];
+  const int64_t i = rows[blockIdx.x];
+  for (int w = threadIdx.x; w < nwords; w += 256) bits[w] = 0u;
+  __syncthreads();
+  mm_mark_wide(i, Xptr, Xcol, Yptr, Ycol, bits);
+  __syncthreads();
+  int c = 0;
+  for (int w = threadIdx.x; w < nwords; w += 256) c += __popc(bits[w]);
+  int total = 0;
+  block_exclusive_scan256(c, tmp, &total);
+  if (threadIdx.x == 0) cnt[i] = total;
+}
+
+__global__ __launch_bounds__(256) void k_mm_fill_wide(const int32_t* __restrict__ rows,
+                                                      const int64_t* __restrict__ Xptr,
+                                                      const int32_t* __restrict__ Xcol,
+                                                      const int64_t* __restrict__ Yptr,
+                                                      const int32_t* __restrict__ Ycol, int nwords,
+                                                      const int64_t* __restrict__ Cptr,
+                                                      int32_t* __restrict__ Ccol) {
+  extern __shared__ uint32_t bits[];   // nwords
+  __shared__ int tmp[256];
+  const int64_t i = rows[blockIdx.x];
+  for (int w = threadIdx.x; w < nwords; w += 256) bits[w] = 0u;
+  __syncthreads();
+  mm_mark_wide(i, Xptr, Xcol, Yptr, Ycol, bits);
+  __syncthreads();
+  // thread t lists the set bits of words [w0, w1) in order
+  const int per = (nwords + 255) / 256;
+  const int w0 = min(nwords, (int)threadIdx.x * per), w1 = min(nwords, w0 + per);
+  int c = 0;
+  for (int w = w0; w < w1; ++w) c += __popc(bits[w]);
+  int pos = block_exclusive_scan256(c, tmp, nullptr);
+  int32_t* out = Ccol + Cptr[i];
+  for (int w = w0; w < w1; ++w) {
+    uint32_t b = bits[w];
+    while (b) {
+      const int lsb = __ffs(b) - 1;
+      out[pos++] = w * 32 + lsb;
+      b &= b - 1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_mm_vals_wide(
+    const int32_t* __restrict__ rows, const int64_t* __restrict__ Xptr,
+    const int32_t* __restrict__ Xcol, const double* __restrict__ Xval,
+    const int64_t* __restrict__ Yptr, const int32_t* __restrict__ Ycol,
+    const double* __restrict__ Yval, int nwords, const int64_t* __restrict__ Cptr,
+    const int32_t* __restrict__ Ccol, double* __restrict__ Cval) {
+  extern __shared__ uint32_t bits[];   // nwords bits, then nwords prefix counts
+  int32_t* rank0 = (int32_t*)(bits + nwords);
+  const int64_t i = rows[blockIdx.x];
+  const int64_t o = Cptr[i];
+  const int m = (int)(Cptr[i + 1] - o);
+  const int lane = threadIdx.x;
+  for (int w = lane; w < nwords; w += 64) bits[w] = 0u;
+  __syncthreads();
+  for (int t = lane; t < m; t += 64) {
+    const int32_t J = Ccol[o + t];
+    atomicOr(&bits[J >> 5], 1u << (J & 31));
+    Cval[o + t] = 0.0;
+  }
+  __syncthreads();
+  if (lane == 0) {
+    int run = 0;
+    for (int w = 0; w < nwords; ++w) {
+      rank0[w] = run;
+      run += __popc(bits[w]);
+    }
+  }
+  __syncthreads();
+  // same order as k_mm_vals: X's entries in stored order, lanes over the
+  // distinct columns of one Y row, so each C entry is summed in a fixed order
+  for (int64_t t = Xptr[i]; t < Xptr[i + 1]; ++t) {
+    const int32_t k = Xcol[t];
+    const double x = Xval[t];
+    for (int64_t u = Yptr[k] + lane; u < Yptr[k + 1]; u += 64) {
+      const int32_t J = Ycol[u];
+      const uint32_t w = bits[J >> 5];
+      if (w & (1u << (J & 31))) {
+        const int pos = rank0[J >> 5] + __popc(w & ((1u << (J & 31)) - 1u));
+        Cval[o + pos] += x * Yval[u];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+size_t mm_wide_lds(int64_t ncols) { return (size_t)((ncols + 31) / 32) * 2 * sizeof(uint32_t); }
+
+void mm_count_wide(int64_t nw, const int32_t* rows, const CsrPat& X, const CsrPat& Y, int64_t ncols,
+                   int64_t* cnt, hipStream_t st) {
+  if (nw <= 0) return;
+  const int nwords = (int)((ncols + 31) / 32);
+  hipLaunchKernelGGL(k_mm_count_wide, dim3((unsigned)nw), dim3(256), nwords * sizeof(uint32_t), st,
+                     rows, X.ptr, X.col, Y.ptr, Y.col, nwords, cnt);
+}
+void mm_fill_wide(int64_t nw, const int32_t* rows, const CsrPat& X, const CsrPat& Y, int64_t ncols,
+                  const int64_t* Cptr, int32_t* Ccol, hipStream_t st) {
+  if (nw <= 0) return;
+  const int nwords = (int)((ncols + 31) / 32);
+  hipLaunchKernelGGL(k_mm_fill_wide, dim3((unsigned)nw), dim3(256), nwords * sizeof(uint32_t), st,
+                     rows, X.ptr, X.col, Y.ptr, Y.col, nwords, Cptr, Ccol);
+}
+void mm_vals_wide(int64_t nw, const int32_t* rows, const CsrPat& X, const double* Xval,
+                  const CsrPat& Y, const double* Yval, int64_t ncols, const int64_t* Cptr,
+                  const int32_t* Ccol, double* Cval, hipStream_t st) {
+  if (nw <= 0) return;
+  const int nwords = (int)((ncols + 31) / 32);
+  hipLaunchKernelGGL(k_mm_vals_wide, dim3((unsigned)nw), dim3(64), mm_wide_lds(ncols), st, rows,
+                     X.ptr, X.col, Xval, Y.ptr, Y.col, Yval, nwords, Cptr, Ccol, Cval);
+}
+
+// rows with more columns than this take the wide passes (HCAP / 2, or less
+// with HCURL_AMG_MM_WIDE, which also caps the numeric pass's LDS rows)
+int mm_wide_at() {
+  int w = HCAP / 2;
+  if (const char* e = std::getenv("HCURL_AMG_MM_WIDE")) w = std::max(1, std::min(w, std::atoi(e)));
+  return w;
+}
 void mm_count(int64_t nrows, const CsrPat& X, const CsrPat& Y, int64_t* cnt, int* overflow,
               hipStream_t st) {
   if (nrows > 0)
     hipLaunchKernelGGL(k_mm_count, dim3((unsigned)nrows), dim3(256), 0, st, nrows, X.ptr, X.col,
-                       Y.ptr, Y.col, cnt, overflow);
+                       Y.ptr, Y.col, cnt, overflow, mm_wide_at());
 }
 void mm_fill(int64_t nrows, const CsrPat& X, const CsrPat& Y, const int64_t* Cptr, int32_t* Ccol,
              int* overflow, hipStream_t st) {
   if (nrows > 0)
     hipLaunchKernelGGL(k_mm_fill, dim3((unsigned)nrows), dim3(256), 0, st, nrows, X.ptr, X.col,
-                       Y.ptr, Y.col, Cptr, Ccol, overflow);
+                       Y.ptr, Y.col, Cptr, Ccol, overflow, mm_wide_at());
 }
 void mm_vals(int64_t nrows, const CsrPat& X, const double* Xval, const CsrPat& Y,
              const double* Yval, const int64_t* Cptr, const int32_t* Ccol, double* Cval, int mmax,
@@ -949,6 +1290,12 @@ template void schwarz_colour<double>(const SmootherDev<double>&, const CsrDev<do
 template void schwarz_colour<float>(const SmootherDev<float>&, const CsrDev<float>&, int, const float*, float*, hipStream_t);
 template void schwarz_sweep_small<double>(const SmootherDev<double>&, const CsrDev<double>&, int, const double*, double*, hipStream_t);
 template void schwarz_sweep_small<float>(const SmootherDev<float>&, const CsrDev<float>&, int, const float*, float*, hipStream_t);
+template bool dense_sweep_ok<double>(int, int);
+template bool dense_sweep_ok<float>(int, int);
+template void dense_sweep<double>(int, int, int, int, const int64_t*, const int32_t*, const int64_t*,
+                                  const double*, const double*, const double*, double*, hipStream_t);
+template void dense_sweep<float>(int, int, int, int, const int64_t*, const int32_t*, const int64_t*,
+                                 const float*, const float*, const float*, float*, hipStream_t);
 template void dense_solve<double>(int, const double*, const double*, double*, double*, hipStream_t);
 template void dense_solve<float>(int, const double*, const float*, float*, double*, hipStream_t);
 template void fill<double>(int64_t, double, double*, hipStream_t);

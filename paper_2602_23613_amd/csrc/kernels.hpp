@@ -38,6 +38,14 @@ struct SmootherDev {
   const int64_t* fac_off = nullptr;     // packed lower factor offset of each block
   const T* fac = nullptr;
   int lpr = 8;
+  // dense level (nnz = n^2, one block per colour): the sweep keeps r and x in
+  // LDS and updates r from a column-major dense copy of A
+  bool dense = false;
+  int n = 0;
+  int nblocks = 0;
+  int max_block = 0;
+  const T* Acm = nullptr;
+  T* rtmp = nullptr;                    // level-sized scratch for b - A x
 };
 
 // scalar slots of the CG state vector
@@ -59,10 +67,24 @@ template <class T>
 void schwarz_sweep_small(const SmootherDev<T>& S, const CsrDev<T>& A, int backward, const T* b,
                          T* x, hipStream_t st);
 
+template <class T> bool dense_sweep_ok(int n, int max_block);
+template <class T>
+void dense_sweep(int n, int nblocks, int max_block, int backward, const int64_t* sb_ptr,
+                 const int32_t* sb_dofs, const int64_t* fac_off, const T* fac, const T* Acm,
+                 const T* r_in, T* x, hipStream_t st);
+void csr_to_dense_cm(int64_t n, const int64_t* ptr, const int32_t* col, const double* val,
+                     double* D, hipStream_t st);
+
 // one multiplicative Schwarz sweep (all colours) with the launch shape the level uses
 template <class T>
 void schwarz_sweep(const SmootherDev<T>& S, const CsrDev<T>& A, int backward, const T* b, T* x,
                    hipStream_t st) {
+  if (S.dense) {
+    residual<T>(A, x, b, S.rtmp, st);
+    dense_sweep<T>(S.n, S.nblocks, S.max_block, backward, S.sb_ptr, S.sb_dofs, S.fac_off, S.fac,
+                   S.Acm, S.rtmp, x, st);
+    return;
+  }
   if (S.one_launch) {
     schwarz_sweep_small<T>(S, A, backward, b, x, st);
     return;
@@ -87,7 +109,8 @@ void cg_scalar(double* sc, int mode, int flexible, hipStream_t st);
 void cg_dir(int64_t n, const double* sc, const double* z, double* p, int first, hipStream_t st);
 int red_grid();
 
-size_t ext_block_lds(int smax, int cmax);
+size_t ext_block_lds(int smax, int ctile);
+int ext_block_tile(int smax);
 void ext_blocks(int64_t b0, int64_t nb, const int64_t* bptr, const int32_t* bdofs,
                 const int32_t* dof_stage, int stage, const CsrDev<double>& A,
                 const int64_t* Pptr, const int32_t* Pcol, double* Pval, int smax, int cmax,
@@ -106,6 +129,15 @@ void mm_vals(int64_t nrows, const CsrPat& X, const double* Xval, const CsrPat& Y
              const double* Yval, const int64_t* Cptr, const int32_t* Ccol, double* Cval, int mmax,
              hipStream_t st);
 int mm_hash_cap();
+int mm_wide_at();
+size_t mm_wide_lds(int64_t ncols);
+void mm_count_wide(int64_t nw, const int32_t* rows, const CsrPat& X, const CsrPat& Y, int64_t ncols,
+                   int64_t* cnt, hipStream_t st);
+void mm_fill_wide(int64_t nw, const int32_t* rows, const CsrPat& X, const CsrPat& Y, int64_t ncols,
+                  const int64_t* Cptr, int32_t* Ccol, hipStream_t st);
+void mm_vals_wide(int64_t nw, const int32_t* rows, const CsrPat& X, const double* Xval,
+                  const CsrPat& Y, const double* Yval, int64_t ncols, const int64_t* Cptr,
+                  const int32_t* Ccol, double* Cval, hipStream_t st);
 
 void star_chol(int64_t nb, const int64_t* sb_ptr, const int32_t* sb_dofs, const int64_t* fac_off,
                const CsrDev<double>& A, double* fac, int* flag, hipStream_t st);

@@ -430,3 +430,103 @@ def test_sweep_launch_shapes_agree():
         err = np.linalg.norm(out[name] - zo) / np.linalg.norm(zo)
         print(f"{name}: V-cycle rel err vs oracle {err:.2e} (tol {tol:.1e})")
         assert err <= tol
+
+
+def test_dense_level_sweep_matches_oracle():
+    """Level 2 of a 32^3 jump problem (1,176 rows, 68% dense, 343 blocks in
+    241 colours) is swept block by block in one workgroup with r = b - A x
+    kept in LDS and updated.  Forward, backward, forward sweeps from a nonzero
+    start against the oracle's level-2 sweep, and the V-cycle against the
+    row-form sweep."""
+    import os
+    d = dev()
+    p = gen.make_problem("hex", 32, beta=1.0, alpha=lambda m: fields.subdomain_log_uniform(m, 8, 2))
+    Ho = oracle.setup(p.A, p.G)
+    H = amglib.Hierarchy(p.A, p.G)
+    info = H.info()
+    assert info[2]["n"] == 1176 and 2 * info[2]["nblocks"] <= 3 * info[2]["ncolors"]
+    n2 = info[2]["n"]
+    rng = np.random.default_rng(2)
+    b = torch.tensor(rng.standard_normal(n2), device=d)
+    x = torch.tensor(rng.standard_normal(n2), device=d)   # nonzero start: b - A x is formed first
+    x0 = x.cpu().numpy()
+    for bw in (False, True, False):
+        H.sweep(2, b, x, backward=bw)
+    torch.cuda.synchronize()
+    mats = amg._cast(Ho, np.float64)
+    nc = Ho.levels[2].smoother.ncolors
+    bo = b.cpu().numpy()
+    xo = x0.copy()
+    for order in (range(nc), range(nc - 1, -1, -1), range(nc)):
+        xo = amg._schwarz(mats[2], xo, bo, list(order))
+    err = np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo)
+    tol = max(1e-10, 16 * kappas(Ho)[1] * EPS)
+    print(f"level-2 block-sequential sweep: rel err vs oracle {err:.2e} (tol {tol:.1e})")
+    assert err <= tol
+    r = torch.tensor(rng.standard_normal(p.A.shape[0]), device=d)
+    z1 = torch.zeros_like(r)
+    H.vcycle(r, z1)
+    os.environ["HCURL_AMG_DENSE_SWEEP"] = "0"
+    try:
+        H2 = amglib.Hierarchy(p.A, p.G)
+    finally:
+        del os.environ["HCURL_AMG_DENSE_SWEEP"]
+    z2 = torch.zeros_like(r)
+    H2.vcycle(r, z2)
+    torch.cuda.synchronize()
+    e = (torch.linalg.norm(z1 - z2) / torch.linalg.norm(z2)).item()
+    print(f"V-cycle, block-sequential vs row sweep: rel diff {e:.2e}")
+    assert e <= tol
+    zo = oracle.vcycle(Ho, r.cpu().numpy())
+    e2 = np.linalg.norm(z1.cpu().numpy() - zo) / np.linalg.norm(zo)
+    print(f"V-cycle vs oracle: rel err {e2:.2e}")
+    assert e2 <= tol
+    H.close()
+    H2.close()
+
+
+def test_tiled_extension_equals_untiled():
+    """The local extension runs over column tiles when a block's P rows are
+    too wide for LDS; forcing tiles of 5 columns must give the same P and
+    Galerkin operators bit for bit (same summation order per entry)."""
+    import os
+    dev()
+    p, _ = case("hex12_jump")
+    H1 = amglib.Hierarchy(p.A, p.G)
+    os.environ["HCURL_AMG_EXT_TILE"] = "5"
+    try:
+        H2 = amglib.Hierarchy(p.A, p.G)
+    finally:
+        del os.environ["HCURL_AMG_EXT_TILE"]
+    for l in range(len(H1.info()) - 1):
+        A1, P1 = H1.level(l)
+        A2, P2 = H2.level(l)
+        assert np.array_equal(P1.data, P2.data), l
+        assert np.array_equal(A1.data, A2.data), l
+    H1.close()
+    H2.close()
+
+
+def test_wide_row_galerkin_equals_hash_passes():
+    """Rows of A P and P^T (A P) with more columns than the LDS hash holds are
+    counted and listed with a bitset and summed in place by rank.  Forcing
+    every row wider than 8 columns onto those passes must give the same
+    hierarchy bit for bit (same column order, same summation order)."""
+    import os
+    dev()
+    p, _ = case("hex12_jump")
+    H1 = amglib.Hierarchy(p.A, p.G)
+    os.environ["HCURL_AMG_MM_WIDE"] = "8"
+    try:
+        H2 = amglib.Hierarchy(p.A, p.G)
+    finally:
+        del os.environ["HCURL_AMG_MM_WIDE"]
+    i1, i2 = H1.info(), H2.info()
+    assert [l["nnz"] for l in i1] == [l["nnz"] for l in i2]
+    for l in range(len(i1)):
+        A1, _ = H1.level(l)
+        A2, _ = H2.level(l)
+        assert np.array_equal(A1.indptr, A2.indptr) and np.array_equal(A1.indices, A2.indices), l
+        assert np.array_equal(A1.data, A2.data), l
+    H1.close()
+    H2.close()
