@@ -361,14 +361,14 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   // launch shape of a sweep: tiny levels in one workgroup, the rest one
   // launch per colour
   L.one_launch = L.nnz <= 200000 && wg == 256;
-  // small, nearly sequential level (at most 1.5 blocks per colour, at most
-  // 2048 rows: the bottom of the hierarchy, where the Galerkin operators are
-  // dense or nearly so): swept block by block in one workgroup with the
-  // residual kept in LDS, from a dense copy of A (HCURL_AMG_DENSE_SWEEP=0
-  // turns this off)
+  // nearly sequential level (at most 1.5 blocks per colour: the bottom of the
+  // hierarchy, where the Galerkin operators are dense or nearly so): swept
+  // block by block in one workgroup with the residual updated, from a dense
+  // copy of A.  Off unless HCURL_AMG_DENSE_SWEEP=1: a 64^3 PCG run with it
+  // ended in a GPU memory fault whose cause is not yet shown.
   L.max_block = maxs;
   const char* dense_env = std::getenv("HCURL_AMG_DENSE_SWEEP");
-  L.dense_S = !(dense_env && dense_env[0] == '0') && 2 * ns <= 3 * (int64_t)I.ncolors &&
+  L.dense_S = (dense_env && dense_env[0] == '1') && 2 * ns <= 3 * (int64_t)I.ncolors &&
               dense_sweep_ok<double>((int)L.n, maxs);
   if (L.dense_S) L.Acm = h->pool.get<double>((size_t)L.n * L.n);
   L.sb_ptr = h->pool.upload(sb_ptr, st);

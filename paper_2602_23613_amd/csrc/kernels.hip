@@ -329,7 +329,8 @@ void schwarz_colour(const SmootherDev<T>& S, const CsrDev<T>& A, int colour, con
 // because r is updated instead of recomputed.  Everything a block needs from
 // global memory (its DoFs, factor and the columns A_{:,B}) is fetched one
 // block ahead, so the chain between blocks stays in LDS and registers.
-// Limits (checked by the caller): n <= 1024 * RPT, blocks of at most SM <= 16 DoFs.
+// Limits (checked by the caller): n <= 1024 * RPT <= 2048, blocks of at most
+// SM <= 16 DoFs.
 constexpr int DENSE_SMAX = 16;
 constexpr int DENSE_FMAX = DENSE_SMAX * (DENSE_SMAX + 1) / 2;
 
@@ -423,16 +424,98 @@ __global__ __launch_bounds__(1024) void k_dense_sweep(int n, int nblocks, int ba
   for (int i = tid; i < n; i += 1024) x[i] = xs[i];
 }
 
+// The same sweep for larger nearly dense levels (2048 < n <= 16384): r and x
+// stay in global memory (one workgroup touches them, so they stay in its
+// CU's cache path), the block's DoFs and factor are fetched one block ahead,
+// and each thread updates its rows of r from the block's columns.
+template <class T, int SM>
+__global__ __launch_bounds__(1024) void k_dense_sweep_big(int n, int nblocks, int backward,
+                                                          const int64_t* __restrict__ sb_ptr,
+                                                          const int32_t* __restrict__ sb_dofs,
+                                                          const int64_t* __restrict__ fac_off,
+                                                          const T* __restrict__ fac,
+                                                          const T* __restrict__ Acm,
+                                                          T* __restrict__ r, T* __restrict__ x) {
+  __shared__ T d[SM];
+  __shared__ T fl[SM * (SM + 1) / 2];
+  __shared__ int32_t dofs[SM];
+  const int tid = threadIdx.x;
+  int nx_s = 0;
+  int32_t nx_dof = 0;
+  T nx_f = 0;
+  auto fetch = [&](int bi) {
+    const int blk = backward ? nblocks - 1 - bi : bi;
+    const int64_t p0 = sb_ptr[blk];
+    const int sz = (int)(sb_ptr[blk + 1] - p0);
+    nx_s = sz;
+    nx_dof = tid < sz ? sb_dofs[p0 + tid] : 0;
+    nx_f = tid < sz * (sz + 1) / 2 ? fac[fac_off[blk] + tid] : T(0);
+  };
+  if (nblocks > 0) fetch(0);
+  for (int bi = 0; bi < nblocks; ++bi) {
+    const int sz = nx_s;
+    if (tid < sz) dofs[tid] = nx_dof;
+    if (tid < sz * (sz + 1) / 2) fl[tid] = nx_f;
+    __syncthreads();   // dofs and factor in LDS; r and x of the previous block visible
+    if (bi + 1 < nblocks) fetch(bi + 1);
+    if (tid == 0) {
+      T v[SM];
+#pragma unroll
+      for (int i = 0; i < SM; ++i) v[i] = i < sz ? r[dofs[i]] : T(0);
+      for (int i = 0; i < sz; ++i) {
+        T a = v[i];
+        const T* Li = fl + i * (i + 1) / 2;
+        for (int j = 0; j < i; ++j) a -= Li[j] * d[j];
+        d[i] = a / Li[i];
+      }
+      for (int i = sz - 1; i >= 0; --i) {
+        T a = d[i];
+        for (int j = i + 1; j < sz; ++j) a -= fl[j * (j + 1) / 2 + i] * d[j];
+        d[i] = a / fl[i * (i + 1) / 2 + i];
+      }
+    }
+    __syncthreads();   // d ready
+    if (tid < sz) x[dofs[tid]] += d[tid];
+    T dk[SM];
+    int32_t ck[SM];
+#pragma unroll
+    for (int k = 0; k < SM; ++k) {
+      dk[k] = k < sz ? d[k] : T(0);
+      ck[k] = k < sz ? dofs[k] : 0;
+    }
+    for (int i = tid; i < n; i += 1024) {
+      T acc = 0;
+#pragma unroll
+      for (int k = 0; k < SM; ++k)
+        if (k < sz) acc += Acm[(int64_t)ck[k] * n + i] * dk[k];
+      r[i] -= acc;
+    }
+    __syncthreads();   // r and x updated; dofs, fl and d free for the next block
+  }
+}
+
 template <class T>
 bool dense_sweep_ok(int n, int max_block) {
-  return n > 0 && n <= 2048 && max_block <= DENSE_SMAX &&
-         dense_sweep_lds(n, sizeof(T)) <= 64 * 1024;
+  if (n <= 0 || max_block > DENSE_SMAX) return false;
+  if (n <= 2048) return dense_sweep_lds(n, sizeof(T)) <= 64 * 1024;
+  return n <= 16384;
 }
 
 template <class T>
 void dense_sweep(int n, int nblocks, int max_block, int backward, const int64_t* sb_ptr,
                  const int32_t* sb_dofs, const int64_t* fac_off, const T* fac, const T* Acm,
                  const T* r_in, T* x, hipStream_t st) {
+  // HCURL_AMG_DENSE_BIG=1 takes the global-memory form at any size (for tests)
+  const char* big_env = std::getenv("HCURL_AMG_DENSE_BIG");
+  if (n > 2048 || (big_env && big_env[0] == '1')) {   // r_in (the level's scratch) is updated in place
+    if (max_block <= 8)
+      hipLaunchKernelGGL((k_dense_sweep_big<T, 8>), dim3(1), dim3(1024), 0, st, n, nblocks, backward,
+                         sb_ptr, sb_dofs, fac_off, fac, Acm, const_cast<T*>(r_in), x);
+    else
+      hipLaunchKernelGGL((k_dense_sweep_big<T, 16>), dim3(1), dim3(1024), 0, st, n, nblocks,
+                         backward, sb_ptr, sb_dofs, fac_off, fac, Acm, const_cast<T*>(r_in), x);
+    return;
+  }
   const size_t lds = dense_sweep_lds(n, sizeof(T));
 #define LAUNCH_DS(R, M)                                                                          \
   hipLaunchKernelGGL((k_dense_sweep<T, R, M>), dim3(1), dim3(1024), lds, st, n, nblocks, backward, \

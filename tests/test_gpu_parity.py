@@ -432,17 +432,40 @@ def test_sweep_launch_shapes_agree():
         assert err <= tol
 
 
-def test_dense_level_sweep_matches_oracle():
+_hex32 = {}
+
+
+def _hex32_case():
+    if not _hex32:
+        p = gen.make_problem("hex", 32, beta=1.0, alpha=lambda m: fields.subdomain_log_uniform(m, 8, 2))
+        _hex32["p"] = p
+        _hex32["Ho"] = oracle.setup(p.A, p.G)
+    return _hex32["p"], _hex32["Ho"]
+
+
+@pytest.mark.skip(reason="the block-sequential sweep is switched off: a 64^3 PCG run with it ended "
+                         "in a GPU memory fault whose cause is not yet shown")
+@pytest.mark.parametrize("form", ["lds", "global"])
+def test_dense_level_sweep_matches_oracle(form):
     """Level 2 of a 32^3 jump problem (1,176 rows, 68% dense, 343 blocks in
     241 colours) is swept block by block in one workgroup with r = b - A x
-    kept in LDS and updated.  Forward, backward, forward sweeps from a nonzero
-    start against the oracle's level-2 sweep, and the V-cycle against the
-    row-form sweep."""
+    kept in LDS (or, the form used above 2,048 rows, in global memory) and
+    updated.  Forward, backward, forward sweeps from a nonzero start against
+    the oracle's level-2 sweep, and the V-cycle against the row-form sweep."""
     import os
     d = dev()
-    p = gen.make_problem("hex", 32, beta=1.0, alpha=lambda m: fields.subdomain_log_uniform(m, 8, 2))
-    Ho = oracle.setup(p.A, p.G)
-    H = amglib.Hierarchy(p.A, p.G)
+    p, Ho = _hex32_case()
+    if form == "global":
+        os.environ["HCURL_AMG_DENSE_BIG"] = "1"
+    try:
+        H = amglib.Hierarchy(p.A, p.G)
+        _dense_sweep_checks(d, p, Ho, H)
+    finally:
+        os.environ.pop("HCURL_AMG_DENSE_BIG", None)
+
+
+def _dense_sweep_checks(d, p, Ho, H):
+    import os
     info = H.info()
     assert info[2]["n"] == 1176 and 2 * info[2]["nblocks"] <= 3 * info[2]["ncolors"]
     n2 = info[2]["n"]
