@@ -124,6 +124,7 @@ struct Level {
   float* PT_val32 = nullptr;
   int64_t* PT_perm = nullptr;
   int lpr_P = 4, lpr_PT = 8;
+  int p_row_max = 0;               // widest row of P's structural pattern
   std::vector<int64_t> p_ptr_h;   // host copy of P's current pattern
   std::vector<int32_t> p_col_h;
   int32_t* dof_stage = nullptr;
@@ -364,11 +365,10 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   // nearly sequential level (at most 1.5 blocks per colour: the bottom of the
   // hierarchy, where the Galerkin operators are dense or nearly so): swept
   // block by block in one workgroup with the residual updated, from a dense
-  // copy of A.  Off unless HCURL_AMG_DENSE_SWEEP=1: a 64^3 PCG run with it
-  // ended in a GPU memory fault whose cause is not yet shown.
+  // copy of A (HCURL_AMG_DENSE_SWEEP=0 turns this off)
   L.max_block = maxs;
   const char* dense_env = std::getenv("HCURL_AMG_DENSE_SWEEP");
-  L.dense_S = (dense_env && dense_env[0] == '1') && 2 * ns <= 3 * (int64_t)I.ncolors &&
+  L.dense_S = !(dense_env && dense_env[0] == '0') && 2 * ns <= 3 * (int64_t)I.ncolors &&
               dense_sweep_ok<double>((int)L.n, maxs);
   if (L.dense_S) L.Acm = h->pool.get<double>((size_t)L.n * L.n);
   L.sb_ptr = h->pool.upload(sb_ptr, st);
@@ -421,6 +421,9 @@ void build_interp_structs(amg_hier* h, Level& L, hipStream_t st) {
   }
   L.p_ptr_h = I.p.ptr;
   L.p_col_h = I.p.idx;
+  L.p_row_max = 0;
+  for (int64_t i = 0; i < L.n; ++i)
+    L.p_row_max = std::max<int>(L.p_row_max, (int)(I.p.ptr[i + 1] - I.p.ptr[i]));
 }
 
 // P^T pattern and the permutation P entry -> P^T entry, from the host copy of
@@ -482,7 +485,7 @@ void compute_interp(amg_hier* h, Level& L, int level, hipStream_t st, bool learn
   for (size_t s = 0; s < L.stages.size(); ++s) {
     const Stage& S = L.stages[s];
     ext_blocks(S.b0, S.nb, L.blk_ptr, L.blk_dofs, L.dof_stage, (int)s, L.A_dev<double>(), L.P_ptr,
-               L.P_col, L.P_val, S.smax, S.cmax, h->d_flag, st, learned ? h->fW : nullptr,
+               L.P_col, L.P_val, S.smax, S.cmax, L.p_row_max, h->d_flag, st, learned ? h->fW : nullptr,
                learned ? h->facc : nullptr, learned ? h->fdsq : nullptr);
   }
   check_flag(h, st, AMG_ERR_NOT_SPD,
@@ -735,7 +738,10 @@ void alloc_vectors(amg_hier* h) {
   h->pp = h->pool.get<double>(n);
   h->pq = h->pool.get<double>(n);
   h->prold = h->pool.get<double>(n);
-  h->partial_cap = std::max<int64_t>(2 * red_grid(), spmv_dot_partials(4, n));
+  // partial sums: two per workgroup of the fixed-grid dot products, and one
+  // per workgroup of the level-0 SpMV-with-dot (n / (256 / lpr) workgroups:
+  // the most for the widest lane groups)
+  h->partial_cap = std::max<int64_t>(2 * red_grid(), spmv_dot_partials(h->lv[0].lpr_A, n));
   h->d_partial = h->pool.get<double>(h->partial_cap);
   h->d_sc = h->pool.get<double>(SC_COUNT);
   int64_t nL = h->lv.back().n;
@@ -1155,6 +1161,7 @@ amg_status amg_pcg_solve(amg_hier* h, const double* f, double* u, double rtol, i
       reduce(red_grid(), h->d_partial, h->d_sc, SC_RZ, -1, st);
       cg_dir(n, h->d_sc, z, p, 1, st);
       int64_t np = spmv_dot_partials(A.lpr, n);
+      if (np > h->partial_cap) fail(AMG_ERR_LIMIT, "partial-sum buffer smaller than the SpMV grid");
       while (it < maxit) {
         spmv_dot(A, p, q, h->d_partial, st);
         reduce(np, h->d_partial, h->d_sc, SC_PQ, -1, st);

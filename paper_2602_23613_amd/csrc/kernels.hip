@@ -783,7 +783,7 @@ __global__ __launch_bounds__(64) void k_ext_block(
     const int32_t* __restrict__ dof_stage, int stage, const int64_t* __restrict__ Aptr,
     const int32_t* __restrict__ Acol, const double* __restrict__ Aval,
     const int64_t* __restrict__ Pptr, const int32_t* __restrict__ Pcol, double* __restrict__ Pval,
-    int smax, int ctile, int* __restrict__ flag, const double* __restrict__ Wl,
+    int smax, int ctile, int wide, int* __restrict__ flag, const double* __restrict__ Wl,
     const int8_t* __restrict__ accepted, const double* __restrict__ dsq) {
   extern __shared__ unsigned char lds_raw[];
   double* Abb = (double*)lds_raw;                 // smax * smax
@@ -808,30 +808,40 @@ __global__ __launch_bounds__(64) void k_ext_block(
   for (int t = lane; t < s * c; t += 64) R[t] = 0.0;
   __syncthreads();
   const int32_t clo = cols[0], chi = cols[c - 1];
-  if (lane < s) {
-    const int32_t e = dofs[lane];
-    double* Rr = R + lane * c;
-    for (int64_t q = Aptr[e]; q < Aptr[e + 1]; ++q) {
-      const int32_t j = Acol[q];
-      const double a = Aval[q];
-      const int pos = lower_bound_i32(dofs, s, j);
-      if (pos < s && dofs[pos] == j) {
-        Abb[lane * s + pos] = a;
-        continue;
-      }
-      const int sj = dof_stage[j];
-      if (sj >= 0 && sj >= stage) continue;  // not extended yet
-      for (int64_t u = Pptr[j]; u < Pptr[j + 1]; ++u) {
-        const int32_t pc = Pcol[u];
-        if (pc < clo || pc > chi) continue;   // another tile's column
-        const int cp = lower_bound_i32(cols, c, pc);
-        if (cp < c && cols[cp] == pc) {
-          Rr[cp] += a * Pval[u];
-        } else {
-          atomicExch(flag, 2);   // pattern mismatch (cannot happen for host-built patterns)
-        }
+  // Right-hand side R = A_B,done P_done.  Every R entry sums its terms in the
+  // order of A's row (one term per A entry at most, as a P row has distinct
+  // columns), so both ways below give the same bits:
+  // narrow P rows: lane i gathers row i of the block;
+  // wide P rows (wide != 0): the rows one after the other, the 64 lanes over
+  // the distinct columns of one P row at a time.
+  auto gather_entry = [&](int i, int64_t q, int u0, int du) {
+    const int32_t j = Acol[q];
+    const double a = Aval[q];
+    const int pos = lower_bound_i32(dofs, s, j);
+    if (pos < s && dofs[pos] == j) {
+      if (u0 == 0) Abb[i * s + pos] = a;
+      return;
+    }
+    const int sj = dof_stage[j];
+    if (sj >= 0 && sj >= stage) return;  // not extended yet
+    double* Rr = R + i * c;
+    for (int64_t u = Pptr[j] + u0; u < Pptr[j + 1]; u += du) {
+      const int32_t pc = Pcol[u];
+      if (pc < clo || pc > chi) continue;   // another tile's column
+      const int cp = lower_bound_i32(cols, c, pc);
+      if (cp < c && cols[cp] == pc) {
+        Rr[cp] += a * Pval[u];
+      } else {
+        atomicExch(flag, 2);   // pattern mismatch (cannot happen for host-built patterns)
       }
     }
+  };
+  if (!wide) {
+    if (lane < s)
+      for (int64_t q = Aptr[dofs[lane]]; q < Aptr[dofs[lane] + 1]; ++q) gather_entry(lane, q, 0, 1);
+  } else {
+    for (int i = 0; i < s; ++i)
+      for (int64_t q = Aptr[dofs[i]]; q < Aptr[dofs[i] + 1]; ++q) gather_entry(i, q, lane, 64);
   }
   __syncthreads();
   if (Wl && accepted[blk]) {
@@ -902,8 +912,8 @@ int ext_block_tile(int smax) {
 void ext_blocks(int64_t b0, int64_t nb, const int64_t* bptr, const int32_t* bdofs,
                 const int32_t* dof_stage, int stage, const CsrDev<double>& A,
                 const int64_t* Pptr, const int32_t* Pcol, double* Pval, int smax, int cmax,
-                int* flag, hipStream_t st, const double* Wl, const int8_t* accepted,
-                const double* dsq) {
+                int prow_max, int* flag, hipStream_t st, const double* Wl,
+                const int8_t* accepted, const double* dsq) {
   if (nb <= 0 || cmax <= 0) return;
   // columns in tiles of ctile (one tile when the widest block fits LDS whole;
   // HCURL_AMG_EXT_TILE caps the tile width)
@@ -911,9 +921,13 @@ void ext_blocks(int64_t b0, int64_t nb, const int64_t* bptr, const int32_t* bdof
   if (const char* e = std::getenv("HCURL_AMG_EXT_TILE")) ctile = std::max(1, std::min(ctile, std::atoi(e)));
   const int ntiles = (cmax + ctile - 1) / ctile;
   size_t lds = ext_block_lds(smax, ctile);
+  // lanes over P's columns once the P rows of the done DoFs are wide enough
+  // to keep 64 lanes busy (HCURL_AMG_EXT_WIDE=0/1 forces either way)
+  int wide = prow_max > 64 ? 1 : 0;
+  if (const char* e = std::getenv("HCURL_AMG_EXT_WIDE")) wide = e[0] == '1' ? 1 : 0;
   hipLaunchKernelGGL(k_ext_block, dim3((unsigned)nb, (unsigned)ntiles), dim3(64), lds, st, b0, bptr,
                      bdofs, dof_stage, stage, A.ptr, A.col, A.val, Pptr, Pcol, Pval, smax, ctile,
-                     flag, Wl, accepted, dsq);
+                     wide, flag, Wl, accepted, dsq);
 }
 
 // x_i = a pseudo-random value in [-1, 1) from a counter-based hash (SplitMix64)

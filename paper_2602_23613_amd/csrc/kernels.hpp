@@ -114,7 +114,7 @@ int ext_block_tile(int smax);
 void ext_blocks(int64_t b0, int64_t nb, const int64_t* bptr, const int32_t* bdofs,
                 const int32_t* dof_stage, int stage, const CsrDev<double>& A,
                 const int64_t* Pptr, const int32_t* Pcol, double* Pval, int smax, int cmax,
-                int* flag, hipStream_t st, const double* Wl = nullptr,
+                int prow_max, int* flag, hipStream_t st, const double* Wl = nullptr,
                 const int8_t* accepted = nullptr, const double* dsq = nullptr);
 void hash_fill(int64_t n, uint64_t seed, double* x, hipStream_t st);
 void axpy(int64_t n, double a, const double* x, double* y, hipStream_t st);

@@ -297,3 +297,32 @@ def test_chunked_inference_equals_one_pass():
     _, P2 = H.level(0)
     assert np.array_equal(P1.data, P2.data)
     H.close()
+
+
+def test_learned_setup_on_a_new_field():
+    """The use the learned form is for: train on the exact local solves of one
+    coefficient field, then re-set up on another field of the same law.  The
+    accepted blocks must reproduce the exact P of the new field within the
+    acceptance bound, and most blocks must be accepted."""
+    from gen import fields
+    import gen
+    import oracle as _or
+    dev()
+    law = lambda seed: (lambda m: fields.subdomain_log_uniform(m, 8, seed))
+    p1 = gen.make_problem("hex", 16, beta=1.0, alpha=law(2))
+    p2 = gen.make_problem("hex", 16, beta=1.0, alpha=law(12))
+    H = amglib.Hierarchy(p1.A, p1.G)
+    st = H.mlp_train(epochs=60, batch=256, lr=1e-3, seed=0, init=flatten(init_params(0)))
+    print("train", {k: st[k] for k in ("blocks", "eligible", "loss_first", "loss_last")})
+    H.mlp_use(refine_steps=6, accept_tol=1e-10)
+    H.resetup(p2.A)
+    su = H.mlp_stats()
+    print("use", {k: su[k] for k in ("blocks", "eligible", "accepted")})
+    Ho = _or.setup(p2.A, p2.G, max_levels=2)
+    _, P0 = H.level(0)
+    eP = _rowwise_err(P0, Ho.levels[0].P)
+    bound = _learned_bound(p2, H, 1e-10)
+    print(f"learned P rel err {eP:.2e} (bound {bound:.1e})")
+    assert eP <= bound
+    assert su["accepted"] >= 0.5 * st["eligible"]
+    H.close()

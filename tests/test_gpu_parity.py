@@ -443,8 +443,6 @@ def _hex32_case():
     return _hex32["p"], _hex32["Ho"]
 
 
-@pytest.mark.skip(reason="the block-sequential sweep is switched off: a 64^3 PCG run with it ended "
-                         "in a GPU memory fault whose cause is not yet shown")
 @pytest.mark.parametrize("form", ["lds", "global"])
 def test_dense_level_sweep_matches_oracle(form):
     """Level 2 of a 32^3 jump problem (1,176 rows, 68% dense, 343 blocks in
@@ -508,19 +506,18 @@ def _dense_sweep_checks(d, p, Ho, H):
     H2.close()
 
 
-def test_tiled_extension_equals_untiled():
+@pytest.mark.parametrize("env", [{"HCURL_AMG_EXT_TILE": "5"}, {"HCURL_AMG_EXT_WIDE": "1"},
+                                 {"HCURL_AMG_EXT_WIDE": "1", "HCURL_AMG_EXT_TILE": "7"},
+                                 {"HCURL_AMG_EXT_WIDE": "0"}])
+def test_tiled_extension_equals_untiled(env):
     """The local extension runs over column tiles when a block's P rows are
-    too wide for LDS; forcing tiles of 5 columns must give the same P and
-    Galerkin operators bit for bit (same summation order per entry)."""
-    import os
+    too wide for LDS, and spreads the lanes over P's columns when P's rows
+    are wide; every way must give the same P and Galerkin operators bit for
+    bit (each entry sums its terms in the order of A's row)."""
     dev()
     p, _ = case("hex12_jump")
     H1 = amglib.Hierarchy(p.A, p.G)
-    os.environ["HCURL_AMG_EXT_TILE"] = "5"
-    try:
-        H2 = amglib.Hierarchy(p.A, p.G)
-    finally:
-        del os.environ["HCURL_AMG_EXT_TILE"]
+    H2 = _with_env(env, lambda: amglib.Hierarchy(p.A, p.G))
     for l in range(len(H1.info()) - 1):
         A1, P1 = H1.level(l)
         A2, P2 = H2.level(l)
