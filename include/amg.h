@@ -111,6 +111,9 @@ typedef struct {
   int64_t star_rows;       /* sum of block sizes: rows visited by one Schwarz sweep */
   int64_t star_row_nnz;    /* stored entries of A_l in those rows (with repetition) */
   int64_t fac_entries;     /* packed lower-triangular factor entries of all blocks */
+  int sweep_form;          /* how a sweep runs: 0 one launch per colour, 1 one workgroup,
+                              2 colours pipelined in one launch, 3 dense residual-update form */
+  int sweep_lanes;         /* lanes per row of the row forms (0 for the dense form) */
 } amg_level_info;
 
 /* Integer results of one level's setup, for bit-exact comparison.  All
@@ -165,9 +168,17 @@ amg_status amg_pcg_solve(amg_hier *h, const double *f, double *u, double rtol, i
    node-star blocks B of that colour.  prec = 64: b, x are device doubles
    and the FP64 factors are used; prec = 32: device floats and the FP32
    copies (only in a hierarchy built with vcycle_prec = 32).  Asynchronous;
-   used for kernel tests and measurement. */
+   used for kernel tests and measurement.  A sweep whose colours run
+   pipelined in one launch (levels with many colours) bounds each of its
+   waits for the previous colour; a wait that gives up leaves x wrong and
+   raises a flag that amg_check and amg_pcg_solve report. */
 amg_status amg_smoother_sweep(amg_hier *h, int level, int prec, const void *b, void *x,
                               int backward, void *stream);
+
+/* Synchronizes `stream` and reports whether any smoother sweep of this
+   handle gave up a wait (AMG_ERR_HIP; the flag stays set for the handle's
+   lifetime, and every result computed since is suspect).  AMG_OK otherwise. */
+amg_status amg_check(amg_hier *h, void *stream);
 
 /* y = A x with the CSR SpMV kernel of the solve phase (device CSR and
    vectors, FP64).  Used for measurement and kernel tests. */

@@ -13,6 +13,9 @@ import numpy as np
 from . import _lib
 from ._lib import AmgError, load  # noqa: F401
 
+# amg_level_info.sweep_form values
+SWEEP_FORMS = {0: "colour", 1: "one", 2: "pipe", 3: "dense"}
+
 __all__ = ["Hierarchy", "level0_integers", "spmv", "mlp_loss_grad", "load", "AmgError"]
 
 
@@ -125,7 +128,8 @@ class Hierarchy:
         _lib.check(load().amg_hier_info(self._h, arr, cap, C.byref(nl)))
         return [dict(n=x.n, nnz=x.nnz, p_nnz=x.p_nnz, nblocks=x.nblocks, ncolors=x.ncolors,
                      exact_blocks=bool(x.exact_blocks), star_rows=x.star_rows,
-                     star_row_nnz=x.star_row_nnz, fac_entries=x.fac_entries)
+                     star_row_nnz=x.star_row_nnz, fac_entries=x.fac_entries,
+                     sweep_form=SWEEP_FORMS[x.sweep_form], sweep_lanes=x.sweep_lanes)
                 for x in arr[:nl.value]]
 
     def sweep(self, level, b, x, backward=False, stream=None):
@@ -134,6 +138,10 @@ class Hierarchy:
         prec = 32 if b.dtype == torch.float32 else 64
         _lib.check(load().amg_smoother_sweep(self._h, level, prec, b.data_ptr(), x.data_ptr(),
                                              1 if backward else 0, _stream(stream)))
+
+    def check(self, stream=None):
+        """Synchronize and raise if a pipelined smoother sweep gave up a wait."""
+        _lib.check(load().amg_check(self._h, _stream(stream)))
 
     # --- learned setup ---------------------------------------------------
     def mlp_train(self, epochs=4, batch=1024, lr=1e-3, seed=0, eligible_max=50.0, init=None,

@@ -28,7 +28,7 @@ EXPORTED = ["amg_default_options", "amg_setup", "amg_resetup_numeric", "amg_vcyc
             "amg_pcg_solve", "amg_smoother_sweep", "amg_spmv", "amg_hier_info", "amg_export_integers",
             "amg_export_level", "amg_level0_integers", "amg_free_integers", "amg_destroy",
             "amg_last_error", "amg_mlp_nparams", "amg_mlp_train", "amg_mlp_use", "amg_mlp_stats_get",
-            "amg_mlp_params", "amg_mlp_forward", "amg_mlp_backward", "amg_mlp_loss_grad"]
+            "amg_mlp_params", "amg_mlp_forward", "amg_mlp_backward", "amg_mlp_loss_grad", "amg_check"]
 
 
 class AmgError(RuntimeError):
@@ -62,7 +62,8 @@ class amg_solve_stats(C.Structure):
 class amg_level_info(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("p_nnz", C.c_int64),
                 ("nblocks", C.c_int64), ("ncolors", C.c_int), ("exact_blocks", C.c_int),
-                ("star_rows", C.c_int64), ("star_row_nnz", C.c_int64), ("fac_entries", C.c_int64)]
+                ("star_rows", C.c_int64), ("star_row_nnz", C.c_int64), ("fac_entries", C.c_int64),
+                ("sweep_form", C.c_int), ("sweep_lanes", C.c_int)]
 
 
 class amg_int_export(C.Structure):
@@ -127,6 +128,7 @@ def load():
     lib.amg_pcg_solve.argtypes = [P, P, P, C.c_double, C.c_int, C.POINTER(amg_solve_stats), P]
     lib.amg_spmv.argtypes = [C.POINTER(amg_csr), P, P, P]
     lib.amg_smoother_sweep.argtypes = [P, C.c_int, C.c_int, P, P, C.c_int, P]
+    lib.amg_check.argtypes = [P, P]
     lib.amg_hier_info.argtypes = [P, C.POINTER(amg_level_info), C.c_int, C.POINTER(C.c_int)]
     lib.amg_export_integers.argtypes = [P, C.c_int, C.POINTER(amg_int_export)]
     lib.amg_export_level.argtypes = [P, C.c_int, P, P, P, P, P, P]
@@ -148,7 +150,7 @@ def load():
     lib.amg_mlp_backward.argtypes = [P, P, C.c_int64, P, P, P]
     lib.amg_mlp_loss_grad.argtypes = [P, P, P, C.c_int64, C.c_int64, P, P, P]
     for name in ("amg_setup", "amg_resetup_numeric", "amg_vcycle", "amg_pcg_solve", "amg_spmv",
-                 "amg_smoother_sweep",
+                 "amg_smoother_sweep", "amg_check",
                  "amg_hier_info", "amg_export_integers", "amg_export_level",
                  "amg_level0_integers", "amg_mlp_train", "amg_mlp_use", "amg_mlp_stats_get",
                  "amg_mlp_params", "amg_mlp_forward", "amg_mlp_backward", "amg_mlp_loss_grad"):

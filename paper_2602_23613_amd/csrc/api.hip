@@ -144,9 +144,19 @@ struct Level {
   int ncolours = 0;
   std::vector<int> colour_chunk;
   int32_t* colour_chunk_dev = nullptr;
-  bool one_launch = false;
+  int32_t* chunk_colour = nullptr;
+  int sweep_mode = SWEEP_COLOUR;
   int wg_S = 256;
+  int pipe_grid = 0;
+  int32_t* sweep_sync = nullptr;   // pipelined sweep: ticket + per-colour counters
   int32_t* chunk_blk = nullptr;
+  int32_t* ck_row0 = nullptr;
+  int64_t* ck_fac0 = nullptr;
+  int64_t srow_nnz = 0;
+  int64_t* srow_ptr = nullptr;     // the smoother's copy of A's rows in star order
+  int32_t* scol = nullptr;
+  double* sval = nullptr;
+  float* sval32 = nullptr;
   int64_t* sb_ptr = nullptr;
   int32_t* sb_dofs = nullptr;
   int64_t* fac_off = nullptr;
@@ -157,7 +167,6 @@ struct Level {
   float* dinv32 = nullptr;
   int lpr_S = 8;
   int max_block = 0;
-  bool dense_S = false;          // dense level: residual-update sweep on a dense copy of A
   double* Acm = nullptr;         // column-major dense A (dense levels only)
   float* Acm32 = nullptr;
   // device: cycle vectors
@@ -188,14 +197,21 @@ struct Level {
     return m;
   }
   template <class T>
-  SmootherDev<T> S_dev() const {
+  SmootherDev<T> S_dev(int* err, int spin_max) const {
     SmootherDev<T> s;
-    s.ncolours = ncolours; s.colour_chunk = colour_chunk; s.chunk_blk = chunk_blk;
-    s.colour_chunk_dev = colour_chunk_dev; s.one_launch = one_launch;
-    s.wg = wg_S;
-    s.sb_ptr = sb_ptr; s.sb_dofs = sb_dofs; s.fac_off = fac_off; s.lpr = lpr_S;
-    if constexpr (std::is_same<T, double>::value) s.fac = fac; else s.fac = fac32;
-    s.dense = dense_S;
+    s.ncolours = ncolours; s.colour_chunk = colour_chunk_dev; s.colour_chunk_h = colour_chunk;
+    s.chunk_colour = chunk_colour; s.chunk_blk = chunk_blk;
+    s.sb_ptr = sb_ptr; s.sb_dofs = sb_dofs; s.fac_off = fac_off;
+    s.ck_row0 = ck_row0; s.ck_fac0 = ck_fac0; s.srow_ptr = srow_ptr; s.scol = scol;
+    if constexpr (std::is_same<T, double>::value) {
+      s.fac = fac;
+      s.sval = sval;
+    } else {
+      s.fac = fac32;
+      s.sval = sval32;
+    }
+    s.sync = sweep_sync; s.err = err; s.spin_max = spin_max;
+    s.mode = sweep_mode; s.wg = wg_S; s.lpr = lpr_S; s.pipe_grid = pipe_grid;
     s.n = (int)n;
     s.nblocks = (int)nstars;
     s.max_block = max_block;
@@ -218,6 +234,9 @@ struct amg_hier {
   Pool pool;
   int prec = 64;
   int* d_flag = nullptr;        // non-SPD / overflow flags
+  int* d_sweep_err = nullptr;   // set by a pipelined smoother sweep whose wait gave up
+  int spin_max = 1 << 20;       // polls before such a wait gives up
+  int cu_count = 256;
   double* d_sc = nullptr;       // CG scalars
   double* d_partial = nullptr;  // reduction partials
   int64_t partial_cap = 0;
@@ -278,6 +297,15 @@ void check_flag(amg_hier* h, hipStream_t st, amg_status code, const std::string&
   }
 }
 
+// A pipelined smoother sweep whose wait gave up leaves its result wrong and
+// raises this flag (sticky for the handle's lifetime).
+void check_sweep_err(amg_hier* h, hipStream_t st) {
+  int f = 0;
+  HIPC(hipMemcpyAsync(&f, h->d_sweep_err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  if (f) fail(AMG_ERR_HIP, "a pipelined smoother sweep timed out waiting for the previous colour");
+}
+
 // Host copies of a CSR (pattern, and values if wanted).
 void host_csr(const amg_csr* M, std::vector<int64_t>& ptr, std::vector<int32_t>& col,
               std::vector<double>* val) {
@@ -301,6 +329,36 @@ void host_csr(const amg_csr* M, std::vector<int64_t>& ptr, std::vector<int32_t>&
 }
 
 // --- smoother: colour-sorted star blocks, chunks, factors, l1 diagonal ---
+// Sweep form of a level:
+//   dense   nearly sequential level (at most 1.5 blocks per colour: the
+//           bottom of the hierarchy, where the Galerkin operators are dense or
+//           nearly so): block by block in one workgroup with the residual
+//           updated, from a dense copy of A;
+//   pipe    many colours (16 or more): one launch, colours pipelined across
+//           workgroups (a launch per colour would leave the GPU idle between
+//           short colours);
+//   one     small level otherwise: the whole sweep in one workgroup;
+//   colour  one launch per colour.
+// HCURL_AMG_SWEEP=colour|one|pipe|dense forces a form where it applies
+// (dense needs a level that fits the dense kernel); HCURL_AMG_DENSE_SWEEP=0
+// turns the dense form off.
+int sweep_mode_for(int64_t n, int64_t nnz, int64_t ns, int ncolours, int maxs) {
+  const char* dense_env = std::getenv("HCURL_AMG_DENSE_SWEEP");
+  const bool dense_ok = !(dense_env && dense_env[0] == '0') && dense_sweep_ok<double>((int)n, maxs);
+  int mode = SWEEP_COLOUR;
+  if (dense_ok && 2 * ns <= 3 * (int64_t)ncolours) mode = SWEEP_DENSE;
+  else if (ncolours >= 16) mode = SWEEP_PIPE;
+  else if (nnz <= 200000) mode = SWEEP_ONE;
+  if (const char* e = std::getenv("HCURL_AMG_SWEEP")) {
+    const std::string f(e);
+    if (f == "colour") mode = SWEEP_COLOUR;
+    else if (f == "one") mode = SWEEP_ONE;
+    else if (f == "pipe") mode = SWEEP_PIPE;
+    else if (f == "dense" && dense_ok) mode = SWEEP_DENSE;
+  }
+  return mode;
+}
+
 void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   const LevelInts& I = L.ints;
   int64_t ns = (int64_t)I.star_ptr.size() - 1;
@@ -309,16 +367,29 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   int maxs = 0;
   for (int64_t b = 0; b < ns; ++b) maxs = std::max<int>(maxs, (int)(I.star_ptr[b + 1] - I.star_ptr[b]));
   if (maxs > 32) fail(AMG_ERR_LIMIT, "smoother block with more than 32 DoFs");
-  // lanes per row from the row length; the workgroup must hold a whole block
-  // (rows per chunk = wg / lpr >= largest block), up to 1024 threads
+  L.max_block = maxs;
+  L.sweep_mode = sweep_mode_for(L.n, L.nnz, ns, I.ncolors, maxs);
+  // lanes per row from the row length; a chunk (wg / lpr rows) must hold a
+  // whole block
   int lpr = L.lpr_A;
   int wg = 256;
-  while (wg / lpr < std::max(maxs, 1) && wg < 1024) wg *= 2;
-  while (wg / lpr < std::max(maxs, 1) && lpr > 4) lpr /= 2;
-  if (wg > 256 && lpr < 16) {   // wide workgroups only pay off with wide rows
-    wg = 256;
-    while (256 / lpr < std::max(maxs, 1)) lpr /= 2;
+  if (L.sweep_mode == SWEEP_PIPE) {
+    // one chunk per 1024-thread workgroup; rows of about 8-16 entries per lane
+    const double avg_row = L.n > 0 ? (double)L.nnz / (double)L.n : 0.0;
+    wg = 1024;
+    lpr = 8;
+    while (lpr < 256 && avg_row > 16.0 * lpr && 1024 / (2 * lpr) >= std::max(maxs, 1)) lpr *= 2;
+    while (1024 / lpr < std::max(maxs, 1)) lpr /= 2;
+  } else {
+    while (wg / lpr < std::max(maxs, 1) && wg < 1024) wg *= 2;
+    while (wg / lpr < std::max(maxs, 1) && lpr > 4) lpr /= 2;
+    if (wg > 256 && lpr < 16) {   // wide workgroups only pay off with wide rows
+      wg = 256;
+      while (256 / lpr < std::max(maxs, 1)) lpr /= 2;
+    }
   }
+  if (!schwarz_shape_ok(lpr, wg) || wg / lpr < std::max(maxs, 1))
+    fail(AMG_ERR_LIMIT, "no smoother launch shape for this level");
   L.lpr_S = lpr;
   L.wg_S = wg;
   const int rpb = wg / lpr;
@@ -340,37 +411,71 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
     sb_ptr[t + 1] = sb_ptr[t] + s;
     fac_off[t + 1] = fac_off[t] + s * (s + 1) / 2;
   }
+  if (sb_ptr[ns] > INT32_MAX) fail(AMG_ERR_LIMIT, "more than 2^31 smoother rows on one level");
   // chunks: consecutive blocks of one colour with at most rpb rows
-  std::vector<int32_t> chunk_blk;
+  std::vector<int32_t> chunk_blk, chunk_colour;
   L.colour_chunk.assign(I.ncolors + 1, 0);
+  bool every_colour = true;
   int64_t t = 0;
   for (int c = 0; c < I.ncolors; ++c) {
     L.colour_chunk[c] = (int)chunk_blk.size();
     while (t < ns && I.star_color[order[t]] == c) {
       chunk_blk.push_back((int32_t)t);
+      chunk_colour.push_back(c);
       int64_t rows = 0;
       while (t < ns && I.star_color[order[t]] == c && rows + (sb_ptr[t + 1] - sb_ptr[t]) <= rpb) {
         rows += sb_ptr[t + 1] - sb_ptr[t];
         ++t;
       }
     }
+    every_colour = every_colour && (int)chunk_blk.size() > L.colour_chunk[c];
   }
   L.colour_chunk[I.ncolors] = (int)chunk_blk.size();
   chunk_blk.push_back((int32_t)ns);
+  const int nchunks = L.colour_chunk[I.ncolors];
+  // the pipelined sweep waits on the colour before in sweep order, so every
+  // colour must hold a chunk (greedy colourings use every colour they count)
+  if (L.sweep_mode == SWEEP_PIPE && !every_colour) L.sweep_mode = SWEEP_COLOUR;
+  // per-chunk first row and first factor entry, so that a chunk finds its
+  // rows and factors with one lookup
+  std::vector<int32_t> ck_row0(chunk_blk.size());
+  std::vector<int64_t> ck_fac0(chunk_blk.size());
+  for (size_t c = 0; c < chunk_blk.size(); ++c) {
+    ck_row0[c] = (int32_t)sb_ptr[chunk_blk[c]];
+    ck_fac0[c] = fac_off[chunk_blk[c]];
+  }
+  L.ck_row0 = h->pool.upload(ck_row0, st);
+  L.ck_fac0 = h->pool.upload(ck_fac0, st);
+  L.chunk_colour = h->pool.upload(chunk_colour.empty() ? std::vector<int32_t>{0} : chunk_colour, st);
+  // the smoother's copy of A's rows in star order (pattern here, values at
+  // every numeric setup)
+  {
+    const int64_t nr = sb_ptr[ns];
+    std::vector<int64_t> srow_ptr(nr + 1, 0);
+    for (int64_t r = 0; r < nr; ++r) {
+      const int32_t d = sb_dofs[r];
+      srow_ptr[r + 1] = srow_ptr[r] + (L.Apat.ptr[d + 1] - L.Apat.ptr[d]);
+    }
+    std::vector<int32_t> scol(std::max<int64_t>(srow_ptr[nr], 1));
+    parallel_for(nr, [&](int64_t rb, int64_t re) {
+      for (int64_t r = rb; r < re; ++r) {
+        const int32_t d = sb_dofs[r];
+        std::copy(L.Apat.idx.begin() + L.Apat.ptr[d], L.Apat.idx.begin() + L.Apat.ptr[d + 1],
+                  scol.begin() + srow_ptr[r]);
+      }
+    });
+    L.srow_nnz = srow_ptr[nr];
+    L.srow_ptr = h->pool.upload(srow_ptr, st);
+    L.scol = h->pool.upload(scol, st);
+    L.sval = h->pool.get<double>(std::max<int64_t>(L.srow_nnz, 1));
+  }
   L.chunk_blk = h->pool.upload(chunk_blk, st);
   L.colour_chunk_dev = h->pool.upload(std::vector<int32_t>(L.colour_chunk.begin(), L.colour_chunk.end()), st);
-  // launch shape of a sweep: tiny levels in one workgroup, the rest one
-  // launch per colour
-  L.one_launch = L.nnz <= 200000 && wg == 256;
-  // nearly sequential level (at most 1.5 blocks per colour: the bottom of the
-  // hierarchy, where the Galerkin operators are dense or nearly so): swept
-  // block by block in one workgroup with the residual updated, from a dense
-  // copy of A (HCURL_AMG_DENSE_SWEEP=0 turns this off)
-  L.max_block = maxs;
-  const char* dense_env = std::getenv("HCURL_AMG_DENSE_SWEEP");
-  L.dense_S = !(dense_env && dense_env[0] == '0') && 2 * ns <= 3 * (int64_t)I.ncolors &&
-              dense_sweep_ok<double>((int)L.n, maxs);
-  if (L.dense_S) L.Acm = h->pool.get<double>((size_t)L.n * L.n);
+  L.sweep_sync = h->pool.get<int32_t>((size_t)I.ncolors + 1);
+  int grid = h->cu_count;
+  if (const char* e = std::getenv("HCURL_AMG_PIPE_GRID")) grid = std::max(1, std::atoi(e));
+  L.pipe_grid = std::max(1, std::min(nchunks, grid));
+  if (L.sweep_mode == SWEEP_DENSE) L.Acm = h->pool.get<double>((size_t)L.n * L.n);
   L.sb_ptr = h->pool.upload(sb_ptr, st);
   L.sb_dofs = h->pool.upload(sb_dofs, st);
   L.fac_off = h->pool.upload(fac_off, st);
@@ -380,7 +485,8 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
 }
 
 void factor_smoother(amg_hier* h, Level& L, int level, hipStream_t st) {
-  if (L.dense_S) csr_to_dense_cm(L.n, L.A_ptr, L.A_col, L.A_val, L.Acm, st);
+  if (L.sweep_mode == SWEEP_DENSE) csr_to_dense_cm(L.n, L.A_ptr, L.A_col, L.A_val, L.Acm, st);
+  star_rows((int64_t)L.ints.star_dofs.size(), L.sb_dofs, L.A_ptr, L.A_val, L.srow_ptr, L.sval, st);
   star_chol(L.nstars, L.sb_ptr, L.sb_dofs, L.fac_off, L.A_dev<double>(), L.fac, h->d_flag, st);
   check_flag(h, st, AMG_ERR_NOT_SPD, "smoother block Cholesky: non-positive pivot on level " +
                                          std::to_string(level));
@@ -591,12 +697,14 @@ void cast_level(amg_hier* h, Level& L, hipStream_t st) {
     L.PT_val32 = h->pool.get<float>(L.p_nnz);
     L.fac32 = h->pool.get<float>(L.fac_total);
     L.dinv32 = h->pool.get<float>(L.n);
+    L.sval32 = h->pool.get<float>(std::max<int64_t>(L.srow_nnz, 1));
   }
+  cast<double, float>(L.srow_nnz, L.sval, L.sval32, st);
   cast<double, float>(L.p_nnz, L.P_val, L.P_val32, st);
   cast<double, float>(L.p_nnz, L.PT_val, L.PT_val32, st);
   cast<double, float>(L.fac_total, L.fac, L.fac32, st);
   cast<double, float>(L.n, L.dinv, L.dinv32, st);
-  if (L.dense_S) {
+  if (L.sweep_mode == SWEEP_DENSE) {
     if (!L.Acm32) L.Acm32 = h->pool.get<float>((size_t)L.n * L.n);
     cast<double, float>(L.n * L.n, L.Acm, L.Acm32, st);
   }
@@ -766,7 +874,7 @@ void vcycle_T(amg_hier* h, const T* b0, T* x0, hipStream_t st) {
   for (size_t l = 0; l + 1 < nl; ++l) {
     Level& L = h->lv[l];
     CsrDev<T> A = L.A_dev<T>();
-    SmootherDev<T> S = L.S_dev<T>();
+    SmootherDev<T> S = L.S_dev<T>(h->d_sweep_err, h->spin_max);
     T* x = X(l);
     fill<T>(L.n, (T)0, x, st);
     schwarz_sweep<T>(S, A, 0, B(l), x, st);
@@ -780,7 +888,7 @@ void vcycle_T(amg_hier* h, const T* b0, T* x0, hipStream_t st) {
   for (size_t l = nl - 1; l-- > 0;) {
     Level& L = h->lv[l];
     CsrDev<T> A = L.A_dev<T>();
-    SmootherDev<T> S = L.S_dev<T>();
+    SmootherDev<T> S = L.S_dev<T>(h->d_sweep_err, h->spin_max);
     spmv_add<T>(L.P_dev<T>(), X(l + 1), Vec<T>::t(L), st);
     T* x = X(l);
     jacobi<T>(A, Vec<T>::t(L), B(l), Vec<T>::dinv(L), x, st);
@@ -999,6 +1107,15 @@ amg_status amg_setup(const amg_csr* A, const amg_csr* G, const amg_options* opt,
     h->prec = o.vcycle_prec;
     h->d_flag = h->pool.get<int>(1);
     HIPC(hipMemsetAsync(h->d_flag, 0, sizeof(int), st));
+    h->d_sweep_err = h->pool.get<int>(1);
+    HIPC(hipMemsetAsync(h->d_sweep_err, 0, sizeof(int), st));
+    {
+      int dev = 0, cus = 0;
+      HIPC(hipGetDevice(&dev));
+      HIPC(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+      if (cus > 0) h->cu_count = cus;
+      if (const char* e = std::getenv("HCURL_AMG_SPIN_MAX")) h->spin_max = std::max(1, std::atoi(e));
+    }
     HIPC(hipHostMalloc((void**)&h->h_sc, SC_COUNT * sizeof(double), hipHostMallocDefault));
     PhaseClock clk;
     Level0Host l0;
@@ -1186,6 +1303,7 @@ amg_status amg_pcg_solve(amg_hier* h, const double* f, double* u, double rtol, i
     }
     HIPC(hipStreamSynchronize(st));
     auto t1 = std::chrono::steady_clock::now();
+    check_sweep_err(h, st);
     if (stats) {
       stats->iterations = it;
       stats->relres = r0 > 0 ? nr / r0 : 0.0;
@@ -1212,9 +1330,19 @@ amg_status amg_smoother_sweep(amg_hier* h, int level, int prec, const void* b, v
     hipStream_t st = (hipStream_t)stream;
     auto run = [&](auto tag) {
       using T = decltype(tag);
-      schwarz_sweep<T>(L.S_dev<T>(), L.A_dev<T>(), backward, (const T*)b, (T*)x, st);
+      schwarz_sweep<T>(L.S_dev<T>(h->d_sweep_err, h->spin_max), L.A_dev<T>(), backward, (const T*)b,
+                       (T*)x, st);
     };
     if (prec == 64) run(double()); else run(float());
+    HIPC(hipGetLastError());
+    return AMG_OK;
+  });
+}
+
+amg_status amg_check(amg_hier* h, void* stream) {
+  return guarded([&]() -> amg_status {
+    if (!h) fail(AMG_ERR_ARG, "NULL handle");
+    check_sweep_err(h, (hipStream_t)stream);
     HIPC(hipGetLastError());
     return AMG_OK;
   });
@@ -1260,6 +1388,8 @@ amg_status amg_hier_info(const amg_hier* h, amg_level_info* lv, int cap, int* nl
       lv[l].star_rows = rows;
       lv[l].star_row_nnz = rnnz;
       lv[l].fac_entries = L.coarsest ? 0 : L.fac_total;
+      lv[l].sweep_form = L.coarsest ? 0 : L.sweep_mode;
+      lv[l].sweep_lanes = (L.coarsest || L.sweep_mode == SWEEP_DENSE) ? 0 : L.lpr_S;
     }
     return AMG_OK;
   });

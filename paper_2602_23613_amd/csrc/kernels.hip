@@ -6,7 +6,8 @@
 //                 prolongation add, dot-product partials)
 //   k_schwarz     one colour of the multiplicative Schwarz sweep over
 //                 node-star blocks (residual rows -> LDS, block Cholesky
-//                 solve, update)
+//                 solve, update); k_schwarz_pipe runs a whole sweep with
+//                 the colours pipelined across workgroups
 //   k_dense_solve coarsest-level FP64 Cholesky solve (one workgroup)
 //   PCG helpers   deterministic two-stage reductions and vector updates
 // Setup phase:
@@ -156,38 +157,168 @@ void spmv_dot(const CsrDev<double>& A, const double* x, double* y, double* parti
 }
 
 // ---------------------------------------------------------------------------
-// multiplicative Schwarz: one colour
+// multiplicative Schwarz over node-star blocks
 // ---------------------------------------------------------------------------
-// chunk c covers blocks [chunk_blk[c], chunk_blk[c+1]); their rows are
-// contiguous in sb_dofs and number at most 256/LPR.  Blocks of one colour
-// share no DoF and no coupling, so chunks update x independently.
-template <class T, int LPR, int WG>
-__global__ __launch_bounds__(WG) void k_schwarz(
-    const int32_t* __restrict__ chunk_blk, int chunk0, const int64_t* __restrict__ sb_ptr,
-    const int32_t* __restrict__ sb_dofs, const int64_t* __restrict__ fac_off,
-    const T* __restrict__ fac, const int64_t* __restrict__ Aptr, const int32_t* __restrict__ Acol,
-    const T* __restrict__ Aval, const T* __restrict__ b, T* __restrict__ x) {
-  constexpr int RPB = WG / LPR;
-  __shared__ T res[RPB];
-  const int c = chunk0 + blockIdx.x;
-  const int blk0 = chunk_blk[c], blk1 = chunk_blk[c + 1];
-  const int64_t r0 = sb_ptr[blk0];
-  const int nrows = (int)(sb_ptr[blk1] - r0);
-  const int grp = threadIdx.x / LPR, lane = threadIdx.x % LPR;
-  if (grp < nrows) {
-    const int32_t dof = sb_dofs[r0 + grp];
-    T s = row_dot<LPR, T>(Aptr[dof], Aptr[dof + 1], lane, Acol, Aval, x);
-    s = group_sum<LPR>(s);
-    if (lane == 0) res[grp] = b[dof] - s;
+// A chunk is a run of blocks of one colour with at most WGS / LPR rows in all.
+// The smoother keeps its own copy of A's rows in star order (srow_ptr, scol,
+// sval: star row r is row sb_dofs[r] of A), so a chunk streams one contiguous
+// range.  A group of WGS threads does one chunk in two phases:
+//   chunk_load    chunk bounds, row bounds, DoFs, packed factors and the first
+//                 U (column, value) pairs per lane of every row: everything
+//                 that does not depend on x;
+//   chunk_finish  b and x entries, row sums (lane sums in entry order, then a
+//                 shuffle tree), residuals in LDS, the block Cholesky solves
+//                 (one thread per block), x_B += d.
+// Blocks of one colour share no DoF and no coupling, so the chunks of a colour
+// update x independently and in any order.
+
+// LDS of one chunk: residuals of its rows, per-wave partial sums when a row
+// spans several wavefronts (LPR > 64), and the chunk's packed factors.  A
+// chunk holds at most RPB rows in blocks of at most min(RPB, 32) rows, so its
+// packed factors take at most RPB (min(RPB, 32) + 1) / 2 entries.
+template <class T, int LPR, int WGS>
+struct ChunkLds {
+  static constexpr int RPB = WGS / LPR;
+  static constexpr int WPR = LPR > 64 ? LPR / 64 : 1;
+  static constexpr int SMAX = RPB < 32 ? RPB : 32;
+  static constexpr int FL = RPB * (SMAX + 1) / 2;
+  T res[RPB];
+  T part[WPR > 1 ? RPB * WPR : 1];
+  T fl[FL];
+};
+
+// Per-thread state of a loaded chunk.
+template <class T, int LPR, int WGS, int U>
+struct ChunkRegs {
+  static constexpr int FPT = (ChunkLds<T, LPR, WGS>::FL + WGS - 1) / WGS;
+  int blk0, nblk, r0, nrows, nf;
+  int64_t f0, q0, q1, p0, p1, fo;
+  int32_t rdof, mydof;
+  T fv[FPT];
+  int32_t c[U];
+  T v[U];
+};
+
+template <class T, int LPR, int WGS, int U>
+__device__ __forceinline__ void chunk_load(bool act, int c, int tid, const SmootherArgs<T>& D,
+                                           ChunkRegs<T, LPR, WGS, U>& R) {
+  constexpr int FPT = ChunkRegs<T, LPR, WGS, U>::FPT;
+  R.blk0 = R.nblk = R.r0 = R.nrows = R.nf = 0;
+  R.f0 = 0;
+  if (act) {
+    R.blk0 = D.chunk_blk[c];
+    R.nblk = D.chunk_blk[c + 1] - R.blk0;
+    R.r0 = D.ck_row0[c];
+    R.nrows = D.ck_row0[c + 1] - R.r0;
+    R.f0 = D.ck_fac0[c];
+    R.nf = (int)(D.ck_fac0[c + 1] - R.f0);
+  }
+  const int grp = tid / LPR, lane = tid % LPR;
+  R.q0 = R.q1 = 0;
+  R.rdof = R.mydof = 0;
+  if (grp < R.nrows) {
+    const int64_t r = (int64_t)R.r0 + grp;
+    R.q0 = D.srow_ptr[r];
+    R.q1 = D.srow_ptr[r + 1];
+    if (lane == 0) R.rdof = D.sb_dofs[r];
+  }
+  if (tid < R.nrows) R.mydof = D.sb_dofs[R.r0 + tid];
+  R.p0 = R.p1 = R.fo = 0;
+  if (tid < R.nblk) {
+    R.p0 = D.sb_ptr[R.blk0 + tid];
+    R.p1 = D.sb_ptr[R.blk0 + tid + 1];
+    R.fo = D.fac_off[R.blk0 + tid];
+  }
+#pragma unroll
+  for (int k = 0; k < FPT; ++k) {
+    const int t = tid + k * WGS;
+    R.fv[k] = t < R.nf ? D.fac[R.f0 + t] : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t q = R.q0 + lane + (int64_t)u * LPR;
+    const bool in = q < R.q1;
+    R.c[u] = in ? D.scol[q] : -1;
+    R.v[u] = in ? D.sval[q] : T(0);
+  }
+}
+
+// Accesses of x.  COH: x is written by other workgroups while the kernel
+// runs (the pipelined sweep), so its loads and stores are agent-scope
+// relaxed atomics: coherent across the XCDs' L2 caches without cache-wide
+// write-back or invalidation.
+template <class T, bool COH>
+__device__ __forceinline__ T ld_x(const T* p) {
+  if constexpr (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return *p;
+}
+template <class T, bool COH>
+__device__ __forceinline__ void st_x(T* p, T v) {
+  if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else *p = v;
+}
+
+template <class T, int LPR, int WGS, int U, bool COH = false>
+__device__ __forceinline__ void chunk_finish(int tid, const ChunkRegs<T, LPR, WGS, U>& R,
+                                             ChunkLds<T, LPR, WGS>& S, const SmootherArgs<T>& D,
+                                             const T* b, T* x) {
+  constexpr int WPR = ChunkLds<T, LPR, WGS>::WPR;
+  constexpr int FPT = ChunkRegs<T, LPR, WGS, U>::FPT;
+  const int grp = tid / LPR, lane = tid % LPR;
+  const bool row_act = grp < R.nrows;
+  T bv = 0, myx = 0;
+  if (row_act && lane == 0) bv = b[R.rdof];
+  if (tid < R.nrows) myx = ld_x<T, COH>(x + R.mydof);   // only this chunk changes these in its colour
+  T s = 0;
+  if (row_act) {
+    T xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = R.c[u] >= 0 ? ld_x<T, COH>(x + R.c[u]) : T(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += R.v[u] * xv[u];
+    for (int64_t q0 = R.q0 + lane + (int64_t)U * LPR; q0 < R.q1; q0 += (int64_t)U * LPR) {
+      int32_t c[U];
+      T v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t q = q0 + (int64_t)u * LPR;
+        const bool in = q < R.q1;
+        c[u] = in ? D.scol[q] : -1;
+        v[u] = in ? D.sval[q] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) xv[u] = c[u] >= 0 ? ld_x<T, COH>(x + c[u]) : T(0);
+#pragma unroll
+      for (int u = 0; u < U; ++u) s += v[u] * xv[u];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < FPT; ++k) {
+    const int t = tid + k * WGS;
+    if (t < R.nf) S.fl[t] = R.fv[k];
+  }
+  if (row_act) {
+    if constexpr (LPR <= 64) {
+      s = group_sum<LPR>(s);
+      if (lane == 0) S.res[grp] = bv - s;
+    } else {
+      s = group_sum<64>(s);
+      if (lane % 64 == 0) S.part[grp * WPR + lane / 64] = s;
+      if (lane == 0) S.res[grp] = bv;
+    }
   }
   __syncthreads();
-  const int t = threadIdx.x;
-  if (t < blk1 - blk0) {
-    const int blk = blk0 + t;
-    const int off = (int)(sb_ptr[blk] - r0);
-    const int sz = (int)(sb_ptr[blk + 1] - sb_ptr[blk]);
-    const T* L = fac + fac_off[blk];
-    T* v = res + off;
+  if (tid < R.nblk) {
+    const int boff = (int)(R.p0 - R.r0), sz = (int)(R.p1 - R.p0);
+    const T* L = S.fl + (R.fo - R.f0);
+    T* v = S.res + boff;
+    if constexpr (WPR > 1) {
+      for (int i = 0; i < sz; ++i) {
+        T p = 0;
+        for (int w = 0; w < WPR; ++w) p += S.part[(boff + i) * WPR + w];
+        v[i] -= p;
+      }
+    }
     for (int i = 0; i < sz; ++i) {
       T a = v[i];
       const T* Li = L + i * (i + 1) / 2;
@@ -201,118 +332,188 @@ __global__ __launch_bounds__(WG) void k_schwarz(
     }
   }
   __syncthreads();
-  if (threadIdx.x < nrows) x[sb_dofs[r0 + threadIdx.x]] += res[threadIdx.x];
+  if (tid < R.nrows) st_x<T, COH>(x + R.mydof, myx + S.res[tid]);
 }
 
-// Whole sweep of a small level in one launch: a 1024-thread workgroup walks
-// the colours in order; its four 256-thread groups take chunks of the current
-// colour in turn.  __syncthreads after each round makes the x updates of one
-// colour visible before the next colour reads x.
-template <class T, int LPR>
-__global__ __launch_bounds__(1024) void k_schwarz_sweep1(
-    int ncolours, const int32_t* __restrict__ colour_chunk, int backward,
-    const int32_t* __restrict__ chunk_blk, const int64_t* __restrict__ sb_ptr,
-    const int32_t* __restrict__ sb_dofs, const int64_t* __restrict__ fac_off,
-    const T* __restrict__ fac, const int64_t* __restrict__ Aptr, const int32_t* __restrict__ Acol,
-    const T* __restrict__ Aval, const T* __restrict__ b, T* __restrict__ x) {
-  constexpr int RPB = 256 / LPR;
-  __shared__ T res_all[4][RPB];
-  const int sub = threadIdx.x / 256;
-  const int tid = threadIdx.x % 256;
-  T* res = res_all[sub];
-  const int grp = tid / LPR, lane = tid % LPR;
-  for (int ci = 0; ci < ncolours; ++ci) {
-    const int col = backward ? ncolours - 1 - ci : ci;
-    const int c0 = colour_chunk[col], c1 = colour_chunk[col + 1];
-    for (int base = c0; base < c1; base += 4) {
+template <int LPR>
+constexpr int unroll_for() { return LPR >= 64 ? 16 : 8; }
+
+// one colour: chunk chunk0 + blockIdx.x per workgroup
+template <class T, int LPR, int WG>
+__global__ __launch_bounds__(WG) void k_schwarz(SmootherArgs<T> D, int chunk0, const T* b, T* x) {
+  constexpr int U = unroll_for<LPR>();
+  __shared__ ChunkLds<T, LPR, WG> S;
+  ChunkRegs<T, LPR, WG, U> R;
+  chunk_load<T, LPR, WG, U>(true, chunk0 + blockIdx.x, threadIdx.x, D, R);
+  chunk_finish<T, LPR, WG, U>(threadIdx.x, R, S, D, b, x);
+}
+
+// Whole sweep of a small level in one workgroup: the 1024 threads walk the
+// colours in order, their 1024 / WGS groups taking the chunks of the current
+// colour in turn.  The barriers inside chunk_finish and the one after each
+// round make the x updates of a colour visible before the next colour reads x.
+template <class T, int LPR, int WGS>
+__global__ __launch_bounds__(1024) void k_schwarz_sweep1(SmootherArgs<T> D, int backward,
+                                                         const T* b, T* x) {
+  constexpr int U = unroll_for<LPR>();
+  constexpr int NSUB = 1024 / WGS;
+  __shared__ ChunkLds<T, LPR, WGS> S_all[NSUB];
+  const int sub = threadIdx.x / WGS;
+  const int tid = threadIdx.x % WGS;
+  for (int ci = 0; ci < D.ncolours; ++ci) {
+    const int colour = backward ? D.ncolours - 1 - ci : ci;
+    const int c0 = D.colour_chunk[colour], c1 = D.colour_chunk[colour + 1];
+    for (int base = c0; base < c1; base += NSUB) {
       const int c = base + sub;
-      const bool act = c < c1;
-      int blk0 = 0, blk1 = 0, nrows = 0;
-      int64_t r0 = 0;
-      if (act) {
-        blk0 = chunk_blk[c];
-        blk1 = chunk_blk[c + 1];
-        r0 = sb_ptr[blk0];
-        nrows = (int)(sb_ptr[blk1] - r0);
-      }
-      if (act && grp < nrows) {
-        const int32_t dof = sb_dofs[r0 + grp];
-        T s = row_dot<LPR, T>(Aptr[dof], Aptr[dof + 1], lane, Acol, Aval, x);
-        s = group_sum<LPR>(s);
-        if (lane == 0) res[grp] = b[dof] - s;
-      }
-      __syncthreads();
-      if (act && tid < blk1 - blk0) {
-        const int blk = blk0 + tid;
-        const int off = (int)(sb_ptr[blk] - r0);
-        const int sz = (int)(sb_ptr[blk + 1] - sb_ptr[blk]);
-        const T* L = fac + fac_off[blk];
-        T* v = res + off;
-        for (int i = 0; i < sz; ++i) {
-          T a = v[i];
-          const T* Li = L + i * (i + 1) / 2;
-          for (int j = 0; j < i; ++j) a -= Li[j] * v[j];
-          v[i] = a / Li[i];
-        }
-        for (int i = sz - 1; i >= 0; --i) {
-          T a = v[i];
-          for (int j = i + 1; j < sz; ++j) a -= L[j * (j + 1) / 2 + i] * v[j];
-          v[i] = a / L[i * (i + 1) / 2 + i];
-        }
-      }
-      __syncthreads();
-      if (act && tid < nrows) x[sb_dofs[r0 + tid]] += res[tid];
+      ChunkRegs<T, LPR, WGS, U> R;
+      chunk_load<T, LPR, WGS, U>(c < c1, c, tid, D, R);
+      chunk_finish<T, LPR, WGS, U>(tid, R, S_all[sub], D, b, x);
       __syncthreads();
     }
   }
 }
 
-template <class T>
-void schwarz_sweep_small(const SmootherDev<T>& S, const CsrDev<T>& A, int backward, const T* b,
-                         T* x, hipStream_t st) {
-#define LAUNCH_SW1(L)                                                                         \
-  hipLaunchKernelGGL((k_schwarz_sweep1<T, L>), dim3(1), dim3(1024), 0, st, S.ncolours,        \
-                     S.colour_chunk_dev, backward, S.chunk_blk, S.sb_ptr, S.sb_dofs, S.fac_off,  \
-                     S.fac, A.ptr, A.col, A.val, b, x);
-  switch (S.lpr) {
-    case 4: LAUNCH_SW1(4); break;
-    case 8: LAUNCH_SW1(8); break;
-    case 16: LAUNCH_SW1(16); break;
-    case 32: LAUNCH_SW1(32); break;
-    default: LAUNCH_SW1(64); break;
+// Whole sweep in one launch with the colours pipelined across workgroups.
+// Chunks are numbered in sweep order (colour by colour) and handed out by a
+// ticket counter, sync[0]; sync[1 + c] counts the finished chunks of colour c.
+// A workgroup loads its chunk's structure at once and starts the x-dependent
+// work when every chunk of the colour before it in sweep order has finished;
+// those chunks waited in turn for theirs, so every earlier colour is done and
+// the sweep computes what the colour-by-colour launches compute.
+// Progress: tickets are taken in increasing order and a workgroup finishes its
+// chunks in ticket order, so the unfinished chunk with the smallest ticket
+// only waits on finished chunks and always belongs to a running workgroup; no
+// assumption on how many workgroups are resident is needed.
+// Visibility: x is loaded and stored with agent-scope (all XCDs) coherent
+// accesses; a chunk's stores have completed (each storing thread waits for
+// its memory counter) before the workgroup barrier that precedes the raise
+// of its count, and a waiting chunk loads x only after the barrier that
+// follows its wait.  Every wait is bounded: after spin_max polls the wait
+// sets *err and gives up (the sweep result is then wrong and the caller
+// reports the error), and once *err is set no wait blocks, so the grid always
+// drains.  The caller zeroes sync before each sweep.
+template <class T, int LPR>
+__global__ __launch_bounds__(1024) void k_schwarz_pipe(SmootherArgs<T> D, int backward,
+                                                       const T* b, T* x) {
+  constexpr int U = unroll_for<LPR>();
+  __shared__ ChunkLds<T, LPR, 1024> S;
+  __shared__ int ticket[2];
+  int* sync = D.sync;
+  const int nchunks = D.colour_chunk[D.ncolours];
+  const int tid = threadIdx.x;
+  if (tid == 0) ticket[0] = __hip_atomic_fetch_add(&sync[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  int t = ticket[0];
+  while (t < nchunks) {
+    int next = 0;
+    if (tid == 0) next = __hip_atomic_fetch_add(&sync[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int c = backward ? nchunks - 1 - t : t;
+    const int colour = D.chunk_colour[c];
+    const int prev = backward ? colour + 1 : colour - 1;
+    ChunkRegs<T, LPR, 1024, U> R;
+    chunk_load<T, LPR, 1024, U>(true, c, tid, D, R);
+    if (tid == 0 && prev >= 0 && prev < D.ncolours) {
+      const int need = D.colour_chunk[prev + 1] - D.colour_chunk[prev];
+      int spins = 0;
+      while (__hip_atomic_load(&sync[1 + prev], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+        if ((++spins & 255) == 0 &&
+            __hip_atomic_load(D.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+          break;
+        if (spins > D.spin_max) {
+          __hip_atomic_store(D.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __syncthreads();
+    chunk_finish<T, LPR, 1024, U, true>(tid, R, S, D, b, x);
+    __builtin_amdgcn_s_waitcnt(0);   // this thread's x stores have completed
+    __syncthreads();
+    if (tid == 0) {
+      __hip_atomic_fetch_add(&sync[1 + colour], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ticket[1] = next;
+    }
+    __syncthreads();
+    t = ticket[1];
   }
+}
+
+// (lanes per row, threads per chunk) pairs of the colour and one-launch forms
+bool schwarz_shape_ok(int lpr, int wg) {
+  if (wg == 256) return lpr == 4 || lpr == 8 || lpr == 16 || lpr == 32 || lpr == 64;
+  if (wg == 512) return lpr == 16 || lpr == 32 || lpr == 64 || lpr == 128;
+  if (wg == 1024) return lpr == 8 || lpr == 16 || lpr == 32 || lpr == 64 || lpr == 128 || lpr == 256;
+  return false;
+}
+
+#define SCHWARZ_SHAPES(X)                                                                        \
+  X(4, 256) X(8, 256) X(16, 256) X(32, 256) X(64, 256) X(16, 512) X(32, 512) X(64, 512)         \
+  X(128, 512) X(8, 1024) X(16, 1024) X(32, 1024) X(64, 1024) X(128, 1024) X(256, 1024)
+
+template <class T>
+void schwarz_sweep_small(const SmootherDev<T>& S, int backward, const T* b, T* x, hipStream_t st) {
+  const SmootherArgs<T> D = S;
+#define LAUNCH_SW1(L, W)                                                                         \
+  if (S.lpr == L && S.wg == W) {                                                                 \
+    hipLaunchKernelGGL((k_schwarz_sweep1<T, L, W>), dim3(1), dim3(1024), 0, st, D, backward, b,   \
+                       x);                                                                       \
+    return;                                                                                      \
+  }
+  SCHWARZ_SHAPES(LAUNCH_SW1)
 #undef LAUNCH_SW1
 }
 
 template <class T>
-void schwarz_colour(const SmootherDev<T>& S, const CsrDev<T>& A, int colour, const T* b, T* x,
-                    hipStream_t st) {
-  int c0 = S.colour_chunk[colour], c1 = S.colour_chunk[colour + 1];
+void schwarz_colour(const SmootherDev<T>& S, int colour, const T* b, T* x, hipStream_t st) {
+  int c0 = S.colour_chunk_h[colour], c1 = S.colour_chunk_h[colour + 1];
   if (c1 <= c0) return;
-#define LAUNCH_SW(L, W)                                                                        \
-  hipLaunchKernelGGL((k_schwarz<T, L, W>), dim3(c1 - c0), dim3(W), 0, st, S.chunk_blk, c0,      \
-                     S.sb_ptr, S.sb_dofs, S.fac_off, S.fac, A.ptr, A.col, A.val, b, x);
-  if (S.wg == 1024) {
-    switch (S.lpr) {
-      case 32: LAUNCH_SW(32, 1024); break;
-      default: LAUNCH_SW(64, 1024); break;
-    }
-  } else if (S.wg == 512) {
-    switch (S.lpr) {
-      case 16: LAUNCH_SW(16, 512); break;
-      case 32: LAUNCH_SW(32, 512); break;
-      default: LAUNCH_SW(64, 512); break;
-    }
-  } else {
-    switch (S.lpr) {
-      case 4: LAUNCH_SW(4, 256); break;
-      case 8: LAUNCH_SW(8, 256); break;
-      case 16: LAUNCH_SW(16, 256); break;
-      case 32: LAUNCH_SW(32, 256); break;
-      default: LAUNCH_SW(64, 256); break;
-    }
+  const SmootherArgs<T> D = S;
+#define LAUNCH_SW(L, W)                                                                          \
+  if (S.lpr == L && S.wg == W) {                                                                 \
+    hipLaunchKernelGGL((k_schwarz<T, L, W>), dim3(c1 - c0), dim3(W), 0, st, D, c0, b, x);         \
+    return;                                                                                      \
   }
+  SCHWARZ_SHAPES(LAUNCH_SW)
 #undef LAUNCH_SW
+}
+
+__global__ void k_zero_i32(int n, int* __restrict__ p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+template <class T>
+void schwarz_pipe(const SmootherDev<T>& S, int backward, const T* b, T* x, hipStream_t st) {
+  const int nsync = S.ncolours + 1;
+  hipLaunchKernelGGL(k_zero_i32, dim3((nsync + 255) / 256), dim3(256), 0, st, nsync, S.sync);
+  const SmootherArgs<T> D = S;
+#define LAUNCH_PIPE(L)                                                                           \
+  if (S.lpr == L) {                                                                              \
+    hipLaunchKernelGGL((k_schwarz_pipe<T, L>), dim3(S.pipe_grid), dim3(1024), 0, st, D, backward, \
+                       b, x);                                                                    \
+    return;                                                                                      \
+  }
+  LAUNCH_PIPE(8) LAUNCH_PIPE(16) LAUNCH_PIPE(32) LAUNCH_PIPE(64) LAUNCH_PIPE(128) LAUNCH_PIPE(256)
+#undef LAUNCH_PIPE
+}
+
+// values of the smoother's row copy: star row r is row sb_dofs[r] of A
+__global__ void k_star_rows(int64_t nrows, const int32_t* __restrict__ sb_dofs,
+                            const int64_t* __restrict__ Aptr, const double* __restrict__ Aval,
+                            const int64_t* __restrict__ srow_ptr, double* __restrict__ sval) {
+  const int64_t r = (int64_t)blockIdx.x * 8 + threadIdx.x / 32;
+  const int lane = threadIdx.x % 32;
+  if (r >= nrows) return;
+  const int64_t a0 = Aptr[sb_dofs[r]];
+  const int64_t s0 = srow_ptr[r], len = srow_ptr[r + 1] - s0;
+  for (int64_t q = lane; q < len; q += 32) sval[s0 + q] = Aval[a0 + q];
+}
+void star_rows(int64_t nrows, const int32_t* sb_dofs, const int64_t* Aptr, const double* Aval,
+               const int64_t* srow_ptr, double* sval, hipStream_t st) {
+  if (nrows > 0)
+    hipLaunchKernelGGL(k_star_rows, dim3((unsigned)((nrows + 7) / 8)), dim3(256), 0, st, nrows,
+                       sb_dofs, Aptr, Aval, srow_ptr, sval);
 }
 
 // ---------------------------------------------------------------------------
@@ -1383,10 +1584,12 @@ template void jacobi<double>(const CsrDev<double>&, const double*, const double*
 template void jacobi<float>(const CsrDev<float>&, const float*, const float*, const float*, float*, hipStream_t);
 template void spmv_add<double>(const CsrDev<double>&, const double*, double*, hipStream_t);
 template void spmv_add<float>(const CsrDev<float>&, const float*, float*, hipStream_t);
-template void schwarz_colour<double>(const SmootherDev<double>&, const CsrDev<double>&, int, const double*, double*, hipStream_t);
-template void schwarz_colour<float>(const SmootherDev<float>&, const CsrDev<float>&, int, const float*, float*, hipStream_t);
-template void schwarz_sweep_small<double>(const SmootherDev<double>&, const CsrDev<double>&, int, const double*, double*, hipStream_t);
-template void schwarz_sweep_small<float>(const SmootherDev<float>&, const CsrDev<float>&, int, const float*, float*, hipStream_t);
+template void schwarz_colour<double>(const SmootherDev<double>&, int, const double*, double*, hipStream_t);
+template void schwarz_colour<float>(const SmootherDev<float>&, int, const float*, float*, hipStream_t);
+template void schwarz_sweep_small<double>(const SmootherDev<double>&, int, const double*, double*, hipStream_t);
+template void schwarz_sweep_small<float>(const SmootherDev<float>&, int, const float*, float*, hipStream_t);
+template void schwarz_pipe<double>(const SmootherDev<double>&, int, const double*, double*, hipStream_t);
+template void schwarz_pipe<float>(const SmootherDev<float>&, int, const float*, float*, hipStream_t);
 template bool dense_sweep_ok<double>(int, int);
 template bool dense_sweep_ok<float>(int, int);
 template void dense_sweep<double>(int, int, int, int, const int64_t*, const int32_t*, const int64_t*,

@@ -24,23 +24,39 @@ struct CsrPat {
   const int32_t* col = nullptr;
 };
 
-// Smoother blocks sorted by colour and packed into chunks for k_schwarz.
+// Smoother blocks sorted by colour and packed into chunks: the device side (a
+// plain struct, passed to the kernels by value) ...
 template <class T>
-struct SmootherDev {
+struct SmootherArgs {
   int ncolours = 0;
-  std::vector<int> colour_chunk;        // host: chunk range of each colour
-  const int32_t* colour_chunk_dev = nullptr;   // the same on the device
-  bool one_launch = false;              // tiny level: whole sweep in one workgroup
-  int wg = 256;                         // workgroup size of k_schwarz (rows per chunk = wg / lpr)
-  const int32_t* chunk_blk = nullptr;   // first block of each chunk (+ sentinel)
-  const int64_t* sb_ptr = nullptr;      // rows of each block (colour order)
+  const int32_t* colour_chunk = nullptr;  // chunk range of each colour (+ sentinel)
+  const int32_t* chunk_colour = nullptr;  // colour of each chunk
+  const int32_t* chunk_blk = nullptr;     // first block of each chunk (+ sentinel)
+  const int64_t* sb_ptr = nullptr;        // rows of each block (colour order)
   const int32_t* sb_dofs = nullptr;
-  const int64_t* fac_off = nullptr;     // packed lower factor offset of each block
+  const int64_t* fac_off = nullptr;       // packed lower factor offset of each block
   const T* fac = nullptr;
+  const int32_t* ck_row0 = nullptr;       // first star row of each chunk (+ sentinel)
+  const int64_t* ck_fac0 = nullptr;       // first factor entry of each chunk (+ sentinel)
+  const int64_t* srow_ptr = nullptr;      // the smoother's copy of A's rows in star order
+  const int32_t* scol = nullptr;
+  const T* sval = nullptr;
+  int* sync = nullptr;                    // pipelined sweep: ticket + per-colour counters
+  int* err = nullptr;                     // pipelined sweep: set when a wait gave up
+  int spin_max = 0;
+};
+
+// ... and the host side: launch shape and the dense-level form.
+enum { SWEEP_COLOUR = 0, SWEEP_ONE = 1, SWEEP_PIPE = 2, SWEEP_DENSE = 3 };
+template <class T>
+struct SmootherDev : SmootherArgs<T> {
+  std::vector<int> colour_chunk_h;      // host copy of colour_chunk
+  int mode = SWEEP_COLOUR;
+  int wg = 256;                         // threads per chunk (rows per chunk = wg / lpr)
   int lpr = 8;
+  int pipe_grid = 0;                    // workgroups of the pipelined sweep
   // dense level (nnz = n^2, one block per colour): the sweep keeps r and x in
   // LDS and updates r from a column-major dense copy of A
-  bool dense = false;
   int n = 0;
   int nblocks = 0;
   int max_block = 0;
@@ -60,12 +76,15 @@ template <class T> void spmv_add(const CsrDev<T>& A, const T* x, T* y, hipStream
 void spmv_dot(const CsrDev<double>& A, const double* x, double* y, double* partial, hipStream_t st);
 int64_t spmv_dot_partials(int lpr, int64_t n);
 
+bool schwarz_shape_ok(int lpr, int wg);
 template <class T>
-void schwarz_colour(const SmootherDev<T>& S, const CsrDev<T>& A, int colour, const T* b, T* x,
-                    hipStream_t st);
+void schwarz_colour(const SmootherDev<T>& S, int colour, const T* b, T* x, hipStream_t st);
 template <class T>
-void schwarz_sweep_small(const SmootherDev<T>& S, const CsrDev<T>& A, int backward, const T* b,
-                         T* x, hipStream_t st);
+void schwarz_sweep_small(const SmootherDev<T>& S, int backward, const T* b, T* x, hipStream_t st);
+template <class T>
+void schwarz_pipe(const SmootherDev<T>& S, int backward, const T* b, T* x, hipStream_t st);
+void star_rows(int64_t nrows, const int32_t* sb_dofs, const int64_t* Aptr, const double* Aval,
+               const int64_t* srow_ptr, double* sval, hipStream_t st);
 
 template <class T> bool dense_sweep_ok(int n, int max_block);
 template <class T>
@@ -79,18 +98,22 @@ void csr_to_dense_cm(int64_t n, const int64_t* ptr, const int32_t* col, const do
 template <class T>
 void schwarz_sweep(const SmootherDev<T>& S, const CsrDev<T>& A, int backward, const T* b, T* x,
                    hipStream_t st) {
-  if (S.dense) {
-    residual<T>(A, x, b, S.rtmp, st);
-    dense_sweep<T>(S.n, S.nblocks, S.max_block, backward, S.sb_ptr, S.sb_dofs, S.fac_off, S.fac,
-                   S.Acm, S.rtmp, x, st);
-    return;
+  switch (S.mode) {
+    case SWEEP_DENSE:
+      residual<T>(A, x, b, S.rtmp, st);
+      dense_sweep<T>(S.n, S.nblocks, S.max_block, backward, S.sb_ptr, S.sb_dofs, S.fac_off, S.fac,
+                     S.Acm, S.rtmp, x, st);
+      return;
+    case SWEEP_ONE:
+      schwarz_sweep_small<T>(S, backward, b, x, st);
+      return;
+    case SWEEP_PIPE:
+      schwarz_pipe<T>(S, backward, b, x, st);
+      return;
+    default:
+      for (int k = 0; k < S.ncolours; ++k)
+        schwarz_colour<T>(S, backward ? S.ncolours - 1 - k : k, b, x, st);
   }
-  if (S.one_launch) {
-    schwarz_sweep_small<T>(S, A, backward, b, x, st);
-    return;
-  }
-  for (int k = 0; k < S.ncolours; ++k)
-    schwarz_colour<T>(S, A, backward ? S.ncolours - 1 - k : k, b, x, st);
 }
 template <class T>
 void dense_solve(int n, const double* L, const T* b, T* x, double* work, hipStream_t st);

@@ -399,37 +399,73 @@ def _with_env(env, fn):
                 os.environ[k] = v
 
 
-@pytest.mark.skip(reason="the two-wavefront-row / generalised one-launch smoother variant it covers "
-                         "is switched off: a 64^3 PCG run with it ended in a GPU memory fault whose "
-                         "cause is not yet shown")
-def test_sweep_launch_shapes_agree():
-    """The 16^3 jump case has a dense level (1176 rows of 1176 entries), which
-    takes the two-wavefront rows and the one-launch sweep.  Forcing one launch
-    per colour runs the same chunks with the same per-row summation order, so
-    the V-cycle must not change by a bit; narrower rows (one wavefront) only
-    change the rounding, and stay within the oracle tolerance."""
+@pytest.mark.parametrize("which", ["hex16_jump_b1e-3", "hex32"])
+def test_sweep_forms_agree(which):
+    """Every level swept by each form (one launch per colour, one workgroup,
+    colours pipelined in one launch) against the oracle's colour sweep: one
+    forward, backward, forward sweep from the same b.  The forms differ only
+    in lanes per row (so in rounding), not in the order of the colours."""
     d = dev()
-    p, Ho = case("hex16_jump_b1e-3")
-    rng = np.random.default_rng(21)
-    r = torch.tensor(rng.standard_normal(p.A.shape[0]), device=d)
-    out = {}
-    for name, env in [("default", {}), ("per_colour", {"HCURL_AMG_ONE_LAUNCH": "0"}),
-                      ("one_launch", {"HCURL_AMG_ONE_LAUNCH": "1"}),
-                      ("narrow", {"HCURL_AMG_WIDE_ROWS": "0"})]:
-        H = _with_env(env, lambda: amglib.Hierarchy(p.A, p.G))
-        z = torch.zeros_like(r)
-        H.vcycle(r, z)
-        torch.cuda.synchronize()
-        out[name] = z.cpu().numpy()
-        H.close()
-    assert np.array_equal(out["default"], out["per_colour"])
-    assert np.array_equal(out["default"], out["one_launch"])
-    zo = oracle.vcycle(Ho, r.cpu().numpy())
+    if which == "hex32":
+        p, Ho = _hex32_case()
+    else:
+        p, Ho = case(which)
+    mats = amg._cast(Ho, np.float64)
     tol = max(1e-10, 16 * kappas(Ho)[1] * EPS)
-    for name in ("default", "narrow"):
-        err = np.linalg.norm(out[name] - zo) / np.linalg.norm(zo)
-        print(f"{name}: V-cycle rel err vs oracle {err:.2e} (tol {tol:.1e})")
-        assert err <= tol
+    rng = np.random.default_rng(33)
+    forms = {}
+    for form in ("colour", "one", "pipe"):
+        H = _with_env({"HCURL_AMG_SWEEP": form, "HCURL_AMG_DENSE_SWEEP": "0"},
+                      lambda: amglib.Hierarchy(p.A, p.G))
+        info = H.info()
+        assert all(lv["sweep_form"] == form for lv in info[:-1]), [lv["sweep_form"] for lv in info]
+        xs = []
+        for lvl in range(len(info) - 1):
+            n = info[lvl]["n"]
+            b = rng.standard_normal(n) if form == "colour" else forms["colour"][lvl][0]
+            bt = torch.tensor(b, device=d)
+            xt = torch.zeros_like(bt)
+            for bw in (False, True, False):
+                H.sweep(lvl, bt, xt, backward=bw)
+            H.check()
+            xs.append((b, xt.cpu().numpy()))
+        forms[form] = xs
+        H.close()
+    for lvl, (b, _) in enumerate(forms["colour"]):
+        nc = Ho.levels[lvl].smoother.ncolors
+        xo = np.zeros_like(b)
+        for order in (range(nc), range(nc - 1, -1, -1), range(nc)):
+            xo = amg._schwarz(mats[lvl], xo, b, list(order))
+        for form, xs in forms.items():
+            err = np.linalg.norm(xs[lvl][1] - xo) / np.linalg.norm(xo)
+            print(f"{which} level {lvl} ({nc} colours) {form}: rel err vs oracle {err:.2e} (tol {tol:.1e})")
+            assert err <= tol, (lvl, form)
+
+
+def test_pipelined_sweep_reports_a_wait_that_gives_up():
+    """The pipelined sweep bounds every wait for the previous colour.  With a
+    limit of one poll (set from the host) the waits give up: the kernel still
+    ends, the handle's flag is raised and amg_check reports it; a handle with
+    the normal limit on the same problem reports nothing."""
+    d = dev()
+    p, _ = case("hex16_jump_b1e-3")
+    env = {"HCURL_AMG_SWEEP": "pipe", "HCURL_AMG_DENSE_SWEEP": "0"}
+    H = _with_env(dict(env, HCURL_AMG_SPIN_MAX="1"), lambda: amglib.Hierarchy(p.A, p.G))
+    lvl = max(range(len(H.info()) - 1), key=lambda l: H.info()[l]["ncolors"])
+    n = H.info()[lvl]["n"]
+    b = torch.ones(n, dtype=torch.float64, device=d)
+    x = torch.zeros_like(b)
+    for _ in range(3):
+        H.sweep(lvl, b, x)
+    with pytest.raises(amglib.AmgError):
+        H.check()
+    H.close()
+    H = _with_env(env, lambda: amglib.Hierarchy(p.A, p.G))
+    x.zero_()
+    for _ in range(3):
+        H.sweep(lvl, b, x)
+    H.check()
+    H.close()
 
 
 _hex32 = {}
