@@ -112,8 +112,9 @@ typedef struct {
   int64_t star_row_nnz;    /* stored entries of A_l in those rows (with repetition) */
   int64_t fac_entries;     /* packed lower-triangular factor entries of all blocks */
   int sweep_form;          /* how a sweep runs: 0 one launch per colour, 1 one workgroup,
-                              2 colours pipelined in one launch, 3 dense residual-update form */
-  int sweep_lanes;         /* lanes per row of the row forms (0 for the dense form) */
+                              2 colours pipelined in one launch, 3 dense residual-update form
+                              in one workgroup, 4 panel residual-update form (wide levels) */
+  int sweep_lanes;         /* lanes per row of the row forms (0 for the dense and panel forms) */
 } amg_level_info;
 
 /* Integer results of one level's setup, for bit-exact comparison.  All

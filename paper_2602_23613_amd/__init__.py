@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import AmgError, load  # noqa: F401
 
 # amg_level_info.sweep_form values
-SWEEP_FORMS = {0: "colour", 1: "one", 2: "pipe", 3: "dense"}
+SWEEP_FORMS = {0: "colour", 1: "one", 2: "pipe", 3: "dense", 4: "panel"}
 
 __all__ = ["Hierarchy", "level0_integers", "spmv", "mlp_loss_grad", "load", "AmgError"]
 

@@ -163,12 +163,29 @@ struct Level {
   int64_t fac_total = 0;
   double* fac = nullptr;
   float* fac32 = nullptr;
+  double* binv = nullptr;        // symmetric block inverses, packed like fac
+  float* binv32 = nullptr;
+  int32_t* row_blk = nullptr;    // block of each star row
   double* dinv = nullptr;
   float* dinv32 = nullptr;
   int lpr_S = 8;
   int max_block = 0;
-  double* Acm = nullptr;         // column-major dense A (dense levels only)
+  double* Acm = nullptr;         // column-major dense A (dense and panel forms)
   float* Acm32 = nullptr;
+  int ngroups = 0;               // panel form: groups of consecutive blocks
+  int32_t* grp_blk = nullptr;
+  int32_t* dgrp = nullptr;
+  int32_t* sdup = nullptr;
+  double* dsl = nullptr;
+  float* dsl32 = nullptr;
+  int64_t* slc_off = nullptr;    // panel form: per-group slices and inter-group blocks of A
+  int64_t* cor_off = nullptr;
+  int64_t slc_total = 0, cor_total = 0;
+  double* slc = nullptr;
+  double* cor = nullptr;
+  float* slc32 = nullptr;
+  float* cor32 = nullptr;
+  int* psync = nullptr;
   // device: cycle vectors
   double *x = nullptr, *t = nullptr, *b = nullptr, *r = nullptr;
   float *x32 = nullptr, *t32 = nullptr, *b32 = nullptr, *r32 = nullptr;
@@ -205,14 +222,24 @@ struct Level {
     s.ck_row0 = ck_row0; s.ck_fac0 = ck_fac0; s.srow_ptr = srow_ptr; s.scol = scol;
     if constexpr (std::is_same<T, double>::value) {
       s.fac = fac;
+      s.binv = binv;
       s.sval = sval;
     } else {
       s.fac = fac32;
+      s.binv = binv32;
       s.sval = sval32;
     }
+    s.row_blk = row_blk;
     s.sync = sweep_sync; s.err = err; s.spin_max = spin_max;
     s.mode = sweep_mode; s.wg = wg_S; s.lpr = lpr_S; s.pipe_grid = pipe_grid;
     s.n = (int)n;
+    s.ngroups = ngroups; s.grp_blk = grp_blk; s.dgrp = dgrp; s.sdup = sdup; s.psync = psync;
+    if constexpr (std::is_same<T, double>::value) {
+      s.dsl = dsl; s.slc = slc; s.cor = cor;
+    } else {
+      s.dsl = dsl32; s.slc = slc32; s.cor = cor32;
+    }
+    s.slc_off = slc_off; s.cor_off = cor_off;
     s.nblocks = (int)nstars;
     s.max_block = max_block;
     if constexpr (std::is_same<T, double>::value) {
@@ -329,34 +356,87 @@ void host_csr(const amg_csr* M, std::vector<int64_t>& ptr, std::vector<int32_t>&
 }
 
 // --- smoother: colour-sorted star blocks, chunks, factors, l1 diagonal ---
-// Sweep form of a level:
-//   dense   nearly sequential level (at most 1.5 blocks per colour: the
-//           bottom of the hierarchy, where the Galerkin operators are dense or
-//           nearly so): block by block in one workgroup with the residual
-//           updated, from a dense copy of A;
-//   pipe    many colours (16 or more): one launch, colours pipelined across
+// Sweep form of a level (chosen from measurements on MI355X):
+//   pipe    16 or more colours: one launch, colours pipelined across
 //           workgroups (a launch per colour would leave the GPU idle between
 //           short colours);
-//   one     small level otherwise: the whole sweep in one workgroup;
-//   colour  one launch per colour.
-// HCURL_AMG_SWEEP=colour|one|pipe|dense forces a form where it applies
-// (dense needs a level that fits the dense kernel); HCURL_AMG_DENSE_SWEEP=0
+//   panel   16 or more colours and rows longer than 4096 entries (n <=
+//           32768): the Galerkin operators near the bottom of a large
+//           hierarchy are nearly dense, and a pipelined chunk would stream
+//           tens of thousands of entries per block; instead one workgroup
+//           chains groups of blocks while the others apply each group's
+//           residual update to their rows from a dense copy of A;
+//   one     small level with fewer colours: the whole sweep in one workgroup;
+//   colour  one launch per colour (the finest levels: few colours, many blocks);
+//   dense   nearly sequential level (at most 1.5 blocks per colour): block by
+//           block in one workgroup with the residual and a dense copy of A
+//           in LDS (n <= 2048, or in global memory up to 16384 rows);
+//           available on request.
+// HCURL_AMG_SWEEP=colour|one|pipe|dense|panel forces a form where it applies
+// (dense and panel need a level that fits their kernels); HCURL_AMG_DENSE_SWEEP=0
 // turns the dense form off.
 int sweep_mode_for(int64_t n, int64_t nnz, int64_t ns, int ncolours, int maxs) {
   const char* dense_env = std::getenv("HCURL_AMG_DENSE_SWEEP");
-  const bool dense_ok = !(dense_env && dense_env[0] == '0') && dense_sweep_ok<double>((int)n, maxs);
+  const bool dense_any = !(dense_env && dense_env[0] == '0') && dense_sweep_ok<double>((int)n, maxs);
+  const bool panel_ok = panel_sweep_ok((int)std::min<int64_t>(n, INT32_MAX), maxs);
   int mode = SWEEP_COLOUR;
-  if (dense_ok && 2 * ns <= 3 * (int64_t)ncolours) mode = SWEEP_DENSE;
-  else if (ncolours >= 16) mode = SWEEP_PIPE;
+  if (ncolours >= 16) mode = (panel_ok && nnz > 4096 * n) ? SWEEP_PANEL : SWEEP_PIPE;
   else if (nnz <= 200000) mode = SWEEP_ONE;
   if (const char* e = std::getenv("HCURL_AMG_SWEEP")) {
     const std::string f(e);
     if (f == "colour") mode = SWEEP_COLOUR;
     else if (f == "one") mode = SWEEP_ONE;
     else if (f == "pipe") mode = SWEEP_PIPE;
-    else if (f == "dense" && dense_ok) mode = SWEEP_DENSE;
+    else if (f == "dense" && dense_any && 2 * ns <= 3 * (int64_t)ncolours) mode = SWEEP_DENSE;
+    else if (f == "panel" && panel_ok) mode = SWEEP_PANEL;
   }
   return mode;
+}
+
+// Groups of the panel form: consecutive blocks (colour order) with at most
+// PANEL_GROUP_SLOTS rows; each DoF's groups (at most two: a DoF lies in at
+// most two node stars) and, per star row, the other row of the same DoF in
+// its group.  False if a DoF lies in more than two groups, or in more than
+// two rows of one group (the form then does not apply).
+bool build_panel_groups(const std::vector<int64_t>& sb_ptr, const std::vector<int32_t>& sb_dofs,
+                        int64_t n, std::vector<int32_t>& grp_blk, std::vector<int32_t>& dgrp,
+                        std::vector<int32_t>& sdup) {
+  const int64_t ns = (int64_t)sb_ptr.size() - 1;
+  grp_blk.clear();
+  int64_t t = 0;
+  while (t < ns) {
+    grp_blk.push_back((int32_t)t);
+    int64_t rows = 0;
+    while (t < ns && rows + (sb_ptr[t + 1] - sb_ptr[t]) <= PANEL_GROUP_SLOTS) {
+      rows += sb_ptr[t + 1] - sb_ptr[t];
+      ++t;
+    }
+    if (rows == 0) return false;   // a block larger than a group
+  }
+  grp_blk.push_back((int32_t)ns);
+  dgrp.assign(2 * n, -1);
+  sdup.assign(sb_dofs.size(), -1);
+  std::vector<int32_t> seen(n, -1);   // row of the DoF inside the current group
+  const int G = (int)grp_blk.size() - 1;
+  for (int g = 0; g < G; ++g) {
+    const int64_t q0 = sb_ptr[grp_blk[g]], q1 = sb_ptr[grp_blk[g + 1]];
+    for (int64_t q = q0; q < q1; ++q) {
+      const int32_t d = sb_dofs[q];
+      if (seen[d] >= 0) {
+        const int64_t q2 = q0 + seen[d];
+        if (sdup[q2] >= 0) return false;   // a third row of one DoF in a group
+        sdup[q2] = (int32_t)(q - q0);
+        sdup[q] = seen[d];
+        continue;
+      }
+      seen[d] = (int32_t)(q - q0);
+      if (dgrp[2 * d] < 0) dgrp[2 * d] = g;
+      else if (dgrp[2 * d + 1] < 0) dgrp[2 * d + 1] = g;
+      else return false;                   // a DoF in a third group
+    }
+    for (int64_t q = q0; q < q1; ++q) seen[sb_dofs[q]] = -1;
+  }
+  return true;
 }
 
 void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
@@ -475,21 +555,60 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   int grid = h->cu_count;
   if (const char* e = std::getenv("HCURL_AMG_PIPE_GRID")) grid = std::max(1, std::atoi(e));
   L.pipe_grid = std::max(1, std::min(nchunks, grid));
-  if (L.sweep_mode == SWEEP_DENSE) L.Acm = h->pool.get<double>((size_t)L.n * L.n);
+  if (L.sweep_mode == SWEEP_PANEL) {
+    std::vector<int32_t> grp_blk, dgrp, sdup;
+    if (build_panel_groups(sb_ptr, sb_dofs, L.n, grp_blk, dgrp, sdup)) {
+      L.ngroups = (int)grp_blk.size() - 1;
+      L.grp_blk = h->pool.upload(grp_blk, st);
+      L.dgrp = h->pool.upload(dgrp, st);
+      L.sdup = h->pool.upload(sdup, st);
+      L.dsl = h->pool.get<double>((size_t)std::max(L.ngroups, 1) * PANEL_GROUP_SLOTS);
+      L.psync = h->pool.get<int>((size_t)std::max(L.ngroups, 1) * 2);
+      std::vector<int64_t> so(L.ngroups + 1, 0), co(L.ngroups + 1, 0);
+      for (int g = 0; g < L.ngroups; ++g) {
+        const int64_t m = sb_ptr[grp_blk[g + 1]] - sb_ptr[grp_blk[g]];
+        const int64_t mn = g + 1 < L.ngroups ? sb_ptr[grp_blk[g + 2]] - sb_ptr[grp_blk[g + 1]] : 0;
+        so[g + 1] = so[g] + m * m;
+        co[g + 1] = co[g] + m * mn;
+      }
+      L.slc_total = so[L.ngroups];
+      L.cor_total = co[L.ngroups];
+      L.slc_off = h->pool.upload(so, st);
+      L.cor_off = h->pool.upload(co, st);
+      L.slc = h->pool.get<double>(std::max<int64_t>(L.slc_total, 1));
+      L.cor = h->pool.get<double>(std::max<int64_t>(L.cor_total, 1));
+    } else {
+      L.sweep_mode = SWEEP_PIPE;
+    }
+  }
+  if (L.sweep_mode == SWEEP_DENSE || L.sweep_mode == SWEEP_PANEL)
+    L.Acm = h->pool.get<double>((size_t)L.n * L.n);
   L.sb_ptr = h->pool.upload(sb_ptr, st);
   L.sb_dofs = h->pool.upload(sb_dofs, st);
   L.fac_off = h->pool.upload(fac_off, st);
   L.fac_total = fac_off[ns];
   L.fac = h->pool.get<double>(L.fac_total);
+  L.binv = h->pool.get<double>(std::max<int64_t>(L.fac_total, 1));
+  {
+    std::vector<int32_t> row_blk(std::max<int64_t>(sb_ptr[ns], 1), 0);
+    for (int64_t b = 0; b < ns; ++b)
+      for (int64_t r = sb_ptr[b]; r < sb_ptr[b + 1]; ++r) row_blk[r] = (int32_t)b;
+    L.row_blk = h->pool.upload(row_blk, st);
+  }
   L.dinv = h->pool.get<double>(L.n);
 }
 
 void factor_smoother(amg_hier* h, Level& L, int level, hipStream_t st) {
-  if (L.sweep_mode == SWEEP_DENSE) csr_to_dense_cm(L.n, L.A_ptr, L.A_col, L.A_val, L.Acm, st);
+  if (L.sweep_mode == SWEEP_DENSE || L.sweep_mode == SWEEP_PANEL)
+    csr_to_dense_cm(L.n, L.A_ptr, L.A_col, L.A_val, L.Acm, st);
+  if (L.sweep_mode == SWEEP_PANEL)
+    panel_slices<double>(L.ngroups, L.n, L.grp_blk, L.sb_ptr, L.sb_dofs, L.Acm, L.slc_off, L.cor_off,
+                         L.slc, L.cor, st);
   star_rows((int64_t)L.ints.star_dofs.size(), L.sb_dofs, L.A_ptr, L.A_val, L.srow_ptr, L.sval, st);
   star_chol(L.nstars, L.sb_ptr, L.sb_dofs, L.fac_off, L.A_dev<double>(), L.fac, h->d_flag, st);
   check_flag(h, st, AMG_ERR_NOT_SPD, "smoother block Cholesky: non-positive pivot on level " +
                                          std::to_string(level));
+  star_inv((int64_t)L.ints.star_dofs.size(), L.row_blk, L.sb_ptr, L.fac_off, L.fac, L.binv, st);
   l1inv(L.A_dev<double>(), L.dinv, st);
 }
 
@@ -696,6 +815,7 @@ void cast_level(amg_hier* h, Level& L, hipStream_t st) {
     L.P_val32 = h->pool.get<float>(L.p_nnz);
     L.PT_val32 = h->pool.get<float>(L.p_nnz);
     L.fac32 = h->pool.get<float>(L.fac_total);
+    L.binv32 = h->pool.get<float>(std::max<int64_t>(L.fac_total, 1));
     L.dinv32 = h->pool.get<float>(L.n);
     L.sval32 = h->pool.get<float>(std::max<int64_t>(L.srow_nnz, 1));
   }
@@ -703,8 +823,18 @@ void cast_level(amg_hier* h, Level& L, hipStream_t st) {
   cast<double, float>(L.p_nnz, L.P_val, L.P_val32, st);
   cast<double, float>(L.p_nnz, L.PT_val, L.PT_val32, st);
   cast<double, float>(L.fac_total, L.fac, L.fac32, st);
+  cast<double, float>(L.fac_total, L.binv, L.binv32, st);
   cast<double, float>(L.n, L.dinv, L.dinv32, st);
-  if (L.sweep_mode == SWEEP_DENSE) {
+  if (L.sweep_mode == SWEEP_PANEL) {
+    if (!L.dsl32) {
+      L.dsl32 = h->pool.get<float>((size_t)std::max(L.ngroups, 1) * PANEL_GROUP_SLOTS);
+      L.slc32 = h->pool.get<float>(std::max<int64_t>(L.slc_total, 1));
+      L.cor32 = h->pool.get<float>(std::max<int64_t>(L.cor_total, 1));
+    }
+    cast<double, float>(L.slc_total, L.slc, L.slc32, st);
+    cast<double, float>(L.cor_total, L.cor, L.cor32, st);
+  }
+  if (L.sweep_mode == SWEEP_DENSE || L.sweep_mode == SWEEP_PANEL) {
     if (!L.Acm32) L.Acm32 = h->pool.get<float>((size_t)L.n * L.n);
     cast<double, float>(L.n * L.n, L.Acm, L.Acm32, st);
   }
@@ -1389,7 +1519,7 @@ amg_status amg_hier_info(const amg_hier* h, amg_level_info* lv, int cap, int* nl
       lv[l].star_row_nnz = rnnz;
       lv[l].fac_entries = L.coarsest ? 0 : L.fac_total;
       lv[l].sweep_form = L.coarsest ? 0 : L.sweep_mode;
-      lv[l].sweep_lanes = (L.coarsest || L.sweep_mode == SWEEP_DENSE) ? 0 : L.lpr_S;
+      lv[l].sweep_lanes = (L.coarsest || L.sweep_mode == SWEEP_DENSE || L.sweep_mode == SWEEP_PANEL) ? 0 : L.lpr_S;
     }
     return AMG_OK;
   });

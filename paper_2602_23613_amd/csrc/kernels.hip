@@ -163,19 +163,21 @@ void spmv_dot(const CsrDev<double>& A, const double* x, double* y, double* parti
 // The smoother keeps its own copy of A's rows in star order (srow_ptr, scol,
 // sval: star row r is row sb_dofs[r] of A), so a chunk streams one contiguous
 // range.  A group of WGS threads does one chunk in two phases:
-//   chunk_load    chunk bounds, row bounds, DoFs, packed factors and the first
-//                 U (column, value) pairs per lane of every row: everything
-//                 that does not depend on x;
+//   chunk_load    chunk bounds, row bounds, DoFs, each row's block, the
+//                 blocks' packed inverses and the first U (column, value)
+//                 pairs per lane of every row: everything that does not
+//                 depend on x;
 //   chunk_finish  b and x entries, row sums (lane sums in entry order, then a
-//                 shuffle tree), residuals in LDS, the block Cholesky solves
-//                 (one thread per block), x_B += d.
+//                 shuffle tree), residuals in LDS, d = A_BB^{-1} r_B (one
+//                 thread per row: its row of the block's symmetric inverse
+//                 times the block's residuals), x_B += d.
 // Blocks of one colour share no DoF and no coupling, so the chunks of a colour
 // update x independently and in any order.
 
 // LDS of one chunk: residuals of its rows, per-wave partial sums when a row
-// spans several wavefronts (LPR > 64), and the chunk's packed factors.  A
-// chunk holds at most RPB rows in blocks of at most min(RPB, 32) rows, so its
-// packed factors take at most RPB (min(RPB, 32) + 1) / 2 entries.
+// spans several wavefronts (LPR > 64), and the chunk's packed block inverses.
+// A chunk holds at most RPB rows in blocks of at most min(RPB, 32) rows, so
+// its packed inverses take at most RPB (min(RPB, 32) + 1) / 2 entries.
 template <class T, int LPR, int WGS>
 struct ChunkLds {
   static constexpr int RPB = WGS / LPR;
@@ -192,7 +194,8 @@ template <class T, int LPR, int WGS, int U>
 struct ChunkRegs {
   static constexpr int FPT = (ChunkLds<T, LPR, WGS>::FL + WGS - 1) / WGS;
   int blk0, nblk, r0, nrows, nf;
-  int64_t f0, q0, q1, p0, p1, fo;
+  int64_t f0, q0, q1;
+  int bp, bs, bfo;        // this thread's row: its block's first row (in the chunk), size, inverse offset
   int32_t rdof, mydof;
   T fv[FPT];
   int32_t c[U];
@@ -222,17 +225,19 @@ __device__ __forceinline__ void chunk_load(bool act, int c, int tid, const Smoot
     R.q1 = D.srow_ptr[r + 1];
     if (lane == 0) R.rdof = D.sb_dofs[r];
   }
-  if (tid < R.nrows) R.mydof = D.sb_dofs[R.r0 + tid];
-  R.p0 = R.p1 = R.fo = 0;
-  if (tid < R.nblk) {
-    R.p0 = D.sb_ptr[R.blk0 + tid];
-    R.p1 = D.sb_ptr[R.blk0 + tid + 1];
-    R.fo = D.fac_off[R.blk0 + tid];
+  R.bp = R.bs = R.bfo = 0;
+  if (tid < R.nrows) {
+    R.mydof = D.sb_dofs[R.r0 + tid];
+    const int rb = D.row_blk[R.r0 + tid];
+    const int64_t p0 = D.sb_ptr[rb];
+    R.bp = (int)(p0 - R.r0);
+    R.bs = (int)(D.sb_ptr[rb + 1] - p0);
+    R.bfo = (int)(D.fac_off[rb] - R.f0);
   }
 #pragma unroll
   for (int k = 0; k < FPT; ++k) {
     const int t = tid + k * WGS;
-    R.fv[k] = t < R.nf ? D.fac[R.f0 + t] : T(0);
+    R.fv[k] = t < R.nf ? D.binv[R.f0 + t] : T(0);
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -308,31 +313,26 @@ __device__ __forceinline__ void chunk_finish(int tid, const ChunkRegs<T, LPR, WG
     }
   }
   __syncthreads();
-  if (tid < R.nblk) {
-    const int boff = (int)(R.p0 - R.r0), sz = (int)(R.p1 - R.p0);
-    const T* L = S.fl + (R.fo - R.f0);
-    T* v = S.res + boff;
-    if constexpr (WPR > 1) {
-      for (int i = 0; i < sz; ++i) {
-        T p = 0;
-        for (int w = 0; w < WPR; ++w) p += S.part[(boff + i) * WPR + w];
-        v[i] -= p;
-      }
+  if constexpr (WPR > 1) {
+    if (tid < R.nrows) {
+      T p = 0;
+      for (int w = 0; w < WPR; ++w) p += S.part[tid * WPR + w];
+      S.res[tid] -= p;
     }
-    for (int i = 0; i < sz; ++i) {
-      T a = v[i];
-      const T* Li = L + i * (i + 1) / 2;
-      for (int j = 0; j < i; ++j) a -= Li[j] * v[j];
-      v[i] = a / Li[i];
-    }
-    for (int i = sz - 1; i >= 0; --i) {
-      T a = v[i];
-      for (int j = i + 1; j < sz; ++j) a -= L[j * (j + 1) / 2 + i] * v[j];
-      v[i] = a / L[i * (i + 1) / 2 + i];
-    }
+    __syncthreads();
   }
-  __syncthreads();
-  if (tid < R.nrows) st_x<T, COH>(x + R.mydof, myx + S.res[tid]);
+  if (tid < R.nrows) {
+    // d_i = sum_j (A_BB^{-1})_ij r_j, the inverse stored packed (lower half)
+    const int i = tid - R.bp;
+    const T* Bi = S.fl + R.bfo;
+    const T* v = S.res + R.bp;
+    T d = 0;
+    for (int j = 0; j < R.bs; ++j) {
+      const int hi = i > j ? i : j, lo = i > j ? j : i;
+      d += Bi[hi * (hi + 1) / 2 + lo] * v[j];
+    }
+    st_x<T, COH>(x + R.mydof, myx + d);
+  }
 }
 
 template <int LPR>
@@ -727,6 +727,419 @@ void dense_sweep(int n, int nblocks, int max_block, int backward, const int64_t*
     if (max_block <= 8) LAUNCH_DS(2, 8); else LAUNCH_DS(2, 16);
   }
 #undef LAUNCH_DS
+}
+
+// ---------------------------------------------------------------------------
+// multiplicative Schwarz on a wide level: the panel sweep
+// ---------------------------------------------------------------------------
+// Coarse Galerkin operators near the bottom of the hierarchy have rows of
+// thousands of entries and hundreds to thousands of colours with a few blocks
+// each, so a sweep is a long chain of small steps.  The panel form keeps
+// r = b - A x and follows the blocks in sweep order in groups of consecutive
+// blocks with at most PANEL_SLOTS rows in all (a row of a group is a "slot";
+// a DoF in two blocks of one group has two slots).  Workgroup 0 (the chain)
+// takes the groups in turn: it loads the group's slice A(D_g, D_g) and
+// residual entries, and for each block B in sweep order forms
+// d = A_BB^{-1} r_B (the lanes of B's slots, each with its row of the
+// block's symmetric inverse) and updates the residual of every slot of the
+// group, all in one wavefront; x_B += d follows at the end of the group.  The other workgroups own tiles of PANEL_TILE rows
+// and apply each group's update r_i -= sum_k A(i, dof_k) d_k to their rows,
+// reading A from a column-major dense copy.  Exactly-once rule for the update
+// of group h on row i: the chain applies it when i is in D_h (inside the
+// group) or in the next group D_h' (as a correction it carries to h'), the
+// tiles otherwise.  The chain reads the residual of D_g after the tiles have
+// applied every group two or more positions back (they skip rows of D_g for
+// the group just before it), so the chain only waits when the tiles fall
+// more than a group behind.  The result is the multiplicative Schwarz sweep
+// in residual-update form (only the rounding differs from the row form).
+// Shared data (r, the published d) use agent-coherent accesses; a stored
+// value is complete (memory counter drained) before the barrier that precedes
+// its flag.  Every wait is bounded as in the pipelined sweep.  All
+// workgroups of the grid must be able to run at once (1 + n / PANEL_TILE of
+// 256 threads, n <= PANEL_NMAX, on an otherwise idle device).
+constexpr int PANEL_SLOTS = PANEL_GROUP_SLOTS;
+constexpr int PANEL_TILE = 256;
+constexpr int PANEL_NMAX = 32768;
+constexpr int PANEL_SMAX = 16;
+constexpr int PANEL_FMAX = PANEL_SLOTS * (PANEL_SMAX + 1) / 2;
+
+template <class T>
+struct PanelArgs {
+  int n = 0, ngroups = 0, ntiles = 0, backward = 0, spin_max = 0;
+  const int32_t* grp_blk = nullptr;   // first block of each group (+ sentinel), colour order
+  const int64_t* sb_ptr = nullptr;
+  const int32_t* sb_dofs = nullptr;
+  const int64_t* fac_off = nullptr;
+  const T* binv = nullptr;            // packed symmetric inverses of the blocks
+  const T* Acm = nullptr;             // A(i, j) at Acm[j n + i]
+  const T* slc = nullptr;             // per group: A(D_g, D_g), column-major m_g x m_g
+  const T* cor = nullptr;             // per group g < G-1: A(D_g+1, D_g), column-major
+  const int64_t* slc_off = nullptr;
+  const int64_t* cor_off = nullptr;
+  const int32_t* dgrp = nullptr;      // the (at most two) groups holding each DoF, -1 if none
+  const int32_t* sdup = nullptr;      // per slot: the group's other slot of the same DoF, or -1
+  T* r = nullptr;                     // b - A x on entry, kept equal to it
+  T* x = nullptr;
+  T* dsl = nullptr;                   // per sweep position: d of each slot of the group
+  int* flag = nullptr;                // per sweep position: the chain has published dsl
+  int* done = nullptr;                // per sweep position: tiles that have applied it
+  int* err = nullptr;
+};
+
+__device__ __forceinline__ void panel_wait(const int* p, int need, int* err, int spin_max) {
+  int spins = 0;
+  while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+    if ((++spins & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+      return;
+    if (spins > spin_max) {
+      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// value of a uniform lane, broadcast through the scalar unit
+__device__ __forceinline__ double lane_bcast(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane_bcast(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Structure of one group, as the chain workgroup stages it: DoFs, the other
+// slot of a repeated DoF, block offsets / sizes / factor offsets, packed
+// factors and the slice A(D_g, D_g).
+struct PanelGroup {
+  int g, bb0, nbk, m, nf;
+  int64_t q0, f0;
+};
+
+template <class T>
+__device__ __forceinline__ PanelGroup panel_group(const PanelArgs<T>& P, int pos) {
+  PanelGroup q;
+  q.g = P.backward ? P.ngroups - 1 - pos : pos;
+  q.bb0 = P.grp_blk[q.g];
+  const int bb1 = P.grp_blk[q.g + 1];
+  q.nbk = bb1 - q.bb0;
+  q.q0 = P.sb_ptr[q.bb0];
+  q.m = (int)(P.sb_ptr[bb1] - q.q0);
+  q.f0 = P.fac_off[q.bb0];
+  q.nf = (int)(P.fac_off[bb1] - q.f0);
+  return q;
+}
+
+// entries of the 64 x 64 slot matrices that one of the 192 staging threads
+// holds: e = t + 192 j
+constexpr int PANEL_STAGE = 192;
+constexpr int PANEL_PER = (PANEL_SLOTS * PANEL_SLOTS + PANEL_STAGE - 1) / PANEL_STAGE;   // 22
+constexpr int PANEL_FPER = (PANEL_FMAX + PANEL_STAGE - 1) / PANEL_STAGE;                 // 6
+
+template <class T>
+__global__ __launch_bounds__(256) void k_schwarz_panel(PanelArgs<T> P) {
+  __shared__ T Aloc[PANEL_SLOTS * PANEL_SLOTS];   // Aloc[l * 64 + k] = A(dof_k, dof_l)
+  __shared__ T fl[PANEL_FMAX];
+  __shared__ T part[3][PANEL_SLOTS];
+  __shared__ T ds_s[PANEL_SLOTS];
+  __shared__ T corr[PANEL_SLOTS];
+  __shared__ int dof_s[PANEL_SLOTS];
+  __shared__ int sdup_s[PANEL_SLOTS];
+  __shared__ int inprev_s[PANEL_SLOTS];
+  __shared__ int blk_p[PANEL_SLOTS], blk_s[PANEL_SLOTS], blk_f[PANEL_SLOTS];
+  const int tid = threadIdx.x;
+  const int G = P.ngroups;
+  const int64_t n = P.n;
+  if (blockIdx.x == 0) {
+    // ---------------- the chain ----------------
+    // prologue: stage group 0
+    {
+      const PanelGroup q = panel_group(P, 0);
+      if (tid < q.m) {
+        dof_s[tid] = P.sb_dofs[q.q0 + tid];
+        sdup_s[tid] = P.sdup[q.q0 + tid];
+        inprev_s[tid] = 0;
+      }
+      if (tid < q.nbk) {
+        const int blk = q.bb0 + tid;
+        const int bp = (int)(P.sb_ptr[blk] - q.q0), bs = (int)(P.sb_ptr[blk + 1] - P.sb_ptr[blk]);
+        const int64_t bf = P.fac_off[blk];
+        blk_p[tid] = bp;
+        blk_s[tid] = bs;
+        blk_f[tid] = (int)(bf - q.f0);
+      }
+      for (int t = tid; t < q.nf; t += 256) fl[t] = P.binv[q.f0 + t];
+      __syncthreads();
+      for (int e = tid; e < PANEL_SLOTS * PANEL_SLOTS; e += 256) {
+        const int l = e / PANEL_SLOTS, k = e % PANEL_SLOTS;
+        if (l < q.m && k < q.m) Aloc[e] = P.slc[P.slc_off[q.g] + l * q.m + k];
+      }
+      __syncthreads();
+    }
+    for (int pos = 0; pos < G; ++pos) {
+      const PanelGroup q = panel_group(P, pos);
+      const int m = q.m;
+      const bool more = pos + 1 < G;
+      PanelGroup qn{};
+      if (more) qn = panel_group(P, pos + 1);
+      // the tiles have applied every group two or more positions back
+      if (tid == 0 && pos >= 2) panel_wait(&P.done[pos - 2], P.ntiles, P.err, P.spin_max);
+      __syncthreads();
+      // staging registers of waves 1-3 (next group's structure and slice,
+      // and the entries A(D_next, D_g) of the correction)
+      T an[PANEL_PER], cn[PANEL_PER], fn[PANEL_FPER];
+      int dn = 0, sn = 0, ipn = 0, bpn = 0, bsn = 0, bfn = 0;
+      if (tid < 64) {
+        // wave 0: the chain over the group's blocks; lane k holds slot k
+        const int k = tid;
+        const int dofk = k < m ? dof_s[k] : 0;
+        T rk = 0, dk = 0;
+        if (k < m) {
+          rk = ld_x<T, true>(P.r + dofk);
+          if (pos >= 1 && !inprev_s[k]) rk += corr[k];
+        }
+        for (int jb = 0; jb < q.nbk; ++jb) {
+          const int ib = P.backward ? q.nbk - 1 - jb : jb;
+          // uniform across the wavefront: keeps the broadcasts below on the scalar unit
+          const int p = __builtin_amdgcn_readfirstlane(blk_p[ib]);
+          const int s = __builtin_amdgcn_readfirstlane(blk_s[ib]);
+          const T* Bi = fl + __builtin_amdgcn_readfirstlane(blk_f[ib]);
+          // the lanes of B's slots (p <= k < p + s) form d_k = sum_j
+          // (A_BB^{-1})_{k-p, j} r_{p+j}; then every slot's residual drops by
+          // A(slot, B) d.  Operands come into registers first; values are
+          // broadcast through the scalar unit.
+          const bool mine = k >= p && k < p + s;
+          const int i = k - p;
+          T Br[PANEL_SMAX], Ac[PANEL_SMAX];
+#pragma unroll
+          for (int j = 0; j < PANEL_SMAX; ++j) {
+            const int hi = i > j ? i : j, lo = i > j ? j : i;
+            Br[j] = (mine && j < s) ? Bi[hi * (hi + 1) / 2 + lo] : T(0);
+            Ac[j] = (j < s && k < m) ? Aloc[(p + j) * PANEL_SLOTS + k] : T(0);
+          }
+          T d = 0;
+#pragma unroll
+          for (int j = 0; j < PANEL_SMAX; ++j)
+            if (j < s) d += Br[j] * lane_bcast(rk, p + j);
+          if (mine) dk = d;
+#pragma unroll
+          for (int j = 0; j < PANEL_SMAX; ++j)
+            if (j < s) rk -= Ac[j] * lane_bcast(d, p + j);
+        }
+        // x_B += d for the group's blocks in sweep order: a DoF in two blocks
+        // of the group (slots k and dup) gets both updates from the lower slot's lane
+        const int dup = k < m ? sdup_s[k] : -1;
+        const T ddup = __shfl(dk, dup & 63);
+        if (k < m) {
+          if (dup < 0) {
+            st_x<T, true>(P.x + dofk, ld_x<T, true>(P.x + dofk) + dk);
+          } else if (k < dup) {
+            const T x0 = ld_x<T, true>(P.x + dofk);
+            st_x<T, true>(P.x + dofk, P.backward ? (x0 + ddup) + dk : (x0 + dk) + ddup);
+          }
+          st_x<T, true>(P.r + dofk, rk);
+          st_x<T, true>(P.dsl + (int64_t)pos * PANEL_SLOTS + k, dk);
+          ds_s[k] = dk;
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+      } else if (more) {
+        // waves 1-3: load the next group while the chain runs
+        const int t = tid - 64;
+        const int mn = qn.m;
+        const int64_t dq = qn.q0;
+        if (t < mn) {
+          dn = P.sb_dofs[dq + t];
+          sn = P.sdup[dq + t];
+          const int d = dn;
+          ipn = P.dgrp[2 * d] == q.g || P.dgrp[2 * d + 1] == q.g;
+        }
+        if (t < qn.nbk) {
+          const int blk = qn.bb0 + t;
+          bpn = (int)(P.sb_ptr[blk] - dq);
+          bsn = (int)(P.sb_ptr[blk + 1] - P.sb_ptr[blk]);
+          bfn = (int)(P.fac_off[blk] - qn.f0);
+        }
+#pragma unroll
+        for (int j = 0; j < PANEL_FPER; ++j) {
+          const int e = t + PANEL_STAGE * j;
+          fn[j] = e < qn.nf ? P.binv[qn.f0 + e] : T(0);
+        }
+        // slice of the next group (stored contiguously): entry e = l * 64 + k
+        const T* Sn = P.slc + P.slc_off[qn.g];
+#pragma unroll
+        for (int j = 0; j < PANEL_PER; ++j) {
+          const int e = t + PANEL_STAGE * j;
+          const int l = e / PANEL_SLOTS, k = e % PANEL_SLOTS;
+          an[j] = (l < mn && k < mn) ? Sn[l * mn + k] : T(0);
+        }
+        // correction entries: thread (kn, part) holds A(dof_n[kn], dof_s[k])
+        // for k = part, part + 3, ...; the block between two consecutive
+        // groups is stored once (forward order) and read transposed backward
+        const int kn = t % PANEL_SLOTS, pt = t / PANEL_SLOTS;
+        const T* Cg = P.cor + P.cor_off[P.backward ? qn.g : q.g];
+#pragma unroll
+        for (int j = 0; j < PANEL_PER; ++j) {
+          const int k = pt + 3 * j;
+          cn[j] = T(0);
+          if (kn < mn && k < m) cn[j] = P.backward ? Cg[kn * m + k] : Cg[k * mn + kn];
+        }
+      }
+      __syncthreads();
+      if (tid == 0) __hip_atomic_store(&P.flag[pos], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (!more) break;
+      // correction partial sums (this group's d is in ds_s) and the next group's staging
+      if (tid >= 64) {
+        const int t = tid - 64;
+        const int kn = t % PANEL_SLOTS, pt = t / PANEL_SLOTS;
+        T acc = 0;
+#pragma unroll
+        for (int j = 0; j < PANEL_PER; ++j) {
+          const int k = pt + 3 * j;
+          if (k < m) acc += cn[j] * ds_s[k];
+        }
+        part[pt][kn] = acc;
+      }
+      __syncthreads();
+      if (tid < qn.m) corr[tid] = -((part[0][tid] + part[1][tid]) + part[2][tid]);
+      if (tid >= 64) {
+        const int t = tid - 64;
+        if (t < qn.m) {
+          dof_s[t] = dn;
+          sdup_s[t] = sn;
+          inprev_s[t] = ipn;
+        }
+        if (t < qn.nbk) {
+          blk_p[t] = bpn;
+          blk_s[t] = bsn;
+          blk_f[t] = bfn;
+        }
+#pragma unroll
+        for (int j = 0; j < PANEL_FPER; ++j) {
+          const int e = t + PANEL_STAGE * j;
+          if (e < qn.nf) fl[e] = fn[j];
+        }
+#pragma unroll
+        for (int j = 0; j < PANEL_PER; ++j) {
+          const int e = t + PANEL_STAGE * j;
+          const int l = e / PANEL_SLOTS, k = e % PANEL_SLOTS;
+          if (l < qn.m && k < qn.m) Aloc[e] = an[j];
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
+  // ---------------- the tiles ----------------
+  // Each thread owns row i; for every group it loads the group's columns of
+  // its row (and the row's residual) before waiting for the group's d.
+  const int64_t i = (int64_t)(blockIdx.x - 1) * PANEL_TILE + tid;
+  const bool row = i < n;
+  const int ga = row ? P.dgrp[2 * i] : -1, gb = row ? P.dgrp[2 * i + 1] : -1;
+  for (int pos = 0; pos < G; ++pos) {
+    const int g = P.backward ? G - 1 - pos : pos;
+    const int gn = pos + 1 < G ? (P.backward ? g - 1 : g + 1) : -2;
+    const int64_t q0 = P.sb_ptr[P.grp_blk[g]];
+    const int m = (int)(P.sb_ptr[P.grp_blk[g + 1]] - q0);
+    const bool upd = row && ga != g && ga != gn && gb != g && gb != gn;
+    if (tid < m) dof_s[tid] = P.sb_dofs[q0 + tid];
+    __syncthreads();
+    T a[PANEL_SLOTS];
+#pragma unroll
+    for (int k = 0; k < PANEL_SLOTS; ++k) a[k] = (upd && k < m) ? P.Acm[(int64_t)dof_s[k] * n + i] : T(0);
+    // the tile wrote r_i last itself, or the chain did before an earlier flag
+    const T ri = upd ? ld_x<T, true>(P.r + i) : T(0);
+    if (tid == 0) panel_wait(&P.flag[pos], 1, P.err, P.spin_max);
+    __syncthreads();
+    if (tid < m) ds_s[tid] = ld_x<T, true>(P.dsl + (int64_t)pos * PANEL_SLOTS + tid);
+    __syncthreads();
+    if (upd) {
+      T acc = 0;
+#pragma unroll
+      for (int k = 0; k < PANEL_SLOTS; ++k)
+        if (k < m) acc += a[k] * ds_s[k];
+      st_x<T, true>(P.r + i, ri - acc);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) __hip_atomic_fetch_add(&P.done[pos], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+bool panel_sweep_ok(int n, int max_block) {
+  return n > 0 && n <= PANEL_NMAX && max_block <= PANEL_SMAX;
+}
+
+int panel_tiles(int n) { return (n + PANEL_TILE - 1) / PANEL_TILE; }
+
+// The panel form's per-group slices A(D_g, D_g) and inter-group blocks
+// A(D_g+1, D_g), gathered from the dense copy once per numeric setup.
+template <class T>
+__global__ void k_panel_slices(int ngroups, int64_t n, const int32_t* __restrict__ grp_blk,
+                               const int64_t* __restrict__ sb_ptr, const int32_t* __restrict__ sb_dofs,
+                               const T* __restrict__ Acm, const int64_t* __restrict__ slc_off,
+                               const int64_t* __restrict__ cor_off, T* __restrict__ slc,
+                               T* __restrict__ cor) {
+  const int g = blockIdx.x;
+  const int64_t q0 = sb_ptr[grp_blk[g]];
+  const int m = (int)(sb_ptr[grp_blk[g + 1]] - q0);
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+    const int l = e / m, k = e % m;
+    slc[slc_off[g] + e] = Acm[(int64_t)sb_dofs[q0 + l] * n + sb_dofs[q0 + k]];
+  }
+  if (g + 1 < ngroups) {
+    const int64_t q1 = sb_ptr[grp_blk[g + 1]];
+    const int mn = (int)(sb_ptr[grp_blk[g + 2]] - q1);
+    for (int e = threadIdx.x; e < m * mn; e += blockDim.x) {
+      const int k = e / mn, kn = e % mn;
+      cor[cor_off[g] + e] = Acm[(int64_t)sb_dofs[q0 + k] * n + sb_dofs[q1 + kn]];
+    }
+  }
+}
+
+template <class T>
+void panel_slices(int ngroups, int64_t n, const int32_t* grp_blk, const int64_t* sb_ptr,
+                  const int32_t* sb_dofs, const T* Acm, const int64_t* slc_off, const int64_t* cor_off,
+                  T* slc, T* cor, hipStream_t st) {
+  if (ngroups > 0)
+    hipLaunchKernelGGL((k_panel_slices<T>), dim3(ngroups), dim3(256), 0, st, ngroups, n, grp_blk,
+                       sb_ptr, sb_dofs, Acm, slc_off, cor_off, slc, cor);
+}
+
+template <class T>
+void panel_sweep(int n, int ngroups, int backward, const int32_t* grp_blk, const int64_t* sb_ptr,
+                 const int32_t* sb_dofs, const int64_t* fac_off, const T* binv, const T* Acm,
+                 const T* slc, const T* cor, const int64_t* slc_off, const int64_t* cor_off,
+                 const int32_t* dgrp, const int32_t* sdup, T* r, T* x, T* dsl, int* sync, int* err,
+                 int spin_max, hipStream_t st) {
+  if (ngroups <= 0) return;
+  hipLaunchKernelGGL(k_zero_i32, dim3((2 * ngroups + 255) / 256), dim3(256), 0, st, 2 * ngroups, sync);
+  PanelArgs<T> P;
+  P.n = n;
+  P.ngroups = ngroups;
+  P.ntiles = panel_tiles(n);
+  P.backward = backward;
+  P.spin_max = spin_max;
+  P.grp_blk = grp_blk;
+  P.sb_ptr = sb_ptr;
+  P.sb_dofs = sb_dofs;
+  P.fac_off = fac_off;
+  P.binv = binv;
+  P.Acm = Acm;
+  P.slc = slc;
+  P.cor = cor;
+  P.slc_off = slc_off;
+  P.cor_off = cor_off;
+  P.dgrp = dgrp;
+  P.sdup = sdup;
+  P.r = r;
+  P.x = x;
+  P.dsl = dsl;
+  P.flag = sync;
+  P.done = sync + ngroups;
+  P.err = err;
+  hipLaunchKernelGGL((k_schwarz_panel<T>), dim3(1 + P.ntiles), dim3(256), 0, st, P);
 }
 
 // column-major dense copy of a CSR matrix (D(i, j) at D[j n + i])
@@ -1559,6 +1972,41 @@ void star_chol(int64_t nb, const int64_t* sb_ptr, const int32_t* sb_dofs, const 
                        sb_ptr, sb_dofs, fac_off, A.ptr, A.col, A.val, fac, flag);
 }
 
+// Symmetric inverse of each block from its Cholesky factor, packed like the
+// factor (lower half): thread r solves L L^T z = e_j for its row r, the j-th
+// row of block row_blk[r], and writes entries (i >= j) of column j.
+__global__ void k_star_inv(int64_t nrows, const int32_t* __restrict__ row_blk,
+                           const int64_t* __restrict__ sb_ptr, const int64_t* __restrict__ fac_off,
+                           const double* __restrict__ fac, double* __restrict__ binv) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const int b = row_blk[r];
+  const int64_t p0 = sb_ptr[b];
+  const int s = (int)(sb_ptr[b + 1] - p0);
+  const int j = (int)(r - p0);
+  const double* L = fac + fac_off[b];
+  double* B = binv + fac_off[b];
+  double y[32];
+  for (int i = 0; i < s; ++i) {
+    double a = i == j ? 1.0 : 0.0;
+    for (int q = 0; q < i; ++q) a -= L[i * (i + 1) / 2 + q] * y[q];
+    y[i] = a / L[i * (i + 1) / 2 + i];
+  }
+  for (int i = s - 1; i >= 0; --i) {
+    double a = y[i];
+    for (int q = i + 1; q < s; ++q) a -= L[q * (q + 1) / 2 + i] * y[q];
+    y[i] = a / L[i * (i + 1) / 2 + i];
+  }
+  for (int i = j; i < s; ++i) B[i * (i + 1) / 2 + j] = y[i];
+}
+
+void star_inv(int64_t nrows, const int32_t* row_blk, const int64_t* sb_ptr, const int64_t* fac_off,
+              const double* fac, double* binv, hipStream_t st) {
+  if (nrows > 0)
+    hipLaunchKernelGGL(k_star_inv, dim3((unsigned)((nrows + 127) / 128)), dim3(128), 0, st, nrows,
+                       row_blk, sb_ptr, fac_off, fac, binv);
+}
+
 __global__ void k_l1inv(int64_t n, const int64_t* __restrict__ ptr, const double* __restrict__ val,
                         double* __restrict__ dinv) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -1590,6 +2038,19 @@ template void schwarz_sweep_small<double>(const SmootherDev<double>&, int, const
 template void schwarz_sweep_small<float>(const SmootherDev<float>&, int, const float*, float*, hipStream_t);
 template void schwarz_pipe<double>(const SmootherDev<double>&, int, const double*, double*, hipStream_t);
 template void schwarz_pipe<float>(const SmootherDev<float>&, int, const float*, float*, hipStream_t);
+template void panel_sweep<double>(int, int, int, const int32_t*, const int64_t*, const int32_t*,
+                                  const int64_t*, const double*, const double*, const double*,
+                                  const double*, const int64_t*, const int64_t*, const int32_t*,
+                                  const int32_t*, double*, double*, double*, int*, int*, int,
+                                  hipStream_t);
+template void panel_sweep<float>(int, int, int, const int32_t*, const int64_t*, const int32_t*,
+                                 const int64_t*, const float*, const float*, const float*,
+                                 const float*, const int64_t*, const int64_t*, const int32_t*,
+                                 const int32_t*, float*, float*, float*, int*, int*, int,
+                                 hipStream_t);
+template void panel_slices<double>(int, int64_t, const int32_t*, const int64_t*, const int32_t*,
+                                   const double*, const int64_t*, const int64_t*, double*, double*,
+                                   hipStream_t);
 template bool dense_sweep_ok<double>(int, int);
 template bool dense_sweep_ok<float>(int, int);
 template void dense_sweep<double>(int, int, int, int, const int64_t*, const int32_t*, const int64_t*,

@@ -35,7 +35,9 @@ struct SmootherArgs {
   const int64_t* sb_ptr = nullptr;        // rows of each block (colour order)
   const int32_t* sb_dofs = nullptr;
   const int64_t* fac_off = nullptr;       // packed lower factor offset of each block
-  const T* fac = nullptr;
+  const T* fac = nullptr;                 // Cholesky factors (dense form)
+  const T* binv = nullptr;                // symmetric inverses, packed like fac (row forms)
+  const int32_t* row_blk = nullptr;       // block of each star row
   const int32_t* ck_row0 = nullptr;       // first star row of each chunk (+ sentinel)
   const int64_t* ck_fac0 = nullptr;       // first factor entry of each chunk (+ sentinel)
   const int64_t* srow_ptr = nullptr;      // the smoother's copy of A's rows in star order
@@ -47,7 +49,7 @@ struct SmootherArgs {
 };
 
 // ... and the host side: launch shape and the dense-level form.
-enum { SWEEP_COLOUR = 0, SWEEP_ONE = 1, SWEEP_PIPE = 2, SWEEP_DENSE = 3 };
+enum { SWEEP_COLOUR = 0, SWEEP_ONE = 1, SWEEP_PIPE = 2, SWEEP_DENSE = 3, SWEEP_PANEL = 4 };
 template <class T>
 struct SmootherDev : SmootherArgs<T> {
   std::vector<int> colour_chunk_h;      // host copy of colour_chunk
@@ -62,6 +64,17 @@ struct SmootherDev : SmootherArgs<T> {
   int max_block = 0;
   const T* Acm = nullptr;
   T* rtmp = nullptr;                    // level-sized scratch for b - A x
+  // panel form (wide levels): groups of consecutive blocks in colour order
+  int ngroups = 0;
+  const int32_t* grp_blk = nullptr;     // first block of each group (+ sentinel)
+  const int32_t* dgrp = nullptr;        // the (at most two) groups of each DoF
+  const int32_t* sdup = nullptr;        // per star row: the group's other slot of its DoF
+  T* dsl = nullptr;                     // published block updates (64 per group)
+  const T* slc = nullptr;               // per group A(D_g, D_g), and A(D_g+1, D_g)
+  const T* cor = nullptr;
+  const int64_t* slc_off = nullptr;
+  const int64_t* cor_off = nullptr;
+  int* psync = nullptr;                 // flags and tile counters (2 per group)
 };
 
 // scalar slots of the CG state vector
@@ -85,6 +98,19 @@ template <class T>
 void schwarz_pipe(const SmootherDev<T>& S, int backward, const T* b, T* x, hipStream_t st);
 void star_rows(int64_t nrows, const int32_t* sb_dofs, const int64_t* Aptr, const double* Aval,
                const int64_t* srow_ptr, double* sval, hipStream_t st);
+bool panel_sweep_ok(int n, int max_block);
+int panel_tiles(int n);
+constexpr int PANEL_GROUP_SLOTS = 64;
+template <class T>
+void panel_sweep(int n, int ngroups, int backward, const int32_t* grp_blk, const int64_t* sb_ptr,
+                 const int32_t* sb_dofs, const int64_t* fac_off, const T* binv, const T* Acm,
+                 const T* slc, const T* cor, const int64_t* slc_off, const int64_t* cor_off,
+                 const int32_t* dgrp, const int32_t* sdup, T* r, T* x, T* dsl, int* sync, int* err,
+                 int spin_max, hipStream_t st);
+template <class T>
+void panel_slices(int ngroups, int64_t n, const int32_t* grp_blk, const int64_t* sb_ptr,
+                  const int32_t* sb_dofs, const T* Acm, const int64_t* slc_off, const int64_t* cor_off,
+                  T* slc, T* cor, hipStream_t st);
 
 template <class T> bool dense_sweep_ok(int n, int max_block);
 template <class T>
@@ -109,6 +135,12 @@ void schwarz_sweep(const SmootherDev<T>& S, const CsrDev<T>& A, int backward, co
       return;
     case SWEEP_PIPE:
       schwarz_pipe<T>(S, backward, b, x, st);
+      return;
+    case SWEEP_PANEL:
+      residual<T>(A, x, b, S.rtmp, st);
+      panel_sweep<T>(S.n, S.ngroups, backward, S.grp_blk, S.sb_ptr, S.sb_dofs, S.fac_off, S.binv,
+                     S.Acm, S.slc, S.cor, S.slc_off, S.cor_off, S.dgrp, S.sdup, S.rtmp, x, S.dsl,
+                     S.psync, S.err, S.spin_max, st);
       return;
     default:
       for (int k = 0; k < S.ncolours; ++k)
@@ -162,6 +194,8 @@ void mm_vals_wide(int64_t nw, const int32_t* rows, const CsrPat& X, const double
                   const CsrPat& Y, const double* Yval, int64_t ncols, const int64_t* Cptr,
                   const int32_t* Ccol, double* Cval, hipStream_t st);
 
+void star_inv(int64_t nrows, const int32_t* row_blk, const int64_t* sb_ptr, const int64_t* fac_off,
+              const double* fac, double* binv, hipStream_t st);
 void star_chol(int64_t nb, const int64_t* sb_ptr, const int32_t* sb_dofs, const int64_t* fac_off,
                const CsrDev<double>& A, double* fac, int* flag, hipStream_t st);
 void l1inv(const CsrDev<double>& A, double* dinv, hipStream_t st);

@@ -402,9 +402,11 @@ def _with_env(env, fn):
 @pytest.mark.parametrize("which", ["hex16_jump_b1e-3", "hex32"])
 def test_sweep_forms_agree(which):
     """Every level swept by each form (one launch per colour, one workgroup,
-    colours pipelined in one launch) against the oracle's colour sweep: one
-    forward, backward, forward sweep from the same b.  The forms differ only
-    in lanes per row (so in rounding), not in the order of the colours."""
+    colours pipelined in one launch, the panel residual-update form) against
+    the oracle's colour sweep: one forward, backward, forward sweep from the
+    same b.  The forms differ in rounding only (lanes per row; the panel form
+    updates the residual instead of recomputing it), not in the order of the
+    blocks."""
     d = dev()
     if which == "hex32":
         p, Ho = _hex32_case()
@@ -414,11 +416,13 @@ def test_sweep_forms_agree(which):
     tol = max(1e-10, 16 * kappas(Ho)[1] * EPS)
     rng = np.random.default_rng(33)
     forms = {}
-    for form in ("colour", "one", "pipe"):
+    for form in ("colour", "one", "pipe", "panel"):
         H = _with_env({"HCURL_AMG_SWEEP": form, "HCURL_AMG_DENSE_SWEEP": "0"},
                       lambda: amglib.Hierarchy(p.A, p.G))
         info = H.info()
-        assert all(lv["sweep_form"] == form for lv in info[:-1]), [lv["sweep_form"] for lv in info]
+        # the panel form needs n <= 32768 (its grid of row tiles runs at once)
+        assert all(lv["sweep_form"] == form for lv in info[:-1] if form != "panel" or lv["n"] <= 32768), \
+            [lv["sweep_form"] for lv in info]
         xs = []
         for lvl in range(len(info) - 1):
             n = info[lvl]["n"]
@@ -482,17 +486,22 @@ def _hex32_case():
 @pytest.mark.parametrize("form", ["lds", "global"])
 def test_dense_level_sweep_matches_oracle(form):
     """Level 2 of a 32^3 jump problem (1,176 rows, 68% dense, 343 blocks in
-    241 colours) is swept block by block in one workgroup with r = b - A x
-    kept in LDS (or, the form used above 2,048 rows, in global memory) and
-    updated.  Forward, backward, forward sweeps from a nonzero start against
-    the oracle's level-2 sweep, and the V-cycle against the row-form sweep."""
+    241 colours), with the dense form requested, is swept block by block in
+    one workgroup with r = b - A x kept in LDS (or, the form used above 2,048
+    rows, in global memory) and updated.  Forward, backward, forward sweeps
+    from a nonzero start against the oracle's level-2 sweep, and the V-cycle
+    against the row-form sweep."""
     import os
     d = dev()
     p, Ho = _hex32_case()
+    env = {"HCURL_AMG_SWEEP": "dense"}
     if form == "global":
-        os.environ["HCURL_AMG_DENSE_BIG"] = "1"
+        env["HCURL_AMG_DENSE_BIG"] = "1"
+    H = _with_env(env, lambda: amglib.Hierarchy(p.A, p.G))
+    assert H.info()[2]["sweep_form"] == "dense"
     try:
-        H = amglib.Hierarchy(p.A, p.G)
+        if form == "global":
+            os.environ["HCURL_AMG_DENSE_BIG"] = "1"
         _dense_sweep_checks(d, p, Ho, H)
     finally:
         os.environ.pop("HCURL_AMG_DENSE_BIG", None)
