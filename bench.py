@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 FETCH_SIZE / WRITE_SIZE passes (calibrated on a 1 GiB copy) summarised in
 # profiles/k_schwarz_l0_hex64_counters.md; valid for that kernel and workload only
 # (None while the kernel has changed since the counters were taken)
-SCHWARZ_L0_TRAFFIC_64 = None
+SCHWARZ_L0_TRAFFIC_64 = (2.0 * 55640.8 + 3561.0) * 1024
 
 
 def log(*a):
