@@ -108,11 +108,22 @@ def one_step(amg, Ad, Gd, f, torch, prec, maxit, p_trunc=0.0):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     u = torch.zeros_like(f)
-    st = H.pcg(f, u, rtol=1e-8, maxit=maxit)
+    try:
+        st = H.pcg(f, u, rtol=1e-8, maxit=maxit)
+    except amg.AmgError as e:
+        # the FP32 form can break down (an indefinite FP32 preconditioner);
+        # record it as not converged instead of ending the measurement
+        if prec == 64:
+            raise
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return H, dict(setup_s=t1 - t0, solve_s=t2 - t1, total_s=t2 - t0, iterations=None,
+                       relres=None, true_relres=None, status=-1, replacements=0, error=str(e))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     return H, dict(setup_s=t1 - t0, solve_s=t2 - t1, total_s=t2 - t0, iterations=st["iterations"],
-                   relres=st["relres"], true_relres=st["true_relres"], status=st["status"])
+                   relres=st["relres"], true_relres=st["true_relres"], status=st["status"],
+                   replacements=st["replacements"])
 
 
 def time_kernels(amg, H, f, torch, reps=20):
@@ -349,6 +360,7 @@ def main():
         t1 = time.perf_counter()
         if prec == 64:
             fp64_its[tau] = runs[-1]["iterations"]
+        extra = {"error": runs[-1]["error"]} if "error" in runs[-1] else {}
         kt = time_kernels(amg, H, f, torch)
         log(f"{name} kernels: {kt}")
         info = H.info()
@@ -356,11 +368,13 @@ def main():
             seconds=(t1 - t0) / steps, setup_s=float(np.mean([r["setup_s"] for r in runs])),
             solve_s=float(np.mean([r["solve_s"] for r in runs])), iterations=runs[-1]["iterations"],
             converged=runs[-1]["status"] == 0, relres=runs[-1]["relres"],
-            true_relres=runs[-1]["true_relres"], p_trunc=tau, vcycle_ms=kt["vcycle_ms"],
+            true_relres=runs[-1]["true_relres"], replacements=runs[-1]["replacements"],
+            p_trunc=tau, vcycle_ms=kt["vcycle_ms"],
             vcycle_GBs=kt["vcycle_GBs"], vcycle_hbm_frac=kt["vcycle_GBs"] / HBM_PEAK_GBS,
             level0_sweep_ms=kt["sweep_ms"], level0_sweep_GBs=kt["sweep_GBs"],
             sweep_ms_per_level=kt["per_level"],
-            levels=[l["n"] for l in info], oc=sum(l["nnz"] for l in info) / info[0]["nnz"])
+            levels=[l["n"] for l in info], oc=sum(l["nnz"] for l in info) / info[0]["nnz"],
+            sweep_forms=[l["sweep_form"] for l in info[:-1]], **extra)
         if is_head:
             headline = (t1 - t0) / steps, runs, kt
         H.close()

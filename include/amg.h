@@ -100,6 +100,7 @@ typedef struct {
   double true_relres;      /* final true residual recomputed with one extra SpMV */
   double seconds;          /* wall time of the solve on the host clock */
   double *history;         /* optional caller buffer (maxit + 1 doubles) of residual norms, or NULL */
+  int replacements;        /* times CG continued from the true residual (see amg_pcg_solve) */
 } amg_solve_stats;
 
 typedef struct {
@@ -158,8 +159,15 @@ amg_status amg_vcycle(amg_hier *h, const double *r, double *z, void *stream);
 /* Preconditioned CG on A u = f (FP64 vectors, reductions and updates; the
    V-cycle in the handle's precision, with the flexible Polak-Ribiere beta
    for the FP32 form).  f, u: device buffers of n doubles; u holds the
-   initial guess on entry and the iterate on exit.  Stops when
-   ||r_k|| <= rtol ||r_0||.  Returns AMG_NOT_CONVERGED after maxit. */
+   initial guess on entry and the iterate on exit.  Stops when the
+   recursively updated residual satisfies ||r|| <= rtol ||f - A u0|| and the
+   true residual f - A u does too; rounding makes the two drift apart over
+   many iterations on ill-conditioned systems, so when only the recursive one
+   meets the tolerance, CG continues from the true residual with a fresh
+   direction, until the true residual meets it or a restart no longer halves
+   it (the attainable accuracy of FP64 on that system; stats->true_relres
+   then reports it, above rtol).  Returns AMG_NOT_CONVERGED after maxit
+   iterations. */
 amg_status amg_pcg_solve(amg_hier *h, const double *f, double *u, double rtol, int maxit,
                          amg_solve_stats *stats, void *stream);
 

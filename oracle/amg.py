@@ -690,9 +690,14 @@ def vcycle(H, b, dtype=np.float64, level=0):
 
 def pcg(H, A, f, x0=None, rtol=1e-8, maxit=500, dtype=np.float64, flexible=None):
     """Preconditioned CG (FP64) with one V-cycle as preconditioner; stops when
-    ||f - A x_k|| <= rtol ||f - A x_0|| (recursive residual).  With an FP32
-    V-cycle the Polak-Ribiere (flexible) beta is used.  Returns
-    (x, iterations, residual-norm history)."""
+    ||f - A x_k|| <= rtol ||f - A x_0|| (R14: the test is on the residual of
+    the system).  CG updates its residual recursively; when that one meets
+    the tolerance, f - A x_k is formed, and if it does not meet it CG goes on
+    from it with a fresh direction (rounding makes the two drift apart over
+    long runs), until it does or a restart no longer halves it (the
+    attainable accuracy of FP64 on the system).  With an FP32 V-cycle the
+    Polak-Ribiere (flexible) beta is used.  Returns (x, iterations,
+    residual-norm history)."""
     A = sp.csr_matrix(A)
     f = np.asarray(f, dtype=np.float64)
     x = np.zeros_like(f) if x0 is None else np.array(x0, dtype=np.float64)
@@ -707,6 +712,7 @@ def pcg(H, A, f, x0=None, rtol=1e-8, maxit=500, dtype=np.float64, flexible=None)
     p = z.copy()
     rz = r @ z
     it = 0
+    restarts, t_last = 0, 0.0
     while it < maxit:
         q = A @ p
         alpha = rz / (p @ q)
@@ -717,7 +723,15 @@ def pcg(H, A, f, x0=None, rtol=1e-8, maxit=500, dtype=np.float64, flexible=None)
         nr = np.linalg.norm(r)
         hist.append(nr)
         if nr <= rtol * r0:
-            break
+            r = f - A @ x
+            t = np.linalg.norm(r)
+            if t <= rtol * r0 or it >= maxit or (restarts > 0 and t > 0.5 * t_last):
+                break
+            restarts, t_last = restarts + 1, t
+            z = vcycle(H, r, dtype).astype(np.float64)
+            rz = r @ z
+            p = z.copy()
+            continue
         z = vcycle(H, r, dtype).astype(np.float64)
         rz_new = r @ z
         beta = ((r - r_old) @ z) / rz if flexible else rz_new / rz

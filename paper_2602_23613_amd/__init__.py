@@ -116,7 +116,7 @@ class Hierarchy:
         status = _lib.check(load().amg_pcg_solve(self._h, f.data_ptr(), u.data_ptr(), rtol, maxit,
                                                  C.byref(st), _stream(stream)))
         out = dict(status=status, iterations=st.iterations, relres=st.relres,
-                   true_relres=st.true_relres, seconds=st.seconds)
+                   true_relres=st.true_relres, seconds=st.seconds, replacements=st.replacements)
         if history:
             out["history"] = hist[:st.iterations + 1].copy()
         return out

@@ -56,7 +56,8 @@ class amg_options(C.Structure):
 
 class amg_solve_stats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("relres", C.c_double), ("true_relres", C.c_double),
-                ("seconds", C.c_double), ("history", C.POINTER(C.c_double))]
+                ("seconds", C.c_double), ("history", C.POINTER(C.c_double)),
+                ("replacements", C.c_int)]
 
 
 class amg_level_info(C.Structure):

@@ -1399,8 +1399,9 @@ amg_status amg_pcg_solve(amg_hier* h, const double* f, double* u, double rtol, i
     reduce(red_grid(), h->d_partial, h->d_sc, SC_RR, -1, st);
     double r0 = std::sqrt(read_scalar(h, SC_RR, st));
     if (!std::isfinite(r0)) fail(AMG_ERR_NOT_FINITE, "initial residual is not finite");
-    int it = 0;
-    double nr = r0;
+    int it = 0, replacements = 0;
+    bool converged = r0 == 0.0;
+    double nr = r0, tr_last = 0.0;
     if (stats && stats->history) stats->history[0] = r0;
     if (r0 > 0.0) {
       vcycle_graph(h, r, z, st);
@@ -1423,7 +1424,29 @@ amg_status amg_pcg_solve(amg_hier* h, const double* f, double* u, double rtol, i
           std::fprintf(stderr, "[amg] pcg iteration %d relres %.3e\n", it, nr / r0);
           std::fflush(stderr);
         }
-        if (nr <= rtol * r0) break;
+        if (nr <= rtol * r0) {
+          // the recursive residual has drifted from f - A u by rounding:
+          // stop once the true residual meets the tolerance, or once a
+          // restart no longer halves it (it sits at the attainable accuracy
+          // of FP64 on this system); else continue from it with a fresh
+          // direction
+          converged = true;
+          residual<double>(A, u, f, r, st);
+          dot2(n, r, r, nullptr, h->d_partial, st);
+          reduce(red_grid(), h->d_partial, h->d_sc, SC_RR, -1, st);
+          const double tr = std::sqrt(read_scalar(h, SC_RR, st));
+          if (!std::isfinite(tr)) fail(AMG_ERR_NOT_FINITE, "residual became non-finite");
+          if (tr <= rtol * r0 || it >= maxit || (replacements > 0 && tr > 0.5 * tr_last)) break;
+          converged = false;
+          tr_last = tr;
+          nr = tr;
+          ++replacements;
+          vcycle_graph(h, r, z, st);
+          dot2(n, r, z, nullptr, h->d_partial, st);
+          reduce(red_grid(), h->d_partial, h->d_sc, SC_RZ, -1, st);
+          cg_dir(n, h->d_sc, z, p, 1, st);
+          continue;
+        }
         vcycle_graph(h, r, z, st);
         dot2(n, r, z, rold, h->d_partial, st);
         reduce(red_grid(), h->d_partial, h->d_sc, SC_RZNEW, flexible ? SC_ROLDZ : -1, st);
@@ -1443,9 +1466,10 @@ amg_status amg_pcg_solve(amg_hier* h, const double* f, double* u, double rtol, i
       reduce(red_grid(), h->d_partial, h->d_sc, SC_RR, -1, st);
       double tr = std::sqrt(read_scalar(h, SC_RR, st));
       stats->true_relres = r0 > 0 ? tr / r0 : 0.0;
+      stats->replacements = replacements;
     }
     HIPC(hipGetLastError());
-    return (r0 == 0.0 || nr <= rtol * r0) ? AMG_OK : AMG_NOT_CONVERGED;
+    return converged ? AMG_OK : AMG_NOT_CONVERGED;
   });
 }
 

@@ -832,6 +832,44 @@ __device__ __forceinline__ PanelGroup panel_group(const PanelArgs<T>& P, int pos
   return q;
 }
 
+// One block B (slots p .. p+s-1, s <= SB) of the panel chain, in one
+// wavefront (lane k = slot k): the lanes of B form d_k = sum_j
+// (A_BB^{-1})_{k-p, j} r_{p+j}, then every slot's residual drops by
+// sum_j A(slot, p+j) d_j.  Operands come into registers first; the values
+// of other lanes are broadcast through the scalar unit, all independent of
+// each other; each sum is a fixed pairwise tree, so the dependent chain is
+// two tree depths instead of 2 s multiply-adds.
+template <class T, int SB>
+__device__ __forceinline__ T tree_sum(T (&v)[SB]) {
+#pragma unroll
+  for (int w = SB / 2; w > 0; w /= 2)
+#pragma unroll
+    for (int j = 0; j < w; ++j) v[j] = v[j] + v[j + w];
+  return v[0];
+}
+
+template <class T, int SB>
+__device__ __forceinline__ void panel_step(int k, int m, int p, int s, const T* Bi, const T* Aloc,
+                                           T& rk, T& dk) {
+  const bool mine = k >= p && k < p + s;
+  const int i = k - p;
+  T v[SB];
+#pragma unroll
+  for (int j = 0; j < SB; ++j) {
+    const int hi = i > j ? i : j, lo = i > j ? j : i;
+    const T b = (mine && j < s) ? Bi[hi * (hi + 1) / 2 + lo] : T(0);
+    v[j] = b * (j < s ? lane_bcast(rk, p + j) : T(0));
+  }
+  const T d = tree_sum<T, SB>(v);
+  if (mine) dk = d;
+#pragma unroll
+  for (int j = 0; j < SB; ++j) {
+    const T a = (j < s && k < m) ? Aloc[(p + j) * PANEL_SLOTS + k] : T(0);
+    v[j] = a * (j < s ? lane_bcast(d, p + j) : T(0));
+  }
+  rk -= tree_sum<T, SB>(v);
+}
+
 // entries of the 64 x 64 slot matrices that one of the 192 staging threads
 // holds: e = t + 192 j
 constexpr int PANEL_STAGE = 192;
@@ -902,31 +940,14 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelArgs<T> P) {
         }
         for (int jb = 0; jb < q.nbk; ++jb) {
           const int ib = P.backward ? q.nbk - 1 - jb : jb;
-          // uniform across the wavefront: keeps the broadcasts below on the scalar unit
+          // uniform across the wavefront: keeps the broadcasts on the scalar unit
           const int p = __builtin_amdgcn_readfirstlane(blk_p[ib]);
           const int s = __builtin_amdgcn_readfirstlane(blk_s[ib]);
           const T* Bi = fl + __builtin_amdgcn_readfirstlane(blk_f[ib]);
-          // the lanes of B's slots (p <= k < p + s) form d_k = sum_j
-          // (A_BB^{-1})_{k-p, j} r_{p+j}; then every slot's residual drops by
-          // A(slot, B) d.  Operands come into registers first; values are
-          // broadcast through the scalar unit.
-          const bool mine = k >= p && k < p + s;
-          const int i = k - p;
-          T Br[PANEL_SMAX], Ac[PANEL_SMAX];
-#pragma unroll
-          for (int j = 0; j < PANEL_SMAX; ++j) {
-            const int hi = i > j ? i : j, lo = i > j ? j : i;
-            Br[j] = (mine && j < s) ? Bi[hi * (hi + 1) / 2 + lo] : T(0);
-            Ac[j] = (j < s && k < m) ? Aloc[(p + j) * PANEL_SLOTS + k] : T(0);
-          }
-          T d = 0;
-#pragma unroll
-          for (int j = 0; j < PANEL_SMAX; ++j)
-            if (j < s) d += Br[j] * lane_bcast(rk, p + j);
-          if (mine) dk = d;
-#pragma unroll
-          for (int j = 0; j < PANEL_SMAX; ++j)
-            if (j < s) rk -= Ac[j] * lane_bcast(d, p + j);
+          if (s <= PANEL_SMAX / 2)
+            panel_step<T, PANEL_SMAX / 2>(k, m, p, s, Bi, Aloc, rk, dk);
+          else
+            panel_step<T, PANEL_SMAX>(k, m, p, s, Bi, Aloc, rk, dk);
         }
         // x_B += d for the group's blocks in sweep order: a DoF in two blocks
         // of the group (slots k and dup) gets both updates from the lower slot's lane

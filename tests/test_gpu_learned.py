@@ -178,7 +178,8 @@ def test_learned_setup_matches_exact(name, loss_ratio, acc_frac):
     u = torch.zeros_like(f)
     s = H.pcg(f, u, rtol=1e-8, maxit=500)
     _, it_o, _ = oracle.pcg(Ho, p.A, p.f, maxit=500)
-    assert s["status"] == 0 and abs(s["iterations"] - it_o) <= 1, (s["iterations"], it_o)
+    tol_its = 1 if s["replacements"] == 0 else max(3, 0.1 * it_o)
+    assert s["status"] == 0 and abs(s["iterations"] - it_o) <= tol_its, (s["iterations"], it_o)
     uu = u.cpu().numpy()
     assert np.linalg.norm(p.f - p.A @ uu) / np.linalg.norm(p.f) <= 2e-8
     H.close()
