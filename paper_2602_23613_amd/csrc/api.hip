@@ -551,7 +551,7 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   }
   L.chunk_blk = h->pool.upload(chunk_blk, st);
   L.colour_chunk_dev = h->pool.upload(std::vector<int32_t>(L.colour_chunk.begin(), L.colour_chunk.end()), st);
-  L.sweep_sync = h->pool.get<int32_t>((size_t)I.ncolors + 1);
+  L.sweep_sync = h->pool.get<int32_t>((size_t)SYNC_STRIDE * (I.ncolors + 1));
   int grid = h->cu_count;
   if (const char* e = std::getenv("HCURL_AMG_PIPE_GRID")) grid = std::max(1, std::atoi(e));
   L.pipe_grid = std::max(1, std::min(nchunks, grid));
@@ -563,7 +563,7 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
       L.dgrp = h->pool.upload(dgrp, st);
       L.sdup = h->pool.upload(sdup, st);
       L.dsl = h->pool.get<double>((size_t)std::max(L.ngroups, 1) * PANEL_GROUP_SLOTS);
-      L.psync = h->pool.get<int>((size_t)std::max(L.ngroups, 1) * 2);
+      L.psync = h->pool.get<int>((size_t)std::max(L.ngroups, 1) * 2 * SYNC_STRIDE);
       std::vector<int64_t> so(L.ngroups + 1, 0), co(L.ngroups + 1, 0);
       for (int g = 0; g < L.ngroups; ++g) {
         const int64_t m = sb_ptr[grp_blk[g + 1]] - sb_ptr[grp_blk[g]];

@@ -375,7 +375,9 @@ __global__ __launch_bounds__(1024) void k_schwarz_sweep1(SmootherArgs<T> D, int 
 
 // Whole sweep in one launch with the colours pipelined across workgroups.
 // Chunks are numbered in sweep order (colour by colour) and handed out by a
-// ticket counter, sync[0]; sync[1 + c] counts the finished chunks of colour c.
+// ticket counter, sync[0]; sync[SYNC_STRIDE (1 + c)] counts the finished
+// chunks of colour c (each counter on a cache line of its own: they are
+// polled by many workgroups at once).
 // A workgroup loads its chunk's structure at once and starts the x-dependent
 // work when every chunk of the colour before it in sweep order has finished;
 // those chunks waited in turn for theirs, so every earlier colour is done and
@@ -415,7 +417,7 @@ __global__ __launch_bounds__(1024) void k_schwarz_pipe(SmootherArgs<T> D, int ba
     if (tid == 0 && prev >= 0 && prev < D.ncolours) {
       const int need = D.colour_chunk[prev + 1] - D.colour_chunk[prev];
       int spins = 0;
-      while (__hip_atomic_load(&sync[1 + prev], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+      while (__hip_atomic_load(&sync[SYNC_STRIDE * (1 + prev)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
         if ((++spins & 255) == 0 &&
             __hip_atomic_load(D.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
           break;
@@ -431,7 +433,7 @@ __global__ __launch_bounds__(1024) void k_schwarz_pipe(SmootherArgs<T> D, int ba
     __builtin_amdgcn_s_waitcnt(0);   // this thread's x stores have completed
     __syncthreads();
     if (tid == 0) {
-      __hip_atomic_fetch_add(&sync[1 + colour], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&sync[SYNC_STRIDE * (1 + colour)], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       ticket[1] = next;
     }
     __syncthreads();
@@ -485,7 +487,7 @@ __global__ void k_zero_i32(int n, int* __restrict__ p) {
 
 template <class T>
 void schwarz_pipe(const SmootherDev<T>& S, int backward, const T* b, T* x, hipStream_t st) {
-  const int nsync = S.ncolours + 1;
+  const int nsync = SYNC_STRIDE * (S.ncolours + 1);
   hipLaunchKernelGGL(k_zero_i32, dim3((nsync + 255) / 256), dim3(256), 0, st, nsync, S.sync);
   const SmootherArgs<T> D = S;
 #define LAUNCH_PIPE(L)                                                                           \
@@ -781,8 +783,8 @@ struct PanelArgs {
   T* r = nullptr;                     // b - A x on entry, kept equal to it
   T* x = nullptr;
   T* dsl = nullptr;                   // per sweep position: d of each slot of the group
-  int* flag = nullptr;                // per sweep position: the chain has published dsl
-  int* done = nullptr;                // per sweep position: tiles that have applied it
+  int* flag = nullptr;                // per sweep position (stride SYNC_STRIDE): dsl is published
+  int* done = nullptr;                // per sweep position (stride SYNC_STRIDE): tiles that applied it
   int* err = nullptr;
 };
 
@@ -923,7 +925,7 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelArgs<T> P) {
       PanelGroup qn{};
       if (more) qn = panel_group(P, pos + 1);
       // the tiles have applied every group two or more positions back
-      if (tid == 0 && pos >= 2) panel_wait(&P.done[pos - 2], P.ntiles, P.err, P.spin_max);
+      if (tid == 0 && pos >= 2) panel_wait(&P.done[SYNC_STRIDE * (pos - 2)], P.ntiles, P.err, P.spin_max);
       __syncthreads();
       // staging registers of waves 1-3 (next group's structure and slice,
       // and the entries A(D_next, D_g) of the correction)
@@ -1008,7 +1010,7 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelArgs<T> P) {
         }
       }
       __syncthreads();
-      if (tid == 0) __hip_atomic_store(&P.flag[pos], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (tid == 0) __hip_atomic_store(&P.flag[SYNC_STRIDE * pos], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (!more) break;
       // correction partial sums (this group's d is in ds_s) and the next group's staging
       if (tid >= 64) {
@@ -1071,7 +1073,7 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelArgs<T> P) {
     for (int k = 0; k < PANEL_SLOTS; ++k) a[k] = (upd && k < m) ? P.Acm[(int64_t)dof_s[k] * n + i] : T(0);
     // the tile wrote r_i last itself, or the chain did before an earlier flag
     const T ri = upd ? ld_x<T, true>(P.r + i) : T(0);
-    if (tid == 0) panel_wait(&P.flag[pos], 1, P.err, P.spin_max);
+    if (tid == 0) panel_wait(&P.flag[SYNC_STRIDE * pos], 1, P.err, P.spin_max);
     __syncthreads();
     if (tid < m) ds_s[tid] = ld_x<T, true>(P.dsl + (int64_t)pos * PANEL_SLOTS + tid);
     __syncthreads();
@@ -1084,7 +1086,7 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelArgs<T> P) {
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (tid == 0) __hip_atomic_fetch_add(&P.done[pos], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) __hip_atomic_fetch_add(&P.done[SYNC_STRIDE * pos], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -1135,7 +1137,8 @@ void panel_sweep(int n, int ngroups, int backward, const int32_t* grp_blk, const
                  const int32_t* dgrp, const int32_t* sdup, T* r, T* x, T* dsl, int* sync, int* err,
                  int spin_max, hipStream_t st) {
   if (ngroups <= 0) return;
-  hipLaunchKernelGGL(k_zero_i32, dim3((2 * ngroups + 255) / 256), dim3(256), 0, st, 2 * ngroups, sync);
+  const int nsync = 2 * SYNC_STRIDE * ngroups;
+  hipLaunchKernelGGL(k_zero_i32, dim3((nsync + 255) / 256), dim3(256), 0, st, nsync, sync);
   PanelArgs<T> P;
   P.n = n;
   P.ngroups = ngroups;
@@ -1158,7 +1161,7 @@ void panel_sweep(int n, int ngroups, int backward, const int32_t* grp_blk, const
   P.x = x;
   P.dsl = dsl;
   P.flag = sync;
-  P.done = sync + ngroups;
+  P.done = sync + SYNC_STRIDE * ngroups;
   P.err = err;
   hipLaunchKernelGGL((k_schwarz_panel<T>), dim3(1 + P.ntiles), dim3(256), 0, st, P);
 }

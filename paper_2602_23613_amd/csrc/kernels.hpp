@@ -24,6 +24,10 @@ struct CsrPat {
   const int32_t* col = nullptr;
 };
 
+// Counters of the one-launch sweeps sit SYNC_STRIDE ints (128 bytes) apart,
+// one cache line each.
+constexpr int SYNC_STRIDE = 32;
+
 // Smoother blocks sorted by colour and packed into chunks: the device side (a
 // plain struct, passed to the kernels by value) ...
 template <class T>
@@ -43,7 +47,7 @@ struct SmootherArgs {
   const int64_t* srow_ptr = nullptr;      // the smoother's copy of A's rows in star order
   const int32_t* scol = nullptr;
   const T* sval = nullptr;
-  int* sync = nullptr;                    // pipelined sweep: ticket + per-colour counters
+  int* sync = nullptr;                    // pipelined sweep: ticket + per-colour counters (SYNC_STRIDE apart)
   int* err = nullptr;                     // pipelined sweep: set when a wait gave up
   int spin_max = 0;
 };
@@ -74,7 +78,7 @@ struct SmootherDev : SmootherArgs<T> {
   const T* cor = nullptr;
   const int64_t* slc_off = nullptr;
   const int64_t* cor_off = nullptr;
-  int* psync = nullptr;                 // flags and tile counters (2 per group)
+  int* psync = nullptr;                 // flags and tile counters (2 per group, SYNC_STRIDE apart)
 };
 
 // scalar slots of the CG state vector
