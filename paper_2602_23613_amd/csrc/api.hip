@@ -181,6 +181,8 @@ struct Level {
   int64_t* slc_off = nullptr;    // panel form: per-group slices and inter-group blocks of A
   int64_t* cor_off = nullptr;
   int64_t slc_total = 0, cor_total = 0;
+  double* binv_pad = nullptr;    // panel form: per star row, its row of the block inverse (padded)
+  float* binv_pad32 = nullptr;
   double* slc = nullptr;
   double* cor = nullptr;
   float* slc32 = nullptr;
@@ -235,9 +237,9 @@ struct Level {
     s.n = (int)n;
     s.ngroups = ngroups; s.grp_blk = grp_blk; s.dgrp = dgrp; s.sdup = sdup; s.psync = psync;
     if constexpr (std::is_same<T, double>::value) {
-      s.dsl = dsl; s.slc = slc; s.cor = cor;
+      s.dsl = dsl; s.slc = slc; s.cor = cor; s.binv_pad = binv_pad;
     } else {
-      s.dsl = dsl32; s.slc = slc32; s.cor = cor32;
+      s.dsl = dsl32; s.slc = slc32; s.cor = cor32; s.binv_pad = binv_pad32;
     }
     s.slc_off = slc_off; s.cor_off = cor_off;
     s.nblocks = (int)nstars;
@@ -360,12 +362,14 @@ void host_csr(const amg_csr* M, std::vector<int64_t>& ptr, std::vector<int32_t>&
 //   pipe    16 or more colours: one launch, colours pipelined across
 //           workgroups (a launch per colour would leave the GPU idle between
 //           short colours);
-//   panel   16 or more colours and rows longer than 4096 entries (n <=
-//           32768): the Galerkin operators near the bottom of a large
-//           hierarchy are nearly dense, and a pipelined chunk would stream
-//           tens of thousands of entries per block; instead one workgroup
-//           chains groups of blocks while the others apply each group's
-//           residual update to their rows from a dense copy of A;
+//   panel   16 or more colours, n <= 32768, and rows longer than 4096
+//           entries or at most 1.5 blocks per colour: the Galerkin operators
+//           near the bottom of the hierarchy are nearly dense, a pipelined
+//           chunk would stream tens of thousands of entries per block, and
+//           with one block per colour every colour step is a full round of
+//           inter-workgroup signalling; instead one workgroup chains groups
+//           of blocks while the others apply each group's residual update to
+//           their rows from a dense copy of A;
 //   one     small level with fewer colours: the whole sweep in one workgroup;
 //   colour  one launch per colour (the finest levels: few colours, many blocks);
 //   dense   nearly sequential level (at most 1.5 blocks per colour): block by
@@ -380,7 +384,8 @@ int sweep_mode_for(int64_t n, int64_t nnz, int64_t ns, int ncolours, int maxs) {
   const bool dense_any = !(dense_env && dense_env[0] == '0') && dense_sweep_ok<double>((int)n, maxs);
   const bool panel_ok = panel_sweep_ok((int)std::min<int64_t>(n, INT32_MAX), maxs);
   int mode = SWEEP_COLOUR;
-  if (ncolours >= 16) mode = (panel_ok && nnz > 4096 * n) ? SWEEP_PANEL : SWEEP_PIPE;
+  if (ncolours >= 16)
+    mode = (panel_ok && (nnz > 4096 * n || 2 * ns <= 3 * (int64_t)ncolours)) ? SWEEP_PANEL : SWEEP_PIPE;
   else if (nnz <= 200000) mode = SWEEP_ONE;
   if (const char* e = std::getenv("HCURL_AMG_SWEEP")) {
     const std::string f(e);
@@ -577,6 +582,7 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
       L.cor_off = h->pool.upload(co, st);
       L.slc = h->pool.get<double>(std::max<int64_t>(L.slc_total, 1));
       L.cor = h->pool.get<double>(std::max<int64_t>(L.cor_total, 1));
+      L.binv_pad = h->pool.get<double>((size_t)std::max<int64_t>(sb_ptr[ns], 1) * PANEL_ROW_WIDTH);
     } else {
       L.sweep_mode = SWEEP_PIPE;
     }
@@ -609,6 +615,8 @@ void factor_smoother(amg_hier* h, Level& L, int level, hipStream_t st) {
   check_flag(h, st, AMG_ERR_NOT_SPD, "smoother block Cholesky: non-positive pivot on level " +
                                          std::to_string(level));
   star_inv((int64_t)L.ints.star_dofs.size(), L.row_blk, L.sb_ptr, L.fac_off, L.fac, L.binv, st);
+  if (L.sweep_mode == SWEEP_PANEL)
+    pad_inv((int64_t)L.ints.star_dofs.size(), L.row_blk, L.sb_ptr, L.fac_off, L.binv, L.binv_pad, st);
   l1inv(L.A_dev<double>(), L.dinv, st);
 }
 
@@ -831,8 +839,11 @@ void cast_level(amg_hier* h, Level& L, hipStream_t st) {
       L.slc32 = h->pool.get<float>(std::max<int64_t>(L.slc_total, 1));
       L.cor32 = h->pool.get<float>(std::max<int64_t>(L.cor_total, 1));
     }
+    const int64_t npad = (int64_t)L.ints.star_dofs.size() * PANEL_ROW_WIDTH;
+    if (!L.binv_pad32) L.binv_pad32 = h->pool.get<float>(std::max<int64_t>(npad, 1));
     cast<double, float>(L.slc_total, L.slc, L.slc32, st);
     cast<double, float>(L.cor_total, L.cor, L.cor32, st);
+    cast<double, float>(npad, L.binv_pad, L.binv_pad32, st);
   }
   if (L.sweep_mode == SWEEP_DENSE || L.sweep_mode == SWEEP_PANEL) {
     if (!L.Acm32) L.Acm32 = h->pool.get<float>((size_t)L.n * L.n);

@@ -762,7 +762,7 @@ void dense_sweep(int n, int nblocks, int max_block, int backward, const int64_t*
 constexpr int PANEL_SLOTS = PANEL_GROUP_SLOTS;
 constexpr int PANEL_TILE = 256;
 constexpr int PANEL_NMAX = 32768;
-constexpr int PANEL_SMAX = 16;
+constexpr int PANEL_SMAX = PANEL_ROW_WIDTH;
 constexpr int PANEL_FMAX = PANEL_SLOTS * (PANEL_SMAX + 1) / 2;
 
 template <class T>
@@ -772,7 +772,7 @@ struct PanelArgs {
   const int64_t* sb_ptr = nullptr;
   const int32_t* sb_dofs = nullptr;
   const int64_t* fac_off = nullptr;
-  const T* binv = nullptr;            // packed symmetric inverses of the blocks
+  const T* binv_pad = nullptr;        // per star row: its row of the block inverse, 16 wide, zero-padded
   const T* Acm = nullptr;             // A(i, j) at Acm[j n + i]
   const T* slc = nullptr;             // per group: A(D_g, D_g), column-major m_g x m_g
   const T* cor = nullptr;             // per group g < G-1: A(D_g+1, D_g), column-major
@@ -851,23 +851,20 @@ __device__ __forceinline__ T tree_sum(T (&v)[SB]) {
 }
 
 template <class T, int SB>
-__device__ __forceinline__ void panel_step(int k, int m, int p, int s, const T* Bi, const T* Aloc,
+__device__ __forceinline__ void panel_step(int k, int m, int p, int s, const T* brow, const T* Aloc,
                                            T& rk, T& dk) {
-  const bool mine = k >= p && k < p + s;
-  const int i = k - p;
+  // brow: this lane's row of its block's inverse, zero beyond the block
+  // (meaningful for the lanes of B only; the others' d is never used)
   T v[SB];
 #pragma unroll
-  for (int j = 0; j < SB; ++j) {
-    const int hi = i > j ? i : j, lo = i > j ? j : i;
-    const T b = (mine && j < s) ? Bi[hi * (hi + 1) / 2 + lo] : T(0);
-    v[j] = b * (j < s ? lane_bcast(rk, p + j) : T(0));
-  }
+  for (int j = 0; j < SB; ++j) v[j] = brow[j] * (j < s ? lane_bcast(rk, p + j) : T(0));
   const T d = tree_sum<T, SB>(v);
-  if (mine) dk = d;
+  if (k >= p && k < p + s) dk = d;
+  const T* acol = Aloc + p * PANEL_SLOTS + k;
 #pragma unroll
   for (int j = 0; j < SB; ++j) {
-    const T a = (j < s && k < m) ? Aloc[(p + j) * PANEL_SLOTS + k] : T(0);
-    v[j] = a * (j < s ? lane_bcast(d, p + j) : T(0));
+    const T a = acol[j * PANEL_SLOTS];
+    v[j] = (j < s && k < m ? a : T(0)) * (j < s ? lane_bcast(d, p + j) : T(0));
   }
   rk -= tree_sum<T, SB>(v);
 }
@@ -876,12 +873,12 @@ __device__ __forceinline__ void panel_step(int k, int m, int p, int s, const T* 
 // holds: e = t + 192 j
 constexpr int PANEL_STAGE = 192;
 constexpr int PANEL_PER = (PANEL_SLOTS * PANEL_SLOTS + PANEL_STAGE - 1) / PANEL_STAGE;   // 22
-constexpr int PANEL_FPER = (PANEL_FMAX + PANEL_STAGE - 1) / PANEL_STAGE;                 // 6
+constexpr int PANEL_FPER = (PANEL_SLOTS * PANEL_SMAX + PANEL_STAGE - 1) / PANEL_STAGE;  // 6
 
 template <class T>
 __global__ __launch_bounds__(256) void k_schwarz_panel(PanelArgs<T> P) {
   __shared__ T Aloc[PANEL_SLOTS * PANEL_SLOTS];   // Aloc[l * 64 + k] = A(dof_k, dof_l)
-  __shared__ T fl[PANEL_FMAX];
+  __shared__ T fl[PANEL_SLOTS * PANEL_SMAX];   // per slot: its row of the block inverse (padded)
   __shared__ T part[3][PANEL_SLOTS];
   __shared__ T ds_s[PANEL_SLOTS];
   __shared__ T corr[PANEL_SLOTS];
@@ -910,7 +907,8 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelArgs<T> P) {
         blk_s[tid] = bs;
         blk_f[tid] = (int)(bf - q.f0);
       }
-      for (int t = tid; t < q.nf; t += 256) fl[t] = P.binv[q.f0 + t];
+      for (int t = tid; t < PANEL_SLOTS * PANEL_SMAX; t += 256)
+        fl[t] = t < q.m * PANEL_SMAX ? P.binv_pad[q.q0 * PANEL_SMAX + t] : T(0);
       __syncthreads();
       for (int e = tid; e < PANEL_SLOTS * PANEL_SLOTS; e += 256) {
         const int l = e / PANEL_SLOTS, k = e % PANEL_SLOTS;
@@ -945,11 +943,11 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelArgs<T> P) {
           // uniform across the wavefront: keeps the broadcasts on the scalar unit
           const int p = __builtin_amdgcn_readfirstlane(blk_p[ib]);
           const int s = __builtin_amdgcn_readfirstlane(blk_s[ib]);
-          const T* Bi = fl + __builtin_amdgcn_readfirstlane(blk_f[ib]);
+          const T* brow = fl + (k < m ? k : 0) * PANEL_SMAX;
           if (s <= PANEL_SMAX / 2)
-            panel_step<T, PANEL_SMAX / 2>(k, m, p, s, Bi, Aloc, rk, dk);
+            panel_step<T, PANEL_SMAX / 2>(k, m, p, s, brow, Aloc, rk, dk);
           else
-            panel_step<T, PANEL_SMAX>(k, m, p, s, Bi, Aloc, rk, dk);
+            panel_step<T, PANEL_SMAX>(k, m, p, s, brow, Aloc, rk, dk);
         }
         // x_B += d for the group's blocks in sweep order: a DoF in two blocks
         // of the group (slots k and dup) gets both updates from the lower slot's lane
@@ -987,7 +985,7 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelArgs<T> P) {
 #pragma unroll
         for (int j = 0; j < PANEL_FPER; ++j) {
           const int e = t + PANEL_STAGE * j;
-          fn[j] = e < qn.nf ? P.binv[qn.f0 + e] : T(0);
+          fn[j] = e < qn.m * PANEL_SMAX ? P.binv_pad[qn.q0 * PANEL_SMAX + e] : T(0);
         }
         // slice of the next group (stored contiguously): entry e = l * 64 + k
         const T* Sn = P.slc + P.slc_off[qn.g];
@@ -1041,7 +1039,7 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelArgs<T> P) {
 #pragma unroll
         for (int j = 0; j < PANEL_FPER; ++j) {
           const int e = t + PANEL_STAGE * j;
-          if (e < qn.nf) fl[e] = fn[j];
+          if (e < PANEL_SLOTS * PANEL_SMAX) fl[e] = fn[j];
         }
 #pragma unroll
         for (int j = 0; j < PANEL_PER; ++j) {
@@ -1149,7 +1147,7 @@ void panel_sweep(int n, int ngroups, int backward, const int32_t* grp_blk, const
   P.sb_ptr = sb_ptr;
   P.sb_dofs = sb_dofs;
   P.fac_off = fac_off;
-  P.binv = binv;
+  P.binv_pad = binv;
   P.Acm = Acm;
   P.slc = slc;
   P.cor = cor;
@@ -2022,6 +2020,30 @@ __global__ void k_star_inv(int64_t nrows, const int32_t* __restrict__ row_blk,
     y[i] = a / L[i * (i + 1) / 2 + i];
   }
   for (int i = j; i < s; ++i) B[i * (i + 1) / 2 + j] = y[i];
+}
+
+// Each star row's row of its block's inverse, PANEL_SMAX wide, zero beyond
+// the block (the panel form's operand layout).
+__global__ void k_pad_inv(int64_t nrows, const int32_t* __restrict__ row_blk,
+                          const int64_t* __restrict__ sb_ptr, const int64_t* __restrict__ fac_off,
+                          const double* __restrict__ binv, double* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const int b = row_blk[r];
+  const int s = (int)(sb_ptr[b + 1] - sb_ptr[b]);
+  const int i = (int)(r - sb_ptr[b]);
+  const double* B = binv + fac_off[b];
+  for (int j = 0; j < PANEL_SMAX; ++j) {
+    const int hi = i > j ? i : j, lo = i > j ? j : i;
+    out[r * PANEL_SMAX + j] = j < s ? B[hi * (hi + 1) / 2 + lo] : 0.0;
+  }
+}
+
+void pad_inv(int64_t nrows, const int32_t* row_blk, const int64_t* sb_ptr, const int64_t* fac_off,
+             const double* binv, double* out, hipStream_t st) {
+  if (nrows > 0)
+    hipLaunchKernelGGL(k_pad_inv, dim3((unsigned)((nrows + 127) / 128)), dim3(128), 0, st, nrows,
+                       row_blk, sb_ptr, fac_off, binv, out);
 }
 
 void star_inv(int64_t nrows, const int32_t* row_blk, const int64_t* sb_ptr, const int64_t* fac_off,

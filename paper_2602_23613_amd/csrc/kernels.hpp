@@ -74,6 +74,7 @@ struct SmootherDev : SmootherArgs<T> {
   const int32_t* dgrp = nullptr;        // the (at most two) groups of each DoF
   const int32_t* sdup = nullptr;        // per star row: the group's other slot of its DoF
   T* dsl = nullptr;                     // published block updates (64 per group)
+  const T* binv_pad = nullptr;          // per star row: its row of the block inverse, 16 wide
   const T* slc = nullptr;               // per group A(D_g, D_g), and A(D_g+1, D_g)
   const T* cor = nullptr;
   const int64_t* slc_off = nullptr;
@@ -105,6 +106,7 @@ void star_rows(int64_t nrows, const int32_t* sb_dofs, const int64_t* Aptr, const
 bool panel_sweep_ok(int n, int max_block);
 int panel_tiles(int n);
 constexpr int PANEL_GROUP_SLOTS = 64;
+constexpr int PANEL_ROW_WIDTH = 16;   // largest block of the panel form; width of its inverse rows
 template <class T>
 void panel_sweep(int n, int ngroups, int backward, const int32_t* grp_blk, const int64_t* sb_ptr,
                  const int32_t* sb_dofs, const int64_t* fac_off, const T* binv, const T* Acm,
@@ -142,7 +144,7 @@ void schwarz_sweep(const SmootherDev<T>& S, const CsrDev<T>& A, int backward, co
       return;
     case SWEEP_PANEL:
       residual<T>(A, x, b, S.rtmp, st);
-      panel_sweep<T>(S.n, S.ngroups, backward, S.grp_blk, S.sb_ptr, S.sb_dofs, S.fac_off, S.binv,
+      panel_sweep<T>(S.n, S.ngroups, backward, S.grp_blk, S.sb_ptr, S.sb_dofs, S.fac_off, S.binv_pad,
                      S.Acm, S.slc, S.cor, S.slc_off, S.cor_off, S.dgrp, S.sdup, S.rtmp, x, S.dsl,
                      S.psync, S.err, S.spin_max, st);
       return;
@@ -198,6 +200,8 @@ void mm_vals_wide(int64_t nw, const int32_t* rows, const CsrPat& X, const double
                   const CsrPat& Y, const double* Yval, int64_t ncols, const int64_t* Cptr,
                   const int32_t* Ccol, double* Cval, hipStream_t st);
 
+void pad_inv(int64_t nrows, const int32_t* row_blk, const int64_t* sb_ptr, const int64_t* fac_off,
+             const double* binv, double* out, hipStream_t st);
 void star_inv(int64_t nrows, const int32_t* row_blk, const int64_t* sb_ptr, const int64_t* fac_off,
               const double* fac, double* binv, hipStream_t st);
 void star_chol(int64_t nb, const int64_t* sb_ptr, const int32_t* sb_dofs, const int64_t* fac_off,
