@@ -45,12 +45,29 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def make_workload(N, beta, seed_alpha=None, seed_f=None):
+WORKLOADS = {
+    "hex-jump": "hex N^3 Nedelec, 8^3 subdomains log10(alpha)~U(-4,4)",
+    "tet-checker": "Kuhn 6-tet split of N^3 cubes, vertex jitter 0.2h, checkerboard alpha in "
+                   "{1e-4, 1e4} on 8^3 subdomains",
+}
+
+
+def make_workload(N, beta, seed_alpha=None, seed_f=None, kind="hex-jump", variant=0):
+    """The synthetic workloads.  hex-jump: seeded log-uniform alpha on 8^3
+    subdomains (variant > 0: another seed).  tet-checker: jittered tetrahedra
+    with the binary checkerboard (variant > 0: the checkerboard with lo and hi
+    swapped, a new field of the same law on the same pattern)."""
     import gen
     from gen import fields
     sub = 8
+    if kind == "tet-checker":
+        lo, hi = (1e-4, 1e4) if variant == 0 else (1e4, 1e-4)
+        return gen.make_problem("tet", N, beta=beta, alpha=lambda m: fields.checkerboard(m, sub, lo, hi),
+                                f=lambda n: fields.rhs_uniform(n, 104 if seed_f is None else seed_f),
+                                jitter=0.2, mesh_seed=4)
     if seed_alpha is None:
         seed_alpha, seed_f = (2, 102) if N <= 64 else (3, 103)
+    seed_alpha += 10 * variant
     p = gen.make_problem("hex", N, beta=beta,
                          alpha=lambda m: fields.subdomain_log_uniform(m, sub, seed_alpha),
                          f=lambda n: fields.rhs_uniform(n, seed_f))
@@ -185,14 +202,15 @@ def learned_form(amg, Ad, Gd, f, torch, a):
     field drawn with another seed (same mesh, same pattern)."""
     from gen.mlp_init import init_params, flatten
     seed_alpha = (2 if a.size <= 64 else 3) + 10
-    p2 = make_workload(a.size, a.beta, seed_alpha=seed_alpha, seed_f=0)
+    p2 = make_workload(a.size, a.beta, seed_f=0, kind=a.workload, variant=1)
     A2 = (Ad[0], Ad[1], torch.from_numpy(p2.A.data.astype(np.float64)).to(f.device), Ad[3], Ad[4])
     del p2
     H = amg.Hierarchy(Ad, Gd, vcycle_prec=64)
     st = H.mlp_train(epochs=a.learn_epochs, batch=1024, lr=1e-3, seed=0,
                      init=flatten(init_params(0)), global_iters=a.learn_check_iters)
     log(f"learned: trained {st}")
-    out = dict(field_seed=seed_alpha, train=dict(
+    out = dict(field_seed=seed_alpha if a.workload == "hex-jump" else "checkerboard, lo/hi swapped",
+               train=dict(
         epochs=a.learn_epochs, batch=1024, blocks=st["blocks"], eligible=st["eligible"],
         loss_first=st["loss_first"], loss_last=st["loss_last"], train_s=st["train_seconds"],
         rho_reference=st["rho_reference"]))
@@ -226,11 +244,11 @@ def learned_form(amg, Ad, Gd, f, torch, a):
     return out
 
 
-def cpu_baseline_worker(N, beta, its):
+def cpu_baseline_worker(N, beta, its, kind):
     """Run the oracle on a bounded sample: the same field law on an N^3 mesh,
     full setup plus `its` PCG iterations (test infrastructure timed here only)."""
     import oracle
-    p = make_workload(N, beta)
+    p = make_workload(N, beta, kind=kind)
     t0 = time.perf_counter()
     Ho = oracle.setup(p.A, p.G)
     t1 = time.perf_counter()
@@ -239,10 +257,10 @@ def cpu_baseline_worker(N, beta, its):
     print(json.dumps(dict(n=p.A.shape[0], setup_s=t1 - t0, solve_s=t2 - t1, its=it)))
 
 
-def cpu_baseline(n_full, its_full, N=32, beta=1.0, its=30):
+def cpu_baseline(n_full, its_full, N=32, beta=1.0, its=30, kind="hex-jump"):
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker", str(N), str(beta),
-           str(its)]
+           str(its), kind]
     t0 = time.perf_counter()
     out = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600, check=True)
     wall = time.perf_counter() - t0
@@ -250,7 +268,7 @@ def cpu_baseline(n_full, its_full, N=32, beta=1.0, its=30):
     scale = n_full / r["n"]
     est = r["setup_s"] * scale + r["solve_s"] / r["its"] * its_full * scale
     return dict(value=est, unit="s", cores=1, kind="oracle",
-                sample=(f"oracle on the same field law at {N}^3 hexahedra ({r['n']} DoFs): full setup "
+                sample=(f"oracle on the same field law at {N}^3 ({kind}, {r['n']} DoFs): full setup "
                         f"{r['setup_s']:.1f} s + {r['its']} PCG iterations {r['solve_s']:.1f} s "
                         f"(wall {wall:.0f} s, 1 thread); scaled linearly in DoFs to {n_full} DoFs "
                         f"and to the GPU run's {its_full} iterations"))
@@ -262,7 +280,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--size", type=int, default=64)
-    ap.add_argument("--beta", type=float, default=1.0)
+    ap.add_argument("--beta", type=float, default=None,
+                    help="default 1 (hex-jump) or 1e-2 (tet-checker)")
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--p-trunc", type=float, default=0.0,
                     help="drop interior P entries below this fraction of the row max "
@@ -279,11 +298,14 @@ def main():
                          "(a short program for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE passes)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="setup once and time the V-cycle / level-0 sweep only (for profiling)")
-    ap.add_argument("--cpu-baseline-worker", nargs=3, default=None)
+    ap.add_argument("--cpu-baseline-worker", nargs=4, default=None)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="hex-jump",
+                    help="hex-jump (64^3 and 128^3 configurations) or tet-checker (jittered "
+                         "tetrahedra, checkerboard coefficient)")
     a = ap.parse_args()
     if a.cpu_baseline_worker:
-        N, beta, its = a.cpu_baseline_worker
-        cpu_baseline_worker(int(N), float(beta), int(its))
+        N, beta, its, kind = a.cpu_baseline_worker
+        cpu_baseline_worker(int(N), float(beta), int(its), kind)
         return
     if a.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {a.gpus}); the multi-GPU design is "
@@ -296,9 +318,11 @@ def main():
     amg.load()
     assert torch.cuda.is_available(), "needs a GPU"
     t = time.perf_counter()
-    p = make_workload(a.size, a.beta)
+    if a.beta is None:
+        a.beta = 1e-2 if a.workload == "tet-checker" else 1.0
+    p = make_workload(a.size, a.beta, kind=a.workload)
     n, nnz = p.A.shape[0], p.A.nnz
-    log(f"generated {a.size}^3 hex problem: n={n} nnz={nnz} in {time.perf_counter() - t:.1f}s")
+    log(f"generated {a.workload} {a.size}^3 problem: n={n} nnz={nnz} in {time.perf_counter() - t:.1f}s")
     Ad, Gd, f = to_device(p, torch)
     del p
     torch.cuda.synchronize()
@@ -376,18 +400,19 @@ def main():
             levels=[l["n"] for l in info], oc=sum(l["nnz"] for l in info) / info[0]["nnz"],
             sweep_forms=[l["sweep_form"] for l in info[:-1]], **extra)
         if is_head:
-            headline = (t1 - t0) / steps, runs, kt
+            headline = (t1 - t0) / steps, runs, kt, info[0]
         H.close()
     if not a.no_learned and a.p_trunc == 0.0:
         forms["learned_resetup"] = learned_form(amg, Ad, Gd, f, torch, a)
-    value, runs, kt = headline
+    value, runs, kt, li0 = headline
+    l0_lanes, l0_form = li0["sweep_lanes"], li0["sweep_form"]
     out = {
         "metric": "s to 1e-8 rel. residual + V-cycle HBM GB/s; FP32/learned vs FP64 on GPU",
         "value": value, "unit": "s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": value * 1e3, "higher_is_better": False, "scaling": "strong",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"hex {a.size}^3 Nedelec, 8^3 subdomains log10(alpha)~U(-4,4), "
-                               f"beta={a.beta}, f~U[-1,1], PCG to 1e-8",
+        "config": {"workload": WORKLOADS[a.workload].replace("N^3", f"{a.size}^3")
+                               + f", beta={a.beta}, f~U[-1,1], PCG to 1e-8",
                    "n": n, "nnz": nnz, "setup_s": runs[-1]["setup_s"], "solve_s": runs[-1]["solve_s"],
                    "pcg_iterations": runs[-1]["iterations"], "true_relres": runs[-1]["true_relres"],
                    "interp": "algebraic (Alg. 1-3), local harmonic extension P, p_trunc=%g" % a.p_trunc,
@@ -396,14 +421,18 @@ def main():
         "roofline": {"bound": "hbm", "achieved": kt["launch_bytes"] / (kt["launch_ms"] * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": kt["launch_bytes"] / (kt["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": SCHWARZ_L0_TRAFFIC_64 if a.size == 64 and a.p_trunc == 0.0 else None,
+                     "traffic": (SCHWARZ_L0_TRAFFIC_64 if a.workload == "hex-jump" and a.size == 64
+                                 and a.p_trunc == 0.0 else None),
                      "traffic_unit": "bytes per launch",
-                     "kernel": "k_schwarz<double,8,256> (level-0 colour launch)",
+                     "kernel": (f"k_schwarz<double,{l0_lanes},256> (level-0 colour launch)"
+                                if l0_form == "colour" else f"level-0 sweep ({l0_form} form)"),
                      "bytes_per_launch": kt["launch_bytes"], "launch_ms": kt["launch_ms"]},
     }
     if not a.no_cpu_baseline:
         try:
-            out["cpu_baseline"] = cpu_baseline(n, runs[-1]["iterations"])
+            out["cpu_baseline"] = cpu_baseline(n, runs[-1]["iterations"], beta=a.beta,
+                                               N=32 if a.workload == "hex-jump" else 24,
+                                               kind=a.workload)
         except Exception as e:   # the baseline is reported, never required
             out["cpu_baseline"] = {"value": None, "error": str(e)[:200]}
     print(json.dumps(out), flush=True)
