@@ -1767,11 +1767,13 @@ __global__ __launch_bounds__(64) void k_mm_vals(
 // order-free, so the result is deterministic), counted by popcount,
 // listed in order by a scan, and addressed in the numeric pass by rank
 // (prefix popcount), with the sums accumulated in place in C's row.
+// (each wavefront takes X entries in turn, its lanes the entries of the Y row)
 __device__ void mm_mark_wide(int64_t i, const int64_t* Xptr, const int32_t* Xcol,
                              const int64_t* Yptr, const int32_t* Ycol, uint32_t* bits) {
-  for (int64_t t = Xptr[i] + threadIdx.x; t < Xptr[i + 1]; t += blockDim.x) {
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nwave = blockDim.x / 64;
+  for (int64_t t = Xptr[i] + wave; t < Xptr[i + 1]; t += nwave) {
     const int32_t k = Xcol[t];
-    for (int64_t u = Yptr[k]; u < Yptr[k + 1]; ++u) {
+    for (int64_t u = Yptr[k] + lane; u < Yptr[k + 1]; u += 64) {
       const int32_t J = Ycol[u];
       atomicOr(&bits[J >> 5], 1u << (J & 31));
     }
@@ -1845,7 +1847,8 @@ __global__ __launch_bounds__(256) void k_mm_fill_wide(const int32_t* __restrict_
   }
 }
 
-__global__ __launch_bounds__(64) void k_mm_vals_wide(
+constexpr int MM_WIDE_VALS_WG = 1024;
+__global__ __launch_bounds__(MM_WIDE_VALS_WG) void k_mm_vals_wide(
     const int32_t* __restrict__ rows, const int64_t* __restrict__ Xptr,
     const int32_t* __restrict__ Xcol, const double* __restrict__ Xval,
     const int64_t* __restrict__ Yptr, const int32_t* __restrict__ Ycol,
@@ -1857,9 +1860,9 @@ __global__ __launch_bounds__(64) void k_mm_vals_wide(
   const int64_t o = Cptr[i];
   const int m = (int)(Cptr[i + 1] - o);
   const int lane = threadIdx.x;
-  for (int w = lane; w < nwords; w += 64) bits[w] = 0u;
+  for (int w = lane; w < nwords; w += MM_WIDE_VALS_WG) bits[w] = 0u;
   __syncthreads();
-  for (int t = lane; t < m; t += 64) {
+  for (int t = lane; t < m; t += MM_WIDE_VALS_WG) {
     const int32_t J = Ccol[o + t];
     atomicOr(&bits[J >> 5], 1u << (J & 31));
     Cval[o + t] = 0.0;
@@ -1873,12 +1876,13 @@ __global__ __launch_bounds__(64) void k_mm_vals_wide(
     }
   }
   __syncthreads();
-  // same order as k_mm_vals: X's entries in stored order, lanes over the
-  // distinct columns of one Y row, so each C entry is summed in a fixed order
+  // same order as k_mm_vals: X's entries in stored order, threads over the
+  // distinct columns of one Y row, so each C entry is summed in a fixed
+  // order (the barrier after each X entry orders the updates of C's row)
   for (int64_t t = Xptr[i]; t < Xptr[i + 1]; ++t) {
     const int32_t k = Xcol[t];
     const double x = Xval[t];
-    for (int64_t u = Yptr[k] + lane; u < Yptr[k + 1]; u += 64) {
+    for (int64_t u = Yptr[k] + lane; u < Yptr[k + 1]; u += MM_WIDE_VALS_WG) {
       const int32_t J = Ycol[u];
       const uint32_t w = bits[J >> 5];
       if (w & (1u << (J & 31))) {
@@ -1911,7 +1915,7 @@ void mm_vals_wide(int64_t nw, const int32_t* rows, const CsrPat& X, const double
                   const int32_t* Ccol, double* Cval, hipStream_t st) {
   if (nw <= 0) return;
   const int nwords = (int)((ncols + 31) / 32);
-  hipLaunchKernelGGL(k_mm_vals_wide, dim3((unsigned)nw), dim3(64), mm_wide_lds(ncols), st, rows,
+  hipLaunchKernelGGL(k_mm_vals_wide, dim3((unsigned)nw), dim3(MM_WIDE_VALS_WG), mm_wide_lds(ncols), st, rows,
                      X.ptr, X.col, Xval, Y.ptr, Y.col, Yval, nwords, Cptr, Ccol, Cval);
 }
 
