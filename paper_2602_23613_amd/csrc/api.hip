@@ -172,21 +172,11 @@ struct Level {
   int max_block = 0;
   double* Acm = nullptr;         // column-major dense A (dense and panel forms)
   float* Acm32 = nullptr;
-  int ngroups = 0;               // panel form: groups of consecutive blocks
-  int32_t* grp_blk = nullptr;
-  int32_t* dgrp = nullptr;
-  int32_t* sdup = nullptr;
-  double* dsl = nullptr;
-  float* dsl32 = nullptr;
-  int64_t* slc_off = nullptr;    // panel form: per-group slices and inter-group blocks of A
-  int64_t* cor_off = nullptr;
-  int64_t slc_total = 0, cor_total = 0;
-  double* binv_pad = nullptr;    // panel form: per star row, its row of the block inverse (padded)
-  float* binv_pad32 = nullptr;
-  double* slc = nullptr;
-  double* cor = nullptr;
-  float* slc32 = nullptr;
-  float* cor32 = nullptr;
+  int ngroups = 0;               // panel form: groups of consecutive blocks (PanelDev tables)
+  int32_t *gdof = nullptr, *gsl = nullptr, *gblk = nullptr, *dgrp = nullptr, *docc = nullptr;
+  int32_t* row_slot = nullptr;   // group slot g * 64 + t of each star row
+  double *gslc = nullptr, *gcf = nullptr, *gcb = nullptr, *gbinv = nullptr, *dsl = nullptr;
+  float *gslc32 = nullptr, *gcf32 = nullptr, *gcb32 = nullptr, *gbinv32 = nullptr, *dsl32 = nullptr;
   int* psync = nullptr;
   // device: cycle vectors
   double *x = nullptr, *t = nullptr, *b = nullptr, *r = nullptr;
@@ -235,13 +225,17 @@ struct Level {
     s.sync = sweep_sync; s.err = err; s.spin_max = spin_max;
     s.mode = sweep_mode; s.wg = wg_S; s.lpr = lpr_S; s.pipe_grid = pipe_grid;
     s.n = (int)n;
-    s.ngroups = ngroups; s.grp_blk = grp_blk; s.dgrp = dgrp; s.sdup = sdup; s.psync = psync;
+    s.pn.n = (int)n;
+    s.pn.ngroups = ngroups;
+    s.pn.gdof = gdof; s.pn.gsl = gsl; s.pn.gblk = gblk; s.pn.dgrp = dgrp; s.pn.docc = docc;
+    s.pn.sync = psync;
     if constexpr (std::is_same<T, double>::value) {
-      s.dsl = dsl; s.slc = slc; s.cor = cor; s.binv_pad = binv_pad;
+      s.pn.gslc = gslc; s.pn.gcf = gcf; s.pn.gcb = gcb; s.pn.gbinv = gbinv; s.pn.dsl = dsl;
+      s.pn.Acm = Acm;
     } else {
-      s.dsl = dsl32; s.slc = slc32; s.cor = cor32; s.binv_pad = binv_pad32;
+      s.pn.gslc = gslc32; s.pn.gcf = gcf32; s.pn.gcb = gcb32; s.pn.gbinv = gbinv32; s.pn.dsl = dsl32;
+      s.pn.Acm = Acm32;
     }
-    s.slc_off = slc_off; s.cor_off = cor_off;
     s.nblocks = (int)nstars;
     s.max_block = max_block;
     if constexpr (std::is_same<T, double>::value) {
@@ -444,6 +438,56 @@ bool build_panel_groups(const std::vector<int64_t>& sb_ptr, const std::vector<in
   return true;
 }
 
+// Padded per-group tables of the panel form (layouts in PanelDev): per slot
+// its DoF, its block's first slot and the slot of the same DoF in the
+// neighbouring groups; per block its first slot, size and run of one colour
+// inside the group; per DoF its slots; per star row its group slot.  False
+// if a DoF has more than two slots (the form then does not apply).
+bool build_panel_tables(const std::vector<int64_t>& sb_ptr, const std::vector<int32_t>& sb_dofs,
+                        const std::vector<int32_t>& blk_col, const std::vector<int32_t>& grp_blk,
+                        int64_t n, std::vector<int32_t>& gdof, std::vector<int32_t>& gsl,
+                        std::vector<int32_t>& gblk, std::vector<int32_t>& docc,
+                        std::vector<int32_t>& row_slot) {
+  constexpr int S = PANEL_GROUP_SLOTS;
+  const int G = (int)grp_blk.size() - 1;
+  gdof.assign((size_t)G * S, -1);
+  gsl.assign((size_t)G * S, 0);
+  gblk.assign((size_t)G * S, -1);
+  docc.assign(2 * n, -1);
+  row_slot.assign(sb_dofs.size(), 0);
+  for (int g = 0; g < G; ++g) {
+    const int bb0 = grp_blk[g], bb1 = grp_blk[g + 1];
+    const int64_t q0 = sb_ptr[bb0];
+    for (int b = bb0; b < bb1; ++b) {
+      int lo = b, hi = b;
+      while (lo > bb0 && blk_col[lo - 1] == blk_col[b]) --lo;
+      while (hi + 1 < bb1 && blk_col[hi + 1] == blk_col[b]) ++hi;
+      const int p = (int)(sb_ptr[b] - q0), sz = (int)(sb_ptr[b + 1] - sb_ptr[b]);
+      gblk[(size_t)g * S + (b - bb0)] = p | sz << 8 | (lo - bb0) << 16 | (hi - bb0) << 24;
+      for (int t = p; t < p + sz; ++t) {
+        const int32_t d = sb_dofs[q0 + t];
+        gdof[(size_t)g * S + t] = d;
+        gsl[(size_t)g * S + t] = p;
+        row_slot[q0 + t] = g * S + t;
+        if (docc[2 * d] < 0) docc[2 * d] = g * S + t;
+        else if (docc[2 * d + 1] < 0) docc[2 * d + 1] = g * S + t;
+        else return false;
+      }
+    }
+  }
+  for (int g = 0; g < G; ++g)
+    for (int t = 0; t < S; ++t) {
+      const int32_t d = gdof[(size_t)g * S + t];
+      if (d < 0) continue;
+      const int self = g * S + t;
+      const int other = docc[2 * d] == self ? docc[2 * d + 1] : docc[2 * d];
+      if (other < 0) continue;
+      if (other / S == g - 1) gsl[(size_t)g * S + t] |= (other % S + 1) << 8;
+      if (other / S == g + 1) gsl[(size_t)g * S + t] |= (other % S + 1) << 16;
+    }
+  return true;
+}
+
 void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   const LevelInts& I = L.ints;
   int64_t ns = (int64_t)I.star_ptr.size() - 1;
@@ -561,28 +605,24 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   if (const char* e = std::getenv("HCURL_AMG_PIPE_GRID")) grid = std::max(1, std::atoi(e));
   L.pipe_grid = std::max(1, std::min(nchunks, grid));
   if (L.sweep_mode == SWEEP_PANEL) {
-    std::vector<int32_t> grp_blk, dgrp, sdup;
-    if (build_panel_groups(sb_ptr, sb_dofs, L.n, grp_blk, dgrp, sdup)) {
+    std::vector<int32_t> grp_blk, dgrp, sdup, blk_col(ns), gdof, gsl, gblk, docc, row_slot;
+    for (int64_t t = 0; t < ns; ++t) blk_col[t] = I.star_color[order[t]];
+    if (build_panel_groups(sb_ptr, sb_dofs, L.n, grp_blk, dgrp, sdup) &&
+        build_panel_tables(sb_ptr, sb_dofs, blk_col, grp_blk, L.n, gdof, gsl, gblk, docc, row_slot)) {
       L.ngroups = (int)grp_blk.size() - 1;
-      L.grp_blk = h->pool.upload(grp_blk, st);
+      const size_t G = (size_t)L.ngroups;
+      L.gdof = h->pool.upload(gdof, st);
+      L.gsl = h->pool.upload(gsl, st);
+      L.gblk = h->pool.upload(gblk, st);
       L.dgrp = h->pool.upload(dgrp, st);
-      L.sdup = h->pool.upload(sdup, st);
-      L.dsl = h->pool.get<double>((size_t)std::max(L.ngroups, 1) * PANEL_GROUP_SLOTS);
-      L.psync = h->pool.get<int>((size_t)std::max(L.ngroups, 1) * 2 * SYNC_STRIDE);
-      std::vector<int64_t> so(L.ngroups + 1, 0), co(L.ngroups + 1, 0);
-      for (int g = 0; g < L.ngroups; ++g) {
-        const int64_t m = sb_ptr[grp_blk[g + 1]] - sb_ptr[grp_blk[g]];
-        const int64_t mn = g + 1 < L.ngroups ? sb_ptr[grp_blk[g + 2]] - sb_ptr[grp_blk[g + 1]] : 0;
-        so[g + 1] = so[g] + m * m;
-        co[g + 1] = co[g] + m * mn;
-      }
-      L.slc_total = so[L.ngroups];
-      L.cor_total = co[L.ngroups];
-      L.slc_off = h->pool.upload(so, st);
-      L.cor_off = h->pool.upload(co, st);
-      L.slc = h->pool.get<double>(std::max<int64_t>(L.slc_total, 1));
-      L.cor = h->pool.get<double>(std::max<int64_t>(L.cor_total, 1));
-      L.binv_pad = h->pool.get<double>((size_t)std::max<int64_t>(sb_ptr[ns], 1) * PANEL_ROW_WIDTH);
+      L.docc = h->pool.upload(docc, st);
+      L.row_slot = h->pool.upload(row_slot, st);
+      L.dsl = h->pool.get<double>(G * PANEL_GROUP_SLOTS);
+      L.psync = h->pool.get<int>(G * 2 * SYNC_STRIDE);
+      L.gslc = h->pool.get<double>(G * PANEL_GROUP_SLOTS * PANEL_GROUP_SLOTS);
+      L.gcf = h->pool.get<double>(G * PANEL_GROUP_SLOTS * PANEL_GROUP_SLOTS);
+      L.gcb = h->pool.get<double>(G * PANEL_GROUP_SLOTS * PANEL_GROUP_SLOTS);
+      L.gbinv = h->pool.get<double>(G * PANEL_GROUP_SLOTS * PANEL_ROW_WIDTH);
     } else {
       L.sweep_mode = SWEEP_PIPE;
     }
@@ -608,15 +648,17 @@ void factor_smoother(amg_hier* h, Level& L, int level, hipStream_t st) {
   if (L.sweep_mode == SWEEP_DENSE || L.sweep_mode == SWEEP_PANEL)
     csr_to_dense_cm(L.n, L.A_ptr, L.A_col, L.A_val, L.Acm, st);
   if (L.sweep_mode == SWEEP_PANEL)
-    panel_slices<double>(L.ngroups, L.n, L.grp_blk, L.sb_ptr, L.sb_dofs, L.Acm, L.slc_off, L.cor_off,
-                         L.slc, L.cor, st);
+    panel_slices(L.ngroups, L.n, L.gdof, L.Acm, L.gslc, L.gcf, L.gcb, st);
   star_rows((int64_t)L.ints.star_dofs.size(), L.sb_dofs, L.A_ptr, L.A_val, L.srow_ptr, L.sval, st);
   star_chol(L.nstars, L.sb_ptr, L.sb_dofs, L.fac_off, L.A_dev<double>(), L.fac, h->d_flag, st);
   check_flag(h, st, AMG_ERR_NOT_SPD, "smoother block Cholesky: non-positive pivot on level " +
                                          std::to_string(level));
   star_inv((int64_t)L.ints.star_dofs.size(), L.row_blk, L.sb_ptr, L.fac_off, L.fac, L.binv, st);
-  if (L.sweep_mode == SWEEP_PANEL)
-    pad_inv((int64_t)L.ints.star_dofs.size(), L.row_blk, L.sb_ptr, L.fac_off, L.binv, L.binv_pad, st);
+  if (L.sweep_mode == SWEEP_PANEL) {
+    fill<double>((int64_t)L.ngroups * PANEL_GROUP_SLOTS * PANEL_ROW_WIDTH, 0.0, L.gbinv, st);
+    pad_inv((int64_t)L.ints.star_dofs.size(), L.row_blk, L.row_slot, L.sb_ptr, L.fac_off, L.binv,
+            L.gbinv, st);
+  }
   l1inv(L.A_dev<double>(), L.dinv, st);
 }
 
@@ -834,16 +876,19 @@ void cast_level(amg_hier* h, Level& L, hipStream_t st) {
   cast<double, float>(L.fac_total, L.binv, L.binv32, st);
   cast<double, float>(L.n, L.dinv, L.dinv32, st);
   if (L.sweep_mode == SWEEP_PANEL) {
+    const int64_t ne = (int64_t)L.ngroups * PANEL_GROUP_SLOTS * PANEL_GROUP_SLOTS;
+    const int64_t nf = (int64_t)L.ngroups * PANEL_GROUP_SLOTS * PANEL_ROW_WIDTH;
     if (!L.dsl32) {
-      L.dsl32 = h->pool.get<float>((size_t)std::max(L.ngroups, 1) * PANEL_GROUP_SLOTS);
-      L.slc32 = h->pool.get<float>(std::max<int64_t>(L.slc_total, 1));
-      L.cor32 = h->pool.get<float>(std::max<int64_t>(L.cor_total, 1));
+      L.dsl32 = h->pool.get<float>((size_t)L.ngroups * PANEL_GROUP_SLOTS);
+      L.gslc32 = h->pool.get<float>(ne);
+      L.gcf32 = h->pool.get<float>(ne);
+      L.gcb32 = h->pool.get<float>(ne);
+      L.gbinv32 = h->pool.get<float>(nf);
     }
-    const int64_t npad = (int64_t)L.ints.star_dofs.size() * PANEL_ROW_WIDTH;
-    if (!L.binv_pad32) L.binv_pad32 = h->pool.get<float>(std::max<int64_t>(npad, 1));
-    cast<double, float>(L.slc_total, L.slc, L.slc32, st);
-    cast<double, float>(L.cor_total, L.cor, L.cor32, st);
-    cast<double, float>(npad, L.binv_pad, L.binv_pad32, st);
+    cast<double, float>(ne, L.gslc, L.gslc32, st);
+    cast<double, float>(ne, L.gcf, L.gcf32, st);
+    cast<double, float>(ne, L.gcb, L.gcb32, st);
+    cast<double, float>(nf, L.gbinv, L.gbinv32, st);
   }
   if (L.sweep_mode == SWEEP_DENSE || L.sweep_mode == SWEEP_PANEL) {
     if (!L.Acm32) L.Acm32 = h->pool.get<float>((size_t)L.n * L.n);

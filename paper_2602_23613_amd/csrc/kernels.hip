@@ -739,54 +739,43 @@ void dense_sweep(int n, int nblocks, int max_block, int backward, const int64_t*
 // each, so a sweep is a long chain of small steps.  The panel form keeps
 // r = b - A x and follows the blocks in sweep order in groups of consecutive
 // blocks with at most PANEL_SLOTS rows in all (a row of a group is a "slot";
-// a DoF in two blocks of one group has two slots).  Workgroup 0 (the chain)
-// takes the groups in turn: it loads the group's slice A(D_g, D_g) and
-// residual entries, and for each block B in sweep order forms
-// d = A_BB^{-1} r_B (the lanes of B's slots, each with its row of the
-// block's symmetric inverse) and updates the residual of every slot of the
-// group, all in one wavefront; x_B += d follows at the end of the group.  The other workgroups own tiles of PANEL_TILE rows
-// and apply each group's update r_i -= sum_k A(i, dof_k) d_k to their rows,
-// reading A from a column-major dense copy.  Exactly-once rule for the update
-// of group h on row i: the chain applies it when i is in D_h (inside the
-// group) or in the next group D_h' (as a correction it carries to h'), the
-// tiles otherwise.  The chain reads the residual of D_g after the tiles have
-// applied every group two or more positions back (they skip rows of D_g for
-// the group just before it), so the chain only waits when the tiles fall
-// more than a group behind.  The result is the multiplicative Schwarz sweep
-// in residual-update form (only the rounding differs from the row form).
+// a DoF in two blocks of one group has two slots).
+//
+// Workgroup 0 (the chain) takes the groups in turn.  Its first wavefront
+// holds slot k of the current group in lane k, with the group's slice
+// A(D_g, D_g), the slots' rows of their block inverses and the residual
+// entries in LDS, and for each block B in sweep order forms
+// d = A_BB^{-1} r_B and updates the residual of every slot of the group.
+// A run of consecutive blocks of one colour is one step (such blocks share
+// no DoF and no entry of A).  It then publishes d and the group's residual
+// entries and raises the group's flag.  Meanwhile its other three
+// wavefronts load the next group (padded per-group tables, so every
+// address follows from the group index alone) and the next group's
+// residual entries, which are complete once the tiles have applied every
+// group up to the one before the current; after the flag they form the
+// correction A(D_next, D_g) d and stage the next group in LDS.
+//
+// The other workgroups own tiles of PANEL_TROWS rows (two threads per row,
+// 32 slots each) and apply each group's update r_i -= sum_k A(i, dof_k) d_k
+// to their rows from a column-major dense copy of A, and x_i += d for each
+// slot that holds DoF i.  Exactly-once rule for the update of group h on
+// row i: the chain applies it when i is in D_h (inside the group) or in the
+// next group D_h' (the correction it carries to h'), the tiles otherwise.
+// A DoF in D_g that was also in the group before takes its residual from
+// the chain's own final value of that slot.  The result is the
+// multiplicative Schwarz sweep in residual-update form (only the rounding
+// differs from the row form).
+//
 // Shared data (r, the published d) use agent-coherent accesses; a stored
-// value is complete (memory counter drained) before the barrier that precedes
-// its flag.  Every wait is bounded as in the pipelined sweep.  All
-// workgroups of the grid must be able to run at once (1 + n / PANEL_TILE of
-// 256 threads, n <= PANEL_NMAX, on an otherwise idle device).
+// value is complete (memory counter drained) before its flag or counter is
+// raised.  Every wait is bounded as in the pipelined sweep.  All workgroups
+// of the grid must be able to run at once (1 + n / PANEL_TROWS workgroups
+// of 256 threads, n <= PANEL_NMAX, on an otherwise idle device).
 constexpr int PANEL_SLOTS = PANEL_GROUP_SLOTS;
-constexpr int PANEL_TILE = 256;
+constexpr int PANEL_ELEMS = PANEL_SLOTS * PANEL_SLOTS;
+constexpr int PANEL_TROWS = 128;
 constexpr int PANEL_NMAX = 32768;
 constexpr int PANEL_SMAX = PANEL_ROW_WIDTH;
-constexpr int PANEL_FMAX = PANEL_SLOTS * (PANEL_SMAX + 1) / 2;
-
-template <class T>
-struct PanelArgs {
-  int n = 0, ngroups = 0, ntiles = 0, backward = 0, spin_max = 0;
-  const int32_t* grp_blk = nullptr;   // first block of each group (+ sentinel), colour order
-  const int64_t* sb_ptr = nullptr;
-  const int32_t* sb_dofs = nullptr;
-  const int64_t* fac_off = nullptr;
-  const T* binv_pad = nullptr;        // per star row: its row of the block inverse, 16 wide, zero-padded
-  const T* Acm = nullptr;             // A(i, j) at Acm[j n + i]
-  const T* slc = nullptr;             // per group: A(D_g, D_g), column-major m_g x m_g
-  const T* cor = nullptr;             // per group g < G-1: A(D_g+1, D_g), column-major
-  const int64_t* slc_off = nullptr;
-  const int64_t* cor_off = nullptr;
-  const int32_t* dgrp = nullptr;      // the (at most two) groups holding each DoF, -1 if none
-  const int32_t* sdup = nullptr;      // per slot: the group's other slot of the same DoF, or -1
-  T* r = nullptr;                     // b - A x on entry, kept equal to it
-  T* x = nullptr;
-  T* dsl = nullptr;                   // per sweep position: d of each slot of the group
-  int* flag = nullptr;                // per sweep position (stride SYNC_STRIDE): dsl is published
-  int* done = nullptr;                // per sweep position (stride SYNC_STRIDE): tiles that applied it
-  int* err = nullptr;
-};
 
 __device__ __forceinline__ void panel_wait(const int* p, int need, int* err, int spin_max) {
   int spins = 0;
@@ -812,35 +801,7 @@ __device__ __forceinline__ float lane_bcast(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-// Structure of one group, as the chain workgroup stages it: DoFs, the other
-// slot of a repeated DoF, block offsets / sizes / factor offsets, packed
-// factors and the slice A(D_g, D_g).
-struct PanelGroup {
-  int g, bb0, nbk, m, nf;
-  int64_t q0, f0;
-};
-
-template <class T>
-__device__ __forceinline__ PanelGroup panel_group(const PanelArgs<T>& P, int pos) {
-  PanelGroup q;
-  q.g = P.backward ? P.ngroups - 1 - pos : pos;
-  q.bb0 = P.grp_blk[q.g];
-  const int bb1 = P.grp_blk[q.g + 1];
-  q.nbk = bb1 - q.bb0;
-  q.q0 = P.sb_ptr[q.bb0];
-  q.m = (int)(P.sb_ptr[bb1] - q.q0);
-  q.f0 = P.fac_off[q.bb0];
-  q.nf = (int)(P.fac_off[bb1] - q.f0);
-  return q;
-}
-
-// One block B (slots p .. p+s-1, s <= SB) of the panel chain, in one
-// wavefront (lane k = slot k): the lanes of B form d_k = sum_j
-// (A_BB^{-1})_{k-p, j} r_{p+j}, then every slot's residual drops by
-// sum_j A(slot, p+j) d_j.  Operands come into registers first; the values
-// of other lanes are broadcast through the scalar unit, all independent of
-// each other; each sum is a fixed pairwise tree, so the dependent chain is
-// two tree depths instead of 2 s multiply-adds.
+// fixed pairwise tree over SB values
 template <class T, int SB>
 __device__ __forceinline__ T tree_sum(T (&v)[SB]) {
 #pragma unroll
@@ -850,202 +811,234 @@ __device__ __forceinline__ T tree_sum(T (&v)[SB]) {
   return v[0];
 }
 
+// One block B (slots p .. p+s-1, s <= SB) of the chain, in one wavefront
+// (lane k = slot k): the lanes of B form d_k = sum_j (A_BB^{-1})_{k-p, j}
+// r_{p+j}, then every slot's residual drops by sum_j A(slot, p+j) d_j.
+// br holds this lane's row of its block's inverse (zero beyond the block;
+// meaningful for the lanes of B only, the others' d is never used).  The
+// slice columns are read before the chain needs them, the values of other
+// lanes are broadcast through the scalar unit, all independent of each
+// other, and each sum is a fixed pairwise tree, so the dependent chain is
+// two tree depths instead of 2 s multiply-adds.  The slice is zero past the
+// group's slots, so no lane needs a mask.
 template <class T, int SB>
-__device__ __forceinline__ void panel_step(int k, int m, int p, int s, const T* brow, const T* Aloc,
-                                           T& rk, T& dk) {
-  // brow: this lane's row of its block's inverse, zero beyond the block
-  // (meaningful for the lanes of B only; the others' d is never used)
-  T v[SB];
-#pragma unroll
-  for (int j = 0; j < SB; ++j) v[j] = brow[j] * (j < s ? lane_bcast(rk, p + j) : T(0));
-  const T d = tree_sum<T, SB>(v);
-  if (k >= p && k < p + s) dk = d;
-  const T* acol = Aloc + p * PANEL_SLOTS + k;
+__device__ __forceinline__ void panel_step(int k, int p, int s, const T (&br)[PANEL_SMAX],
+                                           const T* Aloc, T& rk, T& dk) {
+  T a[SB], v[SB];
 #pragma unroll
   for (int j = 0; j < SB; ++j) {
-    const T a = acol[j * PANEL_SLOTS];
-    v[j] = (j < s && k < m ? a : T(0)) * (j < s ? lane_bcast(d, p + j) : T(0));
+    const int l = p + j < PANEL_SLOTS ? p + j : PANEL_SLOTS - 1;
+    a[j] = Aloc[l * PANEL_SLOTS + k];
   }
+#pragma unroll
+  for (int j = 0; j < SB; ++j) v[j] = br[j] * lane_bcast(rk, (p + j) & (PANEL_SLOTS - 1));
+  const T d = tree_sum<T, SB>(v);
+  if (k >= p && k < p + s) dk = d;
+#pragma unroll
+  for (int j = 0; j < SB; ++j) v[j] = a[j] * (j < s ? lane_bcast(d, p + j) : T(0));
   rk -= tree_sum<T, SB>(v);
 }
 
-// entries of the 64 x 64 slot matrices that one of the 192 staging threads
+// A run of consecutive blocks of one colour (slots P0 .. P1-1) in one step:
+// such blocks share no DoF and no entry of A, so each block's d comes from
+// the residual before the run, as it would after its predecessors in the
+// run.  Lane k forms d_k from its own block (first slot pk) with lane
+// shuffles, then every slot's residual drops by sum_l A(slot, l) d_l over
+// the run, summed in trees of sixteen.
+template <class T>
+__device__ __forceinline__ void panel_run(int k, int P0, int P1, int pk, const T (&br)[PANEL_SMAX],
+                                          const T* Aloc, T& rk, T& dk) {
+  T v[PANEL_SMAX];
+#pragma unroll
+  for (int j = 0; j < PANEL_SMAX; ++j) v[j] = br[j] * __shfl(rk, (pk + j) & (PANEL_SLOTS - 1));
+  const T d = tree_sum<T, PANEL_SMAX>(v);
+  if (k >= P0 && k < P1) dk = d;
+  T acc = 0;
+  for (int l0 = P0; l0 < P1; l0 += PANEL_SMAX) {
+#pragma unroll
+    for (int j = 0; j < PANEL_SMAX; ++j) {
+      const int l = l0 + j < P1 ? l0 + j : P0;
+      v[j] = Aloc[l * PANEL_SLOTS + k];
+    }
+#pragma unroll
+    for (int j = 0; j < PANEL_SMAX; ++j) v[j] *= l0 + j < P1 ? lane_bcast(d, l0 + j) : T(0);
+    acc += tree_sum<T, PANEL_SMAX>(v);
+  }
+  rk -= acc;
+}
+
+// entries of a 64 x 64 group matrix that one of the 192 staging threads
 // holds: e = t + 192 j
 constexpr int PANEL_STAGE = 192;
-constexpr int PANEL_PER = (PANEL_SLOTS * PANEL_SLOTS + PANEL_STAGE - 1) / PANEL_STAGE;   // 22
-constexpr int PANEL_FPER = (PANEL_SLOTS * PANEL_SMAX + PANEL_STAGE - 1) / PANEL_STAGE;  // 6
+constexpr int PANEL_PER = (PANEL_ELEMS + PANEL_STAGE - 1) / PANEL_STAGE;                   // 22
+constexpr int PANEL_FPER = (PANEL_SLOTS * PANEL_SMAX + PANEL_STAGE - 1) / PANEL_STAGE;     // 6
 
 template <class T>
-__global__ __launch_bounds__(256) void k_schwarz_panel(PanelArgs<T> P) {
-  __shared__ T Aloc[PANEL_SLOTS * PANEL_SLOTS];   // Aloc[l * 64 + k] = A(dof_k, dof_l)
-  __shared__ T fl[PANEL_SLOTS * PANEL_SMAX];   // per slot: its row of the block inverse (padded)
-  __shared__ T part[3][PANEL_SLOTS];
-  __shared__ T ds_s[PANEL_SLOTS];
-  __shared__ T corr[PANEL_SLOTS];
-  __shared__ int dof_s[PANEL_SLOTS];
-  __shared__ int sdup_s[PANEL_SLOTS];
-  __shared__ int inprev_s[PANEL_SLOTS];
-  __shared__ int blk_p[PANEL_SLOTS], blk_s[PANEL_SLOTS], blk_f[PANEL_SLOTS];
+__global__ __launch_bounds__(256) void k_schwarz_panel(PanelDev<T> P, int backward, T* r, T* x,
+                                                       int* err, int spin_max, int ntiles) {
+  __shared__ T Aloc[PANEL_ELEMS];                 // Aloc[l * 64 + k] = A(dof_k, dof_l)
+  __shared__ T fl[PANEL_SLOTS * PANEL_SMAX];      // per slot: its row of the block inverse (padded)
+  __shared__ T part[3][PANEL_SLOTS];              // partial sums of the correction
+  __shared__ T ds_s[PANEL_SLOTS];                 // the group's d (chain), the published d (tiles)
+  __shared__ T rfin_s[PANEL_SLOTS];               // the chain's final residual of each slot
+  __shared__ T rnx_s[PANEL_SLOTS];                // the next group's residual entries before correction
+  __shared__ int dof_s[2][PANEL_SLOTS];
+  __shared__ int gsl_s[PANEL_SLOTS];
+  __shared__ int gblk_s[PANEL_SLOTS];
+  __shared__ int gmn_s[2];                        // the group's slots and blocks
   const int tid = threadIdx.x;
   const int G = P.ngroups;
   const int64_t n = P.n;
+  int* flag = P.sync;
+  int* done = P.sync + SYNC_STRIDE * G;
   if (blockIdx.x == 0) {
     // ---------------- the chain ----------------
-    // prologue: stage group 0
     {
-      const PanelGroup q = panel_group(P, 0);
-      if (tid < q.m) {
-        dof_s[tid] = P.sb_dofs[q.q0 + tid];
-        sdup_s[tid] = P.sdup[q.q0 + tid];
-        inprev_s[tid] = 0;
-      }
-      if (tid < q.nbk) {
-        const int blk = q.bb0 + tid;
-        const int bp = (int)(P.sb_ptr[blk] - q.q0), bs = (int)(P.sb_ptr[blk + 1] - P.sb_ptr[blk]);
-        const int64_t bf = P.fac_off[blk];
-        blk_p[tid] = bp;
-        blk_s[tid] = bs;
-        blk_f[tid] = (int)(bf - q.f0);
-      }
-      for (int t = tid; t < PANEL_SLOTS * PANEL_SMAX; t += 256)
-        fl[t] = t < q.m * PANEL_SMAX ? P.binv_pad[q.q0 * PANEL_SMAX + t] : T(0);
-      __syncthreads();
-      for (int e = tid; e < PANEL_SLOTS * PANEL_SLOTS; e += 256) {
-        const int l = e / PANEL_SLOTS, k = e % PANEL_SLOTS;
-        if (l < q.m && k < q.m) Aloc[e] = P.slc[P.slc_off[q.g] + l * q.m + k];
+      const int g0 = backward ? G - 1 : 0;
+      // all loads first, then the LDS stores
+      T pa[PANEL_ELEMS / 256], pf[PANEL_SLOTS * PANEL_SMAX / 256];
+#pragma unroll
+      for (int j = 0; j < PANEL_ELEMS / 256; ++j) pa[j] = P.gslc[(int64_t)g0 * PANEL_ELEMS + tid + 256 * j];
+#pragma unroll
+      for (int j = 0; j < PANEL_SLOTS * PANEL_SMAX / 256; ++j)
+        pf[j] = P.gbinv[(int64_t)g0 * PANEL_SLOTS * PANEL_SMAX + tid + 256 * j];
+#pragma unroll
+      for (int j = 0; j < PANEL_ELEMS / 256; ++j) Aloc[tid + 256 * j] = pa[j];
+#pragma unroll
+      for (int j = 0; j < PANEL_SLOTS * PANEL_SMAX / 256; ++j) fl[tid + 256 * j] = pf[j];
+      if (tid < 64) {
+        const int d = P.gdof[g0 * PANEL_SLOTS + tid];
+        const int bk = P.gblk[g0 * PANEL_SLOTS + tid];
+        dof_s[0][tid] = d;
+        gsl_s[tid] = P.gsl[g0 * PANEL_SLOTS + tid];
+        gblk_s[tid] = bk;
+        rnx_s[tid] = d >= 0 ? ld_x<T, true>(r + d) : T(0);
+        const unsigned long long vm = __ballot(d >= 0), vb = __ballot(bk >= 0);
+        if (tid == 0) {
+          gmn_s[0] = __popcll(vm);
+          gmn_s[1] = __popcll(vb);
+        }
       }
       __syncthreads();
     }
     for (int pos = 0; pos < G; ++pos) {
-      const PanelGroup q = panel_group(P, pos);
-      const int m = q.m;
+      const int g = backward ? G - 1 - pos : pos;
       const bool more = pos + 1 < G;
-      PanelGroup qn{};
-      if (more) qn = panel_group(P, pos + 1);
-      // the tiles have applied every group two or more positions back
-      if (tid == 0 && pos >= 2) panel_wait(&P.done[SYNC_STRIDE * (pos - 2)], P.ntiles, P.err, P.spin_max);
-      __syncthreads();
-      // staging registers of waves 1-3 (next group's structure and slice,
-      // and the entries A(D_next, D_g) of the correction)
-      T an[PANEL_PER], cn[PANEL_PER], fn[PANEL_FPER];
-      int dn = 0, sn = 0, ipn = 0, bpn = 0, bsn = 0, bfn = 0;
+      const int gn = backward ? g - 1 : g + 1;
       if (tid < 64) {
         // wave 0: the chain over the group's blocks; lane k holds slot k
         const int k = tid;
-        const int dofk = k < m ? dof_s[k] : 0;
+        const int m = gmn_s[0], nbk = gmn_s[1];
+        const int dofk = dof_s[pos & 1][k];
+        const int sl = gsl_s[k];
+        const int pk = sl & 255;
+        const int ips = ((backward ? sl >> 16 : sl >> 8) & 255) - 1;
         T rk = 0, dk = 0;
         if (k < m) {
-          rk = ld_x<T, true>(P.r + dofk);
-          if (pos >= 1 && !inprev_s[k]) rk += corr[k];
+          if (pos == 0) rk = rnx_s[k];
+          else if (ips >= 0) rk = rfin_s[ips];
+          else rk = rnx_s[k] - ((part[0][k] + part[1][k]) + part[2][k]);
         }
-        for (int jb = 0; jb < q.nbk; ++jb) {
-          const int ib = P.backward ? q.nbk - 1 - jb : jb;
-          // uniform across the wavefront: keeps the broadcasts on the scalar unit
-          const int p = __builtin_amdgcn_readfirstlane(blk_p[ib]);
-          const int s = __builtin_amdgcn_readfirstlane(blk_s[ib]);
-          const T* brow = fl + (k < m ? k : 0) * PANEL_SMAX;
-          if (s <= PANEL_SMAX / 2)
-            panel_step<T, PANEL_SMAX / 2>(k, m, p, s, brow, Aloc, rk, dk);
-          else
-            panel_step<T, PANEL_SMAX>(k, m, p, s, brow, Aloc, rk, dk);
-        }
-        // x_B += d for the group's blocks in sweep order: a DoF in two blocks
-        // of the group (slots k and dup) gets both updates from the lower slot's lane
-        const int dup = k < m ? sdup_s[k] : -1;
-        const T ddup = __shfl(dk, dup & 63);
-        if (k < m) {
-          if (dup < 0) {
-            st_x<T, true>(P.x + dofk, ld_x<T, true>(P.x + dofk) + dk);
-          } else if (k < dup) {
-            const T x0 = ld_x<T, true>(P.x + dofk);
-            st_x<T, true>(P.x + dofk, P.backward ? (x0 + ddup) + dk : (x0 + dk) + ddup);
+        // lane b holds block b's first slot, size and colour run
+        const int bk = k < nbk ? gblk_s[k] : 0;
+        T br[PANEL_SMAX];
+#pragma unroll
+        for (int j = 0; j < PANEL_SMAX; ++j) br[j] = fl[k * PANEL_SMAX + j];
+        int ib = backward ? nbk - 1 : 0;
+        while (backward ? ib >= 0 : ib < nbk) {
+          const int e = __builtin_amdgcn_readlane(bk, ib);
+          const int lo = (e >> 16) & 255, hi = (e >> 24) & 255;
+          if (lo == hi) {
+            const int p = e & 255, s = (e >> 8) & 255;
+            if (s <= PANEL_SMAX / 2)
+              panel_step<T, PANEL_SMAX / 2>(k, p, s, br, Aloc, rk, dk);
+            else
+              panel_step<T, PANEL_SMAX>(k, p, s, br, Aloc, rk, dk);
+          } else {
+            const int e0 = __builtin_amdgcn_readlane(bk, lo), e1 = __builtin_amdgcn_readlane(bk, hi);
+            panel_run<T>(k, e0 & 255, (e1 & 255) + ((e1 >> 8) & 255), pk, br, Aloc, rk, dk);
           }
-          st_x<T, true>(P.r + dofk, rk);
+          ib = backward ? lo - 1 : hi + 1;
+        }
+        if (k < m) {
+          st_x<T, true>(r + dofk, rk);
           st_x<T, true>(P.dsl + (int64_t)pos * PANEL_SLOTS + k, dk);
-          ds_s[k] = dk;
         }
+        rfin_s[k] = rk;
+        ds_s[k] = k < m ? dk : T(0);
         __builtin_amdgcn_s_waitcnt(0);
-      } else if (more) {
-        // waves 1-3: load the next group while the chain runs
-        const int t = tid - 64;
-        const int mn = qn.m;
-        const int64_t dq = qn.q0;
-        if (t < mn) {
-          dn = P.sb_dofs[dq + t];
-          sn = P.sdup[dq + t];
-          const int d = dn;
-          ipn = P.dgrp[2 * d] == q.g || P.dgrp[2 * d + 1] == q.g;
+        if (k == 0) __hip_atomic_store(&flag[SYNC_STRIDE * pos], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (!more) break;
+      // waves 1-3: the next group's tables, slice and inverse rows, and the
+      // entries A(D_next, D_g) of the correction, while the chain runs
+      T an[PANEL_PER], cn[PANEL_PER], fn[PANEL_FPER];
+      int dn = -1, sln = 0, bkn = -1;
+      T rn = 0;
+      const int t = tid - 64;
+      const int kn = t % PANEL_SLOTS, pt = t / PANEL_SLOTS;
+      if (tid >= 64) {
+        const T* Sn = P.gslc + (int64_t)gn * PANEL_ELEMS;
+#pragma unroll
+        for (int j = 0; j < PANEL_PER; ++j) {
+          const int e = t + PANEL_STAGE * j;
+          an[j] = e < PANEL_ELEMS ? Sn[e] : T(0);
         }
-        if (t < qn.nbk) {
-          const int blk = qn.bb0 + t;
-          bpn = (int)(P.sb_ptr[blk] - dq);
-          bsn = (int)(P.sb_ptr[blk + 1] - P.sb_ptr[blk]);
-          bfn = (int)(P.fac_off[blk] - qn.f0);
-        }
+        const T* Fn = P.gbinv + (int64_t)gn * PANEL_SLOTS * PANEL_SMAX;
 #pragma unroll
         for (int j = 0; j < PANEL_FPER; ++j) {
           const int e = t + PANEL_STAGE * j;
-          fn[j] = e < qn.m * PANEL_SMAX ? P.binv_pad[qn.q0 * PANEL_SMAX + e] : T(0);
+          fn[j] = e < PANEL_SLOTS * PANEL_SMAX ? Fn[e] : T(0);
         }
-        // slice of the next group (stored contiguously): entry e = l * 64 + k
-        const T* Sn = P.slc + P.slc_off[qn.g];
-#pragma unroll
-        for (int j = 0; j < PANEL_PER; ++j) {
-          const int e = t + PANEL_STAGE * j;
-          const int l = e / PANEL_SLOTS, k = e % PANEL_SLOTS;
-          an[j] = (l < mn && k < mn) ? Sn[l * mn + k] : T(0);
-        }
-        // correction entries: thread (kn, part) holds A(dof_n[kn], dof_s[k])
-        // for k = part, part + 3, ...; the block between two consecutive
-        // groups is stored once (forward order) and read transposed backward
-        const int kn = t % PANEL_SLOTS, pt = t / PANEL_SLOTS;
-        const T* Cg = P.cor + P.cor_off[P.backward ? qn.g : q.g];
+        // thread (kn, pt) holds A(dof_next[kn], dof_g[k]) for k = pt, pt + 3, ...
+        const T* Cg = (backward ? P.gcb : P.gcf) + (int64_t)g * PANEL_ELEMS;
 #pragma unroll
         for (int j = 0; j < PANEL_PER; ++j) {
           const int k = pt + 3 * j;
-          cn[j] = T(0);
-          if (kn < mn && k < m) cn[j] = P.backward ? Cg[kn * m + k] : Cg[k * mn + kn];
+          cn[j] = k < PANEL_SLOTS ? Cg[k * PANEL_SLOTS + kn] : T(0);
+        }
+        if (tid < 128) {
+          dn = P.gdof[gn * PANEL_SLOTS + t];
+          sln = P.gsl[gn * PANEL_SLOTS + t];
+          bkn = P.gblk[gn * PANEL_SLOTS + t];
+          // residual entries of the next group's new DoFs, once the tiles
+          // have applied every group before the current one
+          if (pos >= 1) panel_wait(&done[SYNC_STRIDE * (pos - 1)], ntiles, err, spin_max);
+          const int ipn = ((backward ? sln >> 16 : sln >> 8) & 255) - 1;
+          if (dn >= 0 && ipn < 0) rn = ld_x<T, true>(r + dn);
         }
       }
       __syncthreads();
-      if (tid == 0) __hip_atomic_store(&P.flag[SYNC_STRIDE * pos], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (!more) break;
-      // correction partial sums (this group's d is in ds_s) and the next group's staging
       if (tid >= 64) {
-        const int t = tid - 64;
-        const int kn = t % PANEL_SLOTS, pt = t / PANEL_SLOTS;
+        // correction partial sums (this group's d is in ds_s), then the
+        // next group's staging
         T acc = 0;
 #pragma unroll
         for (int j = 0; j < PANEL_PER; ++j) {
           const int k = pt + 3 * j;
-          if (k < m) acc += cn[j] * ds_s[k];
+          if (k < PANEL_SLOTS) acc += cn[j] * ds_s[k];
         }
         part[pt][kn] = acc;
-      }
-      __syncthreads();
-      if (tid < qn.m) corr[tid] = -((part[0][tid] + part[1][tid]) + part[2][tid]);
-      if (tid >= 64) {
-        const int t = tid - 64;
-        if (t < qn.m) {
-          dof_s[t] = dn;
-          sdup_s[t] = sn;
-          inprev_s[t] = ipn;
-        }
-        if (t < qn.nbk) {
-          blk_p[t] = bpn;
-          blk_s[t] = bsn;
-          blk_f[t] = bfn;
+#pragma unroll
+        for (int j = 0; j < PANEL_PER; ++j) {
+          const int e = t + PANEL_STAGE * j;
+          if (e < PANEL_ELEMS) Aloc[e] = an[j];
         }
 #pragma unroll
         for (int j = 0; j < PANEL_FPER; ++j) {
           const int e = t + PANEL_STAGE * j;
           if (e < PANEL_SLOTS * PANEL_SMAX) fl[e] = fn[j];
         }
-#pragma unroll
-        for (int j = 0; j < PANEL_PER; ++j) {
-          const int e = t + PANEL_STAGE * j;
-          const int l = e / PANEL_SLOTS, k = e % PANEL_SLOTS;
-          if (l < qn.m && k < qn.m) Aloc[e] = an[j];
+        if (tid < 128) {
+          dof_s[(pos + 1) & 1][t] = dn;
+          gsl_s[t] = sln;
+          gblk_s[t] = bkn;
+          rnx_s[t] = rn;
+          const unsigned long long vm = __ballot(dn >= 0), vb = __ballot(bkn >= 0);
+          if (t == 0) {
+            gmn_s[0] = __popcll(vm);
+            gmn_s[1] = __popcll(vb);
+          }
         }
       }
       __syncthreads();
@@ -1053,115 +1046,100 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelArgs<T> P) {
     return;
   }
   // ---------------- the tiles ----------------
-  // Each thread owns row i; for every group it loads the group's columns of
-  // its row (and the row's residual) before waiting for the group's d.
-  const int64_t i = (int64_t)(blockIdx.x - 1) * PANEL_TILE + tid;
+  // Two threads per row i (slots 0-31 and 32-63).  For every group a tile
+  // loads the group's columns of its rows (and the rows' residuals) and the
+  // next group's DoFs before it waits for the group's d.
+  const int64_t i = (int64_t)(blockIdx.x - 1) * PANEL_TROWS + (tid >> 1);
+  const int half = tid & 1;
   const bool row = i < n;
   const int ga = row ? P.dgrp[2 * i] : -1, gb = row ? P.dgrp[2 * i + 1] : -1;
+  const int o0 = row ? P.docc[2 * i] : -1, o1 = row ? P.docc[2 * i + 1] : -1;
+  const bool xown = row && half == 0 && o0 >= 0;
+  T xi = xown ? x[i] : T(0);   // x_i changes only here during the sweep
+  if (tid < 64) dof_s[0][tid] = P.gdof[(backward ? G - 1 : 0) * PANEL_SLOTS + tid];
+  __syncthreads();
   for (int pos = 0; pos < G; ++pos) {
-    const int g = P.backward ? G - 1 - pos : pos;
-    const int gn = pos + 1 < G ? (P.backward ? g - 1 : g + 1) : -2;
-    const int64_t q0 = P.sb_ptr[P.grp_blk[g]];
-    const int m = (int)(P.sb_ptr[P.grp_blk[g + 1]] - q0);
+    const int b = pos & 1;
+    const int g = backward ? G - 1 - pos : pos;
+    const int gn = pos + 1 < G ? (backward ? g - 1 : g + 1) : -2;
     const bool upd = row && ga != g && ga != gn && gb != g && gb != gn;
-    if (tid < m) dof_s[tid] = P.sb_dofs[q0 + tid];
-    __syncthreads();
-    T a[PANEL_SLOTS];
+    const int dnx = (tid < 64 && gn >= 0) ? P.gdof[gn * PANEL_SLOTS + tid] : -1;
+    T a[PANEL_SLOTS / 2];
 #pragma unroll
-    for (int k = 0; k < PANEL_SLOTS; ++k) a[k] = (upd && k < m) ? P.Acm[(int64_t)dof_s[k] * n + i] : T(0);
+    for (int j = 0; j < PANEL_SLOTS / 2; ++j) {
+      const int d = dof_s[b][half * (PANEL_SLOTS / 2) + j];
+      a[j] = (upd && d >= 0) ? P.Acm[(int64_t)d * n + i] : T(0);
+    }
     // the tile wrote r_i last itself, or the chain did before an earlier flag
-    const T ri = upd ? ld_x<T, true>(P.r + i) : T(0);
-    if (tid == 0) panel_wait(&P.flag[SYNC_STRIDE * pos], 1, P.err, P.spin_max);
+    const T ri = (upd && half == 0) ? ld_x<T, true>(r + i) : T(0);
+    if (tid == 0) panel_wait(&flag[SYNC_STRIDE * pos], 1, err, spin_max);
     __syncthreads();
-    if (tid < m) ds_s[tid] = ld_x<T, true>(P.dsl + (int64_t)pos * PANEL_SLOTS + tid);
+    if (tid < 64) {
+      ds_s[tid] = dof_s[b][tid] >= 0 ? ld_x<T, true>(P.dsl + (int64_t)pos * PANEL_SLOTS + tid) : T(0);
+      dof_s[b ^ 1][tid] = dnx;
+    }
     __syncthreads();
-    if (upd) {
-      T acc = 0;
+    T acc = 0;
 #pragma unroll
-      for (int k = 0; k < PANEL_SLOTS; ++k)
-        if (k < m) acc += a[k] * ds_s[k];
-      st_x<T, true>(P.r + i, ri - acc);
+    for (int j = 0; j < PANEL_SLOTS / 2; ++j) acc += a[j] * ds_s[half * (PANEL_SLOTS / 2) + j];
+    acc += __shfl_xor(acc, 1);
+    if (upd && half == 0) st_x<T, true>(r + i, ri - acc);
+    if (xown) {
+      // x_i += d of the slots that hold DoF i, in sweep order
+      const int e0 = backward ? o1 : o0, e1 = backward ? o0 : o1;
+      if (e0 >= 0 && (e0 >> 6) == g) xi += ds_s[e0 & 63];
+      if (e1 >= 0 && (e1 >> 6) == g) xi += ds_s[e1 & 63];
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (tid == 0) __hip_atomic_fetch_add(&P.done[SYNC_STRIDE * pos], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) __hip_atomic_fetch_add(&done[SYNC_STRIDE * pos], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  if (xown) x[i] = xi;
 }
 
 bool panel_sweep_ok(int n, int max_block) {
   return n > 0 && n <= PANEL_NMAX && max_block <= PANEL_SMAX;
 }
 
-int panel_tiles(int n) { return (n + PANEL_TILE - 1) / PANEL_TILE; }
+int panel_tiles(int n) { return (n + PANEL_TROWS - 1) / PANEL_TROWS; }
 
-// The panel form's per-group slices A(D_g, D_g) and inter-group blocks
-// A(D_g+1, D_g), gathered from the dense copy once per numeric setup.
 template <class T>
-__global__ void k_panel_slices(int ngroups, int64_t n, const int32_t* __restrict__ grp_blk,
-                               const int64_t* __restrict__ sb_ptr, const int32_t* __restrict__ sb_dofs,
-                               const T* __restrict__ Acm, const int64_t* __restrict__ slc_off,
-                               const int64_t* __restrict__ cor_off, T* __restrict__ slc,
-                               T* __restrict__ cor) {
+void panel_sweep(const PanelDev<T>& D, int backward, T* r, T* x, int* err, int spin_max, hipStream_t st) {
+  if (D.ngroups <= 0) return;
+  const int nsync = 2 * SYNC_STRIDE * D.ngroups;
+  hipLaunchKernelGGL(k_zero_i32, dim3((nsync + 255) / 256), dim3(256), 0, st, nsync, D.sync);
+  const int ntiles = panel_tiles(D.n);
+  hipLaunchKernelGGL((k_schwarz_panel<T>), dim3(1 + ntiles), dim3(256), 0, st, D, backward, r, x, err,
+                     spin_max, ntiles);
+}
+
+// The panel form's per-group matrices, gathered from the dense copy once per
+// numeric setup: A(D_g, D_g) (entry l * 64 + k = A(dof_k, dof_l)) and the
+// blocks to the neighbouring groups, A(D_g+1, D_g) and A(D_g-1, D_g) (entry
+// k * 64 + kn = A(dof_{g+-1, kn}, dof_{g, k})), zero past the groups' slots.
+template <class T>
+__global__ void k_panel_slices(int ngroups, int64_t n, const int32_t* __restrict__ gdof,
+                               const T* __restrict__ Acm, T* __restrict__ gslc, T* __restrict__ gcf,
+                               T* __restrict__ gcb) {
   const int g = blockIdx.x;
-  const int64_t q0 = sb_ptr[grp_blk[g]];
-  const int m = (int)(sb_ptr[grp_blk[g + 1]] - q0);
-  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-    const int l = e / m, k = e % m;
-    slc[slc_off[g] + e] = Acm[(int64_t)sb_dofs[q0 + l] * n + sb_dofs[q0 + k]];
-  }
-  if (g + 1 < ngroups) {
-    const int64_t q1 = sb_ptr[grp_blk[g + 1]];
-    const int mn = (int)(sb_ptr[grp_blk[g + 2]] - q1);
-    for (int e = threadIdx.x; e < m * mn; e += blockDim.x) {
-      const int k = e / mn, kn = e % mn;
-      cor[cor_off[g] + e] = Acm[(int64_t)sb_dofs[q0 + k] * n + sb_dofs[q1 + kn]];
-    }
+  const int32_t* D = gdof + (int64_t)g * PANEL_SLOTS;
+  const int32_t* Df = g + 1 < ngroups ? D + PANEL_SLOTS : nullptr;
+  const int32_t* Db = g > 0 ? D - PANEL_SLOTS : nullptr;
+  for (int e = threadIdx.x; e < PANEL_ELEMS; e += blockDim.x) {
+    const int hi = e / PANEL_SLOTS, lo = e % PANEL_SLOTS;
+    const int dh = D[hi], dl = D[lo];
+    gslc[(int64_t)g * PANEL_ELEMS + e] = (dh >= 0 && dl >= 0) ? Acm[(int64_t)dh * n + dl] : T(0);
+    const int df = Df ? Df[lo] : -1, db = Db ? Db[lo] : -1;
+    gcf[(int64_t)g * PANEL_ELEMS + e] = (dh >= 0 && df >= 0) ? Acm[(int64_t)dh * n + df] : T(0);
+    gcb[(int64_t)g * PANEL_ELEMS + e] = (dh >= 0 && db >= 0) ? Acm[(int64_t)dh * n + db] : T(0);
   }
 }
 
-template <class T>
-void panel_slices(int ngroups, int64_t n, const int32_t* grp_blk, const int64_t* sb_ptr,
-                  const int32_t* sb_dofs, const T* Acm, const int64_t* slc_off, const int64_t* cor_off,
-                  T* slc, T* cor, hipStream_t st) {
+void panel_slices(int ngroups, int64_t n, const int32_t* gdof, const double* Acm, double* gslc,
+                  double* gcf, double* gcb, hipStream_t st) {
   if (ngroups > 0)
-    hipLaunchKernelGGL((k_panel_slices<T>), dim3(ngroups), dim3(256), 0, st, ngroups, n, grp_blk,
-                       sb_ptr, sb_dofs, Acm, slc_off, cor_off, slc, cor);
-}
-
-template <class T>
-void panel_sweep(int n, int ngroups, int backward, const int32_t* grp_blk, const int64_t* sb_ptr,
-                 const int32_t* sb_dofs, const int64_t* fac_off, const T* binv, const T* Acm,
-                 const T* slc, const T* cor, const int64_t* slc_off, const int64_t* cor_off,
-                 const int32_t* dgrp, const int32_t* sdup, T* r, T* x, T* dsl, int* sync, int* err,
-                 int spin_max, hipStream_t st) {
-  if (ngroups <= 0) return;
-  const int nsync = 2 * SYNC_STRIDE * ngroups;
-  hipLaunchKernelGGL(k_zero_i32, dim3((nsync + 255) / 256), dim3(256), 0, st, nsync, sync);
-  PanelArgs<T> P;
-  P.n = n;
-  P.ngroups = ngroups;
-  P.ntiles = panel_tiles(n);
-  P.backward = backward;
-  P.spin_max = spin_max;
-  P.grp_blk = grp_blk;
-  P.sb_ptr = sb_ptr;
-  P.sb_dofs = sb_dofs;
-  P.fac_off = fac_off;
-  P.binv_pad = binv;
-  P.Acm = Acm;
-  P.slc = slc;
-  P.cor = cor;
-  P.slc_off = slc_off;
-  P.cor_off = cor_off;
-  P.dgrp = dgrp;
-  P.sdup = sdup;
-  P.r = r;
-  P.x = x;
-  P.dsl = dsl;
-  P.flag = sync;
-  P.done = sync + SYNC_STRIDE * ngroups;
-  P.err = err;
-  hipLaunchKernelGGL((k_schwarz_panel<T>), dim3(1 + P.ntiles), dim3(256), 0, st, P);
+    hipLaunchKernelGGL((k_panel_slices<double>), dim3(ngroups), dim3(256), 0, st, ngroups, n, gdof, Acm,
+                       gslc, gcf, gcb);
 }
 
 // column-major dense copy of a CSR matrix (D(i, j) at D[j n + i])
@@ -2027,10 +2005,11 @@ __global__ void k_star_inv(int64_t nrows, const int32_t* __restrict__ row_blk,
 }
 
 // Each star row's row of its block's inverse, PANEL_SMAX wide, zero beyond
-// the block (the panel form's operand layout).
+// the block, at its group slot (the panel form's operand layout).
 __global__ void k_pad_inv(int64_t nrows, const int32_t* __restrict__ row_blk,
-                          const int64_t* __restrict__ sb_ptr, const int64_t* __restrict__ fac_off,
-                          const double* __restrict__ binv, double* __restrict__ out) {
+                          const int32_t* __restrict__ row_slot, const int64_t* __restrict__ sb_ptr,
+                          const int64_t* __restrict__ fac_off, const double* __restrict__ binv,
+                          double* __restrict__ out) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrows) return;
   const int b = row_blk[r];
@@ -2039,15 +2018,15 @@ __global__ void k_pad_inv(int64_t nrows, const int32_t* __restrict__ row_blk,
   const double* B = binv + fac_off[b];
   for (int j = 0; j < PANEL_SMAX; ++j) {
     const int hi = i > j ? i : j, lo = i > j ? j : i;
-    out[r * PANEL_SMAX + j] = j < s ? B[hi * (hi + 1) / 2 + lo] : 0.0;
+    out[(int64_t)row_slot[r] * PANEL_SMAX + j] = j < s ? B[hi * (hi + 1) / 2 + lo] : 0.0;
   }
 }
 
-void pad_inv(int64_t nrows, const int32_t* row_blk, const int64_t* sb_ptr, const int64_t* fac_off,
-             const double* binv, double* out, hipStream_t st) {
+void pad_inv(int64_t nrows, const int32_t* row_blk, const int32_t* row_slot, const int64_t* sb_ptr,
+             const int64_t* fac_off, const double* binv, double* out, hipStream_t st) {
   if (nrows > 0)
     hipLaunchKernelGGL(k_pad_inv, dim3((unsigned)((nrows + 127) / 128)), dim3(128), 0, st, nrows,
-                       row_blk, sb_ptr, fac_off, binv, out);
+                       row_blk, row_slot, sb_ptr, fac_off, binv, out);
 }
 
 void star_inv(int64_t nrows, const int32_t* row_blk, const int64_t* sb_ptr, const int64_t* fac_off,
@@ -2088,19 +2067,8 @@ template void schwarz_sweep_small<double>(const SmootherDev<double>&, int, const
 template void schwarz_sweep_small<float>(const SmootherDev<float>&, int, const float*, float*, hipStream_t);
 template void schwarz_pipe<double>(const SmootherDev<double>&, int, const double*, double*, hipStream_t);
 template void schwarz_pipe<float>(const SmootherDev<float>&, int, const float*, float*, hipStream_t);
-template void panel_sweep<double>(int, int, int, const int32_t*, const int64_t*, const int32_t*,
-                                  const int64_t*, const double*, const double*, const double*,
-                                  const double*, const int64_t*, const int64_t*, const int32_t*,
-                                  const int32_t*, double*, double*, double*, int*, int*, int,
-                                  hipStream_t);
-template void panel_sweep<float>(int, int, int, const int32_t*, const int64_t*, const int32_t*,
-                                 const int64_t*, const float*, const float*, const float*,
-                                 const float*, const int64_t*, const int64_t*, const int32_t*,
-                                 const int32_t*, float*, float*, float*, int*, int*, int,
-                                 hipStream_t);
-template void panel_slices<double>(int, int64_t, const int32_t*, const int64_t*, const int32_t*,
-                                   const double*, const int64_t*, const int64_t*, double*, double*,
-                                   hipStream_t);
+template void panel_sweep<double>(const PanelDev<double>&, int, double*, double*, int*, int, hipStream_t);
+template void panel_sweep<float>(const PanelDev<float>&, int, float*, float*, int*, int, hipStream_t);
 template bool dense_sweep_ok<double>(int, int);
 template bool dense_sweep_ok<float>(int, int);
 template void dense_sweep<double>(int, int, int, int, const int64_t*, const int32_t*, const int64_t*,

@@ -54,6 +54,32 @@ struct SmootherArgs {
 
 // ... and the host side: launch shape and the dense-level form.
 enum { SWEEP_COLOUR = 0, SWEEP_ONE = 1, SWEEP_PIPE = 2, SWEEP_DENSE = 3, SWEEP_PANEL = 4 };
+constexpr int PANEL_GROUP_SLOTS = 64;
+constexpr int PANEL_ROW_WIDTH = 16;   // largest block of the panel form; width of its inverse rows
+
+// Panel form of a level: groups of consecutive blocks in colour order with at
+// most PANEL_GROUP_SLOTS star rows ("slots") each; every per-group table is
+// padded to PANEL_GROUP_SLOTS slots so that its address follows from the
+// group index.
+template <class T>
+struct PanelDev {
+  int n = 0, ngroups = 0;
+  const int32_t* gdof = nullptr;   // per group slot: its DoF, -1 past the group's rows
+  const int32_t* gsl = nullptr;    // per group slot: first slot of its block | (slot of the same DoF
+                                   // in group g-1, + 1) << 8 | (in group g+1, + 1) << 16
+  const int32_t* gblk = nullptr;   // per group block: first slot | size << 8 | first << 16 and
+                                   // last << 24 block of its run of one colour; -1 past the blocks
+  const int32_t* dgrp = nullptr;   // per DoF: the (at most two) groups holding it, -1 if none
+  const int32_t* docc = nullptr;   // per DoF: its (at most two) slots g * 64 + t, ascending, -1 if none
+  const T* gslc = nullptr;         // per group: A(D_g, D_g), 64 x 64, entry l * 64 + k = A(dof_k, dof_l)
+  const T* gcf = nullptr;          // per group: A(D_g+1, D_g), entry k * 64 + kn = A(dof_{g+1,kn}, dof_{g,k})
+  const T* gcb = nullptr;          // per group: A(D_g-1, D_g), the same layout
+  const T* gbinv = nullptr;        // per group slot: its row of the block inverse, 16 wide
+  const T* Acm = nullptr;          // A(i, j) at Acm[j n + i]
+  T* dsl = nullptr;                // per sweep position: the published d of each slot
+  int* sync = nullptr;             // per sweep position: flag, then tile counter (SYNC_STRIDE apart)
+};
+
 template <class T>
 struct SmootherDev : SmootherArgs<T> {
   std::vector<int> colour_chunk_h;      // host copy of colour_chunk
@@ -68,18 +94,7 @@ struct SmootherDev : SmootherArgs<T> {
   int max_block = 0;
   const T* Acm = nullptr;
   T* rtmp = nullptr;                    // level-sized scratch for b - A x
-  // panel form (wide levels): groups of consecutive blocks in colour order
-  int ngroups = 0;
-  const int32_t* grp_blk = nullptr;     // first block of each group (+ sentinel)
-  const int32_t* dgrp = nullptr;        // the (at most two) groups of each DoF
-  const int32_t* sdup = nullptr;        // per star row: the group's other slot of its DoF
-  T* dsl = nullptr;                     // published block updates (64 per group)
-  const T* binv_pad = nullptr;          // per star row: its row of the block inverse, 16 wide
-  const T* slc = nullptr;               // per group A(D_g, D_g), and A(D_g+1, D_g)
-  const T* cor = nullptr;
-  const int64_t* slc_off = nullptr;
-  const int64_t* cor_off = nullptr;
-  int* psync = nullptr;                 // flags and tile counters (2 per group, SYNC_STRIDE apart)
+  PanelDev<T> pn;                       // panel form (wide levels)
 };
 
 // scalar slots of the CG state vector
@@ -105,18 +120,10 @@ void star_rows(int64_t nrows, const int32_t* sb_dofs, const int64_t* Aptr, const
                const int64_t* srow_ptr, double* sval, hipStream_t st);
 bool panel_sweep_ok(int n, int max_block);
 int panel_tiles(int n);
-constexpr int PANEL_GROUP_SLOTS = 64;
-constexpr int PANEL_ROW_WIDTH = 16;   // largest block of the panel form; width of its inverse rows
 template <class T>
-void panel_sweep(int n, int ngroups, int backward, const int32_t* grp_blk, const int64_t* sb_ptr,
-                 const int32_t* sb_dofs, const int64_t* fac_off, const T* binv, const T* Acm,
-                 const T* slc, const T* cor, const int64_t* slc_off, const int64_t* cor_off,
-                 const int32_t* dgrp, const int32_t* sdup, T* r, T* x, T* dsl, int* sync, int* err,
-                 int spin_max, hipStream_t st);
-template <class T>
-void panel_slices(int ngroups, int64_t n, const int32_t* grp_blk, const int64_t* sb_ptr,
-                  const int32_t* sb_dofs, const T* Acm, const int64_t* slc_off, const int64_t* cor_off,
-                  T* slc, T* cor, hipStream_t st);
+void panel_sweep(const PanelDev<T>& D, int backward, T* r, T* x, int* err, int spin_max, hipStream_t st);
+void panel_slices(int ngroups, int64_t n, const int32_t* gdof, const double* Acm, double* gslc,
+                  double* gcf, double* gcb, hipStream_t st);
 
 template <class T> bool dense_sweep_ok(int n, int max_block);
 template <class T>
@@ -144,9 +151,7 @@ void schwarz_sweep(const SmootherDev<T>& S, const CsrDev<T>& A, int backward, co
       return;
     case SWEEP_PANEL:
       residual<T>(A, x, b, S.rtmp, st);
-      panel_sweep<T>(S.n, S.ngroups, backward, S.grp_blk, S.sb_ptr, S.sb_dofs, S.fac_off, S.binv_pad,
-                     S.Acm, S.slc, S.cor, S.slc_off, S.cor_off, S.dgrp, S.sdup, S.rtmp, x, S.dsl,
-                     S.psync, S.err, S.spin_max, st);
+      panel_sweep<T>(S.pn, backward, S.rtmp, x, S.err, S.spin_max, st);
       return;
     default:
       for (int k = 0; k < S.ncolours; ++k)
@@ -200,8 +205,8 @@ void mm_vals_wide(int64_t nw, const int32_t* rows, const CsrPat& X, const double
                   const CsrPat& Y, const double* Yval, int64_t ncols, const int64_t* Cptr,
                   const int32_t* Ccol, double* Cval, hipStream_t st);
 
-void pad_inv(int64_t nrows, const int32_t* row_blk, const int64_t* sb_ptr, const int64_t* fac_off,
-             const double* binv, double* out, hipStream_t st);
+void pad_inv(int64_t nrows, const int32_t* row_blk, const int32_t* row_slot, const int64_t* sb_ptr,
+             const int64_t* fac_off, const double* binv, double* out, hipStream_t st);
 void star_inv(int64_t nrows, const int32_t* row_blk, const int64_t* sb_ptr, const int64_t* fac_off,
               const double* fac, double* binv, hipStream_t st);
 void star_chol(int64_t nb, const int64_t* sb_ptr, const int32_t* sb_dofs, const int64_t* fac_off,
