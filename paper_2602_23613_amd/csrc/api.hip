@@ -357,13 +357,15 @@ void host_csr(const amg_csr* M, std::vector<int64_t>& ptr, std::vector<int32_t>&
 //           workgroups (a launch per colour would leave the GPU idle between
 //           short colours);
 //   panel   16 or more colours, n <= 32768, and rows longer than 4096
-//           entries or at most 1.5 blocks per colour: the Galerkin operators
-//           near the bottom of the hierarchy are nearly dense, a pipelined
-//           chunk would stream tens of thousands of entries per block, and
-//           with one block per colour every colour step is a full round of
+//           entries, at most 1.5 blocks per colour, or no more groups of 64
+//           star rows than colours (at most 60 star rows per colour): the
+//           Galerkin operators near the bottom of the hierarchy are nearly
+//           dense, a pipelined chunk would stream thousands of entries per
+//           block, and every colour step of the pipe is a full round of
 //           inter-workgroup signalling; instead one workgroup chains groups
-//           of blocks while the others apply each group's residual update to
-//           their rows from a dense copy of A;
+//           of blocks (a group costs about what one pipelined colour does)
+//           while the others apply each group's residual update to their
+//           rows from a dense copy of A;
 //   one     small level with fewer colours: the whole sweep in one workgroup;
 //   colour  one launch per colour (the finest levels: few colours, many blocks);
 //   dense   nearly sequential level (at most 1.5 blocks per colour): block by
@@ -373,13 +375,16 @@ void host_csr(const amg_csr* M, std::vector<int64_t>& ptr, std::vector<int32_t>&
 // HCURL_AMG_SWEEP=colour|one|pipe|dense|panel forces a form where it applies
 // (dense and panel need a level that fits their kernels); HCURL_AMG_DENSE_SWEEP=0
 // turns the dense form off.
-int sweep_mode_for(int64_t n, int64_t nnz, int64_t ns, int ncolours, int maxs) {
+int sweep_mode_for(int64_t n, int64_t nnz, int64_t ns, int64_t nrows, int ncolours, int maxs) {
   const char* dense_env = std::getenv("HCURL_AMG_DENSE_SWEEP");
   const bool dense_any = !(dense_env && dense_env[0] == '0') && dense_sweep_ok<double>((int)n, maxs);
   const bool panel_ok = panel_sweep_ok((int)std::min<int64_t>(n, INT32_MAX), maxs);
   int mode = SWEEP_COLOUR;
   if (ncolours >= 16)
-    mode = (panel_ok && (nnz > 4096 * n || 2 * ns <= 3 * (int64_t)ncolours)) ? SWEEP_PANEL : SWEEP_PIPE;
+    mode = (panel_ok && (nnz > 4096 * n || 2 * ns <= 3 * (int64_t)ncolours ||
+                         nrows <= 60 * (int64_t)ncolours))
+               ? SWEEP_PANEL
+               : SWEEP_PIPE;
   else if (nnz <= 200000) mode = SWEEP_ONE;
   if (const char* e = std::getenv("HCURL_AMG_SWEEP")) {
     const std::string f(e);
@@ -497,7 +502,7 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   for (int64_t b = 0; b < ns; ++b) maxs = std::max<int>(maxs, (int)(I.star_ptr[b + 1] - I.star_ptr[b]));
   if (maxs > 32) fail(AMG_ERR_LIMIT, "smoother block with more than 32 DoFs");
   L.max_block = maxs;
-  L.sweep_mode = sweep_mode_for(L.n, L.nnz, ns, I.ncolors, maxs);
+  L.sweep_mode = sweep_mode_for(L.n, L.nnz, ns, (int64_t)I.star_dofs.size(), I.ncolors, maxs);
   // lanes per row from the row length; a chunk (wg / lpr rows) must hold a
   // whole block
   int lpr = L.lpr_A;

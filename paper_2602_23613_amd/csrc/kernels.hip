@@ -811,19 +811,29 @@ __device__ __forceinline__ T tree_sum(T (&v)[SB]) {
   return v[0];
 }
 
+// Lane values shared through LDS inside the chain's wavefront: LDS
+// operations of one wavefront are performed in order, so the fences only
+// keep the compiler from reordering them.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One block B (slots p .. p+s-1, s <= SB) of the chain, in one wavefront
 // (lane k = slot k): the lanes of B form d_k = sum_j (A_BB^{-1})_{k-p, j}
 // r_{p+j}, then every slot's residual drops by sum_j A(slot, p+j) d_j.
 // br holds this lane's row of its block's inverse (zero beyond the block;
 // meaningful for the lanes of B only, the others' d is never used).  The
-// slice columns are read before the chain needs them, the values of other
-// lanes are broadcast through the scalar unit, all independent of each
-// other, and each sum is a fixed pairwise tree, so the dependent chain is
-// two tree depths instead of 2 s multiply-adds.  The slice is zero past the
-// group's slots, so no lane needs a mask.
+// slice columns are read before the chain needs them; r_B comes through the
+// scalar unit and d_B through LDS (dsh, PANEL_SMAX entries of padding), all
+// reads independent of each other; each sum is a fixed pairwise tree, so
+// the dependent chain is two tree depths instead of 2 s multiply-adds.  The
+// slice is zero past the group's slots and the masks are selects on uniform
+// values, so the step has no branches.
 template <class T, int SB>
 __device__ __forceinline__ void panel_step(int k, int p, int s, const T (&br)[PANEL_SMAX],
-                                           const T* Aloc, T& rk, T& dk) {
+                                           const T* Aloc, T* dsh, T& rk, T& dk) {
   T a[SB], v[SB];
 #pragma unroll
   for (int j = 0; j < SB; ++j) {
@@ -834,34 +844,42 @@ __device__ __forceinline__ void panel_step(int k, int p, int s, const T (&br)[PA
   for (int j = 0; j < SB; ++j) v[j] = br[j] * lane_bcast(rk, (p + j) & (PANEL_SLOTS - 1));
   const T d = tree_sum<T, SB>(v);
   if (k >= p && k < p + s) dk = d;
+  dsh[k] = d;
+  wave_lds_sync();
 #pragma unroll
-  for (int j = 0; j < SB; ++j) v[j] = a[j] * (j < s ? lane_bcast(d, p + j) : T(0));
+  for (int j = 0; j < SB; ++j) {
+    const T dj = dsh[p + j];
+    v[j] = a[j] * (j < s ? dj : T(0));
+  }
   rk -= tree_sum<T, SB>(v);
 }
 
 // A run of consecutive blocks of one colour (slots P0 .. P1-1) in one step:
 // such blocks share no DoF and no entry of A, so each block's d comes from
 // the residual before the run, as it would after its predecessors in the
-// run.  Lane k forms d_k from its own block (first slot pk) with lane
-// shuffles, then every slot's residual drops by sum_l A(slot, l) d_l over
-// the run, summed in trees of sixteen.
+// run.  Lane k forms d_k from its own block (first slot pk; r through LDS,
+// rsh, zero past the slots), then every slot's residual drops by
+// sum_l A(slot, l) d_l over the run, summed in trees of sixteen.
 template <class T>
 __device__ __forceinline__ void panel_run(int k, int P0, int P1, int pk, const T (&br)[PANEL_SMAX],
-                                          const T* Aloc, T& rk, T& dk) {
+                                          const T* Aloc, T* rsh, T* dsh, T& rk, T& dk) {
   T v[PANEL_SMAX];
+  rsh[k] = rk;
+  wave_lds_sync();
 #pragma unroll
-  for (int j = 0; j < PANEL_SMAX; ++j) v[j] = br[j] * __shfl(rk, (pk + j) & (PANEL_SLOTS - 1));
+  for (int j = 0; j < PANEL_SMAX; ++j) v[j] = br[j] * rsh[pk + j];
   const T d = tree_sum<T, PANEL_SMAX>(v);
   if (k >= P0 && k < P1) dk = d;
+  dsh[k] = d;
+  wave_lds_sync();
   T acc = 0;
   for (int l0 = P0; l0 < P1; l0 += PANEL_SMAX) {
 #pragma unroll
     for (int j = 0; j < PANEL_SMAX; ++j) {
-      const int l = l0 + j < P1 ? l0 + j : P0;
-      v[j] = Aloc[l * PANEL_SLOTS + k];
+      const int l = l0 + j < PANEL_SLOTS ? l0 + j : PANEL_SLOTS - 1;
+      const T dl = dsh[l0 + j];
+      v[j] = Aloc[l * PANEL_SLOTS + k] * (l0 + j < P1 ? dl : T(0));
     }
-#pragma unroll
-    for (int j = 0; j < PANEL_SMAX; ++j) v[j] *= l0 + j < P1 ? lane_bcast(d, l0 + j) : T(0);
     acc += tree_sum<T, PANEL_SMAX>(v);
   }
   rk -= acc;
@@ -882,6 +900,8 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelDev<T> P, int backwa
   __shared__ T ds_s[PANEL_SLOTS];                 // the group's d (chain), the published d (tiles)
   __shared__ T rfin_s[PANEL_SLOTS];               // the chain's final residual of each slot
   __shared__ T rnx_s[PANEL_SLOTS];                // the next group's residual entries before correction
+  __shared__ T rsh[PANEL_SLOTS + PANEL_SMAX];     // lane values of the chain's wavefront (zero
+  __shared__ T dsh[PANEL_SLOTS + PANEL_SMAX];     // past the slots)
   __shared__ int dof_s[2][PANEL_SLOTS];
   __shared__ int gsl_s[PANEL_SLOTS];
   __shared__ int gblk_s[PANEL_SLOTS];
@@ -906,6 +926,10 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelDev<T> P, int backwa
       for (int j = 0; j < PANEL_ELEMS / 256; ++j) Aloc[tid + 256 * j] = pa[j];
 #pragma unroll
       for (int j = 0; j < PANEL_SLOTS * PANEL_SMAX / 256; ++j) fl[tid + 256 * j] = pf[j];
+      if (tid < PANEL_SMAX) {
+        rsh[PANEL_SLOTS + tid] = T(0);
+        dsh[PANEL_SLOTS + tid] = T(0);
+      }
       if (tid < 64) {
         const int d = P.gdof[g0 * PANEL_SLOTS + tid];
         const int bk = P.gblk[g0 * PANEL_SLOTS + tid];
@@ -951,12 +975,12 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelDev<T> P, int backwa
           if (lo == hi) {
             const int p = e & 255, s = (e >> 8) & 255;
             if (s <= PANEL_SMAX / 2)
-              panel_step<T, PANEL_SMAX / 2>(k, p, s, br, Aloc, rk, dk);
+              panel_step<T, PANEL_SMAX / 2>(k, p, s, br, Aloc, dsh, rk, dk);
             else
-              panel_step<T, PANEL_SMAX>(k, p, s, br, Aloc, rk, dk);
+              panel_step<T, PANEL_SMAX>(k, p, s, br, Aloc, dsh, rk, dk);
           } else {
             const int e0 = __builtin_amdgcn_readlane(bk, lo), e1 = __builtin_amdgcn_readlane(bk, hi);
-            panel_run<T>(k, e0 & 255, (e1 & 255) + ((e1 >> 8) & 255), pk, br, Aloc, rk, dk);
+            panel_run<T>(k, e0 & 255, (e1 & 255) + ((e1 >> 8) & 255), pk, br, Aloc, rsh, dsh, rk, dk);
           }
           ib = backward ? lo - 1 : hi + 1;
         }
