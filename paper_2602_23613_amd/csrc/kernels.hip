@@ -752,8 +752,9 @@ void dense_sweep(int n, int nblocks, int max_block, int backward, const int64_t*
 // wavefronts load the next group (padded per-group tables, so every
 // address follows from the group index alone) and the next group's
 // residual entries, which are complete once the tiles have applied every
-// group up to the one before the current; after the flag they form the
-// correction A(D_next, D_g) d and stage the next group in LDS.
+// group up to the one before the current, and stage all of it in the other
+// half of double-buffered LDS tables; after the flag they only form the
+// correction A(D_next, D_g) d.
 //
 // The other workgroups own tiles of PANEL_TROWS rows (two threads per row,
 // 32 slots each) and apply each group's update r_i -= sum_k A(i, dof_k) d_k
@@ -774,7 +775,7 @@ void dense_sweep(int n, int nblocks, int max_block, int backward, const int64_t*
 constexpr int PANEL_SLOTS = PANEL_GROUP_SLOTS;
 constexpr int PANEL_ELEMS = PANEL_SLOTS * PANEL_SLOTS;
 constexpr int PANEL_TROWS = 128;
-constexpr int PANEL_NMAX = 32768;
+constexpr int PANEL_NMAX = 16384;
 constexpr int PANEL_SMAX = PANEL_ROW_WIDTH;
 
 __device__ __forceinline__ void panel_wait(const int* p, int need, int* err, int spin_max) {
@@ -894,18 +895,20 @@ constexpr int PANEL_FPER = (PANEL_SLOTS * PANEL_SMAX + PANEL_STAGE - 1) / PANEL_
 template <class T>
 __global__ __launch_bounds__(256) void k_schwarz_panel(PanelDev<T> P, int backward, T* r, T* x,
                                                        int* err, int spin_max, int ntiles) {
-  __shared__ T Aloc[PANEL_ELEMS];                 // Aloc[l * 64 + k] = A(dof_k, dof_l)
-  __shared__ T fl[PANEL_SLOTS * PANEL_SMAX];      // per slot: its row of the block inverse (padded)
+  // the current group's tables in buffer pos & 1 while the next group is
+  // staged in the other
+  __shared__ T Aloc2[2][PANEL_ELEMS];             // Aloc[l * 64 + k] = A(dof_k, dof_l)
+  __shared__ T fl2[2][PANEL_SLOTS * PANEL_SMAX];  // per slot: its row of the block inverse (padded)
   __shared__ T part[3][PANEL_SLOTS];              // partial sums of the correction
   __shared__ T ds_s[PANEL_SLOTS];                 // the group's d (chain), the published d (tiles)
   __shared__ T rfin_s[PANEL_SLOTS];               // the chain's final residual of each slot
-  __shared__ T rnx_s[PANEL_SLOTS];                // the next group's residual entries before correction
+  __shared__ T rnx_s[2][PANEL_SLOTS];             // the group's residual entries before correction
   __shared__ T rsh[PANEL_SLOTS + PANEL_SMAX];     // lane values of the chain's wavefront (zero
   __shared__ T dsh[PANEL_SLOTS + PANEL_SMAX];     // past the slots)
   __shared__ int dof_s[2][PANEL_SLOTS];
-  __shared__ int gsl_s[PANEL_SLOTS];
-  __shared__ int gblk_s[PANEL_SLOTS];
-  __shared__ int gmn_s[2];                        // the group's slots and blocks
+  __shared__ int gsl_s[2][PANEL_SLOTS];
+  __shared__ int gblk_s[2][PANEL_SLOTS];
+  __shared__ int gmn_s[2][2];                     // the group's slots and blocks
   const int tid = threadIdx.x;
   const int G = P.ngroups;
   const int64_t n = P.n;
@@ -923,9 +926,9 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelDev<T> P, int backwa
       for (int j = 0; j < PANEL_SLOTS * PANEL_SMAX / 256; ++j)
         pf[j] = P.gbinv[(int64_t)g0 * PANEL_SLOTS * PANEL_SMAX + tid + 256 * j];
 #pragma unroll
-      for (int j = 0; j < PANEL_ELEMS / 256; ++j) Aloc[tid + 256 * j] = pa[j];
+      for (int j = 0; j < PANEL_ELEMS / 256; ++j) Aloc2[0][tid + 256 * j] = pa[j];
 #pragma unroll
-      for (int j = 0; j < PANEL_SLOTS * PANEL_SMAX / 256; ++j) fl[tid + 256 * j] = pf[j];
+      for (int j = 0; j < PANEL_SLOTS * PANEL_SMAX / 256; ++j) fl2[0][tid + 256 * j] = pf[j];
       if (tid < PANEL_SMAX) {
         rsh[PANEL_SLOTS + tid] = T(0);
         dsh[PANEL_SLOTS + tid] = T(0);
@@ -934,13 +937,13 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelDev<T> P, int backwa
         const int d = P.gdof[g0 * PANEL_SLOTS + tid];
         const int bk = P.gblk[g0 * PANEL_SLOTS + tid];
         dof_s[0][tid] = d;
-        gsl_s[tid] = P.gsl[g0 * PANEL_SLOTS + tid];
-        gblk_s[tid] = bk;
-        rnx_s[tid] = d >= 0 ? ld_x<T, true>(r + d) : T(0);
+        gsl_s[0][tid] = P.gsl[g0 * PANEL_SLOTS + tid];
+        gblk_s[0][tid] = bk;
+        rnx_s[0][tid] = d >= 0 ? ld_x<T, true>(r + d) : T(0);
         const unsigned long long vm = __ballot(d >= 0), vb = __ballot(bk >= 0);
         if (tid == 0) {
-          gmn_s[0] = __popcll(vm);
-          gmn_s[1] = __popcll(vb);
+          gmn_s[0][0] = __popcll(vm);
+          gmn_s[0][1] = __popcll(vb);
         }
       }
       __syncthreads();
@@ -952,19 +955,22 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelDev<T> P, int backwa
       if (tid < 64) {
         // wave 0: the chain over the group's blocks; lane k holds slot k
         const int k = tid;
-        const int m = gmn_s[0], nbk = gmn_s[1];
-        const int dofk = dof_s[pos & 1][k];
-        const int sl = gsl_s[k];
+        const int b = pos & 1;
+        const T* Aloc = Aloc2[b];
+        const T* fl = fl2[b];
+        const int m = gmn_s[b][0], nbk = gmn_s[b][1];
+        const int dofk = dof_s[b][k];
+        const int sl = gsl_s[b][k];
         const int pk = sl & 255;
         const int ips = ((backward ? sl >> 16 : sl >> 8) & 255) - 1;
         T rk = 0, dk = 0;
         if (k < m) {
-          if (pos == 0) rk = rnx_s[k];
+          if (pos == 0) rk = rnx_s[b][k];
           else if (ips >= 0) rk = rfin_s[ips];
-          else rk = rnx_s[k] - ((part[0][k] + part[1][k]) + part[2][k]);
+          else rk = rnx_s[b][k] - ((part[0][k] + part[1][k]) + part[2][k]);
         }
         // lane b holds block b's first slot, size and colour run
-        const int bk = k < nbk ? gblk_s[k] : 0;
+        const int bk = k < nbk ? gblk_s[b][k] : 0;
         T br[PANEL_SMAX];
 #pragma unroll
         for (int j = 0; j < PANEL_SMAX; ++j) br[j] = fl[k * PANEL_SMAX + j];
@@ -1031,11 +1037,34 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelDev<T> P, int backwa
           const int ipn = ((backward ? sln >> 16 : sln >> 8) & 255) - 1;
           if (dn >= 0 && ipn < 0) rn = ld_x<T, true>(r + dn);
         }
+        // the next group into the other buffer (read by the chain one
+        // iteration back, before the last barrier)
+        const int bn = (pos + 1) & 1;
+#pragma unroll
+        for (int j = 0; j < PANEL_PER; ++j) {
+          const int e = t + PANEL_STAGE * j;
+          if (e < PANEL_ELEMS) Aloc2[bn][e] = an[j];
+        }
+#pragma unroll
+        for (int j = 0; j < PANEL_FPER; ++j) {
+          const int e = t + PANEL_STAGE * j;
+          if (e < PANEL_SLOTS * PANEL_SMAX) fl2[bn][e] = fn[j];
+        }
+        if (tid < 128) {
+          dof_s[bn][t] = dn;
+          gsl_s[bn][t] = sln;
+          gblk_s[bn][t] = bkn;
+          rnx_s[bn][t] = rn;
+          const unsigned long long vm = __ballot(dn >= 0), vb = __ballot(bkn >= 0);
+          if (t == 0) {
+            gmn_s[bn][0] = __popcll(vm);
+            gmn_s[bn][1] = __popcll(vb);
+          }
+        }
       }
       __syncthreads();
       if (tid >= 64) {
-        // correction partial sums (this group's d is in ds_s), then the
-        // next group's staging
+        // correction partial sums (this group's d is in ds_s)
         T acc = 0;
 #pragma unroll
         for (int j = 0; j < PANEL_PER; ++j) {
@@ -1043,27 +1072,6 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelDev<T> P, int backwa
           if (k < PANEL_SLOTS) acc += cn[j] * ds_s[k];
         }
         part[pt][kn] = acc;
-#pragma unroll
-        for (int j = 0; j < PANEL_PER; ++j) {
-          const int e = t + PANEL_STAGE * j;
-          if (e < PANEL_ELEMS) Aloc[e] = an[j];
-        }
-#pragma unroll
-        for (int j = 0; j < PANEL_FPER; ++j) {
-          const int e = t + PANEL_STAGE * j;
-          if (e < PANEL_SLOTS * PANEL_SMAX) fl[e] = fn[j];
-        }
-        if (tid < 128) {
-          dof_s[(pos + 1) & 1][t] = dn;
-          gsl_s[t] = sln;
-          gblk_s[t] = bkn;
-          rnx_s[t] = rn;
-          const unsigned long long vm = __ballot(dn >= 0), vb = __ballot(bkn >= 0);
-          if (t == 0) {
-            gmn_s[0] = __popcll(vm);
-            gmn_s[1] = __popcll(vb);
-          }
-        }
       }
       __syncthreads();
     }
