@@ -825,33 +825,29 @@ __device__ __forceinline__ void wave_lds_sync() {
 // (lane k = slot k): the lanes of B form d_k = sum_j (A_BB^{-1})_{k-p, j}
 // r_{p+j}, then every slot's residual drops by sum_j A(slot, p+j) d_j.
 // br holds this lane's row of its block's inverse (zero beyond the block;
-// meaningful for the lanes of B only, the others' d is never used).  The
-// slice columns are read before the chain needs them; r_B comes through the
-// scalar unit and d_B through LDS (dsh, PANEL_SMAX entries of padding), all
-// reads independent of each other; each sum is a fixed pairwise tree, so
-// the dependent chain is two tree depths instead of 2 s multiply-adds.  The
-// slice is zero past the group's slots and the masks are selects on uniform
-// values, so the step has no branches.
+// meaningful for the lanes of B only).  The slice columns are read before
+// the chain needs them; r_B comes through the scalar unit and d_B through
+// LDS (dsh: d on the lanes of B, zero elsewhere and in PANEL_SMAX entries of
+// padding), all reads independent of each other; each sum is a fixed
+// pairwise tree, so the dependent chain is two tree depths instead of 2 s
+// multiply-adds.  The slice is zero past the group's slots, with PANEL_SMAX
+// rows of zero padding, so the step needs no masks and no branches.
 template <class T, int SB>
 __device__ __forceinline__ void panel_step(int k, int p, int s, const T (&br)[PANEL_SMAX],
                                            const T* Aloc, T* dsh, T& rk, T& dk) {
   T a[SB], v[SB];
+  const T* acol = Aloc + p * PANEL_SLOTS + k;
 #pragma unroll
-  for (int j = 0; j < SB; ++j) {
-    const int l = p + j < PANEL_SLOTS ? p + j : PANEL_SLOTS - 1;
-    a[j] = Aloc[l * PANEL_SLOTS + k];
-  }
+  for (int j = 0; j < SB; ++j) a[j] = acol[j * PANEL_SLOTS];
 #pragma unroll
   for (int j = 0; j < SB; ++j) v[j] = br[j] * lane_bcast(rk, (p + j) & (PANEL_SLOTS - 1));
   const T d = tree_sum<T, SB>(v);
-  if (k >= p && k < p + s) dk = d;
-  dsh[k] = d;
+  const bool inb = k >= p && k < p + s;
+  if (inb) dk = d;
+  dsh[k] = inb ? d : T(0);
   wave_lds_sync();
 #pragma unroll
-  for (int j = 0; j < SB; ++j) {
-    const T dj = dsh[p + j];
-    v[j] = a[j] * (j < s ? dj : T(0));
-  }
+  for (int j = 0; j < SB; ++j) v[j] = a[j] * dsh[p + j];
   rk -= tree_sum<T, SB>(v);
 }
 
@@ -860,7 +856,8 @@ __device__ __forceinline__ void panel_step(int k, int p, int s, const T (&br)[PA
 // the residual before the run, as it would after its predecessors in the
 // run.  Lane k forms d_k from its own block (first slot pk; r through LDS,
 // rsh, zero past the slots), then every slot's residual drops by
-// sum_l A(slot, l) d_l over the run, summed in trees of sixteen.
+// sum_l A(slot, l) d_l over the run (d zero outside it), summed in trees of
+// sixteen.
 template <class T>
 __device__ __forceinline__ void panel_run(int k, int P0, int P1, int pk, const T (&br)[PANEL_SMAX],
                                           const T* Aloc, T* rsh, T* dsh, T& rk, T& dk) {
@@ -870,17 +867,15 @@ __device__ __forceinline__ void panel_run(int k, int P0, int P1, int pk, const T
 #pragma unroll
   for (int j = 0; j < PANEL_SMAX; ++j) v[j] = br[j] * rsh[pk + j];
   const T d = tree_sum<T, PANEL_SMAX>(v);
-  if (k >= P0 && k < P1) dk = d;
-  dsh[k] = d;
+  const bool inr = k >= P0 && k < P1;
+  if (inr) dk = d;
+  dsh[k] = inr ? d : T(0);
   wave_lds_sync();
   T acc = 0;
   for (int l0 = P0; l0 < P1; l0 += PANEL_SMAX) {
+    const T* acol = Aloc + l0 * PANEL_SLOTS + k;
 #pragma unroll
-    for (int j = 0; j < PANEL_SMAX; ++j) {
-      const int l = l0 + j < PANEL_SLOTS ? l0 + j : PANEL_SLOTS - 1;
-      const T dl = dsh[l0 + j];
-      v[j] = Aloc[l * PANEL_SLOTS + k] * (l0 + j < P1 ? dl : T(0));
-    }
+    for (int j = 0; j < PANEL_SMAX; ++j) v[j] = acol[j * PANEL_SLOTS] * dsh[l0 + j];
     acc += tree_sum<T, PANEL_SMAX>(v);
   }
   rk -= acc;
@@ -891,13 +886,17 @@ __device__ __forceinline__ void panel_run(int k, int P0, int P1, int pk, const T
 constexpr int PANEL_STAGE = 192;
 constexpr int PANEL_PER = (PANEL_ELEMS + PANEL_STAGE - 1) / PANEL_STAGE;                   // 22
 constexpr int PANEL_FPER = (PANEL_SLOTS * PANEL_SMAX + PANEL_STAGE - 1) / PANEL_STAGE;     // 6
+// all but the last entry of each thread fall inside the matrix
+static_assert(PANEL_STAGE * (PANEL_PER - 1) <= PANEL_ELEMS, "staging layout");
+static_assert(PANEL_STAGE * (PANEL_FPER - 1) <= PANEL_SLOTS * PANEL_SMAX, "staging layout");
 
 template <class T>
 __global__ __launch_bounds__(256) void k_schwarz_panel(PanelDev<T> P, int backward, T* r, T* x,
                                                        int* err, int spin_max, int ntiles) {
   // the current group's tables in buffer pos & 1 while the next group is
   // staged in the other
-  __shared__ T Aloc2[2][PANEL_ELEMS];             // Aloc[l * 64 + k] = A(dof_k, dof_l)
+  __shared__ T Aloc2[2][PANEL_ELEMS + PANEL_SMAX * PANEL_SLOTS];   // Aloc[l * 64 + k] = A(dof_k, dof_l),
+                                                                  // PANEL_SMAX zero rows past l = 63
   __shared__ T fl2[2][PANEL_SLOTS * PANEL_SMAX];  // per slot: its row of the block inverse (padded)
   __shared__ T part[3][PANEL_SLOTS];              // partial sums of the correction
   __shared__ T ds_s[PANEL_SLOTS];                 // the group's d (chain), the published d (tiles)
@@ -932,6 +931,11 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelDev<T> P, int backwa
       if (tid < PANEL_SMAX) {
         rsh[PANEL_SLOTS + tid] = T(0);
         dsh[PANEL_SLOTS + tid] = T(0);
+      }
+#pragma unroll
+      for (int j = 0; j < PANEL_SMAX * PANEL_SLOTS / 256; ++j) {
+        Aloc2[0][PANEL_ELEMS + tid + 256 * j] = T(0);
+        Aloc2[1][PANEL_ELEMS + tid + 256 * j] = T(0);
       }
       if (tid < 64) {
         const int d = P.gdof[g0 * PANEL_SLOTS + tid];
@@ -1010,16 +1014,14 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelDev<T> P, int backwa
       if (tid >= 64) {
         const T* Sn = P.gslc + (int64_t)gn * PANEL_ELEMS;
 #pragma unroll
-        for (int j = 0; j < PANEL_PER; ++j) {
-          const int e = t + PANEL_STAGE * j;
-          an[j] = e < PANEL_ELEMS ? Sn[e] : T(0);
-        }
+        for (int j = 0; j < PANEL_PER - 1; ++j) an[j] = Sn[t + PANEL_STAGE * j];
+        an[PANEL_PER - 1] = t + PANEL_STAGE * (PANEL_PER - 1) < PANEL_ELEMS
+                                ? Sn[t + PANEL_STAGE * (PANEL_PER - 1)] : T(0);
         const T* Fn = P.gbinv + (int64_t)gn * PANEL_SLOTS * PANEL_SMAX;
 #pragma unroll
-        for (int j = 0; j < PANEL_FPER; ++j) {
-          const int e = t + PANEL_STAGE * j;
-          fn[j] = e < PANEL_SLOTS * PANEL_SMAX ? Fn[e] : T(0);
-        }
+        for (int j = 0; j < PANEL_FPER - 1; ++j) fn[j] = Fn[t + PANEL_STAGE * j];
+        fn[PANEL_FPER - 1] = t + PANEL_STAGE * (PANEL_FPER - 1) < PANEL_SLOTS * PANEL_SMAX
+                                 ? Fn[t + PANEL_STAGE * (PANEL_FPER - 1)] : T(0);
         // thread (kn, pt) holds A(dof_next[kn], dof_g[k]) for k = pt, pt + 3, ...
         const T* Cg = (backward ? P.gcb : P.gcf) + (int64_t)g * PANEL_ELEMS;
 #pragma unroll
@@ -1040,16 +1042,15 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelDev<T> P, int backwa
         // the next group into the other buffer (read by the chain one
         // iteration back, before the last barrier)
         const int bn = (pos + 1) & 1;
+        // only the last of each set can fall past the end
 #pragma unroll
-        for (int j = 0; j < PANEL_PER; ++j) {
-          const int e = t + PANEL_STAGE * j;
-          if (e < PANEL_ELEMS) Aloc2[bn][e] = an[j];
-        }
+        for (int j = 0; j < PANEL_PER - 1; ++j) Aloc2[bn][t + PANEL_STAGE * j] = an[j];
+        if (t + PANEL_STAGE * (PANEL_PER - 1) < PANEL_ELEMS)
+          Aloc2[bn][t + PANEL_STAGE * (PANEL_PER - 1)] = an[PANEL_PER - 1];
 #pragma unroll
-        for (int j = 0; j < PANEL_FPER; ++j) {
-          const int e = t + PANEL_STAGE * j;
-          if (e < PANEL_SLOTS * PANEL_SMAX) fl2[bn][e] = fn[j];
-        }
+        for (int j = 0; j < PANEL_FPER - 1; ++j) fl2[bn][t + PANEL_STAGE * j] = fn[j];
+        if (t + PANEL_STAGE * (PANEL_FPER - 1) < PANEL_SLOTS * PANEL_SMAX)
+          fl2[bn][t + PANEL_STAGE * (PANEL_FPER - 1)] = fn[PANEL_FPER - 1];
         if (tid < 128) {
           dof_s[bn][t] = dn;
           gsl_s[bn][t] = sln;
