@@ -461,16 +461,22 @@ def test_sweep_forms_agree(which):
             assert err <= tol, (lvl, form)
 
 
-def test_pipelined_sweep_reports_a_wait_that_gives_up():
-    """The pipelined sweep bounds every wait for the previous colour.  With a
-    limit of one poll (set from the host) the waits give up: the kernel still
-    ends, the handle's flag is raised and amg_check reports it; a handle with
-    the normal limit on the same problem reports nothing."""
+@pytest.mark.parametrize("form", ["pipe", "panel"])
+def test_one_launch_sweep_reports_a_wait_that_gives_up(form):
+    """The one-launch sweeps bound every wait (the pipe's wait for the previous
+    colour; the panel's tiles waiting for a group's d and its chain waiting for
+    the tiles).  With a limit of one poll (set from the host) the waits give
+    up: the kernel still ends, the handle's flag is raised and amg_check
+    reports it; a handle with the normal limit on the same problem reports
+    nothing."""
     d = dev()
     p, _ = case("hex16_jump_b1e-3")
-    env = {"HCURL_AMG_SWEEP": "pipe", "HCURL_AMG_DENSE_SWEEP": "0"}
+    env = {"HCURL_AMG_SWEEP": form, "HCURL_AMG_DENSE_SWEEP": "0"}
     H = _with_env(dict(env, HCURL_AMG_SPIN_MAX="1"), lambda: amglib.Hierarchy(p.A, p.G))
-    lvl = max(range(len(H.info()) - 1), key=lambda l: H.info()[l]["ncolors"])
+    info = H.info()
+    levels = [l for l in range(len(info) - 1) if info[l]["sweep_form"] == form]
+    assert levels, f"no level takes the {form} form"
+    lvl = max(levels, key=lambda l: info[l]["ncolors"])
     n = H.info()[lvl]["n"]
     b = torch.ones(n, dtype=torch.float64, device=d)
     x = torch.zeros_like(b)
