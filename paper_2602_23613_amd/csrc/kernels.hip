@@ -770,12 +770,14 @@ void dense_sweep(int n, int nblocks, int max_block, int backward, const int64_t*
 // Shared data (r, the published d) use agent-coherent accesses; a stored
 // value is complete (memory counter drained) before its flag or counter is
 // raised.  Every wait is bounded as in the pipelined sweep.  All workgroups
-// of the grid must be able to run at once (1 + n / PANEL_TROWS workgroups
-// of 256 threads, n <= PANEL_NMAX, on an otherwise idle device).
+// of the grid must be able to run at once: 1 + n / PANEL_TROWS <= 129
+// workgroups of 256 threads (n <= PANEL_NMAX), each holding more than half
+// a CU's LDS, so one per CU of the 256, on an otherwise idle device.
 constexpr int PANEL_SLOTS = PANEL_GROUP_SLOTS;
 constexpr int PANEL_ELEMS = PANEL_SLOTS * PANEL_SLOTS;
 constexpr int PANEL_TROWS = 128;
 constexpr int PANEL_NMAX = 16384;
+static_assert((long long)PANEL_NMAX * PANEL_NMAX < (1LL << 31), "dense-copy offsets in 32 bits");
 constexpr int PANEL_SMAX = PANEL_ROW_WIDTH;
 
 __device__ __forceinline__ void panel_wait(const int* p, int need, int* err, int spin_max) {
@@ -1097,11 +1099,16 @@ __global__ __launch_bounds__(256) void k_schwarz_panel(PanelDev<T> P, int backwa
     const int gn = pos + 1 < G ? (backward ? g - 1 : g + 1) : -2;
     const bool upd = row && ga != g && ga != gn && gb != g && gb != gn;
     const int dnx = (tid < 64 && gn >= 0) ? P.gdof[gn * PANEL_SLOTS + tid] : -1;
+    // every load is issued, from a clamped address and without a mask (the
+    // published d is zero past the group's slots, and rows that take no
+    // update store nothing), so the 32 loads are in flight together; n <=
+    // PANEL_NMAX, so the offsets into the dense copy fit in 32 bits
+    const int ic = row ? (int)i : 0, ni = (int)n;
     T a[PANEL_SLOTS / 2];
 #pragma unroll
     for (int j = 0; j < PANEL_SLOTS / 2; ++j) {
       const int d = dof_s[b][half * (PANEL_SLOTS / 2) + j];
-      a[j] = (upd && d >= 0) ? P.Acm[(int64_t)d * n + i] : T(0);
+      a[j] = P.Acm[(d >= 0 ? d : 0) * ni + ic];
     }
     // the tile wrote r_i last itself, or the chain did before an earlier flag
     const T ri = (upd && half == 0) ? ld_x<T, true>(r + i) : T(0);
@@ -1142,7 +1149,15 @@ void panel_sweep(const PanelDev<T>& D, int backward, T* r, T* x, int* err, int s
   const int nsync = 2 * SYNC_STRIDE * D.ngroups;
   hipLaunchKernelGGL(k_zero_i32, dim3((nsync + 255) / 256), dim3(256), 0, st, nsync, D.sync);
   const int ntiles = panel_tiles(D.n);
-  hipLaunchKernelGGL((k_schwarz_panel<T>), dim3(1 + ntiles), dim3(256), 0, st, D, backward, r, x, err,
+  // Unused dynamic LDS up to more than half a CU's 160 KB, so that no two
+  // workgroups share a CU: tiles on the chain's CU slow the chain.
+  static const size_t pad = [] {
+    hipFuncAttributes fa{};
+    const size_t want = 80 * 1024 + 1024;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_schwarz_panel<T>)) != hipSuccess) return size_t(0);
+    return fa.sharedSizeBytes >= want ? size_t(0) : want - fa.sharedSizeBytes;
+  }();
+  hipLaunchKernelGGL((k_schwarz_panel<T>), dim3(1 + ntiles), dim3(256), pad, st, D, backward, r, x, err,
                      spin_max, ntiles);
 }
 
