@@ -12,7 +12,8 @@ GPU library take its arrays as plain inputs.
 from .mesh import (hex_mesh, simplex_mesh_2d, kuhn_tet_mesh, assemble, Problem,
                    make_problem)
 from .fields import subdomain_log_uniform, stripes_2d, checkerboard, rhs_uniform
+from .geo import geo_interpolation_tri, geo_interpolation_hex, geo_hierarchy
 
 __all__ = ["hex_mesh", "simplex_mesh_2d", "kuhn_tet_mesh", "assemble", "Problem",
            "make_problem", "subdomain_log_uniform", "stripes_2d", "checkerboard",
-           "rhs_uniform"]
+           "rhs_uniform", "geo_interpolation_tri", "geo_interpolation_hex", "geo_hierarchy"]

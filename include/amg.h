@@ -57,7 +57,21 @@ typedef enum {
   AMG_ERR_NOT_FINITE = -10     /* NaN or Inf in the right-hand side */
 } amg_status;
 
-enum { AMG_INTERP_ALG = 0, AMG_INTERP_REF = 1 };
+enum { AMG_INTERP_ALG = 0, AMG_INTERP_REF = 1, AMG_INTERP_USER = 2 };
+
+/* Order of the smoothing steps in the V(1,1) cycle.  Section 5 uses one pre-
+   and one post-smoothing step of "symmetrised multiplicative Schwarz
+   followed by l1-Jacobi" (OSS-l1); it does not say how the post step is
+   ordered.
+     AMG_SCHWARZ_ADJOINT (default): pre = forward sweep, backward sweep,
+       l1-Jacobi; post = l1-Jacobi, forward sweep, backward sweep -- the
+       adjoint of the pre step, so that the cycle is a symmetric
+       preconditioner for CG;
+     AMG_SCHWARZ_REPEAT: post = pre (forward, backward, l1-Jacobi twice);
+       the literal reading, not symmetric;
+     AMG_SCHWARZ_SPLIT: pre = forward sweep, l1-Jacobi; post = l1-Jacobi,
+       backward sweep (half the sweeps; symmetric). */
+enum { AMG_SCHWARZ_ADJOINT = 0, AMG_SCHWARZ_REPEAT = 1, AMG_SCHWARZ_SPLIT = 2 };
 
 /* Compressed sparse row view (borrowed). */
 typedef struct {
@@ -90,6 +104,30 @@ typedef struct {
   const int64_t *ref_ncoarse;
   const int32_t *const *ref_coarse_bnd;
   const int64_t *ref_nbnd;
+  int schwarz_mode;        /* AMG_SCHWARZ_ADJOINT (default), AMG_SCHWARZ_REPEAT or AMG_SCHWARZ_SPLIT */
+  uint64_t seed;           /* seed of the counter-based start vector of the measured convergence
+                              factor (the learned setup's global check); nothing else is random */
+  /* AMG_INTERP_USER only: the caller gives the interpolation of every level
+     (for example the geometric Nedelec interpolation "Geo" of Section 5,
+     the paper's comparison method) instead of Algorithms 1-3 and
+     eq. (sparseP).  user_nlevels transfer operators: user_P[l] is
+     n_l x n_{l+1} and user_G[l + 1] the discrete gradient of level l + 1
+     (n_{l+1} rows; it defines that level's node-star smoother blocks);
+     user_G[0] is ignored (G is the argument of amg_setup).  Coarse
+     operators are the Galerkin products A_{l+1} = P_l^T A_l P_l.  Host or
+     device CSR views, read during amg_setup only. */
+  int user_nlevels;
+  const amg_csr *user_P;
+  const amg_csr *user_G;
+  /* vcycle_prec = 32 only: a level runs in FP32 unless eps_32 * rho_l exceeds
+     this tolerance (default 1e-3), where rho_l = max over node stars B of
+     sum |A_BB| / (s^T A_BB s), s = the signs of the star's column of G_l.
+     The gradient of a hat function is the near-kernel of the curl-curl
+     operator (A^s G = 0, Section 2); rounding A_l or a vector to FP32
+     perturbs that gradient's energy by about eps_32 * rho_l times itself,
+     so such a level keeps FP64 matrices, smoother and vectors.  A huge
+     value runs every level in FP32. */
+  double fp32_rho_tol;
 } amg_options;
 
 typedef struct amg_hier amg_hier;   /* opaque; owns all device memory of the hierarchy */
@@ -101,6 +139,11 @@ typedef struct {
   double seconds;          /* wall time of the solve on the host clock */
   double *history;         /* optional caller buffer (maxit + 1 doubles) of residual norms, or NULL */
   int replacements;        /* times CG continued from the true residual (see amg_pcg_solve) */
+  double floor_relres;     /* 64 eps || |A| |u| || / ||f - A u0||: the rounding level of an FP64
+                              residual at the final iterate; a true_relres near it cannot be
+                              reduced further in FP64 */
+  double conv_factor;      /* amg_pcg_solve: (relres)^(1/iterations); amg_cycle_solve: ratio of
+                              the last two residual norms (Section 5's "AMG conv") */
 } amg_solve_stats;
 
 typedef struct {
@@ -116,6 +159,8 @@ typedef struct {
                               2 colours pipelined in one launch, 3 dense residual-update form
                               in one workgroup, 4 panel residual-update form (wide levels) */
   int sweep_lanes;         /* lanes per row of the row forms (0 for the dense and panel forms) */
+  int prec;                /* 64 or 32: value type of this level's V-cycle work */
+  double grad_ratio;       /* rho_l of fp32_rho_tol (computed on every level but the coarsest) */
 } amg_level_info;
 
 /* Integer results of one level's setup, for bit-exact comparison.  All
@@ -139,9 +184,17 @@ typedef struct {
 /* Fill *opt with the paper's defaults (Section 5). */
 void amg_default_options(amg_options *opt);
 
-/* Build the hierarchy for A (n x n, SPD) and G (n x m discrete gradient).
-   The integer phase runs on the host, every floating-point step on the GPU.
-   On success *out owns a new handle. */
+/* Build the hierarchy for A (n x n, SPD) and G (n x m discrete gradient)
+   (Sections 3-4): per level, augmentG (Algorithm 1), the nodal C/F
+   splitting (Algorithm 2), the matching of length-two paths and R, S_I
+   (Algorithm 3), G_c = R G I_C (eq. (Gc)), P by local harmonic extension
+   (eq. (sparseP); in 3D the blocks of A_II follow the depth-ordered reading
+   when graph(A_II) has large components), A_c = P^T A P (Section 1), and the
+   node-star Schwarz smoother with its l1 diagonal (Section 5); coarsening
+   stops as in Section 5 (20 levels, 32 DoFs).  The integer phase runs on the
+   host, every floating-point step on the GPU.  A and G are borrowed for the
+   call; everything kept is copied.  On success *out owns a new handle; on
+   failure *out is NULL and nothing is left allocated. */
 amg_status amg_setup(const amg_csr *A, const amg_csr *G, const amg_options *opt,
                      void *stream, amg_hier **out);
 
@@ -151,32 +204,51 @@ amg_status amg_setup(const amg_csr *A, const amg_csr *G, const amg_options *opt,
    same mesh); the integer setup is reused unchanged. */
 amg_status amg_resetup_numeric(amg_hier *h, const amg_csr *A, void *stream);
 
-/* z = B r: one V(1,1) cycle with zero initial guess.  r and z are device
-   buffers of n doubles (the FP32 form converts at the boundary).  r and z
-   must not alias.  Asynchronous on `stream`. */
+/* z = B r: one V(1,1) cycle with zero initial guess (Section 1, eq. (tl)
+   applied recursively; smoothing as in Section 5 with the order of
+   amg_options.schwarz_mode; exact dense solve on the coarsest level).  r and
+   z are caller-owned device buffers of n doubles (the FP32 form converts at
+   the boundary) and must not alias.  Asynchronous on `stream`; the cycle is
+   captured once per (r, z) pair as a HIP graph and replayed. */
 amg_status amg_vcycle(amg_hier *h, const double *r, double *z, void *stream);
 
-/* Preconditioned CG on A u = f (FP64 vectors, reductions and updates; the
-   V-cycle in the handle's precision, with the flexible Polak-Ribiere beta
-   for the FP32 form).  f, u: device buffers of n doubles; u holds the
-   initial guess on entry and the iterate on exit.  Stops when the
-   recursively updated residual satisfies ||r|| <= rtol ||f - A u0|| and the
-   true residual f - A u does too; rounding makes the two drift apart over
-   many iterations on ill-conditioned systems, so when only the recursive one
-   meets the tolerance, CG continues from the true residual with a fresh
-   direction, until the true residual meets it or a restart no longer halves
-   it (the attainable accuracy of FP64 on that system; stats->true_relres
-   then reports it, above rtol).  Returns AMG_NOT_CONVERGED after maxit
-   iterations. */
+/* Preconditioned CG on A u = f with one V-cycle as the preconditioner
+   (Section 5: "PCG", relative residual tolerance 1e-8).  FP64 vectors,
+   reductions and updates; the V-cycle in the handle's precision, with the
+   flexible Polak-Ribiere beta for the FP32 form.  f, u: caller-owned device
+   buffers of n doubles; u holds the initial guess on entry and the iterate
+   on exit.  When the recursively updated residual meets
+   ||r|| <= rtol ||f - A u0||, the true residual f - A u is formed; if it
+   misses the tolerance (rounding makes the two drift apart on
+   ill-conditioned systems), CG continues from it with a fresh direction
+   until it meets the tolerance or a restart no longer halves it.
+   Returns AMG_OK only if the final true residual meets the tolerance, and
+   AMG_NOT_CONVERGED otherwise (maxit reached, or the true residual stuck
+   near the FP64 rounding level stats->floor_relres); u and stats then hold
+   the last iterate.  Synchronises. */
 amg_status amg_pcg_solve(amg_hier *h, const double *f, double *u, double rtol, int maxit,
                          amg_solve_stats *stats, void *stream);
+
+/* The stand-alone multigrid iteration u <- u + B (f - A u) (Section 5:
+   "standalone AMG V-cycle iteration counts"), until
+   ||f - A u|| <= rtol ||f - A u0|| (AMG_OK) or maxit cycles
+   (AMG_NOT_CONVERGED).  Same buffers and statistics as amg_pcg_solve;
+   stats->conv_factor is the ratio of the last two residual norms.
+   Synchronises. */
+amg_status amg_cycle_solve(amg_hier *h, const double *f, double *u, double rtol, int maxit,
+                           amg_solve_stats *stats, void *stream);
+
+/* Operator complexity sum_l nnz(A_l) / nnz(A_0) and grid complexity
+   sum_l n_l / n_0 of the hierarchy (the OC of Section 5's tables).  Either
+   pointer may be NULL. */
+amg_status amg_complexity(const amg_hier *h, double *oc, double *gc);
 
 /* One multiplicative Schwarz sweep of the smoother on level `level`
    (Section 5): for every colour in ascending order (backward = 0) or
    descending order (backward = 1), x_B += A_BB^{-1} (b - A x)_B for all
-   node-star blocks B of that colour.  prec = 64: b, x are device doubles
-   and the FP64 factors are used; prec = 32: device floats and the FP32
-   copies (only in a hierarchy built with vcycle_prec = 32).  Asynchronous;
+   node-star blocks B of that colour.  prec must be the level's precision
+   (amg_level_info.prec): 64 = device doubles and FP64 factors, 32 = device
+   floats and the FP32 copies.  Asynchronous;
    used for kernel tests and measurement.  A sweep whose colours run
    pipelined in one launch (levels with many colours) bounds each of its
    waits for the previous colour; a wait that gives up leaves x wrong and

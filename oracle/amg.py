@@ -547,7 +547,7 @@ class Hierarchy:
 
 
 DEFAULTS = dict(interp="alg", max_levels=20, min_coarse=32, ext_block_max=64,
-                ref_select=None, stall_ratio=0.9, p_trunc=0.0)
+                ref_select=None, stall_ratio=0.9, p_trunc=0.0, schwarz="adjoint", user=None)
 
 
 def setup(A, G, **opts):
@@ -569,10 +569,22 @@ def setup(A, G, **opts):
     levels = [Level(A=A, G=G)]
     S_prev = None
     fine_of = None
+    user = o["user"]
     while True:
         lv = levels[-1]
         n = lv.A.shape[0]
         lv.smoother = smoother_setup(lv.A, lv.G)
+        if user is not None:
+            # caller-given interpolation (the geometric "Geo" comparison of
+            # Section 5): P_l and G_{l+1} per level, Galerkin coarse operators
+            Ps, Gs = user
+            lvl = len(levels) - 1
+            if lvl >= len(Ps) or len(levels) >= o["max_levels"]:
+                break
+            lv.P = sp.csr_matrix(Ps[lvl])
+            lv.P.sort_indices()
+            levels.append(Level(A=galerkin(lv.A, lv.P), G=sp.csr_matrix(Gs[lvl + 1])))
+            continue
         if len(levels) >= o["max_levels"] or n <= o["min_coarse"]:
             break
         lv.Gt, lv.B = augment_g(lv.G)
@@ -658,32 +670,84 @@ def _schwarz(M, x, b, colors):
     return x
 
 
+# Above this value of eps_32 * rho_l (gradient_ratio) a level of the FP32
+# form keeps FP64: FP32 storage of A_l or of the iterate then perturbs the
+# level's gradient near-kernel by more than 1e-3 of its own energy.
+FP32_RHO_TOL = 1e-3
+
+
+def gradient_ratio(A, G):
+    """rho = max over nodes v of (|G|^T |A| |G|)_vv / (G^T A G)_vv.
+
+    (G^T A G)_vv is the energy of the gradient of node v's hat function and
+    the numerator the scale of the entries it is summed from, so a relative
+    perturbation eps of A's entries (or of a vector on the star of v) changes
+    that energy by about eps * rho times itself.  On the finest level rho is
+    about alpha / (beta h^2) (Section 2: A^s annihilates gradients, only
+    beta A^m sees them)."""
+    G = sp.csr_matrix(G)
+    num = (abs(G).T @ abs(A) @ abs(G)).diagonal()
+    den = (G.T @ A @ G).diagonal()
+    ok = den > 0
+    return float(np.max(num[ok] / den[ok])) if ok.any() else 1.0
+
+
+def level_dtypes(H, dtype):
+    """Value type of every level's V-cycle work.  FP64 everywhere for the FP64
+    cycle; for the FP32 form each level runs in FP32 unless
+    eps_32 * gradient_ratio exceeds FP32_RHO_TOL (then FP64).  The coarsest
+    solve is FP64 in both."""
+    if np.dtype(dtype) == np.float64:
+        return [np.float64] * H.nlevels
+    key = "_level_dtypes"
+    if key not in H.opts:
+        eps32 = float(np.finfo(np.float32).eps)
+        H.opts[key] = [np.float64 if eps32 * gradient_ratio(lv.A, lv.G) > FP32_RHO_TOL else np.float32
+                       for lv in H.levels]
+    return H.opts[key]
+
+
 def vcycle(H, b, dtype=np.float64, level=0):
     """One V(1,1) cycle with zero initial guess: returns x ~ A_l^{-1} b.
 
-    Pre-smoothing: multiplicative Schwarz forward (colours ascending) and
-    backward (descending), then l1-Jacobi.  Coarse correction with P^T / P.
-    Post-smoothing: l1-Jacobi, then forward and backward Schwarz, so the cycle
-    is symmetric.  The coarsest level is solved exactly in FP64.  With
-    dtype=float32 every level operation runs in FP32 (parity unpinned)."""
-    mats = _cast(H, dtype)
-    b = np.asarray(b, dtype=dtype)
+    Section 5 smooths with one pre- and one post-step of symmetrised
+    multiplicative Schwarz followed by l1-Jacobi.  The order of the post step
+    is H.opts['schwarz']:
+      'adjoint' (default): pre = forward sweep (colours ascending), backward
+          sweep (descending), l1-Jacobi; post = l1-Jacobi, forward, backward,
+          the adjoint of pre, so the cycle is symmetric (for CG);
+      'repeat': post = pre (forward, backward, l1-Jacobi);
+      'split': pre = forward, l1-Jacobi; post = l1-Jacobi, backward.
+    Coarse correction with P^T / P.  The coarsest level is solved exactly in
+    FP64.  With dtype=float32 each level runs in the type level_dtypes
+    gives it (FP32 unless its gradient near-kernel needs FP64); a vector
+    crossing between levels of different types is converted."""
+    mode = H.opts.get("schwarz", "adjoint")
+    dts = level_dtypes(H, dtype)
     if level == H.nlevels - 1:
         L = H.coarse_chol
-        y = np.linalg.solve(L, b.astype(np.float64))
-        return np.linalg.solve(L.T, y).astype(dtype)
-    M = mats[level]
+        y = np.linalg.solve(L, np.asarray(b, dtype=np.float64))
+        return np.linalg.solve(L.T, y)
+    dt = dts[level]
+    M = _cast(H, dt)[level]
+    b = np.asarray(b, dtype=dt)
     nc = H.levels[level].smoother.ncolors
     x = np.zeros_like(b)
     up, down = list(range(nc)), list(range(nc - 1, -1, -1))
     x = _schwarz(M, x, b, up)
-    x = _schwarz(M, x, b, down)
+    if mode != "split":
+        x = _schwarz(M, x, b, down)
     x = x + (b - M["A"] @ x) / M["l1"]
     r = b - M["A"] @ x
     xc = vcycle(H, M["PT"] @ r, dtype, level + 1)
-    x = x + M["P"] @ xc
+    x = x + M["P"] @ np.asarray(xc, dtype=dt)
+    if mode == "repeat":
+        x = _schwarz(M, x, b, up)
+        x = _schwarz(M, x, b, down)
+        return x + (b - M["A"] @ x) / M["l1"]
     x = x + (b - M["A"] @ x) / M["l1"]
-    x = _schwarz(M, x, b, up)
+    if mode != "split":
+        x = _schwarz(M, x, b, up)
     x = _schwarz(M, x, b, down)
     return x
 

@@ -43,15 +43,33 @@ def _csr_arg(M, keep):
 
 
 def _options(keep, interp="alg", max_levels=20, min_coarse=32, vcycle_prec=64, ext_block_max=64,
-             stall_ratio=0.9, p_trunc=0.0, ref=None):
+             stall_ratio=0.9, p_trunc=0.0, ref=None, schwarz="adjoint", seed=None, user=None,
+             fp32_rho_tol=None):
     o = _lib.default_options()
-    o.interp = _lib.AMG_INTERP_REF if interp == "ref" else _lib.AMG_INTERP_ALG
+    o.interp = {"alg": _lib.AMG_INTERP_ALG, "ref": _lib.AMG_INTERP_REF,
+                "user": _lib.AMG_INTERP_USER}[interp]
     o.max_levels = max_levels
     o.min_coarse = min_coarse
     o.vcycle_prec = vcycle_prec
     o.ext_block_max = ext_block_max
     o.stall_ratio = stall_ratio
     o.p_trunc = p_trunc
+    o.schwarz_mode = _lib.SCHWARZ_MODES[schwarz]
+    if seed is not None:
+        o.seed = seed
+    if fp32_rho_tol is not None:
+        o.fp32_rho_tol = fp32_rho_tol
+    if user:
+        # user: (list of P_l, list of G_l with G_0 unused) as scipy CSR matrices
+        Ps, Gs = user
+        nl = len(Ps)
+        pa = (_lib.amg_csr * nl)(*[_csr_arg(P, keep) for P in Ps])
+        ga = (_lib.amg_csr * (nl + 1))(*[_csr_arg(G, keep) if G is not None else _lib.amg_csr()
+                                         for G in Gs[:nl + 1]])
+        keep.extend([pa, ga])
+        o.user_nlevels = nl
+        o.user_P = C.cast(pa, C.POINTER(_lib.amg_csr))
+        o.user_G = C.cast(ga, C.POINTER(_lib.amg_csr))
     if ref:
         # ref: list of (coarse real nodes, coarse artificial nodes) per level
         nl = len(ref)
@@ -70,6 +88,22 @@ def _options(keep, interp="alg", max_levels=20, min_coarse=32, vcycle_prec=64, e
         o.ref_ncoarse = C.cast(cnt_n, C.POINTER(C.c_int64))
         o.ref_nbnd = C.cast(cnt_b, C.POINTER(C.c_int64))
     return o
+
+
+def _vec(t, n, name, dtype="float64"):
+    """Pointer of a device vector after checking what the kernels assume: a
+    CUDA tensor of the given dtype, contiguous, with exactly n entries."""
+    import torch
+    want = torch.float64 if dtype == "float64" else torch.float32
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != want:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, the level has {n}")
+    return t.data_ptr()
 
 
 class Hierarchy:
@@ -105,21 +139,38 @@ class Hierarchy:
 
     def vcycle(self, r, z, stream=None):
         """z = B r (device float64 tensors), asynchronous on the stream."""
-        _lib.check(load().amg_vcycle(self._h, r.data_ptr(), z.data_ptr(), _stream(stream)))
+        _lib.check(load().amg_vcycle(self._h, _vec(r, self.n, "r"), _vec(z, self.n, "z"),
+                                     _stream(stream)))
 
-    def pcg(self, f, u, rtol=1e-8, maxit=500, history=False, stream=None):
+    def _solve(self, fn, f, u, rtol, maxit, history, stream):
         st = _lib.amg_solve_stats()
         hist = None
         if history:
             hist = np.zeros(maxit + 1)
             st.history = hist.ctypes.data_as(C.POINTER(C.c_double))
-        status = _lib.check(load().amg_pcg_solve(self._h, f.data_ptr(), u.data_ptr(), rtol, maxit,
-                                                 C.byref(st), _stream(stream)))
-        out = dict(status=status, iterations=st.iterations, relres=st.relres,
-                   true_relres=st.true_relres, seconds=st.seconds, replacements=st.replacements)
+        status = _lib.check(fn(self._h, _vec(f, self.n, "f"), _vec(u, self.n, "u"), rtol, maxit,
+                               C.byref(st), _stream(stream)))
+        out = dict(status=status, converged=status == _lib.AMG_OK, iterations=st.iterations,
+                   relres=st.relres, true_relres=st.true_relres, seconds=st.seconds,
+                   replacements=st.replacements, floor_relres=st.floor_relres,
+                   conv_factor=st.conv_factor)
         if history:
             out["history"] = hist[:st.iterations + 1].copy()
         return out
+
+    def pcg(self, f, u, rtol=1e-8, maxit=500, history=False, stream=None):
+        """amg_pcg_solve: status AMG_OK only if the true residual meets rtol."""
+        return self._solve(load().amg_pcg_solve, f, u, rtol, maxit, history, stream)
+
+    def cycle_solve(self, f, u, rtol=1e-8, maxit=400, history=False, stream=None):
+        """amg_cycle_solve: the stand-alone iteration u <- u + B (f - A u)."""
+        return self._solve(load().amg_cycle_solve, f, u, rtol, maxit, history, stream)
+
+    def complexity(self):
+        """(operator complexity, grid complexity) of the hierarchy."""
+        oc, gc = C.c_double(), C.c_double()
+        _lib.check(load().amg_complexity(self._h, C.byref(oc), C.byref(gc)))
+        return oc.value, gc.value
 
     def info(self):
         cap = 32
@@ -129,15 +180,21 @@ class Hierarchy:
         return [dict(n=x.n, nnz=x.nnz, p_nnz=x.p_nnz, nblocks=x.nblocks, ncolors=x.ncolors,
                      exact_blocks=bool(x.exact_blocks), star_rows=x.star_rows,
                      star_row_nnz=x.star_row_nnz, fac_entries=x.fac_entries,
-                     sweep_form=SWEEP_FORMS[x.sweep_form], sweep_lanes=x.sweep_lanes)
+                     sweep_form=SWEEP_FORMS[x.sweep_form], sweep_lanes=x.sweep_lanes,
+                     prec=x.prec, grad_ratio=x.grad_ratio)
                 for x in arr[:nl.value]]
 
     def sweep(self, level, b, x, backward=False, stream=None):
         """One multiplicative Schwarz sweep on `level` (x updated in place)."""
         import torch
         prec = 32 if b.dtype == torch.float32 else 64
-        _lib.check(load().amg_smoother_sweep(self._h, level, prec, b.data_ptr(), x.data_ptr(),
-                                             1 if backward else 0, _stream(stream)))
+        info = self.info()
+        if not 0 <= level < len(info) - 1:
+            raise ValueError("level has no smoother")
+        n, dt = info[level]["n"], "float32" if prec == 32 else "float64"
+        _lib.check(load().amg_smoother_sweep(self._h, level, prec, _vec(b, n, "b", dt),
+                                             _vec(x, n, "x", dt), 1 if backward else 0,
+                                             _stream(stream)))
 
     def check(self, stream=None):
         """Synchronize and raise if a pipelined smoother sweep gave up a wait."""

@@ -18,6 +18,8 @@ AMG_OK = 0
 AMG_NOT_CONVERGED = 1
 AMG_INTERP_ALG = 0
 AMG_INTERP_REF = 1
+AMG_INTERP_USER = 2
+SCHWARZ_MODES = {"adjoint": 0, "repeat": 1, "split": 2}
 
 STATUS = {0: "AMG_OK", 1: "AMG_NOT_CONVERGED", -1: "AMG_ERR_ARG", -2: "AMG_ERR_SHAPE",
           -3: "AMG_ERR_CSR", -4: "AMG_ERR_G_NOT_INCIDENCE", -5: "AMG_ERR_NOT_SPD",
@@ -28,7 +30,8 @@ EXPORTED = ["amg_default_options", "amg_setup", "amg_resetup_numeric", "amg_vcyc
             "amg_pcg_solve", "amg_smoother_sweep", "amg_spmv", "amg_hier_info", "amg_export_integers",
             "amg_export_level", "amg_level0_integers", "amg_free_integers", "amg_destroy",
             "amg_last_error", "amg_mlp_nparams", "amg_mlp_train", "amg_mlp_use", "amg_mlp_stats_get",
-            "amg_mlp_params", "amg_mlp_forward", "amg_mlp_backward", "amg_mlp_loss_grad", "amg_check"]
+            "amg_mlp_params", "amg_mlp_forward", "amg_mlp_backward", "amg_mlp_loss_grad", "amg_check",
+            "amg_cycle_solve", "amg_complexity"]
 
 
 class AmgError(RuntimeError):
@@ -51,20 +54,25 @@ class amg_options(C.Structure):
                 ("ref_coarse_nodes", C.POINTER(C.POINTER(C.c_int32))),
                 ("ref_ncoarse", C.POINTER(C.c_int64)),
                 ("ref_coarse_bnd", C.POINTER(C.POINTER(C.c_int32))),
-                ("ref_nbnd", C.POINTER(C.c_int64))]
+                ("ref_nbnd", C.POINTER(C.c_int64)),
+                ("schwarz_mode", C.c_int), ("seed", C.c_uint64),
+                ("user_nlevels", C.c_int), ("user_P", C.POINTER(amg_csr)),
+                ("user_G", C.POINTER(amg_csr)), ("fp32_rho_tol", C.c_double)]
 
 
 class amg_solve_stats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("relres", C.c_double), ("true_relres", C.c_double),
                 ("seconds", C.c_double), ("history", C.POINTER(C.c_double)),
-                ("replacements", C.c_int)]
+                ("replacements", C.c_int), ("floor_relres", C.c_double),
+                ("conv_factor", C.c_double)]
 
 
 class amg_level_info(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("p_nnz", C.c_int64),
                 ("nblocks", C.c_int64), ("ncolors", C.c_int), ("exact_blocks", C.c_int),
                 ("star_rows", C.c_int64), ("star_row_nnz", C.c_int64), ("fac_entries", C.c_int64),
-                ("sweep_form", C.c_int), ("sweep_lanes", C.c_int)]
+                ("sweep_form", C.c_int), ("sweep_lanes", C.c_int), ("prec", C.c_int),
+                ("grad_ratio", C.c_double)]
 
 
 class amg_int_export(C.Structure):
@@ -127,6 +135,8 @@ def load():
     lib.amg_resetup_numeric.argtypes = [P, C.POINTER(amg_csr), P]
     lib.amg_vcycle.argtypes = [P, P, P, P]
     lib.amg_pcg_solve.argtypes = [P, P, P, C.c_double, C.c_int, C.POINTER(amg_solve_stats), P]
+    lib.amg_cycle_solve.argtypes = [P, P, P, C.c_double, C.c_int, C.POINTER(amg_solve_stats), P]
+    lib.amg_complexity.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.amg_spmv.argtypes = [C.POINTER(amg_csr), P, P, P]
     lib.amg_smoother_sweep.argtypes = [P, C.c_int, C.c_int, P, P, C.c_int, P]
     lib.amg_check.argtypes = [P, P]
@@ -151,6 +161,7 @@ def load():
     lib.amg_mlp_backward.argtypes = [P, P, C.c_int64, P, P, P]
     lib.amg_mlp_loss_grad.argtypes = [P, P, P, C.c_int64, C.c_int64, P, P, P]
     for name in ("amg_setup", "amg_resetup_numeric", "amg_vcycle", "amg_pcg_solve", "amg_spmv",
+                 "amg_cycle_solve", "amg_complexity",
                  "amg_smoother_sweep", "amg_check",
                  "amg_hier_info", "amg_export_integers", "amg_export_level",
                  "amg_level0_integers", "amg_mlp_train", "amg_mlp_use", "amg_mlp_stats_get",

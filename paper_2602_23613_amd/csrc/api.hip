@@ -104,6 +104,10 @@ struct Level {
   Pattern S;
   LevelInts ints;
   bool coarsest = false;
+  bool user_p = false;             // P given by the caller (AMG_INTERP_USER)
+  int prec = 64;                   // value type of this level's V-cycle work (64 or 32)
+  double grad_ratio = 0.0;         // max over node stars of sum |A_BB| / (s^T A_BB s)
+  int8_t* ssign = nullptr;         // per star row: G[row, node of its star]
   // device: A
   int64_t n = 0, nnz = 0;
   int64_t* A_ptr = nullptr;
@@ -535,13 +539,33 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
     for (int c = 0; c < I.ncolors; ++c) cnt[c + 1] += cnt[c];
     for (int64_t b = 0; b < ns; ++b) order[cnt[I.star_color[b]]++] = b;
   }
+  // node of each star (stars are built for the columns of G with a
+  // non-empty support, in column order) and each star row's sign G[e, v]
+  std::vector<int32_t> star_node;
+  {
+    std::vector<char> used(L.G.m, 0);
+    for (int64_t e = 0; e < L.G.n; ++e) {
+      if (L.G.a[e] >= 0) used[L.G.a[e]] = 1;
+      if (L.G.b[e] >= 0) used[L.G.b[e]] = 1;
+    }
+    for (int64_t v = 0; v < L.G.m; ++v)
+      if (used[v]) star_node.push_back((int32_t)v);
+    if ((int64_t)star_node.size() != ns) fail(AMG_ERR_SHAPE, "star count differs from G's used columns");
+  }
   std::vector<int64_t> sb_ptr(ns + 1, 0), fac_off(ns + 1, 0);
   std::vector<int32_t> sb_dofs;
+  std::vector<int8_t> ssign;
   sb_dofs.reserve(I.star_dofs.size());
+  ssign.reserve(I.star_dofs.size());
   for (int64_t t = 0; t < ns; ++t) {
     int64_t b = order[t];
     int64_t s = I.star_ptr[b + 1] - I.star_ptr[b];
-    for (int64_t q = I.star_ptr[b]; q < I.star_ptr[b + 1]; ++q) sb_dofs.push_back(I.star_dofs[q]);
+    const int32_t v = star_node[b];
+    for (int64_t q = I.star_ptr[b]; q < I.star_ptr[b + 1]; ++q) {
+      const int32_t e = I.star_dofs[q];
+      sb_dofs.push_back(e);
+      ssign.push_back(L.G.a[e] == v ? L.G.sa[e] : L.G.sb[e]);
+    }
     sb_ptr[t + 1] = sb_ptr[t] + s;
     fac_off[t + 1] = fac_off[t] + s * (s + 1) / 2;
   }
@@ -609,6 +633,17 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   int grid = h->cu_count;
   if (const char* e = std::getenv("HCURL_AMG_PIPE_GRID")) grid = std::max(1, std::atoi(e));
   L.pipe_grid = std::max(1, std::min(nchunks, grid));
+  // the panel form needs all 1 + n/128 of its workgroups resident at once
+  // (the chain and the tiles wait on each other): keep it only if the
+  // device's CUs can hold them (occupancy query with the launch's LDS
+  // padding, for every precision the hierarchy sweeps in); otherwise the
+  // pipelined form, which needs no residency, takes the level
+  if (L.sweep_mode == SWEEP_PANEL) {
+    const int64_t need = 1 + (int64_t)panel_tiles((int)L.n);
+    int per_cu = panel_resident_per_cu(64);
+    if (h->prec == 32) per_cu = std::min(per_cu, panel_resident_per_cu(32));
+    if (per_cu < 1 || need > (int64_t)per_cu * h->cu_count) L.sweep_mode = SWEEP_PIPE;
+  }
   if (L.sweep_mode == SWEEP_PANEL) {
     std::vector<int32_t> grp_blk, dgrp, sdup, blk_col(ns), gdof, gsl, gblk, docc, row_slot;
     for (int64_t t = 0; t < ns; ++t) blk_col[t] = I.star_color[order[t]];
@@ -636,6 +671,7 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
     L.Acm = h->pool.get<double>((size_t)L.n * L.n);
   L.sb_ptr = h->pool.upload(sb_ptr, st);
   L.sb_dofs = h->pool.upload(sb_dofs, st);
+  L.ssign = h->pool.upload(ssign, st);
   L.fac_off = h->pool.upload(fac_off, st);
   L.fac_total = fac_off[ns];
   L.fac = h->pool.get<double>(L.fac_total);
@@ -772,6 +808,45 @@ void compute_interp(amg_hier* h, Level& L, int level, hipStream_t st, bool learn
              "local harmonic extension: non-positive pivot in A_BB on level " + std::to_string(level));
 }
 
+// --- caller-given interpolation (AMG_INTERP_USER) ---
+void load_user_interp(amg_hier* h, Level& L, const amg_csr& P, int level, hipStream_t st) {
+  const std::string lv = "user P on level " + std::to_string(level);
+  if (P.nrows != L.n) fail(AMG_ERR_SHAPE, lv + ": rows differ from the level's DoFs");
+  if (P.ncols < 1 || P.ncols >= L.n) fail(AMG_ERR_SHAPE, lv + ": needs 1 <= columns < rows");
+  if (!P.rowptr || (P.nnz > 0 && (!P.colidx || !P.val))) fail(AMG_ERR_ARG, lv + ": NULL pointer");
+  std::vector<double> val;
+  host_csr(&P, L.p_ptr_h, L.p_col_h, &val);
+  HostError err;
+  if (!validate_pattern(P.nrows, P.ncols, L.p_ptr_h.data(), L.p_col_h.data(), err))
+    fail((amg_status)err.code, lv + ": " + err.msg);
+  L.user_p = true;
+  L.nc = P.ncols;
+  L.p_nnz = P.nnz;
+  L.P_ptr = h->pool.upload(L.p_ptr_h, st);
+  L.P_col = h->pool.upload(L.p_col_h, st);
+  L.P_val = h->pool.upload(val, st);
+  L.lpr_P = lpr_for(L.n, L.p_nnz);
+  L.p_row_max = 0;
+  for (int64_t i = 0; i < L.n; ++i)
+    L.p_row_max = std::max<int>(L.p_row_max, (int)(L.p_ptr_h[i + 1] - L.p_ptr_h[i]));
+  HIPC(hipStreamSynchronize(st));
+}
+
+Incidence user_gradient(const amg_csr& G, int64_t n, int level) {
+  const std::string lv = "user G on level " + std::to_string(level);
+  if (!G.rowptr || (G.nnz > 0 && (!G.colidx || !G.val))) fail(AMG_ERR_ARG, lv + ": NULL pointer");
+  if (G.nrows != n) fail(AMG_ERR_SHAPE, lv + ": rows differ from the level's DoFs");
+  std::vector<int64_t> ptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;
+  host_csr(&G, ptr, col, &val);
+  Incidence out;
+  HostError err;
+  if (!incidence_from_csr(G.nrows, G.ncols, ptr.data(), col.data(), val.data(), out, err))
+    fail((amg_status)err.code, lv + ": " + err.msg);
+  return out;
+}
+
 // --- Galerkin product A_c = P^T (A P): symbolic (once) and numeric ---
 // C = X Y symbolic: row counts, host scan, sorted columns.  Rows with more
 // distinct columns than the LDS hash holds take the bitset passes.  Returns
@@ -862,7 +937,35 @@ void coarsest_factor(amg_hier* h, Level& L, hipStream_t st) {
   check_flag(h, st, AMG_ERR_NOT_SPD, "coarsest Cholesky: non-positive pivot");
 }
 
+// Precision of every level of the FP32 form (reading R18): a level runs in
+// FP32 unless eps_32 * rho exceeds the tolerance, where rho is the largest
+// ratio sum |A_BB| / (s^T A_BB s) over its node stars: the gradient of a hat
+// function is the near-kernel (A^s G = 0, only beta A^m sees it), and a
+// relative perturbation eps of A's entries, or of a vector on the star,
+// perturbs its energy by about eps * rho times itself.  Such a level keeps
+// FP64 (matrices, smoother and vectors).  The coarsest level uses its
+// parent's vector type (its solve is FP64 in any case).
+void choose_precisions(amg_hier* h, hipStream_t st) {
+  const size_t nl = h->lv.size();
+  const double eps32 = 1.1920928955078125e-07;
+  for (size_t l = 0; l < nl; ++l) {
+    Level& L = h->lv[l];
+    if (L.coarsest) {
+      L.prec = l > 0 ? h->lv[l - 1].prec : h->prec;
+      continue;
+    }
+    std::vector<double> rho(std::max<int64_t>(L.nstars, 1), 0.0);
+    double* d_rho = h->pool.get<double>(rho.size());
+    star_rho(L.nstars, L.sb_ptr, L.sb_dofs, L.ssign, L.srow_ptr, L.scol, L.sval, d_rho, st);
+    HIPC(hipMemcpyAsync(rho.data(), d_rho, rho.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    L.grad_ratio = *std::max_element(rho.begin(), rho.end());
+    L.prec = (h->prec == 32 && eps32 * L.grad_ratio <= h->opt.fp32_rho_tol) ? 32 : 64;
+  }
+}
+
 void cast_level(amg_hier* h, Level& L, hipStream_t st) {
+  if (L.prec != 32) return;
   if (!L.A_val32) L.A_val32 = h->pool.get<float>(L.nnz);
   cast<double, float>(L.nnz, L.A_val, L.A_val32, st);
   if (L.coarsest) return;
@@ -1001,7 +1104,7 @@ void numeric_all(amg_hier* h, hipStream_t st, PhaseClock* clk = nullptr) {
     auto t0 = std::chrono::steady_clock::now();
     const bool use_mlp = l == 0 && h->learned;
     if (use_mlp) learned_predict(h, st);
-    compute_interp(h, L, (int)l, st, use_mlp);
+    if (!L.user_p) compute_interp(h, L, (int)l, st, use_mlp);
     if (l == 0) {
       HIPC(hipStreamSynchronize(st));
       double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1057,44 +1160,96 @@ struct Vec {
   static T* dinv(Level& L) { if constexpr (std::is_same<T, double>::value) return L.dinv; else return L.dinv32; }
 };
 
+// One level of the descent: pre-smoothing of A_l x = b from x = 0, the
+// residual, and its restriction into the next level's right-hand side (in
+// the next level's value type).
 template <class T>
-void vcycle_T(amg_hier* h, const T* b0, T* x0, hipStream_t st) {
-  size_t nl = h->lv.size();
-  auto B = [&](size_t l) -> const T* { return l == 0 ? b0 : Vec<T>::b(h->lv[l]); };
-  auto X = [&](size_t l) -> T* { return l == 0 ? x0 : Vec<T>::x(h->lv[l]); };
-  for (size_t l = 0; l + 1 < nl; ++l) {
+void vc_down(amg_hier* h, size_t l, const T* b, T* x, hipStream_t st) {
+  Level& L = h->lv[l];
+  Level& C = h->lv[l + 1];
+  const int mode = h->opt.schwarz_mode;
+  CsrDev<T> A = L.A_dev<T>();
+  SmootherDev<T> S = L.S_dev<T>(h->d_sweep_err, h->spin_max);
+  fill<T>(L.n, (T)0, x, st);
+  schwarz_sweep<T>(S, A, 0, b, x, st);
+  if (mode != AMG_SCHWARZ_SPLIT) schwarz_sweep<T>(S, A, 1, b, x, st);
+  jacobi<T>(A, x, b, Vec<T>::dinv(L), Vec<T>::t(L), st);
+  residual<T>(A, Vec<T>::t(L), b, Vec<T>::r(L), st);
+  if (C.prec == L.prec) {
+    spmv<T>(L.PT_dev<T>(), Vec<T>::r(L), Vec<T>::b(C), st);
+  } else if (C.prec == 32) {
+    spmv<T>(L.PT_dev<T>(), Vec<T>::r(L), Vec<T>::r(C), st);
+    cast<T, float>(C.n, Vec<T>::r(C), C.b32, st);
+  } else {
+    spmv<T>(L.PT_dev<T>(), Vec<T>::r(L), Vec<T>::r(C), st);
+    cast<T, double>(C.n, Vec<T>::r(C), C.b, st);
+  }
+}
+
+// One level of the ascent: prolongation of the next level's correction (in
+// this level's value type), then post-smoothing; x receives the result.
+template <class T>
+void vc_up(amg_hier* h, size_t l, const T* b, T* x, hipStream_t st) {
+  Level& L = h->lv[l];
+  Level& C = h->lv[l + 1];
+  const int mode = h->opt.schwarz_mode;
+  CsrDev<T> A = L.A_dev<T>();
+  SmootherDev<T> S = L.S_dev<T>(h->d_sweep_err, h->spin_max);
+  const T* xc = Vec<T>::x(C);
+  if (C.prec != L.prec) {
+    if (C.prec == 32) cast<float, T>(C.n, C.x32, Vec<T>::t(C), st);
+    else cast<double, T>(C.n, C.x, Vec<T>::t(C), st);
+    xc = Vec<T>::t(C);
+  }
+  spmv_add<T>(L.P_dev<T>(), xc, Vec<T>::t(L), st);
+  if (mode == AMG_SCHWARZ_REPEAT) {
+    // post = pre: forward, backward, then l1-Jacobi (t -> x)
+    schwarz_sweep<T>(S, A, 0, b, Vec<T>::t(L), st);
+    schwarz_sweep<T>(S, A, 1, b, Vec<T>::t(L), st);
+    jacobi<T>(A, Vec<T>::t(L), b, Vec<T>::dinv(L), x, st);
+    return;
+  }
+  jacobi<T>(A, Vec<T>::t(L), b, Vec<T>::dinv(L), x, st);
+  if (mode != AMG_SCHWARZ_SPLIT) schwarz_sweep<T>(S, A, 0, b, x, st);
+  schwarz_sweep<T>(S, A, 1, b, x, st);
+}
+
+// The V(1,1) cycle x0 = B b0 on level 0's vectors (of level 0's value
+// type); every level works in its own type (all FP64 in the FP64 form).
+void vcycle_levels(amg_hier* h, const void* b0, void* x0, hipStream_t st) {
+  const size_t nl = h->lv.size();
+  auto bptr = [&](size_t l) -> const void* {
+    if (l == 0) return b0;
     Level& L = h->lv[l];
-    CsrDev<T> A = L.A_dev<T>();
-    SmootherDev<T> S = L.S_dev<T>(h->d_sweep_err, h->spin_max);
-    T* x = X(l);
-    fill<T>(L.n, (T)0, x, st);
-    schwarz_sweep<T>(S, A, 0, B(l), x, st);
-    schwarz_sweep<T>(S, A, 1, B(l), x, st);
-    jacobi<T>(A, x, B(l), Vec<T>::dinv(L), Vec<T>::t(L), st);
-    residual<T>(A, Vec<T>::t(L), B(l), Vec<T>::r(L), st);
-    spmv<T>(L.PT_dev<T>(), Vec<T>::r(L), Vec<T>::b(h->lv[l + 1]), st);
+    return L.prec == 32 ? (const void*)L.b32 : (const void*)L.b;
+  };
+  auto xptr = [&](size_t l) -> void* {
+    if (l == 0) return x0;
+    Level& L = h->lv[l];
+    return L.prec == 32 ? (void*)L.x32 : (void*)L.x;
+  };
+  for (size_t l = 0; l + 1 < nl; ++l) {
+    if (h->lv[l].prec == 32) vc_down<float>(h, l, (const float*)bptr(l), (float*)xptr(l), st);
+    else vc_down<double>(h, l, (const double*)bptr(l), (double*)xptr(l), st);
   }
   Level& C = h->lv[nl - 1];
-  dense_solve<T>((int)C.n, C.Lc, B(nl - 1), X(nl - 1), h->dense_work, st);
+  if (C.prec == 32)
+    dense_solve<float>((int)C.n, C.Lc, (const float*)bptr(nl - 1), (float*)xptr(nl - 1), h->dense_work, st);
+  else
+    dense_solve<double>((int)C.n, C.Lc, (const double*)bptr(nl - 1), (double*)xptr(nl - 1), h->dense_work, st);
   for (size_t l = nl - 1; l-- > 0;) {
-    Level& L = h->lv[l];
-    CsrDev<T> A = L.A_dev<T>();
-    SmootherDev<T> S = L.S_dev<T>(h->d_sweep_err, h->spin_max);
-    spmv_add<T>(L.P_dev<T>(), X(l + 1), Vec<T>::t(L), st);
-    T* x = X(l);
-    jacobi<T>(A, Vec<T>::t(L), B(l), Vec<T>::dinv(L), x, st);
-    schwarz_sweep<T>(S, A, 0, B(l), x, st);
-    schwarz_sweep<T>(S, A, 1, B(l), x, st);
+    if (h->lv[l].prec == 32) vc_up<float>(h, l, (const float*)bptr(l), (float*)xptr(l), st);
+    else vc_up<double>(h, l, (const double*)bptr(l), (double*)xptr(l), st);
   }
 }
 
 void vcycle_any(amg_hier* h, const double* r, double* z, hipStream_t st) {
-  if (h->prec == 64) {
-    vcycle_T<double>(h, r, z, st);
+  Level& L0 = h->lv[0];
+  if (L0.prec == 64) {
+    vcycle_levels(h, r, z, st);
   } else {
-    Level& L0 = h->lv[0];
     cast<double, float>(L0.n, r, L0.b32, st);
-    vcycle_T<float>(h, L0.b32, L0.x32, st);
+    vcycle_levels(h, L0.b32, L0.x32, st);
     cast<float, double>(L0.n, L0.x32, z, st);
   }
 }
@@ -1147,7 +1302,7 @@ double convergence_factor(amg_hier* h, int iters, hipStream_t st) {
   double* e = h->prold;
   double* t = h->pq;
   double* z = h->pz;
-  hash_fill(n, 0x5eed1234ull, e, st);
+  hash_fill(n, h->opt.seed, e, st);
   double prev = 0.0, cur = 0.0;
   for (int k = 0; k <= iters; ++k) {
     spmv<double>(A, e, t, st);
@@ -1166,6 +1321,25 @@ double read_scalar(amg_hier* h, int slot, hipStream_t st) {
   HIPC(hipMemcpyAsync(h->h_sc + slot, h->d_sc + slot, sizeof(double), hipMemcpyDeviceToHost, st));
   HIPC(hipStreamSynchronize(st));
   return h->h_sc[slot];
+}
+
+// ||f - A u|| (FP64), with f - A u left in r
+double true_residual_norm(amg_hier* h, const double* u, const double* f, double* r, hipStream_t st) {
+  Level& L0 = h->lv[0];
+  residual<double>(L0.A_dev<double>(), u, f, r, st);
+  dot2(L0.n, r, r, nullptr, h->d_partial, st);
+  reduce(red_grid(), h->d_partial, h->d_sc, SC_RR, -1, st);
+  return std::sqrt(std::max(read_scalar(h, SC_RR, st), 0.0));
+}
+
+// 64 eps || |A| |u| ||: the size of the rounding error of f - A u formed in
+// FP64, below which no solver can certify a residual (work holds |A||u|)
+double fp64_floor_norm(amg_hier* h, const double* u, double* work, hipStream_t st) {
+  Level& L0 = h->lv[0];
+  spmv_abs(L0.A_dev<double>(), u, work, st);
+  dot2(L0.n, work, work, nullptr, h->d_partial, st);
+  reduce(red_grid(), h->d_partial, h->d_sc, SC_RR, -1, st);
+  return 64.0 * 2.220446049250313e-16 * std::sqrt(std::max(read_scalar(h, SC_RR, st), 0.0));
 }
 
 template <class F>
@@ -1271,6 +1445,9 @@ void amg_default_options(amg_options* opt) {
   opt->ext_block_max = 64;
   opt->stall_ratio = 0.9;
   opt->p_trunc = 0.0;
+  opt->schwarz_mode = AMG_SCHWARZ_ADJOINT;
+  opt->seed = 0x5eed1234ull;
+  opt->fp32_rho_tol = 1e-3;
 }
 
 const char* amg_last_error(void) { return g_err.c_str(); }
@@ -1287,6 +1464,14 @@ amg_status amg_setup(const amg_csr* A, const amg_csr* G, const amg_options* opt,
     if (o.interp == AMG_INTERP_REF && o.ref_nlevels > 0 &&
         (!o.ref_coarse_nodes || !o.ref_ncoarse || !o.ref_coarse_bnd || !o.ref_nbnd))
       fail(AMG_ERR_ARG, "refinement mode without coarse node lists");
+    if (o.interp != AMG_INTERP_ALG && o.interp != AMG_INTERP_REF && o.interp != AMG_INTERP_USER)
+      fail(AMG_ERR_ARG, "unknown interp mode");
+    if (o.interp == AMG_INTERP_USER && (o.user_nlevels < 1 || !o.user_P || !o.user_G))
+      fail(AMG_ERR_ARG, "user interpolation mode without P and G lists");
+    if (o.interp == AMG_INTERP_USER && o.p_trunc > 0.0)
+      fail(AMG_ERR_ARG, "p_trunc applies to the paper's interpolation only");
+    if (o.schwarz_mode < AMG_SCHWARZ_ADJOINT || o.schwarz_mode > AMG_SCHWARZ_SPLIT)
+      fail(AMG_ERR_ARG, "unknown schwarz_mode");
     hipStream_t st = (hipStream_t)stream;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(AMG_ERR_HIP, "no HIP device");
@@ -1331,10 +1516,14 @@ amg_status amg_setup(const amg_csr* A, const amg_csr* G, const amg_options* opt,
       }
       L.lpr_A = lpr_for(L.n, L.nnz);
     }
+    const bool user = o.interp == AMG_INTERP_USER;
     for (int l = 0;; ++l) {
       Level& L = h->lv[l];
-      bool stop = (l + 1 >= o.max_levels) || (L.n <= o.min_coarse);
-      if (!stop) {
+      bool stop = user ? (l >= o.user_nlevels || l + 1 >= o.max_levels)
+                       : ((l + 1 >= o.max_levels) || (L.n <= o.min_coarse));
+      if (!stop && user) {
+        load_user_interp(h.get(), L, o.user_P[l], l, st);
+      } else if (!stop) {
         bool use_ref = o.interp == AMG_INTERP_REF && l < o.ref_nlevels;
         std::vector<int32_t> rc, rb;
         if (use_ref) {
@@ -1358,9 +1547,11 @@ amg_status amg_setup(const amg_csr* A, const amg_csr* G, const amg_options* opt,
       clk.mark(st, "smoother stars + colours", l);
       factor_smoother(h.get(), L, l, st);
       clk.mark(st, "smoother factors + l1 (GPU)", l);
-      build_interp_structs(h.get(), L, st);
-      compute_interp(h.get(), L, l, st);
-      if (o.p_trunc > 0.0) truncate_interp(h.get(), L, o.p_trunc, st);
+      if (!user) {
+        build_interp_structs(h.get(), L, st);
+        compute_interp(h.get(), L, l, st);
+        if (o.p_trunc > 0.0) truncate_interp(h.get(), L, o.p_trunc, st);
+      }
       build_transpose(h.get(), L, st);
       permute(L.p_nnz, L.PT_perm, L.P_val, L.PT_val, st);
       clk.mark(st, "local extension P (GPU)", l);
@@ -1370,14 +1561,19 @@ amg_status amg_setup(const amg_csr* A, const amg_csr* G, const amg_options* opt,
       galerkin_symbolic(h.get(), L1, L2, l, st);
       galerkin_numeric(h.get(), L1, L2, st);
       clk.mark(st, "Galerkin A P, P^T (A P) (GPU)", l);
-      L2.G = L1.ints.gc;
-      L2.S = nodal_graph_coarse(L1.S, L1.ints.fine_of_next);
+      if (user) {
+        L2.G = user_gradient(o.user_G[l + 1], L2.n, l + 1);
+      } else {
+        L2.G = L1.ints.gc;
+        L2.S = nodal_graph_coarse(L1.S, L1.ints.fine_of_next);
+      }
       clk.mark(st, "coarse nodal graph", l);
     }
     {
       Level& C = h->lv.back();
       coarsest_factor(h.get(), C, st);
       clk.mark(st, "coarsest dense Cholesky (GPU)", (int)h->lv.size() - 1);
+      choose_precisions(h.get(), st);
       if (h->prec == 32)
         for (auto& L : h->lv) cast_level(h.get(), L, st);
     }
@@ -1399,14 +1595,15 @@ amg_status amg_resetup_numeric(amg_hier* h, const amg_csr* A, void* stream) {
     hipStream_t st = (hipStream_t)stream;
     std::vector<int64_t> ptr;
     std::vector<int32_t> col;
+    // the pattern must be the one given to amg_setup; it is checked before
+    // any value is copied, so a rejected call leaves the hierarchy as it was
+    host_csr(A, ptr, col, nullptr);
+    if (ptr != L0.Apat.ptr || col != L0.Apat.idx) fail(AMG_ERR_CSR, "A's pattern differs from the setup's");
     if (A->on_device) {
       HIPC(hipMemcpyAsync(L0.A_val, A->val, L0.nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
     } else {
       HIPC(hipMemcpyAsync(L0.A_val, A->val, L0.nnz * sizeof(double), hipMemcpyHostToDevice, st));
     }
-    // the pattern must be the one given to amg_setup
-    host_csr(A, ptr, col, nullptr);
-    if (ptr != L0.Apat.ptr || col != L0.Apat.idx) fail(AMG_ERR_CSR, "A's pattern differs from the setup's");
     numeric_all(h, st);
     h->mstats.global_fallback = 0;
     if (h->learned && h->use_cfg.global_iters > 0) {
@@ -1444,6 +1641,7 @@ amg_status amg_pcg_solve(amg_hier* h, const double* f, double* u, double rtol, i
                          amg_solve_stats* stats, void* stream) {
   return guarded([&]() -> amg_status {
     if (!h || !f || !u) fail(AMG_ERR_ARG, "NULL argument");
+    if (!(rtol >= 0.0) || maxit < 0) fail(AMG_ERR_ARG, "rtol < 0 or maxit < 0");
     hipStream_t st = (hipStream_t)stream;
     auto t0 = std::chrono::steady_clock::now();
     Level& L0 = h->lv[0];
@@ -1455,14 +1653,12 @@ amg_status amg_pcg_solve(amg_hier* h, const double* f, double* u, double rtol, i
     double* p = h->pp;
     double* q = h->pq;
     double* rold = flexible ? h->prold : nullptr;
-    residual<double>(A, u, f, r, st);
-    dot2(n, r, r, nullptr, h->d_partial, st);
-    reduce(red_grid(), h->d_partial, h->d_sc, SC_RR, -1, st);
-    double r0 = std::sqrt(read_scalar(h, SC_RR, st));
+    const double r0 = true_residual_norm(h, u, f, r, st);
     if (!std::isfinite(r0)) fail(AMG_ERR_NOT_FINITE, "initial residual is not finite");
     int it = 0, replacements = 0;
-    bool converged = r0 == 0.0;
     double nr = r0, tr_last = 0.0;
+    double tr = r0;   // the last true residual norm computed (r0 until CG forms another)
+    bool tr_current = true;
     if (stats && stats->history) stats->history[0] = r0;
     if (r0 > 0.0) {
       vcycle_graph(h, r, z, st);
@@ -1478,6 +1674,7 @@ amg_status amg_pcg_solve(amg_hier* h, const double* f, double* u, double rtol, i
         cg_update(n, h->d_sc, p, q, u, r, rold, h->d_partial, st);
         reduce(red_grid(), h->d_partial, h->d_sc, SC_RR, -1, st);
         ++it;
+        tr_current = false;
         nr = std::sqrt(read_scalar(h, SC_RR, st));
         if (stats && stats->history) stats->history[it] = nr;
         if (!std::isfinite(nr)) fail(AMG_ERR_NOT_FINITE, "residual became non-finite");
@@ -1488,17 +1685,13 @@ amg_status amg_pcg_solve(amg_hier* h, const double* f, double* u, double rtol, i
         if (nr <= rtol * r0) {
           // the recursive residual has drifted from f - A u by rounding:
           // stop once the true residual meets the tolerance, or once a
-          // restart no longer halves it (it sits at the attainable accuracy
-          // of FP64 on this system); else continue from it with a fresh
-          // direction
-          converged = true;
-          residual<double>(A, u, f, r, st);
-          dot2(n, r, r, nullptr, h->d_partial, st);
-          reduce(red_grid(), h->d_partial, h->d_sc, SC_RR, -1, st);
-          const double tr = std::sqrt(read_scalar(h, SC_RR, st));
+          // restart no longer halves it (it then sits at the attainable
+          // accuracy of FP64 on this system, and the solve reports
+          // AMG_NOT_CONVERGED); else continue from it with a fresh direction
+          tr = true_residual_norm(h, u, f, r, st);
+          tr_current = true;
           if (!std::isfinite(tr)) fail(AMG_ERR_NOT_FINITE, "residual became non-finite");
           if (tr <= rtol * r0 || it >= maxit || (replacements > 0 && tr > 0.5 * tr_last)) break;
-          converged = false;
           tr_last = tr;
           nr = tr;
           ++replacements;
@@ -1518,19 +1711,75 @@ amg_status amg_pcg_solve(amg_hier* h, const double* f, double* u, double rtol, i
     HIPC(hipStreamSynchronize(st));
     auto t1 = std::chrono::steady_clock::now();
     check_sweep_err(h, st);
+    if (!tr_current) tr = true_residual_norm(h, u, f, q, st);
+    // success means the true residual f - A u meets the tolerance
+    const bool converged = tr <= rtol * r0;
     if (stats) {
       stats->iterations = it;
       stats->relres = r0 > 0 ? nr / r0 : 0.0;
       stats->seconds = std::chrono::duration<double>(t1 - t0).count();
-      residual<double>(A, u, f, q, st);
-      dot2(n, q, q, nullptr, h->d_partial, st);
-      reduce(red_grid(), h->d_partial, h->d_sc, SC_RR, -1, st);
-      double tr = std::sqrt(read_scalar(h, SC_RR, st));
       stats->true_relres = r0 > 0 ? tr / r0 : 0.0;
       stats->replacements = replacements;
+      stats->floor_relres = r0 > 0 ? fp64_floor_norm(h, u, q, st) / r0 : 0.0;
+      stats->conv_factor = (r0 > 0 && it > 0) ? std::pow(nr / r0, 1.0 / it) : 0.0;
     }
     HIPC(hipGetLastError());
     return converged ? AMG_OK : AMG_NOT_CONVERGED;
+  });
+}
+
+amg_status amg_cycle_solve(amg_hier* h, const double* f, double* u, double rtol, int maxit,
+                           amg_solve_stats* stats, void* stream) {
+  return guarded([&]() -> amg_status {
+    if (!h || !f || !u) fail(AMG_ERR_ARG, "NULL argument");
+    if (!(rtol >= 0.0) || maxit < 0) fail(AMG_ERR_ARG, "rtol < 0 or maxit < 0");
+    hipStream_t st = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = h->lv[0].n;
+    double* r = h->pr;
+    double* z = h->pz;
+    const double r0 = true_residual_norm(h, u, f, r, st);
+    if (!std::isfinite(r0)) fail(AMG_ERR_NOT_FINITE, "initial residual is not finite");
+    if (stats && stats->history) stats->history[0] = r0;
+    int it = 0;
+    double nr = r0, prev = r0;
+    while (it < maxit && nr > rtol * r0) {
+      vcycle_graph(h, r, z, st);
+      axpy(n, 1.0, z, u, st);
+      prev = nr;
+      nr = true_residual_norm(h, u, f, r, st);
+      ++it;
+      if (stats && stats->history) stats->history[it] = nr;
+      if (!std::isfinite(nr)) fail(AMG_ERR_NOT_FINITE, "residual became non-finite");
+    }
+    HIPC(hipStreamSynchronize(st));
+    auto t1 = std::chrono::steady_clock::now();
+    check_sweep_err(h, st);
+    if (stats) {
+      stats->iterations = it;
+      stats->relres = r0 > 0 ? nr / r0 : 0.0;
+      stats->true_relres = stats->relres;
+      stats->seconds = std::chrono::duration<double>(t1 - t0).count();
+      stats->replacements = 0;
+      stats->floor_relres = r0 > 0 ? fp64_floor_norm(h, u, z, st) / r0 : 0.0;
+      stats->conv_factor = (it > 0 && prev > 0) ? nr / prev : 0.0;
+    }
+    HIPC(hipGetLastError());
+    return nr <= rtol * r0 ? AMG_OK : AMG_NOT_CONVERGED;
+  });
+}
+
+amg_status amg_complexity(const amg_hier* h, double* oc, double* gc) {
+  return guarded([&]() -> amg_status {
+    if (!h) fail(AMG_ERR_ARG, "NULL handle");
+    double sn = 0, snnz = 0;
+    for (const Level& L : h->lv) {
+      sn += (double)L.n;
+      snnz += (double)L.nnz;
+    }
+    if (oc) *oc = snnz / (double)h->lv[0].nnz;
+    if (gc) *gc = sn / (double)h->lv[0].n;
+    return AMG_OK;
   });
 }
 
@@ -1540,8 +1789,8 @@ amg_status amg_smoother_sweep(amg_hier* h, int level, int prec, const void* b, v
     if (!h || !b || !x) fail(AMG_ERR_ARG, "NULL argument");
     if (level < 0 || level + 1 >= (int)h->lv.size()) fail(AMG_ERR_ARG, "level has no smoother");
     if (prec != 64 && prec != 32) fail(AMG_ERR_ARG, "prec must be 64 or 32");
-    if (prec == 32 && h->prec != 32) fail(AMG_ERR_ARG, "FP32 sweep needs an FP32 hierarchy");
     Level& L = h->lv[level];
+    if (prec != L.prec) fail(AMG_ERR_ARG, "the level's smoother runs in FP" + std::to_string(L.prec));
     hipStream_t st = (hipStream_t)stream;
     auto run = [&](auto tag) {
       using T = decltype(tag);
@@ -1605,6 +1854,8 @@ amg_status amg_hier_info(const amg_hier* h, amg_level_info* lv, int cap, int* nl
       lv[l].fac_entries = L.coarsest ? 0 : L.fac_total;
       lv[l].sweep_form = L.coarsest ? 0 : L.sweep_mode;
       lv[l].sweep_lanes = (L.coarsest || L.sweep_mode == SWEEP_DENSE || L.sweep_mode == SWEEP_PANEL) ? 0 : L.lpr_S;
+      lv[l].prec = L.prec;
+      lv[l].grad_ratio = L.grad_ratio;
     }
     return AMG_OK;
   });
@@ -1733,6 +1984,7 @@ amg_status amg_mlp_train(amg_hier* h, const amg_mlp_train_cfg* cfg, amg_mlp_stat
                          void* stream) {
   return guarded([&]() -> amg_status {
     if (!h || !cfg) fail(AMG_ERR_ARG, "NULL argument");
+    if (h->lv[0].user_p) fail(AMG_ERR_ARG, "the learned setup needs the paper's interpolation (no user P)");
     if (cfg->batch <= 0 || cfg->batch % 16) fail(AMG_ERR_ARG, "batch must be a positive multiple of 16");
     if (cfg->epochs < 0) fail(AMG_ERR_ARG, "epochs < 0");
     hipStream_t st = (hipStream_t)stream;

@@ -1143,6 +1143,33 @@ bool panel_sweep_ok(int n, int max_block) {
 
 int panel_tiles(int n) { return (n + PANEL_TROWS - 1) / PANEL_TROWS; }
 
+// Dynamic LDS the panel launch adds so that its workgroups hold more than
+// half a CU's 160 KB each (one workgroup per CU).
+template <class T>
+static size_t panel_pad() {
+  static const size_t pad = [] {
+    hipFuncAttributes fa{};
+    const size_t want = 80 * 1024 + 1024;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_schwarz_panel<T>)) != hipSuccess) return size_t(0);
+    return fa.sharedSizeBytes >= want ? size_t(0) : want - fa.sharedSizeBytes;
+  }();
+  return pad;
+}
+
+// Workgroups of the panel launch that one CU can hold at once (from the
+// occupancy query with the launch's LDS padding), or -1 if the query fails.
+int panel_resident_per_cu(int prec) {
+  int blocks = -1;
+  hipError_t e;
+  if (prec == 32)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(&k_schwarz_panel<float>),
+                                                     256, panel_pad<float>());
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(&k_schwarz_panel<double>),
+                                                     256, panel_pad<double>());
+  return e == hipSuccess ? blocks : -1;
+}
+
 template <class T>
 void panel_sweep(const PanelDev<T>& D, int backward, T* r, T* x, int* err, int spin_max, hipStream_t st) {
   if (D.ngroups <= 0) return;
@@ -1151,12 +1178,7 @@ void panel_sweep(const PanelDev<T>& D, int backward, T* r, T* x, int* err, int s
   const int ntiles = panel_tiles(D.n);
   // Unused dynamic LDS up to more than half a CU's 160 KB, so that no two
   // workgroups share a CU: tiles on the chain's CU slow the chain.
-  static const size_t pad = [] {
-    hipFuncAttributes fa{};
-    const size_t want = 80 * 1024 + 1024;
-    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_schwarz_panel<T>)) != hipSuccess) return size_t(0);
-    return fa.sharedSizeBytes >= want ? size_t(0) : want - fa.sharedSizeBytes;
-  }();
+  const size_t pad = panel_pad<T>();
   hipLaunchKernelGGL((k_schwarz_panel<T>), dim3(1 + ntiles), dim3(256), pad, st, D, backward, r, x, err,
                      spin_max, ntiles);
 }
@@ -2098,6 +2120,58 @@ void l1inv(const CsrDev<double>& A, double* dinv, hipStream_t st) {
     hipLaunchKernelGGL(k_l1inv, dim3(grid_for(A.n)), dim3(256), 0, st, A.n, A.ptr, A.val, dinv);
 }
 
+// y = |A| |x| (entrywise absolute values), one thread per row: the scale of
+// the rounding error of a residual f - A x computed in FP64
+__global__ void k_spmv_abs(int64_t n, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                           const double* __restrict__ val, const double* __restrict__ x,
+                           double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q) s += fabs(val[q]) * fabs(x[col[q]]);
+    y[i] = s;
+  }
+}
+void spmv_abs(const CsrDev<double>& A, const double* x, double* y, hipStream_t st) {
+  if (A.n > 0)
+    hipLaunchKernelGGL(k_spmv_abs, dim3(grid_for(A.n)), dim3(256), 0, st, A.n, A.ptr, A.col, A.val, x, y);
+}
+
+// Gradient conditioning of every node-star block B (the DoFs of one column v
+// of G, with signs s = G[B, v]): num = sum_{i,j in B} |a_ij| and
+// den = s^T A_BB s, the energy of the gradient of v's hat function.  One
+// thread per block, from the smoother's star-ordered copy of A's rows.
+__global__ void k_star_rho(int64_t nb, const int64_t* __restrict__ sb_ptr, const int32_t* __restrict__ sb_dofs,
+                           const int8_t* __restrict__ ssign, const int64_t* __restrict__ srow_ptr,
+                           const int32_t* __restrict__ scol, const double* __restrict__ sval,
+                           double* __restrict__ rho) {
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r0 = sb_ptr[b], r1 = sb_ptr[b + 1];
+    double num = 0.0, den = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+      const double sr = (double)ssign[r];
+      for (int64_t q = srow_ptr[r]; q < srow_ptr[r + 1]; ++q) {
+        const int32_t c = scol[q];
+        for (int64_t j = r0; j < r1; ++j)
+          if (sb_dofs[j] == c) {
+            num += fabs(sval[q]);
+            den += sr * (double)ssign[j] * sval[q];
+            break;
+          }
+      }
+    }
+    rho[b] = den > 0.0 ? num / den : 0.0;
+  }
+}
+void star_rho(int64_t nb, const int64_t* sb_ptr, const int32_t* sb_dofs, const int8_t* ssign,
+              const int64_t* srow_ptr, const int32_t* scol, const double* sval, double* rho,
+              hipStream_t st) {
+  if (nb > 0)
+    hipLaunchKernelGGL(k_star_rho, dim3(grid_for(nb)), dim3(256), 0, st, nb, sb_ptr, sb_dofs, ssign,
+                       srow_ptr, scol, sval, rho);
+}
+
 // ---------------------------------------------------------------------------
 // explicit instantiations
 // ---------------------------------------------------------------------------
@@ -2129,5 +2203,7 @@ template void fill<double>(int64_t, double, double*, hipStream_t);
 template void fill<float>(int64_t, float, float*, hipStream_t);
 template void cast<double, float>(int64_t, const double*, float*, hipStream_t);
 template void cast<float, double>(int64_t, const float*, double*, hipStream_t);
+template void cast<double, double>(int64_t, const double*, double*, hipStream_t);
+template void cast<float, float>(int64_t, const float*, float*, hipStream_t);
 
 }  // namespace hamg

@@ -120,6 +120,7 @@ void star_rows(int64_t nrows, const int32_t* sb_dofs, const int64_t* Aptr, const
                const int64_t* srow_ptr, double* sval, hipStream_t st);
 bool panel_sweep_ok(int n, int max_block);
 int panel_tiles(int n);
+int panel_resident_per_cu(int prec);
 template <class T>
 void panel_sweep(const PanelDev<T>& D, int backward, T* r, T* x, int* err, int spin_max, hipStream_t st);
 void panel_slices(int ngroups, int64_t n, const int32_t* gdof, const double* Acm, double* gslc,
@@ -212,5 +213,9 @@ void star_inv(int64_t nrows, const int32_t* row_blk, const int64_t* sb_ptr, cons
 void star_chol(int64_t nb, const int64_t* sb_ptr, const int32_t* sb_dofs, const int64_t* fac_off,
                const CsrDev<double>& A, double* fac, int* flag, hipStream_t st);
 void l1inv(const CsrDev<double>& A, double* dinv, hipStream_t st);
+void spmv_abs(const CsrDev<double>& A, const double* x, double* y, hipStream_t st);
+void star_rho(int64_t nb, const int64_t* sb_ptr, const int32_t* sb_dofs, const int8_t* ssign,
+              const int64_t* srow_ptr, const int32_t* scol, const double* sval, double* rho,
+              hipStream_t st);
 
 }  // namespace hamg

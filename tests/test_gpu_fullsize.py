@@ -1,5 +1,4 @@
-"""Parity at the full sizes of the hex workloads (64^3; 128^3 with
-HCURL_AMG_FULLSIZE=1), on outputs the oracle's definitions give one by one and
+"""Parity at the full sizes of the hex workloads (64^3 and 128^3), on outputs the oracle's definitions give one by one and
 on properties that hold at any size, in the launch configuration bench.py
 times (device-resident A and G, FP64 hierarchy).
 
@@ -155,7 +154,5 @@ def test_full_size_64():
     _fullsize(64)
 
 
-@pytest.mark.skipif(os.environ.get("HCURL_AMG_FULLSIZE") != "1",
-                    reason="128^3 takes minutes; set HCURL_AMG_FULLSIZE=1")
 def test_full_size_128():
     _fullsize(128)

@@ -242,24 +242,79 @@ def test_table1_refinement_complexities_exact(L):
     assert abs(H.gc() - row["gc_ref"]) < 1e-12
 
 
-@pytest.mark.parametrize("L", [4, 5])
-def test_table1_iteration_counts_isotropic(L):
-    """Isotropic Table 1 counts (random x0, b = (1..n)): PCG within 1, stand-alone AMG within 3."""
-    row = _golden()["table1_uniform_isotropic"][str(L)]
-    p = gen.make_problem("tri", L, beta=0.01)
+def _table_hier(p, L, interp, schwarz):
+    if interp == "ref":
+        return oracle.setup(p.A, p.G, interp="ref", ref_select=RefSelector(p), max_levels=L,
+                            min_coarse=0, schwarz=schwarz)
+    if interp == "geo":
+        return oracle.setup(p.A, p.G, user=gen.geo_hierarchy("tri", L, L), schwarz=schwarz)
+    return oracle.setup(p.A, p.G, schwarz=schwarz)
+
+
+def _table_run(L, alpha, interp, schwarz):
+    """Section 5's protocol: random x0 (seed 0), b = (1..n), tolerance 1e-8."""
+    p = gen.make_problem("tri", L, beta=0.01, alpha=alpha)
     n = p.A.shape[0]
     b = np.arange(1, n + 1, dtype=float)
     x0 = np.random.default_rng(0).random(n)
-    H = oracle.setup(p.A, p.G)
+    H = _table_hier(p, L, interp, schwarz)
     _, it, _ = oracle.pcg(H, p.A, b, x0=x0)
-    _, ita, _ = oracle.amg_solve(H, p.A, b, x0=x0)
-    assert abs(it - row["pcg_alg"]) <= 1
-    assert abs(ita - row["amg_alg"]) <= 3
-    Hr = oracle.setup(p.A, p.G, interp="ref", ref_select=RefSelector(p), max_levels=L, min_coarse=0)
-    _, it, _ = oracle.pcg(Hr, p.A, b, x0=x0)
-    _, ita, _ = oracle.amg_solve(Hr, p.A, b, x0=x0)
-    assert abs(it - row["pcg_ref"]) <= 1
-    assert abs(ita - row["amg_ref"]) <= 6
+    _, ita, h = oracle.amg_solve(H, p.A, b, x0=x0)
+    return H, it, ita, h[-1] / h[-2]
+
+
+@pytest.mark.parametrize("L", [4, 5, 6])
+def test_table1_iteration_counts_all_three_interpolations(L):
+    """Table 1 (isotropic), Geo / Ref / Alg:
+    * OC to every printed digit (Geo's from the Galerkin products of the
+      geometric interpolation, which pins that P's pattern and levels);
+    * PCG counts within one, with the symmetric (adjoint) cycle;
+    * stand-alone AMG ("AMG conv": ratio of the last two residuals) within
+      0.02 of the printed factor, with the literal cycle (post step = pre
+      step); AMG counts within one for Geo and Ref, within three for Alg."""
+    row = _golden()["table1_uniform_isotropic"][str(L)]
+    conv = _golden()["table1_amg_conv"][str(L)]
+    for interp in ("geo", "ref", "alg"):
+        key = "ref" if interp == "geo" else interp      # Table 1 prints Geo = Ref
+        H, it, _, _ = _table_run(L, 1.0, interp, "adjoint")
+        assert abs(H.oc() - row["oc_" + key]) < 1e-12, interp
+        assert abs(it - row["pcg_" + key]) <= 1, (interp, it)
+        _, _, ita, rho = _table_run(L, 1.0, interp, "repeat")
+        assert abs(rho - conv[key]) <= 0.02, (interp, rho)
+        assert abs(ita - row["amg_" + key]) <= (3 if interp == "alg" else 1), (interp, ita)
+
+
+@pytest.mark.parametrize("L", [4, 5])
+def test_table2_algebraic_counts(L):
+    """Table 2 (stripes), Alg: OC to every digit, the AMG convergence factor
+    within 0.01 of the printed one (literal cycle), PCG within two."""
+    row = _golden()["table2_uniform_stripes"][str(L)]
+    conv = _golden()["table2_amg_conv"][str(L)]
+    stripes = lambda m: fields.stripes_2d(m)
+    H, it, _, _ = _table_run(L, stripes, "alg", "adjoint")
+    assert abs(H.oc() - row["oc_alg"]) < 1e-12
+    assert abs(it - row["pcg_alg"]) <= 2
+    _, _, ita, rho = _table_run(L, stripes, "alg", "repeat")
+    assert abs(rho - conv["alg"]) <= 0.01, rho
+
+
+@pytest.mark.parametrize("L", [4, 5])
+def test_table2_ref_and_geo_are_not_reproduced(L):
+    """Table 2 Ref (AMG 8-13, PCG 5) and Geo (AMG 80-320) are NOT reproduced
+    by the node-star smoother reading: the oracle converges at ~0.55-0.62 on
+    Ref (printed 0.17-0.32) and ~0.95 on Geo (printed 0.84-0.96).  No other
+    reading tried reproduces them either (element-patch blocks, blocks from
+    the matching, other stripe layouts); with the same geometric P, printed
+    Table 1 and the Table 2 Alg column are reproduced.  This test records the
+    oracle's values so that a change of reading shows up here."""
+    rec = _golden()["oracle_table2_record"][str(L)]
+    stripes = lambda m: fields.stripes_2d(m)
+    for interp in ("ref", "geo"):
+        H, it, _, _ = _table_run(L, stripes, interp, "adjoint")
+        _, _, ita, rho = _table_run(L, stripes, interp, "repeat")
+        assert abs(H.oc() - _golden()["table2_uniform_stripes"][str(L)]["oc_ref"]) < 1e-12
+        assert it == rec[interp]["pcg"] and ita == rec[interp]["amg"], (interp, it, ita)
+        assert abs(rho - rec[interp]["amg_conv"]) < 1e-3
 
 
 # ----------------------------------------------------------------------------
@@ -475,3 +530,166 @@ def test_pcg_reaches_tolerance_true_residual():
     x, it, hist = oracle.pcg(H, p.A, f)
     assert np.linalg.norm(f - p.A @ x) <= 1.01e-8 * np.linalg.norm(f)
     assert it < 100
+
+
+# ----------------------------------------------------------------------------
+# geometric interpolation "Geo" (Section 5's comparison method; gen/geo.py)
+# ----------------------------------------------------------------------------
+def _rigid_dofs(mesh, a, b):
+    x0 = mesh.coords[mesh.edges[:, 0]]
+    x1 = mesh.coords[mesh.edges[:, 1]]
+    mid = 0.5 * (x0 + x1)
+    if mesh.dim == 3:
+        u = a[None, :] + np.cross(b[None, :], mid)
+    else:
+        u = a[None, :] + b * np.stack([-mid[:, 1], mid[:, 0]], axis=1)
+    return np.einsum("ed,ed->e", u, x1 - x0)
+
+
+@pytest.mark.parametrize("kind,size", [("tri", 3), ("hex", 4)])
+def test_geo_interpolation_reproduces_nedelec_fields(kind, size):
+    """Nested spaces: a field a + b x X lies in the coarse and the fine
+    Nedelec space, so interpolating its coarse DoFs gives its fine DoFs
+    exactly (all edges kept)."""
+    from gen import geo
+    from gen.mesh import hex_mesh, simplex_mesh_2d
+    fine = simplex_mesh_2d(size) if kind == "tri" else hex_mesh(size)
+    coarse = simplex_mesh_2d(size - 1) if kind == "tri" else hex_mesh(size // 2)
+    P = (geo.geo_interpolation_tri(size, dirichlet=False) if kind == "tri"
+         else geo.geo_interpolation_hex(size, dirichlet=False))
+    rng = np.random.default_rng(7)
+    for _ in range(3):
+        a = rng.standard_normal(fine.dim)
+        b = rng.standard_normal(3) if fine.dim == 3 else rng.standard_normal()
+        uc, uf = _rigid_dofs(coarse, a, b), _rigid_dofs(fine, a, b)
+        assert np.abs(P @ uc - uf).max() <= 1e-13 * np.abs(uf).max()
+
+
+def _nodal_interpolant(kind, fine, coarse, phi_c):
+    """Fine nodal values of the P1 (triangles) / Q1 (hexahedra) interpolant of
+    coarse nodal values: a fine node is a coarse node, or the midpoint of a
+    coarse edge, face or cell, and takes the mean of that entity's vertices."""
+    def key(x):
+        return tuple(np.round(x * 2 ** 12).astype(np.int64))
+    fidx = {key(c): i for i, c in enumerate(fine.coords)}
+    out = np.full(fine.coords.shape[0], np.nan)
+    if kind == "tri":
+        groups = [coarse.edges]
+    else:
+        cells = coarse.elems                                   # 8 corners, bit a of the corner = offset in axis a
+        faces = [cells[:, [c for c in range(8) if ((c >> ax) & 1) == side]]
+                 for ax in range(3) for side in (0, 1)]
+        groups = [coarse.edges, np.concatenate(faces), cells]
+    for g in groups:
+        for verts in g:
+            out[fidx[key(coarse.coords[verts].mean(axis=0))]] = phi_c[verts].mean()
+    for i, c in enumerate(coarse.coords):
+        out[fidx[key(c)]] = phi_c[i]
+    assert not np.isnan(out).any()
+    return out
+
+
+@pytest.mark.parametrize("kind,size", [("tri", 3), ("hex", 4)])
+def test_geo_interpolation_commutes_with_nodal_interpolation(kind, size):
+    """P_geo G_c = G P_n (eq. (commuting)) with P_n the nodal P1/Q1
+    interpolation, on the Dirichlet spaces."""
+    from gen import geo
+    from gen.mesh import hex_mesh, simplex_mesh_2d
+    fine = simplex_mesh_2d(size) if kind == "tri" else hex_mesh(size)
+    coarse = simplex_mesh_2d(size - 1) if kind == "tri" else hex_mesh(size // 2)
+    pf = gen.make_problem(kind, size)
+    pc = gen.make_problem(kind, size - 1 if kind == "tri" else size // 2)
+    P = geo.geo_interpolation_tri(size) if kind == "tri" else geo.geo_interpolation_hex(size)
+    rng = np.random.default_rng(3)
+    phi = np.zeros(coarse.coords.shape[0])
+    phi[pc.keep_nodes] = rng.standard_normal(int(pc.keep_nodes.sum()))
+    psi = _nodal_interpolant(kind, fine, coarse, phi)
+    lhs = P @ (pc.G @ phi[pc.keep_nodes])
+    rhs = pf.G @ psi[pf.keep_nodes]
+    assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
+
+
+# ----------------------------------------------------------------------------
+# FP32 form: the per-level precision rule (parity unpinned by the paper)
+# ----------------------------------------------------------------------------
+def test_gradient_ratio_scales_like_alpha_over_beta():
+    """rho = max_v (|G|^T |A| |G|)_vv / (G^T A G)_vv is scale-free and, as
+    beta -> 0 (A^s G = 0, so only beta A^m sees a gradient), grows like 1/beta;
+    the denominator is the energy of a hat gradient, hence positive."""
+    r = {}
+    for alpha, beta in ((1.0, 1.0), (10.0, 10.0), (1.0, 1e-2), (1.0, 1e-4)):
+        p = gen.make_problem("hex", 4, alpha=alpha, beta=beta)
+        assert np.all((p.G.T @ p.A @ p.G).diagonal() > 0)
+        r[(alpha, beta)] = amg.gradient_ratio(p.A, p.G)
+    assert abs(r[(10.0, 10.0)] / r[(1.0, 1.0)] - 1.0) < 1e-12
+    assert abs(r[(1.0, 1e-4)] / r[(1.0, 1e-2)] - 100.0) < 1.0
+
+
+def test_fp32_form_keeps_fp64_where_the_near_kernel_needs_it():
+    """On the 16^3 jump workload (alpha up to 10^4, h = 1/16) eps_32 * rho is
+    ~4 on the finest level, which therefore keeps FP64; the coarse levels
+    run in FP32, and flexible CG reaches 1e-8 with such a cycle, while a cycle
+    entirely in FP32 stalls (the FP32 residual loses the gradients)."""
+    p = gen.make_problem("hex", 16, beta=1.0, alpha=lambda m: fields.subdomain_log_uniform(m, 8, 2),
+                         f=lambda n: fields.rhs_uniform(n, 102))
+    H = oracle.setup(p.A, p.G)
+    dts = amg.level_dtypes(H, np.float32)
+    assert dts[0] == np.float64 and all(d == np.float32 for d in dts[1:-1])
+    x, it, hist = oracle.pcg(H, p.A, p.f, dtype=np.float32, maxit=400)
+    assert np.linalg.norm(p.f - p.A @ x) <= 1.01e-8 * np.linalg.norm(p.f) and it < 400
+    H.opts["_level_dtypes"] = [np.float32] * H.nlevels
+    x, it, hist = oracle.pcg(H, p.A, p.f, dtype=np.float32, maxit=150)
+    assert np.linalg.norm(p.f - p.A @ x) > 1e-6 * np.linalg.norm(p.f)
+
+
+# ----------------------------------------------------------------------------
+# the 3D extension reading (case 2 of the block construction) against the
+# exact interior harmonic extension: measured, not a pin of the paper
+# ----------------------------------------------------------------------------
+def _two_grid_factor(H, P, A):
+    n = A.shape[0]
+    mats = amg._cast(H, np.float64)
+    M = mats[0]
+    nc = H.levels[0].smoother.ncolors
+    up, down = list(range(nc)), list(range(nc - 1, -1, -1))
+    z = np.zeros(n)
+
+    def pre(e):
+        x = amg._schwarz(M, e.copy(), z, up)
+        x = amg._schwarz(M, x, z, down)
+        return x - (M["A"] @ x) / M["l1"]
+
+    def post(e):
+        x = e - (M["A"] @ e) / M["l1"]
+        x = amg._schwarz(M, x, z, up)
+        return amg._schwarz(M, x, z, down)
+    Ad = A.toarray()
+    Epre = np.stack([pre(c) for c in np.eye(n)], axis=1)
+    Epost = np.stack([post(c) for c in np.eye(n)], axis=1)
+    Pi = P @ np.linalg.solve(P.T @ Ad @ P, P.T @ Ad)
+    return float(max(abs(np.linalg.eigvals(Epost @ (np.eye(n) - Pi) @ Epre))))
+
+
+@pytest.mark.parametrize("alpha", ["iso", "jump"])
+def test_depth_ordered_extension_against_exact_interior_extension(alpha):
+    """Hex 6^3: the two-grid factor with the depth-ordered block extension
+    (the 3D reading) against the exact P_app = R^T - S_I A_II^{-1} S_I^T A R^T
+    (eq. (sparseP) with the global A_II^{-1}).  Exact: ~0.07; depth-ordered:
+    0.20 (isotropic) and 0.25 (jumps), i.e. the 3D localisation, not the
+    smoother, is what limits the method here."""
+    al = 1.0 if alpha == "iso" else (lambda m: fields.subdomain_log_uniform(m, 2, 5))
+    p = gen.make_problem("hex", 6, beta=1.0, alpha=al)
+    H = oracle.setup(p.A, p.G, max_levels=2)
+    lv = H.levels[0]
+    assert not lv.exact_blocks
+    n = p.A.shape[0]
+    Rt = amg.r_transpose(lv.rr, n).toarray()
+    Ad = p.A.toarray()
+    I = lv.interior
+    Pex = Rt.copy()
+    Pex[I] = Rt[I] - np.linalg.solve(Ad[np.ix_(I, I)], Ad[I] @ Rt)
+    r9 = _two_grid_factor(H, lv.P.toarray(), p.A)
+    ex = _two_grid_factor(H, Pex, p.A)
+    print(f"two-grid factor: depth-ordered {r9:.3f}, exact P_app {ex:.3f}")
+    assert ex < 0.1
+    assert 0.15 < r9 < 0.3 and r9 > 2.5 * ex
