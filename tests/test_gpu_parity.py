@@ -77,7 +77,7 @@ EPS = np.finfo(np.float64).eps
 def kappa_level(Ho, l):
     """Largest condition number of the extension and smoother blocks of level l."""
     lv = Ho.levels[l]
-    k = max([np.linalg.cond(lv.A[b][:, b].toarray()) for b in lv.blocks] or [1.0])
+    k = max([np.linalg.cond(lv.A[b][:, b].toarray()) for b in lv.blocks or []] or [1.0])
     ks = max([np.linalg.cond(L @ L.T) for L in lv.smoother.chol] or [1.0])
     return max(k, ks)
 
@@ -89,7 +89,7 @@ def kappas(Ho):
         ext = []
         allk = 1.0
         for lv in Ho.levels[:-1]:
-            k = max([np.linalg.cond(lv.A[b][:, b].toarray()) for b in lv.blocks] or [1.0])
+            k = max([np.linalg.cond(lv.A[b][:, b].toarray()) for b in lv.blocks or []] or [1.0])
             ks = max([np.linalg.cond(L @ L.T) for L in lv.smoother.chol] or [1.0])
             ext.append(k)
             allk = max(allk, k, ks)
@@ -223,8 +223,12 @@ def test_fp32_vcycle_against_oracle_fp32_mode(name):
     dts = amg.level_dtypes(Ho, np.float32)
     assert [l["prec"] for l in info[:-1]] == [64 if t == np.float64 else 32 for t in dts[:-1]]
     for l, lv in enumerate(Ho.levels[:-1]):
+        # (G^T A G)_vv cancels the curl part of A exactly in exact arithmetic,
+        # so its rounding error is about eps * (|G|^T |A| |G|)_vv: the ratio
+        # carries a relative error of about eps * rho
         rho = amg.gradient_ratio(lv.A, lv.G)
-        assert abs(info[l]["grad_ratio"] - rho) <= 1e-8 * rho, (l, info[l]["grad_ratio"], rho)
+        tol = max(1e-8, 64 * EPS * rho) * rho
+        assert abs(info[l]["grad_ratio"] - rho) <= tol, (l, info[l]["grad_ratio"], rho)
     r = np.random.default_rng(5).standard_normal(p.A.shape[0])
     rt = torch.tensor(r, device=d)
     zt = torch.zeros_like(rt)
