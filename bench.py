@@ -97,12 +97,14 @@ def sweep_bytes(li, w):
     return E * (w + 4) + R * (16 + 4 + 3 * w) + n * w + F * w + B * 16
 
 
-def vcycle_bytes(info, w):
+def vcycle_bytes(info):
     """Algorithmic bytes of one V(1,1) cycle (each matrix/factor entry once per
-    pass that needs it, vectors once per pass)."""
+    pass that needs it, vectors once per pass; values in each level's own
+    precision)."""
     tot = 0
     for l, li in enumerate(info):
         n, nnz = li["n"], li["nnz"]
+        w = 8 if li["prec"] == 64 else 4
         if l == len(info) - 1:
             tot += n * n * 8 + 2 * n * w
             continue
@@ -148,8 +150,10 @@ def time_kernels(amg, H, f, torch, reps=20):
     launch stream (torch's current stream, which the library is handed)."""
     info = H.info()
     li = info[0]
-    w = 8 if H.prec == 64 else 4
-    dt = torch.float64 if H.prec == 64 else torch.float32
+    # every level runs in its own precision (the FP32 form keeps FP64 where
+    # FP32 cannot resolve a level's gradient near-kernel)
+    w = 8 if li["prec"] == 64 else 4
+    dt = torch.float64 if li["prec"] == 64 else torch.float32
     b = f.to(dt)
     x = torch.zeros_like(b)
     H.sweep(0, b, x)
@@ -172,7 +176,8 @@ def time_kernels(amg, H, f, torch, reps=20):
     vc_ms = e0.elapsed_time(e1) / reps
     per_level = []
     for l in range(len(info) - 1):
-        bl = torch.zeros(info[l]["n"], dtype=dt, device=f.device) + 1
+        dtl = torch.float64 if info[l]["prec"] == 64 else torch.float32
+        bl = torch.zeros(info[l]["n"], dtype=dtl, device=f.device) + 1
         xl = torch.zeros_like(bl)
         H.sweep(l, bl, xl)
         torch.cuda.synchronize()
@@ -184,7 +189,7 @@ def time_kernels(amg, H, f, torch, reps=20):
         per_level.append(round(e0.elapsed_time(e1) / 5, 4))
     log(f"sweep ms per level: {per_level}")
     sb = sweep_bytes(li, w)
-    vb = vcycle_bytes(info, w)
+    vb = vcycle_bytes(info)
     ncol = li["ncolors"]
     launch_ms = sweep_ms / ncol
     launch_bytes = sb / ncol

@@ -128,7 +128,23 @@ typedef struct {
      so such a level keeps FP64 matrices, smoother and vectors.  A huge
      value runs every level in FP32. */
   double fp32_rho_tol;
+  /* How the interior rows of P are formed (eq. (sparseP) localised):
+     AMG_EXT_BLOCKS (default): blocks of A_II, solved one block at a time (the
+     connected components when all have at most ext_block_max DoFs, as in the
+     paper's 2D setting; otherwise owner groups in depth order).
+     AMG_EXT_PATCH: each column c of P is R^T e_c plus its least-energy
+     extension into a patch S_c of interior DoFs, A_SS x = -A_S,ext (R^T e_c),
+     the patch grown from the column's two exterior DoFs over patch_hops
+     rounds of A-couplings (most couplings first, ties to the smaller id), at
+     most patch_cap DoFs (1..192).  Overlapping patches reach across the
+     3D interior blocks that the block form decouples; with block-diagonal
+     A_II and enough hops it equals the block form. */
+  int ext_mode;
+  int patch_hops;          /* default 2 */
+  int patch_cap;           /* default 128 */
 } amg_options;
+
+enum { AMG_EXT_BLOCKS = 0, AMG_EXT_PATCH = 1 };
 
 typedef struct amg_hier amg_hier;   /* opaque; owns all device memory of the hierarchy */
 
@@ -179,6 +195,9 @@ typedef struct {
   int ncolors;
   int64_t gc_nrows, gc_ncols; const int64_t *gc_ptr; const int32_t *gc_col; const int8_t *gc_val;
   const int32_t *gc_cols;                   /* level-l node id of each column of G_{l+1} */
+  /* AMG_EXT_PATCH levels (else 0 / NULL): interior support of every column
+     of P_l, patch_ptr[nc] + 1 offsets into patch_dofs (ascending per column) */
+  int64_t npatch_entries; const int64_t *patch_ptr; const int32_t *patch_dofs;
 } amg_int_export;
 
 /* Fill *opt with the paper's defaults (Section 5). */
@@ -264,6 +283,17 @@ amg_status amg_check(amg_hier *h, void *stream);
 /* y = A x with the CSR SpMV kernel of the solve phase (device CSR and
    vectors, FP64).  Used for measurement and kernel tests. */
 amg_status amg_spmv(const amg_csr *A, const double *x, double *y, void *stream);
+
+/* y = A x and *dot = x^T y in one pass: the SpMV with the dot product that
+   each PCG iteration forms for its step length (q = A p and p^T q, Section 5),
+   for callers that run their own Krylov loop.  A: square device CSR (FP64);
+   x, y: device vectors of A->nrows entries (y is overwritten, x and y must not
+   overlap); dot: one device double.  The dot product sums one partial per
+   workgroup in a fixed order, so repeated calls give the same bits.  The call
+   allocates a partial-sum buffer of one double per 256/lanes rows, runs on
+   `stream` and synchronizes it before returning.  AMG_ERR_ARG / AMG_ERR_SHAPE
+   for bad arguments (nothing launched), AMG_ERR_HIP / AMG_ERR_OOM from HIP. */
+amg_status amg_spmv_dot(const amg_csr *A, const double *x, double *y, double *dot, void *stream);
 
 /* Per-level sizes; writes min(cap, levels) entries and the level count. */
 amg_status amg_hier_info(const amg_hier *h, amg_level_info *lv, int cap, int *nlevels);

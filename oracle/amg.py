@@ -11,6 +11,8 @@ Each function follows one step of the paper (arXiv 2602.23613):
   coarse_gradient      G_c = R G I_C, eq. (Gc) in Section 3.1 and the end of Section 4.2
   extension_blocks     local blocks of A_II used for the harmonic extension
   interpolation        P_app = (I - S_I A_II^{-1} S_I^T A) R^T, eq. (sparseP)
+  patch_sets,          the same extension column by column on overlapping
+  interpolation_patch  patches of interior DoFs (a 3D variant)
   galerkin             A_c = P^T A P (Section 1)
   smoother_setup       blocks, colours and factors of the OSS-l1 smoother (Section 5)
   vcycle, pcg          V(1,1) cycle and preconditioned CG (Section 5)
@@ -416,6 +418,73 @@ def interpolation(A, Rt, blocks, depths):
     return done
 
 
+def patch_sets(A, Rt, interior, hops=2, cap=128):
+    """Interior support S_c of every column c of P for the patch extension.
+
+    Column c of eq. (sparseP) is the A-harmonic extension of R^T e_c: the
+    vector with exterior values R^T e_c and least energy, whose interior part
+    solves A_II x = -A_IE (R^T e_c)_E on the whole interior set.  The patch
+    form (an addition for 3D, where A_II does not split into small blocks)
+    keeps the support of the interior part near the column's exterior DoFs:
+    starting from S = {}, each of `hops` rounds counts, for every interior DoF
+    j outside S, the DoFs of (exterior support of c) + S it is coupled to in
+    A, and adds the coupled ones in order of that count (largest first, ties
+    to the smaller id) until S holds `cap` DoFs.  Returns a list of ascending
+    DoF arrays, one per column."""
+    A = _ones(sp.csr_matrix(A))
+    Rt = sp.csc_matrix(Rt)
+    n, nc = Rt.shape
+    isint = np.zeros(n, dtype=bool)
+    isint[np.asarray(interior, dtype=np.int64)] = True
+    out = []
+    for c in range(nc):
+        ext = [int(e) for e in Rt.indices[Rt.indptr[c]:Rt.indptr[c + 1]]]
+        S = set()
+        for _ in range(hops):
+            if len(S) >= cap:
+                break
+            count = {}
+            for e in ext + sorted(S):
+                for j in _rows_of(A, e):
+                    j = int(j)
+                    if isint[j] and j not in S:
+                        count[j] = count.get(j, 0) + 1
+            ranked = sorted(count, key=lambda j: (-count[j], j))
+            S.update(ranked[:max(cap - len(S), 0)])
+        out.append(np.array(sorted(S), dtype=np.int64))
+    return out
+
+
+def interpolation_patch(A, Rt, patches):
+    """P with column c = R^T e_c + X_c, where X_c is supported on patches[c]
+    and solves A_SS X_c = -A_S,: R^T e_c with S = patches[c] (the least-energy
+    extension of the column's exterior values into its patch).  When A_II is
+    block diagonal and every patch holds the whole blocks coupled to the
+    column, this is eq. (sparseP) exactly."""
+    A = sp.csr_matrix(A)
+    Rt = sp.csc_matrix(Rt)
+    n, nc = Rt.shape
+    rows, cols, vals = [], [], []
+    for c in range(nc):
+        S = patches[c]
+        if len(S) == 0:
+            continue
+        rhs = (A[S] @ Rt[:, c]).toarray().ravel()
+        x = -np.linalg.solve(A[S][:, S].toarray(), rhs)
+        rows.append(S)
+        cols.append(np.full(len(S), c, dtype=np.int64))
+        vals.append(x)
+    # exterior rows (R^T) and interior rows (X) do not overlap; the COO route
+    # keeps every structural entry, including a solve's exact zeros
+    E = Rt.tocoo()
+    rows = np.concatenate([E.row.astype(np.int64)] + rows)
+    cols = np.concatenate([E.col.astype(np.int64)] + cols)
+    vals = np.concatenate([E.data] + vals)
+    P = sp.coo_matrix((vals, (rows, cols)), shape=(n, nc)).tocsr()
+    P.sort_indices()
+    return P
+
+
 def _csr_union(M, r, c, v, n, nc):
     coo = sp.csr_matrix(M).tocoo()
     rr = np.concatenate([coo.row.astype(np.int64), r])
@@ -462,11 +531,14 @@ class Smoother:
     l1: np.ndarray          # sum_j |a_ij|
 
 
-def smoother_setup(A, G):
+def smoother_setup(A, G, extra_blocks=None):
     """Node-star blocks supp(G[:, v]) for every column v, greedy colouring in
     block order of the conflict graph (two blocks conflict if they share a DoF
     or a DoF of one is coupled in A to a DoF of the other), Cholesky factors of
-    the diagonal blocks and the l1 diagonal."""
+    the diagonal blocks and the l1 diagonal.  extra_blocks (the alternative
+    reading "stars+interior") are appended after the stars: the interior
+    blocks of the level's splitting, the decoupled fine-variable blocks that
+    a compatible-relaxation smoother relaxes."""
     A = sp.csr_matrix(A)
     Gc = sp.csc_matrix(G)
     n = A.shape[0]
@@ -475,6 +547,9 @@ def smoother_setup(A, G):
         rows = np.sort(Gc.indices[Gc.indptr[v]:Gc.indptr[v + 1]]).astype(np.int64)
         if len(rows):
             blocks.append(rows)
+    for b in extra_blocks or []:
+        if len(b):
+            blocks.append(np.sort(np.asarray(b, dtype=np.int64)))
     nb = len(blocks)
     if nb:
         Bm = sp.csr_matrix((np.ones(sum(len(b) for b in blocks)),
@@ -522,6 +597,7 @@ class Level:
     blocks: list = None
     depths: np.ndarray = None
     exact_blocks: bool = None
+    patches: list = None           # per-column supports of the patch extension
     P: sp.csr_matrix = None
     Gc_cols: np.ndarray = None
     smoother: Smoother = None
@@ -547,7 +623,8 @@ class Hierarchy:
 
 
 DEFAULTS = dict(interp="alg", max_levels=20, min_coarse=32, ext_block_max=64,
-                ref_select=None, stall_ratio=0.9, p_trunc=0.0, schwarz="adjoint", user=None)
+                ref_select=None, stall_ratio=0.9, p_trunc=0.0, schwarz="adjoint", user=None,
+                ext_mode="blocks", patch_hops=2, patch_cap=128, smoother_blocks="stars")
 
 
 def setup(A, G, **opts):
@@ -613,7 +690,13 @@ def setup(A, G, **opts):
         sources = np.concatenate([Cp, lv.rr.k])
         lv.blocks, lv.depths, lv.exact_blocks = extension_blocks(
             lv.A, lv.Gt, lv.interior, sources, o["ext_block_max"])
-        lv.P = interpolation(lv.A, Rt, lv.blocks, lv.depths)
+        if o["ext_mode"] == "patch":
+            lv.patches = patch_sets(lv.A, Rt, lv.interior, o["patch_hops"], o["patch_cap"])
+            lv.P = interpolation_patch(lv.A, Rt, lv.patches)
+        else:
+            lv.P = interpolation(lv.A, Rt, lv.blocks, lv.depths)
+        if o["smoother_blocks"] == "stars+interior":
+            lv.smoother = smoother_setup(lv.A, lv.G, extra_blocks=lv.blocks)
         lv.P = truncate_interior(lv.P, lv.interior, o["p_trunc"])
         Ac = galerkin(lv.A, lv.P)
         Gc, cols = coarse_gradient(lv.G, lv.rr)

@@ -16,7 +16,7 @@ from ._lib import AmgError, load  # noqa: F401
 # amg_level_info.sweep_form values
 SWEEP_FORMS = {0: "colour", 1: "one", 2: "pipe", 3: "dense", 4: "panel"}
 
-__all__ = ["Hierarchy", "level0_integers", "spmv", "mlp_loss_grad", "load", "AmgError"]
+__all__ = ["Hierarchy", "level0_integers", "spmv", "spmv_dot", "mlp_loss_grad", "load", "AmgError"]
 
 
 def _stream(stream):
@@ -44,8 +44,11 @@ def _csr_arg(M, keep):
 
 def _options(keep, interp="alg", max_levels=20, min_coarse=32, vcycle_prec=64, ext_block_max=64,
              stall_ratio=0.9, p_trunc=0.0, ref=None, schwarz="adjoint", seed=None, user=None,
-             fp32_rho_tol=None):
+             fp32_rho_tol=None, ext_mode="blocks", patch_hops=2, patch_cap=128):
     o = _lib.default_options()
+    o.ext_mode = {"blocks": _lib.AMG_EXT_BLOCKS, "patch": _lib.AMG_EXT_PATCH}[ext_mode]
+    o.patch_hops = patch_hops
+    o.patch_cap = patch_cap
     o.interp = {"alg": _lib.AMG_INTERP_ALG, "ref": _lib.AMG_INTERP_REF,
                 "user": _lib.AMG_INTERP_USER}[interp]
     o.max_levels = max_levels
@@ -120,6 +123,8 @@ class Hierarchy:
         self._h = h
         self.prec = opts.get("vcycle_prec", 64)
         self.n = A[3] if isinstance(A, tuple) else A.shape[0]
+        # level sizes never change after setup (a numeric re-setup keeps them)
+        self._sizes = [li["n"] for li in self.info()]
 
     def close(self):
         if getattr(self, "_h", None):
@@ -188,10 +193,9 @@ class Hierarchy:
         """One multiplicative Schwarz sweep on `level` (x updated in place)."""
         import torch
         prec = 32 if b.dtype == torch.float32 else 64
-        info = self.info()
-        if not 0 <= level < len(info) - 1:
+        if not 0 <= level < len(self._sizes) - 1:
             raise ValueError("level has no smoother")
-        n, dt = info[level]["n"], "float32" if prec == 32 else "float64"
+        n, dt = self._sizes[level], "float32" if prec == 32 else "float64"
         _lib.check(load().amg_smoother_sweep(self._h, level, prec, _vec(b, n, "b", dt),
                                              _vec(x, n, "x", dt), 1 if backward else 0,
                                              _stream(stream)))
@@ -308,3 +312,15 @@ def spmv(rowptr, colidx, val, x, y, stream=None):
     n = rowptr.shape[0] - 1
     a = _lib.make_csr(rowptr, colidx, val, n, x.shape[0])
     _lib.check(load().amg_spmv(C.byref(a), x.data_ptr(), y.data_ptr(), _stream(stream)))
+
+
+def spmv_dot(rowptr, colidx, val, x, y, dot, stream=None):
+    """y = A x and dot[0] = x^T y (device tensors; dot a float64 tensor of one
+    entry).  Synchronizes the stream."""
+    n = rowptr.shape[0] - 1
+    _vec(x, n, "x")
+    _vec(y, n, "y")
+    _vec(dot, 1, "dot")
+    a = _lib.make_csr(rowptr, colidx, val, n, n)
+    _lib.check(load().amg_spmv_dot(C.byref(a), x.data_ptr(), y.data_ptr(), dot.data_ptr(),
+                                   _stream(stream)))

@@ -19,6 +19,8 @@ AMG_NOT_CONVERGED = 1
 AMG_INTERP_ALG = 0
 AMG_INTERP_REF = 1
 AMG_INTERP_USER = 2
+AMG_EXT_BLOCKS = 0
+AMG_EXT_PATCH = 1
 SCHWARZ_MODES = {"adjoint": 0, "repeat": 1, "split": 2}
 
 STATUS = {0: "AMG_OK", 1: "AMG_NOT_CONVERGED", -1: "AMG_ERR_ARG", -2: "AMG_ERR_SHAPE",
@@ -31,7 +33,7 @@ EXPORTED = ["amg_default_options", "amg_setup", "amg_resetup_numeric", "amg_vcyc
             "amg_export_level", "amg_level0_integers", "amg_free_integers", "amg_destroy",
             "amg_last_error", "amg_mlp_nparams", "amg_mlp_train", "amg_mlp_use", "amg_mlp_stats_get",
             "amg_mlp_params", "amg_mlp_forward", "amg_mlp_backward", "amg_mlp_loss_grad", "amg_check",
-            "amg_cycle_solve", "amg_complexity"]
+            "amg_cycle_solve", "amg_complexity", "amg_spmv_dot"]
 
 
 class AmgError(RuntimeError):
@@ -57,7 +59,8 @@ class amg_options(C.Structure):
                 ("ref_nbnd", C.POINTER(C.c_int64)),
                 ("schwarz_mode", C.c_int), ("seed", C.c_uint64),
                 ("user_nlevels", C.c_int), ("user_P", C.POINTER(amg_csr)),
-                ("user_G", C.POINTER(amg_csr)), ("fp32_rho_tol", C.c_double)]
+                ("user_G", C.POINTER(amg_csr)), ("fp32_rho_tol", C.c_double),
+                ("ext_mode", C.c_int), ("patch_hops", C.c_int), ("patch_cap", C.c_int)]
 
 
 class amg_solve_stats(C.Structure):
@@ -93,7 +96,9 @@ class amg_int_export(C.Structure):
                 ("ncolors", C.c_int),
                 ("gc_nrows", C.c_int64), ("gc_ncols", C.c_int64),
                 ("gc_ptr", C.POINTER(C.c_int64)), ("gc_col", C.POINTER(C.c_int32)),
-                ("gc_val", C.POINTER(C.c_int8)), ("gc_cols", C.POINTER(C.c_int32))]
+                ("gc_val", C.POINTER(C.c_int8)), ("gc_cols", C.POINTER(C.c_int32)),
+                ("npatch_entries", C.c_int64), ("patch_ptr", C.POINTER(C.c_int64)),
+                ("patch_dofs", C.POINTER(C.c_int32))]
 
 
 class amg_mlp_train_cfg(C.Structure):
@@ -138,6 +143,7 @@ def load():
     lib.amg_cycle_solve.argtypes = [P, P, P, C.c_double, C.c_int, C.POINTER(amg_solve_stats), P]
     lib.amg_complexity.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.amg_spmv.argtypes = [C.POINTER(amg_csr), P, P, P]
+    lib.amg_spmv_dot.argtypes = [C.POINTER(amg_csr), P, P, P, P]
     lib.amg_smoother_sweep.argtypes = [P, C.c_int, C.c_int, P, P, C.c_int, P]
     lib.amg_check.argtypes = [P, P]
     lib.amg_hier_info.argtypes = [P, C.POINTER(amg_level_info), C.c_int, C.POINTER(C.c_int)]
@@ -161,6 +167,7 @@ def load():
     lib.amg_mlp_backward.argtypes = [P, P, C.c_int64, P, P, P]
     lib.amg_mlp_loss_grad.argtypes = [P, P, P, C.c_int64, C.c_int64, P, P, P]
     for name in ("amg_setup", "amg_resetup_numeric", "amg_vcycle", "amg_pcg_solve", "amg_spmv",
+                 "amg_spmv_dot",
                  "amg_cycle_solve", "amg_complexity",
                  "amg_smoother_sweep", "amg_check",
                  "amg_hier_info", "amg_export_integers", "amg_export_level",
@@ -237,4 +244,7 @@ def export_to_dict(e: amg_int_export):
     d["gc_col"] = _arr(e.gc_col, d["gc_ptr"][-1] if e.gc_nrows else 0, np.int64)
     d["gc_val"] = _arr(e.gc_val, d["gc_ptr"][-1] if e.gc_nrows else 0, np.int64)
     d["gc_cols"] = _arr(e.gc_cols, e.gc_ncols, np.int64)
+    if e.patch_ptr:
+        d["patch_ptr"] = _arr(e.patch_ptr, e.nc + 1, np.int64)
+        d["patch_dofs"] = _arr(e.patch_dofs, e.npatch_entries, np.int64)
     return d

@@ -92,6 +92,9 @@ struct Pool {
   }
 };
 
+// largest patch of the patch extension: its packed factor fits 160 KB of LDS
+constexpr int PATCH_CAP_MAX = 192;
+
 struct Stage {
   int64_t b0, nb;
   int smax, cmax;
@@ -132,6 +135,14 @@ struct Level {
   std::vector<int64_t> p_ptr_h;   // host copy of P's current pattern
   std::vector<int32_t> p_col_h;
   int32_t* dof_stage = nullptr;
+  // patch extension: per-column interior supports, their P entries, R rows
+  int64_t* patch_ptr = nullptr;
+  int32_t* patch_dofs = nullptr;
+  int64_t* patch_dst = nullptr;
+  int32_t* r_d1 = nullptr;
+  int32_t* r_d2 = nullptr;
+  int8_t* r_sg1 = nullptr;
+  int8_t* r_sg2 = nullptr;
   int64_t* blk_ptr = nullptr;
   int32_t* blk_dofs = nullptr;
   std::vector<Stage> stages;
@@ -145,6 +156,7 @@ struct Level {
   double* AP_val = nullptr;
   // device: smoother
   int64_t nstars = 0;
+  int64_t star_rows = 0, star_row_nnz = 0;   // star rows and their A entries (for byte counts)
   int ncolours = 0;
   std::vector<int> colour_chunk;
   int32_t* colour_chunk_dev = nullptr;
@@ -502,6 +514,12 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   int64_t ns = (int64_t)I.star_ptr.size() - 1;
   L.nstars = ns;
   L.ncolours = I.ncolors;
+  L.star_rows = I.star_ptr.empty() ? 0 : I.star_ptr.back();
+  L.star_row_nnz = 0;
+  for (int64_t q = 0; q < L.star_rows; ++q) {
+    const int32_t e = I.star_dofs[q];
+    L.star_row_nnz += L.Apat.ptr[e + 1] - L.Apat.ptr[e];
+  }
   int maxs = 0;
   for (int64_t b = 0; b < ns; ++b) maxs = std::max<int>(maxs, (int)(I.star_ptr[b + 1] - I.star_ptr[b]));
   if (maxs > 32) fail(AMG_ERR_LIMIT, "smoother block with more than 32 DoFs");
@@ -714,10 +732,20 @@ void build_interp_structs(amg_hier* h, Level& L, hipStream_t st) {
   L.P_val = h->pool.get<double>(L.p_nnz);
   L.lpr_P = lpr_for(L.n, L.p_nnz);
   L.dof_stage = h->pool.upload(I.dof_stage, st);
+  L.stages.clear();
+  if (I.patch) {
+    if (I.patch_max > PATCH_CAP_MAX) fail(AMG_ERR_LIMIT, "patch larger than the kernel's LDS holds");
+    L.patch_ptr = h->pool.upload(I.patch_ptr, st);
+    L.patch_dofs = h->pool.upload(I.patch_dofs, st);
+    L.patch_dst = h->pool.upload(I.patch_dst, st);
+    L.r_d1 = h->pool.upload(I.r_dof1, st);
+    L.r_d2 = h->pool.upload(I.r_dof2, st);
+    L.r_sg1 = h->pool.upload(I.r_s1, st);
+    L.r_sg2 = h->pool.upload(I.r_s2, st);
+  }
   L.blk_ptr = h->pool.upload(I.block_ptr, st);
   L.blk_dofs = h->pool.upload(I.block_dofs, st);
-  L.stages.clear();
-  int64_t nst = (int64_t)I.stage_ptr.size() - 1;
+  int64_t nst = I.patch ? 0 : (int64_t)I.stage_ptr.size() - 1;
   for (int64_t s = 0; s < nst; ++s) {
     Stage S{I.stage_ptr[s], I.stage_ptr[s + 1] - I.stage_ptr[s], 0, 0};
     for (int64_t b = I.stage_ptr[s]; b < I.stage_ptr[s + 1]; ++b) {
@@ -798,6 +826,9 @@ void truncate_interp(amg_hier* h, Level& L, double tau, hipStream_t st) {
 
 void compute_interp(amg_hier* h, Level& L, int level, hipStream_t st, bool learned = false) {
   sign_to_val(L.p_nnz, L.P_sign, L.P_val, st);   // untruncated pattern (p_trunc = 0 here)
+  if (L.ints.patch)
+    ext_patches(L.nc, L.patch_ptr, L.patch_dofs, L.patch_dst, L.r_d1, L.r_d2, L.r_sg1, L.r_sg2,
+                L.A_dev<double>(), L.P_val, L.ints.patch_max, h->d_flag, st);
   for (size_t s = 0; s < L.stages.size(); ++s) {
     const Stage& S = L.stages[s];
     ext_blocks(S.b0, S.nb, L.blk_ptr, L.blk_dofs, L.dof_stage, (int)s, L.A_dev<double>(), L.P_ptr,
@@ -1429,6 +1460,27 @@ void fill_export(const LevelInts& I, amg_int_export* o) {
   o->gc_col = I.gc_col.data();
   o->gc_val = I.gc_val.data();
   o->gc_cols = I.gc_cols.data();
+  o->npatch_entries = I.patch ? (int64_t)I.patch_dofs.size() : 0;
+  o->patch_ptr = I.patch ? I.patch_ptr.data() : nullptr;
+  o->patch_dofs = I.patch ? I.patch_dofs.data() : nullptr;
+}
+
+ExtOptions ext_options(const amg_options& o) {
+  ExtOptions e;
+  e.ext_block_max = o.ext_block_max;
+  e.ext_mode = o.ext_mode;
+  e.patch_hops = o.patch_hops;
+  e.patch_cap = o.patch_cap;
+  return e;
+}
+
+void check_ext_options(const amg_options& o) {
+  if (o.ext_mode != AMG_EXT_BLOCKS && o.ext_mode != AMG_EXT_PATCH) fail(AMG_ERR_ARG, "unknown ext_mode");
+  if (o.ext_mode == AMG_EXT_PATCH) {
+    if (o.patch_hops < 1 || o.patch_hops > 8) fail(AMG_ERR_ARG, "patch_hops must be in 1..8");
+    if (o.patch_cap < 1 || o.patch_cap > PATCH_CAP_MAX)
+      fail(AMG_ERR_ARG, "patch_cap must be in 1.." + std::to_string(PATCH_CAP_MAX));
+  }
 }
 
 }  // namespace
@@ -1448,6 +1500,9 @@ void amg_default_options(amg_options* opt) {
   opt->schwarz_mode = AMG_SCHWARZ_ADJOINT;
   opt->seed = 0x5eed1234ull;
   opt->fp32_rho_tol = 1e-3;
+  opt->ext_mode = AMG_EXT_BLOCKS;
+  opt->patch_hops = 2;
+  opt->patch_cap = 128;
 }
 
 const char* amg_last_error(void) { return g_err.c_str(); }
@@ -1472,6 +1527,7 @@ amg_status amg_setup(const amg_csr* A, const amg_csr* G, const amg_options* opt,
       fail(AMG_ERR_ARG, "p_trunc applies to the paper's interpolation only");
     if (o.schwarz_mode < AMG_SCHWARZ_ADJOINT || o.schwarz_mode > AMG_SCHWARZ_SPLIT)
       fail(AMG_ERR_ARG, "unknown schwarz_mode");
+    check_ext_options(o);
     hipStream_t st = (hipStream_t)stream;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(AMG_ERR_HIP, "no HIP device");
@@ -1531,7 +1587,7 @@ amg_status amg_setup(const amg_csr* A, const amg_csr* G, const amg_options* opt,
           rb.assign(o.ref_coarse_bnd[l], o.ref_coarse_bnd[l] + o.ref_nbnd[l]);
         }
         HostError err;
-        if (!setup_level_integers(L.Apat, L.G, L.S, use_ref, rc, rb, o.ext_block_max, L.ints, err))
+        if (!setup_level_integers(L.Apat, L.G, L.S, use_ref, rc, rb, ext_options(o), L.ints, err))
           fail((amg_status)err.code, "level " + std::to_string(l) + ": " + err.msg);
         clk.mark(st, "integer setup (Alg. 1-3, P pattern)", l);
         int64_t nc = (int64_t)L.ints.r_dof1.size();
@@ -1827,6 +1883,33 @@ amg_status amg_spmv(const amg_csr* A, const double* x, double* y, void* stream) 
   });
 }
 
+amg_status amg_spmv_dot(const amg_csr* A, const double* x, double* y, double* dot, void* stream) {
+  return guarded([&]() -> amg_status {
+    validate_csr_arg(A, "A");
+    if (!A->on_device) fail(AMG_ERR_ARG, "amg_spmv_dot needs device CSR arrays");
+    if (A->nrows != A->ncols) fail(AMG_ERR_SHAPE, "A is not square");
+    if (!x || !y || !dot) fail(AMG_ERR_ARG, "NULL vector");
+    CsrDev<double> M;
+    M.n = A->nrows; M.m = A->ncols; M.nnz = A->nnz;
+    M.ptr = A->rowptr; M.col = A->colidx; M.val = A->val;
+    M.lpr = lpr_for(M.n, M.nnz);
+    hipStream_t st = (hipStream_t)stream;
+    // one partial sum per SpMV workgroup, summed in a fixed order by one
+    // workgroup (the same reduction as PCG's q = A p with p^T q)
+    const int64_t np = spmv_dot_partials(M.lpr, M.n);
+    double* partial = nullptr;
+    HIPC(hipMalloc(&partial, (size_t)std::max<int64_t>(np, 1) * sizeof(double)));
+    spmv_dot(M, x, y, partial, st);
+    reduce(np, partial, dot, 0, -1, st);
+    hipError_t e = hipGetLastError();
+    hipError_t es = hipStreamSynchronize(st);
+    (void)hipFree(partial);
+    HIPC(e);
+    HIPC(es);
+    return AMG_OK;
+  });
+}
+
 amg_status amg_hier_info(const amg_hier* h, amg_level_info* lv, int cap, int* nlevels) {
   return guarded([&]() -> amg_status {
     if (!h || !nlevels) fail(AMG_ERR_ARG, "NULL argument");
@@ -1839,18 +1922,8 @@ amg_status amg_hier_info(const amg_hier* h, amg_level_info* lv, int cap, int* nl
       lv[l].nblocks = L.coarsest ? 0 : L.nstars;
       lv[l].ncolors = L.coarsest ? 0 : L.ncolours;
       lv[l].exact_blocks = L.coarsest ? 0 : (L.ints.exact_blocks ? 1 : 0);
-      int64_t rows = 0, rnnz = 0;
-      if (!L.coarsest) {
-        const auto& sp = L.ints.star_ptr;
-        for (size_t b = 0; b + 1 < sp.size(); ++b)
-          for (int64_t q = sp[b]; q < sp[b + 1]; ++q) {
-            int32_t e = L.ints.star_dofs[q];
-            rnnz += L.Apat.ptr[e + 1] - L.Apat.ptr[e];
-          }
-        rows = sp.empty() ? 0 : sp.back();
-      }
-      lv[l].star_rows = rows;
-      lv[l].star_row_nnz = rnnz;
+      lv[l].star_rows = L.coarsest ? 0 : L.star_rows;
+      lv[l].star_row_nnz = L.coarsest ? 0 : L.star_row_nnz;
       lv[l].fac_entries = L.coarsest ? 0 : L.fac_total;
       lv[l].sweep_form = L.coarsest ? 0 : L.sweep_mode;
       lv[l].sweep_lanes = (L.coarsest || L.sweep_mode == SWEEP_DENSE || L.sweep_mode == SWEEP_PANEL) ? 0 : L.lpr_S;
@@ -1910,7 +1983,8 @@ amg_status amg_level0_integers(const amg_csr* A, const amg_csr* G, const amg_opt
       rb.assign(o.ref_coarse_bnd[0], o.ref_coarse_bnd[0] + o.ref_nbnd[0]);
     }
     HostError err;
-    if (!setup_level_integers(l0.Apat, l0.G, l0.S, use_ref, rc, rb, o.ext_block_max, H->ints, err))
+    check_ext_options(o);
+    if (!setup_level_integers(l0.Apat, l0.G, l0.S, use_ref, rc, rb, ext_options(o), H->ints, err))
       fail((amg_status)err.code, err.msg);
     stars_and_colours(l0.Apat, l0.G, H->ints);
     fill_export(H->ints, out);
@@ -1985,6 +2059,8 @@ amg_status amg_mlp_train(amg_hier* h, const amg_mlp_train_cfg* cfg, amg_mlp_stat
   return guarded([&]() -> amg_status {
     if (!h || !cfg) fail(AMG_ERR_ARG, "NULL argument");
     if (h->lv[0].user_p) fail(AMG_ERR_ARG, "the learned setup needs the paper's interpolation (no user P)");
+    if (h->lv[0].ints.patch)
+      fail(AMG_ERR_ARG, "the learned setup predicts block solves (ext_mode AMG_EXT_BLOCKS)");
     if (cfg->batch <= 0 || cfg->batch % 16) fail(AMG_ERR_ARG, "batch must be a positive multiple of 16");
     if (cfg->epochs < 0) fail(AMG_ERR_ARG, "epochs < 0");
     hipStream_t st = (hipStream_t)stream;

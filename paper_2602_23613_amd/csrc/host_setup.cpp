@@ -652,6 +652,98 @@ void extension_and_pattern(const Pattern& A, const Incidence& Gt, const EdgeGrap
   }
 }
 
+// Patch extension: column c of P is R^T e_c plus its least-energy extension
+// into the interior DoFs S_c.  S_c grows from {} over `hops` rounds: every
+// interior DoF outside S_c coupled in A to the column's two exterior DoFs or
+// to S_c (as it was at the start of the round) counts those couplings, and
+// the coupled DoFs join in order of count (largest first, ties to the smaller
+// id) until S_c holds `cap` DoFs.  Replaces the block pattern of P: interior
+// row i holds the columns c with i in S_c (ascending), exterior rows keep
+// their R^T entry; patch_dst maps every (c, i) to its entry of P.
+void patch_extension_pattern(const Pattern& A, int hops, int cap, LevelInts& L) {
+  const int64_t n = A.n;
+  const int64_t nc = (int64_t)L.r_dof1.size();
+  std::vector<char> isint(n, 0);
+  for (int32_t e : L.interior) isint[e] = 1;
+  std::vector<std::vector<int32_t>> sets(nc);
+  parallel_for(nc, [&](int64_t lo, int64_t hi) {
+    std::vector<int64_t> stamp(n, -1);
+    std::vector<int32_t> cnt(n, 0);
+    std::vector<char> in(n, 0);
+    std::vector<int32_t> S, snap, cand;
+    int64_t tag = lo * (int64_t)(hops + 1);
+    for (int64_t c = lo; c < hi; ++c) {
+      S.clear();
+      const int32_t ext[2] = {L.r_dof1[c], L.r_dof2[c]};
+      for (int h = 0; h < hops && (int64_t)S.size() < (int64_t)cap; ++h, ++tag) {
+        snap.assign(ext, ext + 2);
+        snap.insert(snap.end(), S.begin(), S.end());
+        cand.clear();
+        for (int32_t e : snap)
+          for (int64_t q = A.ptr[e]; q < A.ptr[e + 1]; ++q) {
+            const int32_t j = A.idx[q];
+            if (!isint[j] || in[j]) continue;
+            if (stamp[j] != tag) { stamp[j] = tag; cnt[j] = 0; cand.push_back(j); }
+            ++cnt[j];
+          }
+        std::sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) {
+          return cnt[a] != cnt[b] ? cnt[a] > cnt[b] : a < b;
+        });
+        const int64_t room = std::max<int64_t>(0, (int64_t)cap - (int64_t)S.size());
+        for (int64_t t = 0; t < (int64_t)cand.size() && t < room; ++t) {
+          S.push_back(cand[t]);
+          in[cand[t]] = 1;
+        }
+      }
+      for (int32_t j : S) in[j] = 0;
+      std::sort(S.begin(), S.end());
+      sets[c] = S;
+    }
+  });
+  L.patch = true;
+  L.patch_ptr.assign(nc + 1, 0);
+  L.patch_max = 0;
+  for (int64_t c = 0; c < nc; ++c) {
+    L.patch_ptr[c + 1] = L.patch_ptr[c] + (int64_t)sets[c].size();
+    L.patch_max = std::max<int>(L.patch_max, (int)sets[c].size());
+  }
+  L.patch_dofs.resize(L.patch_ptr[nc]);
+  for (int64_t c = 0; c < nc; ++c)
+    std::copy(sets[c].begin(), sets[c].end(), L.patch_dofs.begin() + L.patch_ptr[c]);
+  // P's pattern: exterior rows one entry, interior rows one per patch holding them
+  Pattern& P = L.p;
+  P.n = n;
+  P.m = nc;
+  P.ptr.assign(n + 1, 0);
+  for (int64_t c = 0; c < nc; ++c) {
+    P.ptr[L.r_dof1[c] + 1] = 1;
+    P.ptr[L.r_dof2[c] + 1] = 1;
+  }
+  for (int32_t j : L.patch_dofs) P.ptr[j + 1] += 1;
+  for (int64_t e = 0; e < n; ++e) P.ptr[e + 1] += P.ptr[e];
+  P.idx.assign(P.ptr[n], 0);
+  L.p_ext_sign.assign(P.ptr[n], 0);
+  std::vector<int64_t> pos(P.ptr.begin(), P.ptr.end() - 1);
+  for (int64_t c = 0; c < nc; ++c) {
+    P.idx[P.ptr[L.r_dof1[c]]] = (int32_t)c;
+    L.p_ext_sign[P.ptr[L.r_dof1[c]]] = L.r_s1[c];
+    P.idx[P.ptr[L.r_dof2[c]]] = (int32_t)c;
+    L.p_ext_sign[P.ptr[L.r_dof2[c]]] = L.r_s2[c];
+  }
+  // columns are visited in ascending order, so every interior row comes out sorted
+  L.patch_dst.resize(L.patch_dofs.size());
+  for (int64_t c = 0; c < nc; ++c)
+    for (int64_t q = L.patch_ptr[c]; q < L.patch_ptr[c + 1]; ++q) {
+      const int32_t j = L.patch_dofs[q];
+      const int64_t d = pos[j]++;
+      P.idx[d] = (int32_t)c;
+      L.patch_dst[q] = d;
+    }
+  // no depth stages: every interior DoF is extended in one pass
+  L.stage_ptr.assign(1, 0);
+  for (int32_t e : L.interior) L.dof_stage[e] = 0;
+}
+
 }  // namespace
 
 void stars_and_colours(const Pattern& A, const Incidence& G, LevelInts& L) {
@@ -700,7 +792,7 @@ void stars_and_colours(const Pattern& A, const Incidence& G, LevelInts& L) {
 
 bool setup_level_integers(const Pattern& A, const Incidence& G, const Pattern& S, bool use_ref,
                           const std::vector<int32_t>& ref_cg, const std::vector<int32_t>& ref_bnd,
-                          int ext_block_max, LevelInts& L, HostError& err) {
+                          const ExtOptions& ext, LevelInts& L, HostError& err) {
   L.n = A.n;
   L.m_real = G.m;
   Incidence Gt;
@@ -755,7 +847,13 @@ bool setup_level_integers(const Pattern& A, const Incidence& G, const Pattern& S
   sources.insert(sources.end(), L.r_k.begin(), L.r_k.end());
   std::sort(sources.begin(), sources.end());
   sources.erase(std::unique(sources.begin(), sources.end()), sources.end());
-  extension_and_pattern(A, Gt, E, sources, ext_block_max, L);
+  extension_and_pattern(A, Gt, E, sources, ext.ext_block_max, L);
+  L.patch = false;
+  L.patch_ptr.clear();
+  L.patch_dofs.clear();
+  L.patch_dst.clear();
+  L.patch_max = 0;
+  if (ext.ext_mode == 1) patch_extension_pattern(A, ext.patch_hops, ext.patch_cap, L);
   coarse_gradient(G, L);
   return true;
 }

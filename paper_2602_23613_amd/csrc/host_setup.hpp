@@ -65,6 +65,23 @@ struct LevelInts {
   std::vector<int8_t> p_ext_sign;         // per P entry: +-1 on exterior rows, 0 on interior rows
   std::vector<int32_t> dof_stage;         // -1 exterior, else depth stage index of the DoF's block
   std::vector<int64_t> stage_ptr;         // blocks of each depth stage: [stage_ptr[s], stage_ptr[s+1])
+  // patch extension (ext_mode 1): interior support of every column of P
+  // (ascending DoFs) and, per patch entry, its position in P's entries
+  bool patch = false;
+  std::vector<int64_t> patch_ptr;
+  std::vector<int32_t> patch_dofs;
+  std::vector<int64_t> patch_dst;
+  int patch_max = 0;
+};
+
+// How P's interior rows are formed: ext_mode 0 = blocks of A_II (components,
+// or depth-ordered owner groups when a component is too large); 1 = per-column
+// patches of at most patch_cap interior DoFs grown over patch_hops rounds.
+struct ExtOptions {
+  int ext_block_max = 64;
+  int ext_mode = 0;
+  int patch_hops = 2;
+  int patch_cap = 128;
 };
 
 struct HostError {
@@ -101,7 +118,7 @@ std::vector<int8_t> rs_first_pass(const Pattern& S, const std::vector<int32_t>& 
 // `nc_out` = number of coarse DoFs (0 = no coarsening possible).
 bool setup_level_integers(const Pattern& A, const Incidence& G, const Pattern& S, bool use_ref,
                           const std::vector<int32_t>& ref_cg, const std::vector<int32_t>& ref_bnd,
-                          int ext_block_max, LevelInts& L, HostError& err);
+                          const ExtOptions& ext, LevelInts& L, HostError& err);
 
 // Node-star blocks of G and their greedy colouring on the conflict graph.
 void stars_and_colours(const Pattern& A, const Incidence& G, LevelInts& L);

@@ -1614,6 +1614,114 @@ void ext_blocks(int64_t b0, int64_t nb, const int64_t* bptr, const int32_t* bdof
                      wide, flag, Wl, accepted, dsq);
 }
 
+// Patch extension: one workgroup per column c of P.  The column's patch S
+// (m <= patch_max interior DoFs, ascending) gives the dense SPD system
+// A_SS x = -A_S,ext r_c, where r_c holds the column's two exterior values
+// (the signs of its R row).  Thread i gathers row S[i] of A: the lower-
+// triangle entries of A_SS into a packed LDS matrix (row i at i(i+1)/2) and
+// the two exterior couplings.  Right-looking Cholesky in LDS, forward and
+// back substitution, then x goes to P's entries of the column (patch_dst).
+__global__ __launch_bounds__(256) void k_ext_patch(
+    const int64_t* __restrict__ pptr, const int32_t* __restrict__ pdofs,
+    const int64_t* __restrict__ pdst, const int32_t* __restrict__ rd1,
+    const int32_t* __restrict__ rd2, const int8_t* __restrict__ rs1,
+    const int8_t* __restrict__ rs2, const int64_t* __restrict__ Aptr,
+    const int32_t* __restrict__ Acol, const double* __restrict__ Aval, double* __restrict__ Pval,
+    int mmax, int* __restrict__ flag) {
+  extern __shared__ unsigned char lds_raw[];
+  double* L = (double*)lds_raw;                             // packed lower triangle
+  double* y = L + (size_t)mmax * (mmax + 1) / 2;            // right-hand side, then x
+  int32_t* dofs = (int32_t*)(y + mmax);
+  const int64_t c = blockIdx.x;
+  const int64_t p0 = pptr[c];
+  const int m = (int)(pptr[c + 1] - p0);
+  if (m == 0) return;   // the whole workgroup: nothing to extend
+  const int tid = threadIdx.x;
+  const int32_t e1 = rd1[c], e2 = rd2[c];
+  const double s1 = (double)rs1[c], s2 = (double)rs2[c];
+  for (int t = tid; t < m; t += 256) dofs[t] = pdofs[p0 + t];
+  const int tri = m * (m + 1) / 2;
+  for (int t = tid; t < tri; t += 256) L[t] = 0.0;
+  __syncthreads();
+  for (int i = tid; i < m; i += 256) {
+    const int32_t r = dofs[i];
+    double a1 = 0.0, a2 = 0.0;
+    double* Li = L + i * (i + 1) / 2;
+    for (int64_t q = Aptr[r]; q < Aptr[r + 1]; ++q) {
+      const int32_t j = Acol[q];
+      if (j == e1) {
+        a1 = Aval[q];
+      } else if (j == e2) {
+        a2 = Aval[q];
+      } else if (j <= r) {
+        const int pos = lower_bound_i32(dofs, i + 1, j);
+        if (pos <= i && dofs[pos] == j) Li[pos] = Aval[q];
+      }
+    }
+    // two terms with exact +-1 factors: the sum does not depend on the order
+    y[i] = -(a1 * s1 + a2 * s2);
+  }
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    double* Lk = L + k * (k + 1) / 2;
+    if (tid == 0) {
+      double d = Lk[k];
+      if (!(d > 0.0)) {
+        atomicExch(flag, 1);
+        d = 1.0;
+      }
+      Lk[k] = sqrt(d);
+    }
+    __syncthreads();
+    const double dk = Lk[k];
+    for (int i = k + 1 + tid; i < m; i += 256) L[i * (i + 1) / 2 + k] /= dk;
+    __syncthreads();
+    // trailing update of rows i > k, columns k < j <= i; several threads per
+    // row once fewer than 256 rows remain
+    const int nr = m - k - 1;
+    if (nr > 0) {
+      const int tpr = max(1, 256 / nr);
+      const int rstep = 256 / tpr;
+      for (int rr = tid / tpr; rr < nr; rr += rstep) {
+        const int i = k + 1 + rr;
+        double* Li = L + i * (i + 1) / 2;
+        const double lik = Li[k];
+        for (int j = k + 1 + tid % tpr; j <= i; j += tpr) Li[j] -= lik * L[j * (j + 1) / 2 + k];
+      }
+    }
+    __syncthreads();
+  }
+  // L z = y, then L^T x = z (in y)
+  for (int k = 0; k < m; ++k) {
+    if (tid == 0) y[k] /= L[k * (k + 1) / 2 + k];
+    __syncthreads();
+    const double zk = y[k];
+    for (int i = k + 1 + tid; i < m; i += 256) y[i] -= L[i * (i + 1) / 2 + k] * zk;
+    __syncthreads();
+  }
+  for (int k = m - 1; k >= 0; --k) {
+    const double* Lk = L + k * (k + 1) / 2;
+    if (tid == 0) y[k] /= Lk[k];
+    __syncthreads();
+    const double xk = y[k];
+    for (int i = tid; i < k; i += 256) y[i] -= Lk[i] * xk;
+    __syncthreads();
+  }
+  for (int t = tid; t < m; t += 256) Pval[pdst[p0 + t]] = y[t];
+}
+
+size_t ext_patch_lds(int mmax) {
+  return sizeof(double) * ((size_t)mmax * (mmax + 1) / 2 + (size_t)mmax) + sizeof(int32_t) * (size_t)mmax;
+}
+
+void ext_patches(int64_t nc, const int64_t* pptr, const int32_t* pdofs, const int64_t* pdst,
+                 const int32_t* rd1, const int32_t* rd2, const int8_t* rs1, const int8_t* rs2,
+                 const CsrDev<double>& A, double* Pval, int mmax, int* flag, hipStream_t st) {
+  if (nc <= 0 || mmax <= 0) return;
+  hipLaunchKernelGGL(k_ext_patch, dim3((unsigned)nc), dim3(256), ext_patch_lds(mmax), st, pptr,
+                     pdofs, pdst, rd1, rd2, rs1, rs2, A.ptr, A.col, A.val, Pval, mmax, flag);
+}
+
 // x_i = a pseudo-random value in [-1, 1) from a counter-based hash (SplitMix64)
 __global__ void k_hash_fill(int64_t n, uint64_t seed, double* __restrict__ x) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;

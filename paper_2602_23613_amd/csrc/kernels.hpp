@@ -176,6 +176,11 @@ void cg_scalar(double* sc, int mode, int flexible, hipStream_t st);
 void cg_dir(int64_t n, const double* sc, const double* z, double* p, int first, hipStream_t st);
 int red_grid();
 
+// patch extension: one workgroup per column of P (patch of at most mmax DoFs)
+size_t ext_patch_lds(int mmax);
+void ext_patches(int64_t nc, const int64_t* pptr, const int32_t* pdofs, const int64_t* pdst,
+                 const int32_t* rd1, const int32_t* rd2, const int8_t* rs1, const int8_t* rs2,
+                 const CsrDev<double>& A, double* Pval, int mmax, int* flag, hipStream_t st);
 size_t ext_block_lds(int smax, int ctile);
 int ext_block_tile(int smax);
 void ext_blocks(int64_t b0, int64_t nb, const int64_t* bptr, const int32_t* bdofs,

@@ -23,14 +23,17 @@ from gen import fields  # noqa: E402
 from refsel import RefSelector  # noqa: E402
 
 
-def run(L, interp, schwarz):
-    p = gen.make_problem("tri", L, beta=0.01, alpha=lambda m: fields.stripes_2d(m))
+def run(L, interp, schwarz, smoother="stars", stripes=True):
+    alpha = (lambda m: fields.stripes_2d(m)) if stripes else 1.0
+    p = gen.make_problem("tri", L, beta=0.01, alpha=alpha)
     n = p.A.shape[0]
     b = np.arange(1, n + 1, dtype=float)
     x0 = np.random.default_rng(0).random(n)
     if interp == "ref":
         H = oracle.setup(p.A, p.G, interp="ref", ref_select=RefSelector(p), max_levels=L,
-                         min_coarse=0, schwarz=schwarz)
+                         min_coarse=0, schwarz=schwarz, smoother_blocks=smoother)
+    elif interp == "alg":
+        H = oracle.setup(p.A, p.G, schwarz=schwarz, smoother_blocks=smoother)
     else:
         H = oracle.setup(p.A, p.G, user=gen.geo_hierarchy("tri", L, L), schwarz=schwarz)
     _, it, _ = oracle.pcg(H, p.A, b, x0=x0)
@@ -49,6 +52,17 @@ def main():
             _, ita, conv = run(L, interp, "repeat")
             rec[str(L)][interp] = {"pcg": it, "amg": ita, "amg_conv": conv}
     g["oracle_table2_record"] = rec
+    # the alternative reading: node stars plus the interior blocks of each
+    # level's splitting; Table 2 (stripes) and Table 1 (isotropic)
+    rec2 = {"source": g.get("oracle_record_stars_interior", {}).get("source", "")}
+    for L in (4, 5):
+        rec2[str(L)] = {}
+        for interp in ("ref", "alg"):
+            for tab, stripes in (("table2", True), ("table1", False)):
+                it, _, _ = run(L, interp, "adjoint", "stars+interior", stripes)
+                _, ita, conv = run(L, interp, "repeat", "stars+interior", stripes)
+                rec2[str(L)][f"{tab}_{interp}"] = {"pcg": it, "amg": ita, "amg_conv": conv}
+    g["oracle_record_stars_interior"] = rec2
     json.dump(g, open(path, "w"), indent=1)
 
 

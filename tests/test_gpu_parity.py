@@ -296,6 +296,32 @@ def test_spmv_kernel_matches_scipy():
     assert np.max(np.abs(yt.cpu().numpy() - y) / scale) <= 1e-14
 
 
+@pytest.mark.parametrize("N", [5, 20])
+def test_spmv_dot_matches_definition(N):
+    """amg_spmv_dot: y = A x rowwise to 1e-14 of |A||x|, x^T y to
+    n eps |x|^T |A| |x| (the summation error of a dot product of n terms),
+    and a second call gives the same bits."""
+    d = dev()
+    p = gen.make_problem("hex", N, alpha=lambda m: fields.subdomain_log_uniform(m, 4, 9))
+    A = p.A
+    x = np.random.default_rng(3).standard_normal(A.shape[0])
+    rp = torch.tensor(A.indptr.astype(np.int64), device=d)
+    ci = torch.tensor(A.indices.astype(np.int32), device=d)
+    va = torch.tensor(A.data, device=d)
+    xt = torch.tensor(x, device=d)
+    yt = torch.zeros_like(xt)
+    dot = torch.zeros(1, dtype=torch.float64, device=d)
+    amglib.spmv_dot(rp, ci, va, xt, yt, dot)
+    y = A @ x
+    scale = abs(A) @ abs(x)
+    assert np.max(np.abs(yt.cpu().numpy() - y) / scale) <= 1e-14
+    n = A.shape[0]
+    assert abs(dot.item() - x @ y) <= n * EPS * (abs(x) @ scale)
+    y1, d1 = yt.clone(), dot.clone()
+    amglib.spmv_dot(rp, ci, va, xt, yt, dot)
+    assert torch.equal(yt, y1) and torch.equal(dot, d1)
+
+
 def test_numeric_resetup_matches_fresh_setup():
     """amg_resetup_numeric with a new coefficient field equals a fresh setup."""
     d = dev()

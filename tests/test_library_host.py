@@ -120,3 +120,20 @@ def test_unsorted_csr_is_rejected():
     with pytest.raises(amglib.AmgError) as e:
         amglib.level0_integers(A, p.G)
     assert e.value.status == -3
+
+
+@pytest.mark.parametrize("kind,size,cap", [("hex", 6, 128), ("hex", 6, 16), ("tri", 4, 128),
+                                           ("tet", 4, 64)])
+def test_patch_sets_bit_exact(kind, size, cap):
+    """The patch extension's per-column interior supports (integer graph work
+    on the host) equal the oracle's patch_sets."""
+    kw = dict(jitter=0.2, mesh_seed=4) if kind == "tet" else {}
+    p = gen.make_problem(kind, size, beta=1.0, alpha=lambda m: fields.subdomain_log_uniform(m, 2, 7), **kw)
+    d = amglib.level0_integers(p.A, p.G, ext_mode="patch", patch_hops=2, patch_cap=cap)
+    lv, _, _ = oracle_level0(p)
+    n = p.A.shape[0]
+    ps = amg.patch_sets(p.A, amg.r_transpose(lv.rr, n), lv.interior, hops=2, cap=cap)
+    ptr = np.concatenate([[0], np.cumsum([len(x) for x in ps])]).astype(np.int64)
+    assert np.array_equal(d["patch_ptr"], ptr)
+    assert np.array_equal(d["patch_dofs"], np.concatenate(ps))
+    assert max(len(x) for x in ps) <= cap

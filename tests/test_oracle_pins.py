@@ -317,6 +317,44 @@ def test_table2_ref_and_geo_are_not_reproduced(L):
         assert abs(rho - rec[interp]["amg_conv"]) < 1e-3
 
 
+@pytest.mark.parametrize("L", [4, 5])
+def test_smoother_readings_against_tables_1_and_2(L):
+    """Neither smoother reading reproduces both tables.  Node stars (the
+    reading the library uses) reproduce Table 1 (all three columns) and the
+    Table 2 Alg column, but not Table 2 Ref.  Node stars plus the interior
+    blocks of each level's splitting (the decoupled fine-variable blocks of
+    the matching) reproduce Table 2 Ref at L = 4 (AMG 8, PCG 6 against the
+    printed 8 and 5) but stay at AMG 8 where the paper prints 11, and they
+    break Table 1 (AMG 9 against the printed 22).  Both readings' counts are
+    recorded so that a change of either shows up here."""
+    g = _golden()
+    rec = g["oracle_record_stars_interior"][str(L)]
+    stripes = lambda m: fields.stripes_2d(m)
+    for interp in ("ref", "alg"):
+        for tab, al in (("table2", stripes), ("table1", 1.0)):
+            p = gen.make_problem("tri", L, beta=0.01, alpha=al)
+            n = p.A.shape[0]
+            b = np.arange(1, n + 1, dtype=float)
+            x0 = np.random.default_rng(0).random(n)
+            kw = dict(interp="ref", ref_select=RefSelector(p), max_levels=L, min_coarse=0) \
+                if interp == "ref" else {}
+            H = oracle.setup(p.A, p.G, smoother_blocks="stars+interior", schwarz="adjoint", **kw)
+            _, it, _ = oracle.pcg(H, p.A, b, x0=x0)
+            kw2 = dict(kw, ref_select=RefSelector(p)) if interp == "ref" else {}
+            H = oracle.setup(p.A, p.G, smoother_blocks="stars+interior", schwarz="repeat", **kw2)
+            _, ita, h = oracle.amg_solve(H, p.A, b, x0=x0)
+            r = rec[f"{tab}_{interp}"]
+            assert (it, ita) == (r["pcg"], r["amg"]), (tab, interp, it, ita)
+            assert abs(h[-1] / h[-2] - r["amg_conv"]) < 1e-3
+    printed2 = g["table2_uniform_stripes"][str(L)]
+    printed1 = g["table1_uniform_isotropic"][str(L)]
+    # what each reading matches
+    assert abs(rec["table2_ref"]["amg"] - printed2["amg_ref"]) <= (2 if L == 4 else 3)
+    assert abs(rec["table1_ref"]["amg"] - printed1["amg_ref"]) > 10
+    stars = g["oracle_table2_record"][str(L)]["ref"]
+    assert abs(stars["amg"] - printed2["amg_ref"]) > 10
+
+
 # ----------------------------------------------------------------------------
 # interpolation, theory (Section 3)
 # ----------------------------------------------------------------------------
@@ -693,3 +731,82 @@ def test_depth_ordered_extension_against_exact_interior_extension(alpha):
     print(f"two-grid factor: depth-ordered {r9:.3f}, exact P_app {ex:.3f}")
     assert ex < 0.1
     assert 0.15 < r9 < 0.3 and r9 > 2.5 * ex
+
+
+# ----------------------------------------------------------------------------
+# patch extension (per-column local harmonic extension, the 3D variant)
+# ----------------------------------------------------------------------------
+def test_patch_extension_equals_dense_ideal_formula_in_2d():
+    """2D: A_II is block diagonal (components of at most 64 DoFs), and
+    64 hops from a column's exterior DoFs reach the whole components coupled
+    to it (interior DoFs are coupled only inside their component), so the
+    per-column patch extension is eq. (sparseP) exactly (dense formula)."""
+    for alpha in (1.0, lambda m: fields.stripes_2d(m)):
+        p = gen.make_problem("tri", 3, beta=0.01, alpha=alpha)
+        H = oracle.setup(p.A, p.G, max_levels=2, ext_mode="patch", patch_hops=64,
+                         patch_cap=10 ** 6)
+        lv = H.levels[0]
+        assert lv.exact_blocks
+        n = p.A.shape[0]
+        Rt = amg.r_transpose(lv.rr, n).toarray()
+        Ad = p.A.toarray()
+        I = lv.interior
+        Pd = Rt.copy()
+        Pd[I] = Rt[I] - np.linalg.solve(Ad[np.ix_(I, I)], Ad[I] @ Rt)
+        assert np.abs(lv.P.toarray() - Pd).max() <= 1e-10 * np.abs(Pd).max()
+
+
+@pytest.mark.parametrize("cap", [16, 128])
+def test_patch_columns_are_harmonic_on_their_patch(cap):
+    """Every column x = P e_c of the patch form is A-harmonic on its patch,
+    (A x)_S = 0, has its exterior values R^T e_c, and is zero on the other
+    interior DoFs; the patch is interior, at most `cap` DoFs, and (one hop,
+    no cap) exactly the interior DoFs coupled in A to the exterior ones."""
+    p = gen.make_problem("hex", 6, beta=1.0, alpha=lambda m: fields.subdomain_log_uniform(m, 3, 5))
+    H = oracle.setup(p.A, p.G, max_levels=2, ext_mode="patch", patch_hops=2, patch_cap=cap)
+    lv = H.levels[0]
+    n = p.A.shape[0]
+    Rt = amg.r_transpose(lv.rr, n).tocsc()
+    P = lv.P.tocsc()
+    A = p.A.tocsr()
+    isint = np.zeros(n, dtype=bool)
+    isint[lv.interior] = True
+    assert len(lv.patches) == Rt.shape[1]
+    for c in range(0, Rt.shape[1], 7):
+        S = lv.patches[c]
+        assert len(S) <= cap and isint[S].all()
+        x = P[:, c].toarray().ravel()
+        ext = Rt.indices[Rt.indptr[c]:Rt.indptr[c + 1]]
+        assert np.array_equal(x[~isint], Rt[:, c].toarray().ravel()[~isint])
+        off = np.setdiff1d(np.nonzero(isint)[0], S)
+        assert not x[off].any()
+        Ax = A @ x
+        assert np.abs(Ax[S]).max() <= 1e-12 * (abs(A) @ abs(x))[S].max()
+    one = amg.patch_sets(p.A, Rt, lv.interior, hops=1, cap=10 ** 6)
+    for c in range(0, Rt.shape[1], 11):
+        ext = Rt.indices[Rt.indptr[c]:Rt.indptr[c + 1]]
+        nb = np.unique(np.concatenate([A.indices[A.indptr[e]:A.indptr[e + 1]] for e in ext]))
+        assert np.array_equal(one[c], nb[isint[nb]])
+
+
+def test_patch_extension_two_grid_factor_against_exact_extension():
+    """Hex 6^3 with jumps: the two-grid factor of the patch form lies between
+    the exact P_app's (eq. (sparseP) with the global A_II^{-1}) and the
+    depth-ordered block form's: a measurement of the 3D localisation, the
+    paper has no 3D construction."""
+    al = lambda m: fields.subdomain_log_uniform(m, 2, 5)
+    p = gen.make_problem("hex", 6, beta=1.0, alpha=al)
+    Hb = oracle.setup(p.A, p.G, max_levels=2)
+    Hp = oracle.setup(p.A, p.G, max_levels=2, ext_mode="patch")
+    lv = Hb.levels[0]
+    n = p.A.shape[0]
+    Rt = amg.r_transpose(lv.rr, n).toarray()
+    Ad = p.A.toarray()
+    I = lv.interior
+    Pex = Rt.copy()
+    Pex[I] = Rt[I] - np.linalg.solve(Ad[np.ix_(I, I)], Ad[I] @ Rt)
+    r9 = _two_grid_factor(Hb, lv.P.toarray(), p.A)
+    rp = _two_grid_factor(Hb, Hp.levels[0].P.toarray(), p.A)
+    ex = _two_grid_factor(Hb, Pex, p.A)
+    print(f"two-grid factor: exact {ex:.3f}, patch {rp:.3f}, depth-ordered blocks {r9:.3f}")
+    assert ex <= rp + 1e-9 and rp < r9
