@@ -295,6 +295,20 @@ amg_status amg_spmv(const amg_csr *A, const double *x, double *y, void *stream);
    for bad arguments (nothing launched), AMG_ERR_HIP / AMG_ERR_OOM from HIP. */
 amg_status amg_spmv_dot(const amg_csr *A, const double *x, double *y, double *dot, void *stream);
 
+/* amg_spmv_dot for callers that cannot allocate device memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+   the same kernels and the same bits, with the partial sums in a static
+   2 MiB device array that the library holds on every device it runs on until
+   the process ends.  Allocates nothing and does not synchronize: the results
+   are ready when `stream` reaches them.  At most 262,144 partial sums, one per
+   256/lanes rows (lanes 4, 8, 16, 32 or 64 from the mean row length), e.g.
+   8.4M rows of 9-40 entries; larger A fails with AMG_ERR_LIMIT before any
+   launch.  All calls on one device share that array: calls that overlap on
+   one device (other streams, other threads) race and must be serialized by
+   the caller.  Other errors as amg_spmv_dot. */
+amg_status amg_spmv_dot_noalloc(const amg_csr *A, const double *x, double *y, double *dot,
+                                void *stream);
+
 /* Per-level sizes; writes min(cap, levels) entries and the level count. */
 amg_status amg_hier_info(const amg_hier *h, amg_level_info *lv, int cap, int *nlevels);
 

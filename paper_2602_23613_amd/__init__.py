@@ -314,13 +314,14 @@ def spmv(rowptr, colidx, val, x, y, stream=None):
     _lib.check(load().amg_spmv(C.byref(a), x.data_ptr(), y.data_ptr(), _stream(stream)))
 
 
-def spmv_dot(rowptr, colidx, val, x, y, dot, stream=None):
+def spmv_dot(rowptr, colidx, val, x, y, dot, stream=None, noalloc=False):
     """y = A x and dot[0] = x^T y (device tensors; dot a float64 tensor of one
-    entry).  Synchronizes the stream."""
+    entry).  noalloc=False: amg_spmv_dot (synchronizes the stream);
+    noalloc=True: amg_spmv_dot_noalloc (static scratch, asynchronous)."""
     n = rowptr.shape[0] - 1
     _vec(x, n, "x")
     _vec(y, n, "y")
     _vec(dot, 1, "dot")
     a = _lib.make_csr(rowptr, colidx, val, n, n)
-    _lib.check(load().amg_spmv_dot(C.byref(a), x.data_ptr(), y.data_ptr(), dot.data_ptr(),
-                                   _stream(stream)))
+    fn = load().amg_spmv_dot_noalloc if noalloc else load().amg_spmv_dot
+    _lib.check(fn(C.byref(a), x.data_ptr(), y.data_ptr(), dot.data_ptr(), _stream(stream)))

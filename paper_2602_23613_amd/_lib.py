@@ -33,7 +33,7 @@ EXPORTED = ["amg_default_options", "amg_setup", "amg_resetup_numeric", "amg_vcyc
             "amg_export_level", "amg_level0_integers", "amg_free_integers", "amg_destroy",
             "amg_last_error", "amg_mlp_nparams", "amg_mlp_train", "amg_mlp_use", "amg_mlp_stats_get",
             "amg_mlp_params", "amg_mlp_forward", "amg_mlp_backward", "amg_mlp_loss_grad", "amg_check",
-            "amg_cycle_solve", "amg_complexity", "amg_spmv_dot"]
+            "amg_cycle_solve", "amg_complexity", "amg_spmv_dot", "amg_spmv_dot_noalloc"]
 
 
 class AmgError(RuntimeError):
@@ -144,6 +144,7 @@ def load():
     lib.amg_complexity.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.amg_spmv.argtypes = [C.POINTER(amg_csr), P, P, P]
     lib.amg_spmv_dot.argtypes = [C.POINTER(amg_csr), P, P, P, P]
+    lib.amg_spmv_dot_noalloc.argtypes = [C.POINTER(amg_csr), P, P, P, P]
     lib.amg_smoother_sweep.argtypes = [P, C.c_int, C.c_int, P, P, C.c_int, P]
     lib.amg_check.argtypes = [P, P]
     lib.amg_hier_info.argtypes = [P, C.POINTER(amg_level_info), C.c_int, C.POINTER(C.c_int)]
@@ -167,7 +168,7 @@ def load():
     lib.amg_mlp_backward.argtypes = [P, P, C.c_int64, P, P, P]
     lib.amg_mlp_loss_grad.argtypes = [P, P, P, C.c_int64, C.c_int64, P, P, P]
     for name in ("amg_setup", "amg_resetup_numeric", "amg_vcycle", "amg_pcg_solve", "amg_spmv",
-                 "amg_spmv_dot",
+                 "amg_spmv_dot", "amg_spmv_dot_noalloc",
                  "amg_cycle_solve", "amg_complexity",
                  "amg_smoother_sweep", "amg_check",
                  "amg_hier_info", "amg_export_integers", "amg_export_level",

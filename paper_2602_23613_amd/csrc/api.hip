@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1906,6 +1907,54 @@ amg_status amg_spmv_dot(const amg_csr* A, const double* x, double* y, double* do
     (void)hipFree(partial);
     HIPC(e);
     HIPC(es);
+    return AMG_OK;
+  });
+}
+
+// Scratch of amg_spmv_dot_noalloc: its per-workgroup partial sums (2 MiB).
+// Each device holds its own copy until the process ends; host code uses the
+// per-device address from hipGetSymbolAddress, never the name itself.
+constexpr int64_t NOALLOC_PARTIALS = int64_t(1) << 18;
+static __device__ __align__(256) double scratch[NOALLOC_PARTIALS];
+
+double* noalloc_scratch() {
+  static std::mutex mu;
+  static std::vector<double*> addr;   // by device id
+  int dev = 0;
+  HIPC(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    HIPC(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    addr[dev] = (double*)p;
+  }
+  return addr[dev];
+}
+
+amg_status amg_spmv_dot_noalloc(const amg_csr* A, const double* x, double* y, double* dot,
+                                void* stream) {
+  return guarded([&]() -> amg_status {
+    validate_csr_arg(A, "A");
+    if (!A->on_device) fail(AMG_ERR_ARG, "amg_spmv_dot_noalloc needs device CSR arrays");
+    if (A->nrows != A->ncols) fail(AMG_ERR_SHAPE, "A is not square");
+    if (!x || !y || !dot) fail(AMG_ERR_ARG, "NULL vector");
+    CsrDev<double> M;
+    M.n = A->nrows; M.m = A->ncols; M.nnz = A->nnz;
+    M.ptr = A->rowptr; M.col = A->colidx; M.val = A->val;
+    M.lpr = lpr_for(M.n, M.nnz);
+    const int64_t np = spmv_dot_partials(M.lpr, M.n);
+    if (np > NOALLOC_PARTIALS)
+      fail(AMG_ERR_LIMIT, "amg_spmv_dot_noalloc: " + std::to_string(np) +
+                              " partial sums needed, the static scratch holds " +
+                              std::to_string(NOALLOC_PARTIALS) + " (use amg_spmv_dot)");
+    double* partial = noalloc_scratch();
+    hipStream_t st = (hipStream_t)stream;
+    // every workgroup writes its own partial and the reduction reads exactly
+    // those: nothing in the scratch has to start at zero
+    spmv_dot(M, x, y, partial, st);
+    reduce(np, partial, dot, 0, -1, st);
+    HIPC(hipGetLastError());
     return AMG_OK;
   });
 }

@@ -122,6 +122,29 @@ def test_unsorted_csr_is_rejected():
     assert e.value.status == -3
 
 
+def test_noalloc_spmv_dot_rejects_sizes_beyond_its_scratch():
+    """The allocation-free SpMV-with-dot checks its partial-sum count against
+    the static scratch before any HIP call: a 20M-row descriptor (mean row
+    length 1: 4 lanes, 64 rows per workgroup, 312,500 partials) is refused
+    with AMG_ERR_LIMIT.  Nothing is launched, so host buffers stand in for
+    device ones."""
+    import ctypes as C
+    lib = _lib.load()
+    n = 20_000_000
+    rp = np.zeros(2, dtype=np.int64)
+    ci = np.zeros(1, dtype=np.int32)
+    va = np.zeros(1)
+    a = _lib.amg_csr()
+    a.nrows, a.ncols, a.nnz = n, n, n
+    a.rowptr, a.colidx, a.val = rp.ctypes.data, ci.ctypes.data, va.ctypes.data
+    a.on_device = 1
+    buf = np.zeros(4)
+    st = lib.amg_spmv_dot_noalloc(C.byref(a), buf.ctypes.data, buf.ctypes.data,
+                                  buf.ctypes.data, None)
+    assert st == -9, _lib.STATUS.get(st, st)
+    assert b"static scratch" in lib.amg_last_error()
+
+
 @pytest.mark.parametrize("kind,size,cap", [("hex", 6, 128), ("hex", 6, 16), ("tri", 4, 128),
                                            ("tet", 4, 64)])
 def test_patch_sets_bit_exact(kind, size, cap):
