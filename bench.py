@@ -120,10 +120,13 @@ def vcycle_bytes(info):
     return tot
 
 
+EXT = {}   # extension options of every hierarchy (set from the command line)
+
+
 def one_step(amg, Ad, Gd, f, torch, prec, maxit, p_trunc=0.0):
     log(f"fp{prec}: setup + solve")
     t0 = time.perf_counter()
-    H = amg.Hierarchy(Ad, Gd, vcycle_prec=prec, p_trunc=p_trunc)
+    H = amg.Hierarchy(Ad, Gd, vcycle_prec=prec, p_trunc=p_trunc, **EXT)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     u = torch.zeros_like(f)
@@ -304,6 +307,10 @@ def main():
     ap.add_argument("--kernels-only", action="store_true",
                     help="setup once and time the V-cycle / level-0 sweep only (for profiling)")
     ap.add_argument("--cpu-baseline-worker", nargs=4, default=None)
+    ap.add_argument("--ext-mode", choices=["blocks", "patch"], default="blocks",
+                    help="interior rows of P: depth-ordered blocks, or per-column patches")
+    ap.add_argument("--patch-cap", type=int, default=128)
+    ap.add_argument("--patch-hops", type=int, default=2)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="hex-jump",
                     help="hex-jump (64^3 and 128^3 configurations) or tet-checker (jittered "
                          "tetrahedra, checkerboard coefficient)")
@@ -312,6 +319,7 @@ def main():
         N, beta, its, kind = a.cpu_baseline_worker
         cpu_baseline_worker(int(N), float(beta), int(its), kind)
         return
+    EXT.update(ext_mode=a.ext_mode, patch_cap=a.patch_cap, patch_hops=a.patch_hops)
     if a.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {a.gpus}); the multi-GPU design is "
               "described but not built", file=sys.stderr)
@@ -332,7 +340,7 @@ def main():
     del p
     torch.cuda.synchronize()
     if a.counters:
-        H = amg.Hierarchy(Ad, Gd, vcycle_prec=64, p_trunc=a.p_trunc)
+        H = amg.Hierarchy(Ad, Gd, vcycle_prec=64, p_trunc=a.p_trunc, **EXT)
         b = f.clone()
         x = torch.zeros_like(b)
         for bw in (False, True):
@@ -349,7 +357,7 @@ def main():
         H.close()
         return
     if a.kernels_only:
-        H = amg.Hierarchy(Ad, Gd, vcycle_prec=64, p_trunc=a.p_trunc)
+        H = amg.Hierarchy(Ad, Gd, vcycle_prec=64, p_trunc=a.p_trunc, **EXT)
         log("levels", [(l["n"], l["nnz"], l["ncolors"]) for l in H.info()])
         kt = time_kernels(amg, H, f, torch)
         log(f"kernels: {kt}")
