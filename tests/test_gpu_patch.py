@@ -96,11 +96,17 @@ def test_patch_interpolation_and_galerkin_values(name):
     p, Ho = case(name)
     H = amglib.Hierarchy(p.A, p.G, **OPTS)
     for l in range(len(Ho.levels) - 1):
-        _, P_l = H.level(l)
+        A_l, P_l = H.level(l)
         A_n, _ = H.level(l + 1)
         lv = Ho.levels[l]
         assert np.array_equal(P_l.indptr, lv.P.indptr) and np.array_equal(P_l.indices, lv.P.indices)
         k = patch_kappa(Ho, l)
+        # on coarse levels both sides solve with their own Galerkin A_l, which
+        # differ by delta relative to A_l's row maxima: the patch solves then
+        # agree to kappa (eps + delta)
+        rmax = np.asarray(abs(lv.A).max(axis=1).todense()).ravel()
+        rows_l = np.repeat(np.arange(lv.A.shape[0]), np.diff(lv.A.indptr))
+        delta = float(np.max(np.abs(A_l.data - lv.A.data) / rmax[rows_l]))
         # column by column, relative to the column's largest entry
         Pg = sp.csc_matrix(P_l)
         Po = sp.csc_matrix(lv.P)
@@ -114,9 +120,10 @@ def test_patch_interpolation_and_galerkin_values(name):
         scale = np.asarray(S.max(axis=1).todense()).ravel()
         rows = np.repeat(np.arange(Ao.shape[0]), np.diff(Ao.indptr))
         eA = float(np.max(np.abs(A_n.data - Ao.data) / scale[rows]))
-        print(f"level {l}: patch kappa {k:.1e}  P err {eP:.1e}  A_c err {eA:.1e}")
-        assert eP <= max(1e-13, 8 * k * EPS), (l, eP)
-        assert eA <= max(1e-13, 16 * k * EPS), (l, eA)
+        print(f"level {l}: patch kappa {k:.1e}  A_l delta {delta:.1e}  P err {eP:.1e}  "
+              f"A_c err {eA:.1e}")
+        assert eP <= max(1e-13, 8 * k * (EPS + delta)), (l, eP)
+        assert eA <= max(1e-13, 16 * k * (EPS + delta)), (l, eA)
     H.close()
 
 
