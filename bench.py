@@ -3,27 +3,37 @@
 One step = the whole hot path on one synthetic jump-coefficient problem:
 amg_setup (integer nodal coarsening + matching on the host; local harmonic
 extension, Galerkin SpGEMM, smoother factors on the GPU) followed by
-AMG-preconditioned CG to ||r|| <= 1e-8 ||f||.  Inputs (A, G, f) are resident in
-HBM before the timed region starts.
+AMG-preconditioned CG to ||f - A u|| <= 1e-8 ||f||.  Inputs (A, G, f) are
+resident in HBM before the timed region starts.
 
-Workload (default, --size 64): unit cube, 64^3 hexahedra, lowest-order
-Nedelec edge elements with Dirichlet boundary (762,048 DoFs, 24,526,920
-nonzeros), alpha piecewise constant on 8^3 subdomains of 8^3 cells with
-log10(alpha) ~ U(-4, 4) (seed 2), beta = 1, f ~ U[-1, 1] (seed 102).
---size 128 runs the 128^3 problem (6,193,536 DoFs; 8^3 subdomains of 16^3
-cells, seeds 3 / 103).  The FP64 V-cycle is the headline; the FP32-V-cycle
-form (flexible CG in FP64) is reported beside it.
+Workload (default): unit cube, 128^3 hexahedra, lowest-order Nedelec edge
+elements with Dirichlet boundary (6,193,536 DoFs, 201,867,528 nonzeros),
+alpha piecewise constant on 8^3 subdomains of 16^3 cells with
+log10(alpha) ~ U(-4, 4) (seed 3), beta = 1, f ~ U[-1, 1] (seed 103).
+--size 64 runs the 64^3 problem (762,048 DoFs; seeds 2 / 102).  The
+interior rows of P come from the per-column patch extension (--ext-mode
+patch, the default) or the depth-ordered blocks (--ext-mode blocks).
 
-Also reported: the dominant kernel (one colour launch of the level-0
-multiplicative Schwarz sweep) and the whole V-cycle against the 8 TB/s HBM
-roofline, timed with HIP events on the launch stream, and the CPU oracle on a
-bounded sample of the same workload family.
+Forms reported beside the FP64 headline (one run each, --forms):
+  fp32     FP32 V-cycle inside FP64 flexible CG, with its distance to the
+           FP64 solution
+  beta     the same mesh and field with beta = 1e-3
+  learned  re-setup on a new field with the learned local solves against the
+           exact ones (the network predicts block solves: 64^3, block form)
+  blocks   the depth-ordered block extension of P (slow at 128^3)
+  ptrunc   P truncated at 0.1 of each interior row's maximum
+
+Roofline: the sweep kernel with the largest share of the V-cycle (found at
+run time from per-level sweep times on HIP events on the launch stream) and
+the whole V-cycle against the 8 TB/s HBM peak; the CPU oracle on a bounded
+sample of the same workload family.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size 128]
 """
 import argparse
 import json
 import os
+import re
 import subprocess
 import sys
 import time
@@ -34,11 +44,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per level-0 k_schwarz<double,8,256> launch on the 64^3 workload, from the
-# rocprofv3 FETCH_SIZE / WRITE_SIZE passes (calibrated on a 1 GiB copy) summarised in
-# profiles/k_schwarz_l0_hex64_counters.md; valid for that kernel and workload only
-# (None while the kernel has changed since the counters were taken)
-SCHWARZ_L0_TRAFFIC_64 = (2.0 * 55640.8 + 3561.0) * 1024
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def log(*a):
@@ -123,54 +129,37 @@ def vcycle_bytes(info):
 EXT = {}   # extension options of every hierarchy (set from the command line)
 
 
-def one_step(amg, Ad, Gd, f, torch, prec, maxit, p_trunc=0.0):
+def one_step(amg, Ad, Gd, f, torch, prec, maxit, p_trunc=0.0, ext=None):
     log(f"fp{prec}: setup + solve")
     t0 = time.perf_counter()
-    H = amg.Hierarchy(Ad, Gd, vcycle_prec=prec, p_trunc=p_trunc, **EXT)
+    H = amg.Hierarchy(Ad, Gd, vcycle_prec=prec, p_trunc=p_trunc, **(EXT if ext is None else ext))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     u = torch.zeros_like(f)
-    try:
-        st = H.pcg(f, u, rtol=1e-8, maxit=maxit)
-    except amg.AmgError as e:
-        # the FP32 form can break down (an indefinite FP32 preconditioner);
-        # record it as not converged instead of ending the measurement
-        if prec == 64:
-            raise
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        return H, dict(setup_s=t1 - t0, solve_s=t2 - t1, total_s=t2 - t0, iterations=None,
-                       relres=None, true_relres=None, status=-1, replacements=0, error=str(e))
+    st = H.pcg(f, u, rtol=1e-8, maxit=maxit)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    return H, dict(setup_s=t1 - t0, solve_s=t2 - t1, total_s=t2 - t0, iterations=st["iterations"],
-                   relres=st["relres"], true_relres=st["true_relres"], status=st["status"],
-                   replacements=st["replacements"])
+    return H, u, dict(setup_s=t1 - t0, solve_s=t2 - t1, total_s=t2 - t0, iterations=st["iterations"],
+                      relres=st["relres"], true_relres=st["true_relres"], status=st["status"],
+                      converged=st["status"] == 0, floor_relres=st["floor_relres"],
+                      replacements=st["replacements"])
+
+
+SWEEP_KERNEL = {"colour": "k_schwarz<double,{lanes},256>", "pipe": "k_schwarz_pipe<double,{lanes}>",
+                "panel": "k_schwarz_panel<double>", "one": "k_schwarz_sweep1<double,...>",
+                "dense": "k_dense_sweep"}
 
 
 def time_kernels(amg, H, f, torch, reps=20):
-    """Level-0 Schwarz sweeps and whole V-cycles timed with HIP events on the
-    launch stream (torch's current stream, which the library is handed)."""
+    """Per-level Schwarz sweeps and whole V-cycles timed with HIP events on
+    the launch stream (torch's current stream, which the library is handed).
+    Every level runs in its own precision."""
     info = H.info()
-    li = info[0]
-    # every level runs in its own precision (the FP32 form keeps FP64 where
-    # FP32 cannot resolve a level's gradient near-kernel)
-    w = 8 if li["prec"] == 64 else 4
-    dt = torch.float64 if li["prec"] == 64 else torch.float32
-    b = f.to(dt)
-    x = torch.zeros_like(b)
-    H.sweep(0, b, x)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for k in range(reps):
-        H.sweep(0, b, x, backward=bool(k % 2))
-    e1.record()
-    torch.cuda.synchronize()
-    sweep_ms = e0.elapsed_time(e1) / reps
+    dt = lambda l: torch.float64 if info[l]["prec"] == 64 else torch.float32
     z = torch.zeros_like(f)
     H.vcycle(f, z)
     torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
         H.vcycle(f, z)
@@ -179,46 +168,69 @@ def time_kernels(amg, H, f, torch, reps=20):
     vc_ms = e0.elapsed_time(e1) / reps
     per_level = []
     for l in range(len(info) - 1):
-        dtl = torch.float64 if info[l]["prec"] == 64 else torch.float32
-        bl = torch.zeros(info[l]["n"], dtype=dtl, device=f.device) + 1
+        bl = torch.zeros(info[l]["n"], dtype=dt(l), device=f.device) + 1
         xl = torch.zeros_like(bl)
         H.sweep(l, bl, xl)
         torch.cuda.synchronize()
         e0.record()
-        for k in range(5):
+        for k in range(reps):
             H.sweep(l, bl, xl, backward=bool(k % 2))
         e1.record()
         torch.cuda.synchronize()
-        per_level.append(round(e0.elapsed_time(e1) / 5, 4))
-    log(f"sweep ms per level: {per_level}")
-    sb = sweep_bytes(li, w)
+        per_level.append(e0.elapsed_time(e1) / reps)
+    H.check()
+    log(f"sweep ms per level: {[round(x, 4) for x in per_level]}")
     vb = vcycle_bytes(info)
-    ncol = li["ncolors"]
-    launch_ms = sweep_ms / ncol
-    launch_bytes = sb / ncol
-    return dict(sweep_ms=sweep_ms, sweep_GBs=sb / (sweep_ms * 1e-3) / 1e9, sweep_bytes=sb,
-                per_level=per_level,
-                launch_ms=launch_ms, launch_bytes=launch_bytes,
-                vcycle_ms=vc_ms, vcycle_GBs=vb / (vc_ms * 1e-3) / 1e9, vcycle_bytes=vb,
-                ncolors=ncol)
+    # the dominant kernel: every level does four sweeps per V(1,1) cycle
+    dom = int(np.argmax(per_level))
+    li = info[dom]
+    w = 8 if li["prec"] == 64 else 4
+    sb = sweep_bytes(li, w)
+    form = li["sweep_form"]
+    launches = li["ncolors"] if form == "colour" else 1
+    kernel = SWEEP_KERNEL.get(form, form).format(lanes=li["sweep_lanes"]).replace("double", "double" if w == 8 else "float")
+    return dict(vcycle_ms=vc_ms, vcycle_GBs=vb / (vc_ms * 1e-3) / 1e9, vcycle_bytes=vb,
+                per_level_sweep_ms=per_level, dominant_level=dom, dominant_form=form,
+                dominant_kernel=kernel, dominant_share=4 * per_level[dom] / vc_ms,
+                sweep_ms=per_level[dom], sweep_bytes=sb, launches_per_sweep=launches,
+                launch_ms=per_level[dom] / launches, launch_bytes=sb / launches)
 
 
-def learned_form(amg, Ad, Gd, f, torch, a):
+def counters_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (a line 'traffic_bytes_per_launch:
+    <kernel> | <workload> | <bytes>' in profiles/*.md), or None when no
+    summary covers this kernel and workload."""
+    if not os.path.isdir(PROFILES):
+        return None
+    pat = re.compile(r"^traffic_bytes_per_launch:\s*(.+?)\s*\|\s*(.+?)\s*\|\s*([0-9.eE+]+)\s*$")
+    for fn in sorted(os.listdir(PROFILES)):
+        if not fn.endswith(".md"):
+            continue
+        for line in open(os.path.join(PROFILES, fn)):
+            m = pat.match(line.strip())
+            if m and m.group(1) == kernel and m.group(2) == workload:
+                return float(m.group(3))
+    return None
+
+
+def learned_form(amg, N, beta, torch, a):
     """Re-setup on a new coefficient field of the same law: exact local solves
-    against the learned surrogate.  The network is trained on the GPU on the
-    exact local solves of the headline field, then both re-setups run on a
+    against the learned surrogate (block extension: the network predicts the
+    small block solves).  The network is trained on the GPU on the exact
+    local solves of the headline field's law, then both re-setups run on a
     field drawn with another seed (same mesh, same pattern)."""
     from gen.mlp_init import init_params, flatten
-    seed_alpha = (2 if a.size <= 64 else 3) + 10
-    p2 = make_workload(a.size, a.beta, seed_f=0, kind=a.workload, variant=1)
+    p = make_workload(N, beta, kind=a.workload)
+    Ad, Gd, f = to_device(p, torch)
+    p2 = make_workload(N, beta, seed_f=0, kind=a.workload, variant=1)
     A2 = (Ad[0], Ad[1], torch.from_numpy(p2.A.data.astype(np.float64)).to(f.device), Ad[3], Ad[4])
-    del p2
-    H = amg.Hierarchy(Ad, Gd, vcycle_prec=64)
+    del p, p2
+    H = amg.Hierarchy(Ad, Gd, vcycle_prec=64, ext_mode="blocks")
     st = H.mlp_train(epochs=a.learn_epochs, batch=1024, lr=1e-3, seed=0,
                      init=flatten(init_params(0)), global_iters=a.learn_check_iters)
     log(f"learned: trained {st}")
-    out = dict(field_seed=seed_alpha if a.workload == "hex-jump" else "checkerboard, lo/hi swapped",
-               train=dict(
+    out = dict(workload=f"{N}^3 {a.workload}, block extension", train=dict(
         epochs=a.learn_epochs, batch=1024, blocks=st["blocks"], eligible=st["eligible"],
         loss_first=st["loss_first"], loss_last=st["loss_last"], train_s=st["train_seconds"],
         rho_reference=st["rho_reference"]))
@@ -252,23 +264,26 @@ def learned_form(amg, Ad, Gd, f, torch, a):
     return out
 
 
-def cpu_baseline_worker(N, beta, its, kind):
+def cpu_baseline_worker(N, beta, its, kind, ext_mode):
     """Run the oracle on a bounded sample: the same field law on an N^3 mesh,
     full setup plus `its` PCG iterations (test infrastructure timed here only)."""
     import oracle
     p = make_workload(N, beta, kind=kind)
     t0 = time.perf_counter()
-    Ho = oracle.setup(p.A, p.G)
+    Ho = oracle.setup(p.A, p.G, ext_mode=ext_mode)
     t1 = time.perf_counter()
     _, it, _ = oracle.pcg(Ho, p.A, p.f, maxit=its, rtol=1e-300)
     t2 = time.perf_counter()
     print(json.dumps(dict(n=p.A.shape[0], setup_s=t1 - t0, solve_s=t2 - t1, its=it)))
 
 
-def cpu_baseline(n_full, its_full, N=32, beta=1.0, its=30, kind="hex-jump"):
+def cpu_baseline(n_full, its_full, N=24, beta=1.0, its=30, kind="hex-jump", ext_mode="patch"):
+    # scipy's sparse products, the dense block solves and the oracle's Python
+    # loops run on one core; the worker is pinned to one thread so that the
+    # core count reported is the one used
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker", str(N), str(beta),
-           str(its), kind]
+           str(its), kind, ext_mode]
     t0 = time.perf_counter()
     out = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600, check=True)
     wall = time.perf_counter() - t0
@@ -276,10 +291,11 @@ def cpu_baseline(n_full, its_full, N=32, beta=1.0, its=30, kind="hex-jump"):
     scale = n_full / r["n"]
     est = r["setup_s"] * scale + r["solve_s"] / r["its"] * its_full * scale
     return dict(value=est, unit="s", cores=1, kind="oracle",
-                sample=(f"oracle on the same field law at {N}^3 ({kind}, {r['n']} DoFs): full setup "
-                        f"{r['setup_s']:.1f} s + {r['its']} PCG iterations {r['solve_s']:.1f} s "
-                        f"(wall {wall:.0f} s, 1 thread); scaled linearly in DoFs to {n_full} DoFs "
-                        f"and to the GPU run's {its_full} iterations"))
+                sample=(f"oracle ({ext_mode} extension) on the same field law at {N}^3 ({kind}, "
+                        f"{r['n']} DoFs): full setup {r['setup_s']:.1f} s + {r['its']} PCG "
+                        f"iterations {r['solve_s']:.1f} s (wall {wall:.0f} s, 1 thread, measured); "
+                        f"extrapolated linearly in DoFs to {n_full} DoFs and to the GPU run's "
+                        f"{its_full} iterations"))
 
 
 def main():
@@ -287,43 +303,44 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--size", type=int, default=64)
+    ap.add_argument("--size", type=int, default=128)
     ap.add_argument("--beta", type=float, default=None,
                     help="default 1 (hex-jump) or 1e-2 (tet-checker)")
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--p-trunc", type=float, default=0.0,
                     help="drop interior P entries below this fraction of the row max "
                          "(an option outside the paper; 0 = the paper's P)")
+    ap.add_argument("--ext-mode", choices=["blocks", "patch"], default="patch",
+                    help="interior rows of P: per-column patches (default) or depth-ordered blocks")
+    ap.add_argument("--patch-cap", type=int, default=128)
+    ap.add_argument("--patch-hops", type=int, default=2)
+    ap.add_argument("--forms", default="fp32,beta,learned",
+                    help="comma list of fp32, beta, learned, blocks, ptrunc ('' for none)")
+    ap.add_argument("--learn-size", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--no-trunc-forms", action="store_true")
-    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learn-epochs", type=int, default=30)
     ap.add_argument("--learn-check-iters", type=int, default=10,
                     help="stand-alone V-cycles of the learned setup's global check")
     ap.add_argument("--counters", action="store_true",
-                    help="setup once, then two level-0 sweeps and a 1 GiB device copy only "
-                         "(a short program for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE passes)")
+                    help="setup once, then two sweeps of every level and a 1 GiB device copy "
+                         "only (a short program for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE passes)")
     ap.add_argument("--kernels-only", action="store_true",
-                    help="setup once and time the V-cycle / level-0 sweep only (for profiling)")
-    ap.add_argument("--cpu-baseline-worker", nargs=4, default=None)
-    ap.add_argument("--ext-mode", choices=["blocks", "patch"], default="blocks",
-                    help="interior rows of P: depth-ordered blocks, or per-column patches")
-    ap.add_argument("--patch-cap", type=int, default=128)
-    ap.add_argument("--patch-hops", type=int, default=2)
+                    help="setup once and time the V-cycle / sweeps only (for profiling)")
+    ap.add_argument("--cpu-baseline-worker", nargs=5, default=None)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="hex-jump",
                     help="hex-jump (64^3 and 128^3 configurations) or tet-checker (jittered "
                          "tetrahedra, checkerboard coefficient)")
     a = ap.parse_args()
     if a.cpu_baseline_worker:
-        N, beta, its, kind = a.cpu_baseline_worker
-        cpu_baseline_worker(int(N), float(beta), int(its), kind)
+        N, beta, its, kind, mode = a.cpu_baseline_worker
+        cpu_baseline_worker(int(N), float(beta), int(its), kind, mode)
         return
     EXT.update(ext_mode=a.ext_mode, patch_cap=a.patch_cap, patch_hops=a.patch_hops)
     if a.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {a.gpus}); the multi-GPU design is "
               "described but not built", file=sys.stderr)
         sys.exit(2)
+    forms_wanted = [x for x in a.forms.split(",") if x]
     # progress lines from the library (setup phases, every 100 PCG iterations) on stderr
     os.environ.setdefault("HCURL_AMG_VERBOSE", "1")
     import torch
@@ -339,86 +356,130 @@ def main():
     Ad, Gd, f = to_device(p, torch)
     del p
     torch.cuda.synchronize()
+    wl_name = f"{a.workload} {a.size}^3 beta={a.beta:g} {a.ext_mode}"
     if a.counters:
         H = amg.Hierarchy(Ad, Gd, vcycle_prec=64, p_trunc=a.p_trunc, **EXT)
-        b = f.clone()
-        x = torch.zeros_like(b)
-        for bw in (False, True):
-            H.sweep(0, b, x, backward=bw)
+        info = H.info()
+        for l in range(len(info) - 1):
+            b = torch.ones(info[l]["n"], dtype=torch.float64, device=f.device)
+            x = torch.zeros_like(b)
+            for bw in (False, True):
+                H.sweep(l, b, x, backward=bw)
         # calibration: a plain copy of known size (reads 1 GiB, writes 1 GiB)
         src = torch.ones(1 << 27, dtype=torch.float64, device=f.device)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        li = H.info()[0]
-        print(json.dumps({"counters": True, "level0_sweep_bytes": sweep_bytes(li, 8),
-                          "level0_colours": li["ncolors"], "copy_bytes_each_way": src.numel() * 8}),
-              flush=True)
+        H.check()
+        print(json.dumps({"counters": True, "workload": wl_name,
+                          "levels": [dict(n=li["n"], form=li["sweep_form"], lanes=li["sweep_lanes"],
+                                          colours=li["ncolors"], sweep_bytes=sweep_bytes(li, 8))
+                                     for li in info[:-1]],
+                          "copy_bytes_each_way": src.numel() * 8}), flush=True)
         H.close()
         return
     if a.kernels_only:
         H = amg.Hierarchy(Ad, Gd, vcycle_prec=64, p_trunc=a.p_trunc, **EXT)
-        log("levels", [(l["n"], l["nnz"], l["ncolors"]) for l in H.info()])
+        log("levels", [(l["n"], l["nnz"], l["ncolors"], l["sweep_form"]) for l in H.info()])
         kt = time_kernels(amg, H, f, torch)
         log(f"kernels: {kt}")
-        print(json.dumps({"kernels_only": kt, "levels": H.info()}), flush=True)
+        print(json.dumps({"kernels_only": kt, "workload": wl_name, "levels": H.info()}), flush=True)
         H.close()
         return
-    forms = {}
-    headline = None
-    plan = [("fp64_vcycle", 64, a.p_trunc, True)]
-    if not a.no_fp32:
-        plan.append(("fp32_vcycle", 32, a.p_trunc, False))
-    if not a.no_trunc_forms and a.p_trunc == 0.0:
-        plan.append(("fp64_vcycle_ptrunc0.1", 64, 0.1, False))
-        if not a.no_fp32:
-            plan.append(("fp32_vcycle_ptrunc0.1", 32, 0.1, False))
-    fp64_its = {}
-    for name, prec, tau, is_head in plan:
-        steps = a.steps if is_head else 1
-        warm = a.warmup if is_head else 0
-        # the FP32 form may not resolve the near-kernel: cap it at 2x the FP64 count
-        maxit = a.maxit if prec == 64 else max(100, 2 * fp64_its.get(tau, a.maxit))
-        for w in range(warm):
-            H, r = one_step(amg, Ad, Gd, f, torch, prec, maxit, tau)
-            H.close()
-            log(f"{name} warmup {w}: {r}")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        runs = []
-        H = None
-        for k in range(steps):
-            if H is not None:
-                H.close()
-            H, r = one_step(amg, Ad, Gd, f, torch, prec, maxit, tau)
-            runs.append(r)
-            log(f"{name} step {k}: {r}")
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        if prec == 64:
-            fp64_its[tau] = runs[-1]["iterations"]
-        extra = {"error": runs[-1]["error"]} if "error" in runs[-1] else {}
-        kt = time_kernels(amg, H, f, torch)
-        log(f"{name} kernels: {kt}")
-        info = H.info()
-        forms[name] = dict(
-            seconds=(t1 - t0) / steps, setup_s=float(np.mean([r["setup_s"] for r in runs])),
-            solve_s=float(np.mean([r["solve_s"] for r in runs])), iterations=runs[-1]["iterations"],
-            converged=runs[-1]["status"] == 0, relres=runs[-1]["relres"],
-            true_relres=runs[-1]["true_relres"], replacements=runs[-1]["replacements"],
-            p_trunc=tau, vcycle_ms=kt["vcycle_ms"],
-            vcycle_GBs=kt["vcycle_GBs"], vcycle_hbm_frac=kt["vcycle_GBs"] / HBM_PEAK_GBS,
-            level0_sweep_ms=kt["sweep_ms"], level0_sweep_GBs=kt["sweep_GBs"],
-            sweep_ms_per_level=kt["per_level"],
-            levels=[l["n"] for l in info], oc=sum(l["nnz"] for l in info) / info[0]["nnz"],
-            sweep_forms=[l["sweep_form"] for l in info[:-1]], **extra)
-        if is_head:
-            headline = (t1 - t0) / steps, runs, kt, info[0]
+    # ---- headline: K timed steps of setup + FP64 PCG ----
+    for w in range(a.warmup):
+        H, _, r = one_step(amg, Ad, Gd, f, torch, 64, a.maxit, a.p_trunc)
         H.close()
-    if not a.no_learned and a.p_trunc == 0.0:
-        forms["learned_resetup"] = learned_form(amg, Ad, Gd, f, torch, a)
-    value, runs, kt, li0 = headline
-    l0_lanes, l0_form = li0["sweep_lanes"], li0["sweep_form"]
+        log(f"warmup {w}: {r}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = []
+    H = u64 = None
+    for k in range(a.steps):
+        if H is not None:
+            H.close()
+        H, u64, r = one_step(amg, Ad, Gd, f, torch, 64, a.maxit, a.p_trunc)
+        runs.append(r)
+        log(f"step {k}: {r}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    value = (t1 - t0) / a.steps
+    kt = time_kernels(amg, H, f, torch)
+    log(f"kernels: {kt}")
+    info = H.info()
+    oc, gc = H.complexity()
+    H.close()
+    headline = dict(runs[-1], levels=[l["n"] for l in info], nnz=[l["nnz"] for l in info],
+                    oc=oc, gc=gc, sweep_forms=[l["sweep_form"] for l in info[:-1]],
+                    vcycle_ms=kt["vcycle_ms"], vcycle_GBs=kt["vcycle_GBs"],
+                    vcycle_hbm_frac=kt["vcycle_GBs"] / HBM_PEAK_GBS,
+                    sweep_ms_per_level=[round(x, 4) for x in kt["per_level_sweep_ms"]])
+    forms = {"fp64_vcycle": headline}
+    # ---- forms: one run each (a failure is recorded, not fatal) ----
+    def attempt(name, fn):
+        try:
+            fn()
+        except Exception as e:
+            forms[name] = {"error": str(e)[:300]}
+            log(f"{name}: {e}")
+
+    def form_fp32():
+        H32, u32, r = one_step(amg, Ad, Gd, f, torch, 32, max(200, 3 * runs[-1]["iterations"]),
+                               a.p_trunc)
+        info32 = H32.info()
+        kt32 = time_kernels(amg, H32, f, torch)
+        H32.close()
+        err = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
+        forms["fp32_vcycle"] = dict(r, rel_diff_to_fp64_solution=err,
+                                    level_prec=[l["prec"] for l in info32],
+                                    vcycle_ms=kt32["vcycle_ms"],
+                                    sweep_ms_per_level=[round(x, 4) for x in kt32["per_level_sweep_ms"]])
+        del u32
+        log(f"fp32 form: {forms['fp32_vcycle']}")
+
+    def form_blocks():
+        Hb, _, r = one_step(amg, Ad, Gd, f, torch, 64, a.maxit, a.p_trunc,
+                            ext=dict(ext_mode="blocks"))
+        ktb = time_kernels(amg, Hb, f, torch)
+        ocb, _ = Hb.complexity()
+        Hb.close()
+        forms["fp64_blocks"] = dict(r, oc=ocb, vcycle_ms=ktb["vcycle_ms"])
+        log(f"block extension: {forms['fp64_blocks']}")
+
+    def form_ptrunc():
+        Ht, _, r = one_step(amg, Ad, Gd, f, torch, 64, a.maxit, 0.1)
+        ktt = time_kernels(amg, Ht, f, torch)
+        oct_, _ = Ht.complexity()
+        Ht.close()
+        forms["fp64_ptrunc0.1"] = dict(r, oc=oct_, vcycle_ms=ktt["vcycle_ms"])
+        log(f"truncated P: {forms['fp64_ptrunc0.1']}")
+
+    def form_beta():
+        pb = make_workload(a.size, 1e-3, kind=a.workload)
+        Ab = (Ad[0], Ad[1], torch.from_numpy(pb.A.data.astype(np.float64)).to(f.device), Ad[3], Ad[4])
+        del pb
+        Hb, _, r = one_step(amg, Ab, Gd, f, torch, 64, a.maxit, a.p_trunc)
+        Hb.close()
+        del Ab
+        forms["fp64_beta1e-3"] = r
+        log(f"beta = 1e-3: {r}")
+
+    def form_learned():
+        forms["learned_resetup"] = learned_form(amg, min(a.size, a.learn_size), a.beta, torch, a)
+
+    if "fp32" in forms_wanted:
+        attempt("fp32_vcycle", form_fp32)
+    if "blocks" in forms_wanted and a.ext_mode != "blocks":
+        attempt("fp64_blocks", form_blocks)
+    if "ptrunc" in forms_wanted and a.p_trunc == 0.0:
+        attempt("fp64_ptrunc0.1", form_ptrunc)
+    if "beta" in forms_wanted and a.workload == "hex-jump":
+        attempt("fp64_beta1e-3", form_beta)
+    del u64
+    if "learned" in forms_wanted and a.p_trunc == 0.0:
+        attempt("learned_resetup", form_learned)
+    traffic = counters_traffic(kt["dominant_kernel"], wl_name)
+    achieved = kt["launch_bytes"] / (kt["launch_ms"] * 1e-3) / 1e9
     out = {
         "metric": "s to 1e-8 rel. residual + V-cycle HBM GB/s; FP32/learned vs FP64 on GPU",
         "value": value, "unit": "s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -428,24 +489,25 @@ def main():
                                + f", beta={a.beta}, f~U[-1,1], PCG to 1e-8",
                    "n": n, "nnz": nnz, "setup_s": runs[-1]["setup_s"], "solve_s": runs[-1]["solve_s"],
                    "pcg_iterations": runs[-1]["iterations"], "true_relres": runs[-1]["true_relres"],
-                   "interp": "algebraic (Alg. 1-3), local harmonic extension P, p_trunc=%g" % a.p_trunc,
+                   "converged": runs[-1]["converged"], "floor_relres": runs[-1]["floor_relres"],
+                   "interp": (f"algebraic (Alg. 1-3); P interior rows by {a.ext_mode} extension"
+                              + (f" (patch cap {a.patch_cap}, {a.patch_hops} hops)"
+                                 if a.ext_mode == "patch" else "") + f", p_trunc={a.p_trunc:g}"),
                    "timed": "amg_setup + amg_pcg_solve to 1e-8, inputs resident in HBM"},
         "forms": forms,
-        "roofline": {"bound": "hbm", "achieved": kt["launch_bytes"] / (kt["launch_ms"] * 1e-3) / 1e9,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": kt["launch_bytes"] / (kt["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": (SCHWARZ_L0_TRAFFIC_64 if a.workload == "hex-jump" and a.size == 64
-                                 and a.p_trunc == 0.0 else None),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "bytes per launch",
-                     "kernel": (f"k_schwarz<double,{l0_lanes},256> (level-0 colour launch)"
-                                if l0_form == "colour" else f"level-0 sweep ({l0_form} form)"),
-                     "bytes_per_launch": kt["launch_bytes"], "launch_ms": kt["launch_ms"]},
+                     "kernel": kt["dominant_kernel"],
+                     "kernel_role": (f"level-{kt['dominant_level']} Schwarz sweep ({kt['dominant_form']} "
+                                     f"form), {100 * kt['dominant_share']:.0f}% of the V-cycle"),
+                     "bytes_per_launch": kt["launch_bytes"], "launch_ms": kt["launch_ms"],
+                     "vcycle_GBs": kt["vcycle_GBs"], "vcycle_frac": kt["vcycle_GBs"] / HBM_PEAK_GBS},
     }
     if not a.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(n, runs[-1]["iterations"], beta=a.beta,
-                                               N=32 if a.workload == "hex-jump" else 24,
-                                               kind=a.workload)
+                                               N=24, kind=a.workload, ext_mode=a.ext_mode)
         except Exception as e:   # the baseline is reported, never required
             out["cpu_baseline"] = {"value": None, "error": str(e)[:200]}
     print(json.dumps(out), flush=True)
