@@ -2,6 +2,7 @@
 #include "host_setup.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -25,6 +26,23 @@ unsigned host_threads() {
   }
   return hw;
 }
+
+// HCURL_AMG_VERBOSE=2: wall time of every step of the integer phase on stderr
+struct StepClock {
+  bool on;
+  std::chrono::steady_clock::time_point t;
+  StepClock() : t(std::chrono::steady_clock::now()) {
+    const char* e = std::getenv("HCURL_AMG_VERBOSE");
+    on = e && std::atoi(e) >= 2;
+  }
+  void mark(const char* what) {
+    if (!on) return;
+    auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[amg]   host %-30s %8.3f s\n", what,
+                 std::chrono::duration<double>(now - t).count());
+    t = now;
+  }
+};
 
 void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& body) {
   unsigned hw = host_threads();
@@ -502,7 +520,8 @@ void coarse_gradient(const Incidence& G, LevelInts& L) {
 // groups by BFS depth from the coarse/path nodes), then the structural
 // pattern of P.
 void extension_and_pattern(const Pattern& A, const Incidence& Gt, const EdgeGraph& E,
-                           const std::vector<int32_t>& sources, int ext_block_max, LevelInts& L) {
+                           const std::vector<int32_t>& sources, int ext_block_max, LevelInts& L,
+                           bool want_pattern) {
   int64_t n = A.n;
   int64_t nc = (int64_t)L.r_dof1.size();
   std::vector<char> isint(n, 0);
@@ -602,6 +621,7 @@ void extension_and_pattern(const Pattern& A, const Incidence& Gt, const EdgeGrap
   for (int64_t s = 0; s < nst; ++s)
     for (int64_t b = L.stage_ptr[s]; b < L.stage_ptr[s + 1]; ++b)
       for (int64_t t = L.block_ptr[b]; t < L.block_ptr[b + 1]; ++t) L.dof_stage[L.block_dofs[t]] = (int32_t)s;
+  if (!want_pattern) return;   // the patch extension builds its own pattern
   // --- structural pattern of P: exterior rows from R^T; a block's rows share
   //     the union of the done-row patterns reached through A ---
   std::vector<std::vector<int32_t>> rowcols(n);
@@ -661,6 +681,7 @@ void extension_and_pattern(const Pattern& A, const Incidence& Gt, const EdgeGrap
 // row i holds the columns c with i in S_c (ascending), exterior rows keep
 // their R^T entry; patch_dst maps every (c, i) to its entry of P.
 void patch_extension_pattern(const Pattern& A, int hops, int cap, LevelInts& L) {
+  StepClock clk;
   const int64_t n = A.n;
   const int64_t nc = (int64_t)L.r_dof1.size();
   std::vector<char> isint(n, 0);
@@ -700,6 +721,7 @@ void patch_extension_pattern(const Pattern& A, int hops, int cap, LevelInts& L) 
       sets[c] = S;
     }
   });
+  clk.mark("patch supports");
   L.patch = true;
   L.patch_ptr.assign(nc + 1, 0);
   L.patch_max = 0;
@@ -710,35 +732,66 @@ void patch_extension_pattern(const Pattern& A, int hops, int cap, LevelInts& L) 
   L.patch_dofs.resize(L.patch_ptr[nc]);
   for (int64_t c = 0; c < nc; ++c)
     std::copy(sets[c].begin(), sets[c].end(), L.patch_dofs.begin() + L.patch_ptr[c]);
-  // P's pattern: exterior rows one entry, interior rows one per patch holding them
+  // P's pattern: exterior rows one entry, interior rows one per patch holding
+  // them, in ascending column order.  A parallel transpose of the patch lists:
+  // thread t takes columns [c0(t), c1(t)) and counts its entries per row; a
+  // row's entries from thread t follow those of threads < t, so every row
+  // comes out sorted without a sort.
   Pattern& P = L.p;
   P.n = n;
   P.m = nc;
+  const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), nc / 4096));
+  const int64_t chunk = (nc + nt - 1) / std::max(nt, 1);
+  std::vector<std::vector<int32_t>> cnt(nt);
+  auto run_threads = [&](const std::function<void(int)>& body) {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) th.emplace_back(body, t);
+    for (auto& x : th) x.join();
+  };
+  run_threads([&](int t) {
+    cnt[t].assign(n, 0);
+    const int64_t c0 = std::min(nc, t * chunk), c1 = std::min(nc, c0 + chunk);
+    for (int64_t q = L.patch_ptr[c0]; q < L.patch_ptr[c1]; ++q) ++cnt[t][L.patch_dofs[q]];
+  });
+  std::vector<char> ext(n, 0);
+  for (int64_t c = 0; c < nc; ++c) ext[L.r_dof1[c]] = ext[L.r_dof2[c]] = 1;
   P.ptr.assign(n + 1, 0);
-  for (int64_t c = 0; c < nc; ++c) {
-    P.ptr[L.r_dof1[c] + 1] = 1;
-    P.ptr[L.r_dof2[c] + 1] = 1;
+  for (int64_t e = 0; e < n; ++e) {
+    int64_t len = ext[e];
+    for (int t = 0; t < nt; ++t) len += cnt[t][e];
+    P.ptr[e + 1] = P.ptr[e] + len;
   }
-  for (int32_t j : L.patch_dofs) P.ptr[j + 1] += 1;
-  for (int64_t e = 0; e < n; ++e) P.ptr[e + 1] += P.ptr[e];
+  // per-thread start of each row's run (relative to the row), in place of the counts
+  parallel_for(n, [&](int64_t lo, int64_t hi) {
+    for (int64_t e = lo; e < hi; ++e) {
+      int32_t acc = ext[e];
+      for (int t = 0; t < nt; ++t) {
+        const int32_t c = cnt[t][e];
+        cnt[t][e] = acc;
+        acc += c;
+      }
+    }
+  });
   P.idx.assign(P.ptr[n], 0);
   L.p_ext_sign.assign(P.ptr[n], 0);
-  std::vector<int64_t> pos(P.ptr.begin(), P.ptr.end() - 1);
   for (int64_t c = 0; c < nc; ++c) {
     P.idx[P.ptr[L.r_dof1[c]]] = (int32_t)c;
     L.p_ext_sign[P.ptr[L.r_dof1[c]]] = L.r_s1[c];
     P.idx[P.ptr[L.r_dof2[c]]] = (int32_t)c;
     L.p_ext_sign[P.ptr[L.r_dof2[c]]] = L.r_s2[c];
   }
-  // columns are visited in ascending order, so every interior row comes out sorted
   L.patch_dst.resize(L.patch_dofs.size());
-  for (int64_t c = 0; c < nc; ++c)
-    for (int64_t q = L.patch_ptr[c]; q < L.patch_ptr[c + 1]; ++q) {
-      const int32_t j = L.patch_dofs[q];
-      const int64_t d = pos[j]++;
-      P.idx[d] = (int32_t)c;
-      L.patch_dst[q] = d;
-    }
+  run_threads([&](int t) {
+    const int64_t c0 = std::min(nc, t * chunk), c1 = std::min(nc, c0 + chunk);
+    for (int64_t c = c0; c < c1; ++c)
+      for (int64_t q = L.patch_ptr[c]; q < L.patch_ptr[c + 1]; ++q) {
+        const int32_t j = L.patch_dofs[q];
+        const int64_t d = P.ptr[j] + cnt[t][j]++;
+        P.idx[d] = (int32_t)c;
+        L.patch_dst[q] = d;
+      }
+  });
+  clk.mark("P pattern from the patches");
   // no depth stages: every interior DoF is extended in one pass
   L.stage_ptr.assign(1, 0);
   for (int32_t e : L.interior) L.dof_stage[e] = 0;
@@ -793,11 +846,13 @@ void stars_and_colours(const Pattern& A, const Incidence& G, LevelInts& L) {
 bool setup_level_integers(const Pattern& A, const Incidence& G, const Pattern& S, bool use_ref,
                           const std::vector<int32_t>& ref_cg, const std::vector<int32_t>& ref_bnd,
                           const ExtOptions& ext, LevelInts& L, HostError& err) {
+  StepClock clk;
   L.n = A.n;
   L.m_real = G.m;
   Incidence Gt;
   std::vector<int32_t> B;
   augment_g(G, Gt, B);
+  clk.mark("augmentG");
   L.n_art = (int64_t)B.size();
   if (S.n != Gt.m) {
     err = {-2, "nodal graph size does not match G~"};
@@ -836,25 +891,40 @@ bool setup_level_integers(const Pattern& A, const Incidence& G, const Pattern& S
     Cp = L.cg;
     Cp.insert(Cp.end(), B.begin(), B.end());
   }
+  clk.mark("C/F splitting");
   std::sort(Cp.begin(), Cp.end());
   Cp.erase(std::unique(Cp.begin(), Cp.end()), Cp.end());
   EdgeGraph E = edge_graph(Gt);
+  clk.mark("edge graph");
   L.r_dof1.clear(); L.r_dof2.clear(); L.r_s1.clear(); L.r_s2.clear();
   L.r_i.clear(); L.r_j.clear(); L.r_k.clear();
   form_r(Gt, E, Cp, isB, skip_bb, L);
+  clk.mark("matching (Alg. 3)");
   if (L.r_dof1.empty()) return true;
   std::vector<int32_t> sources = Cp;
   sources.insert(sources.end(), L.r_k.begin(), L.r_k.end());
   std::sort(sources.begin(), sources.end());
   sources.erase(std::unique(sources.begin(), sources.end()), sources.end());
-  extension_and_pattern(A, Gt, E, sources, ext.ext_block_max, L);
   L.patch = false;
   L.patch_ptr.clear();
   L.patch_dofs.clear();
   L.patch_dst.clear();
   L.patch_max = 0;
-  if (ext.ext_mode == 1) patch_extension_pattern(A, ext.patch_hops, ext.patch_cap, L);
+  if (ext.ext_mode == 1) {
+    // no blocks of A_II: every interior DoF is extended through the patches
+    L.exact_blocks = false;
+    L.block_ptr.assign(1, 0);
+    L.block_dofs.clear();
+    L.block_depth.clear();
+    L.dof_stage.assign(A.n, -1);
+    patch_extension_pattern(A, ext.patch_hops, ext.patch_cap, L);
+    clk.mark("patches + P pattern");
+  } else {
+    extension_and_pattern(A, Gt, E, sources, ext.ext_block_max, L, true);
+    clk.mark("extension blocks + P pattern");
+  }
   coarse_gradient(G, L);
+  clk.mark("coarse gradient");
   return true;
 }
 
