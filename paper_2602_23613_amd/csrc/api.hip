@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <future>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -1578,6 +1579,16 @@ amg_status amg_setup(const amg_csr* A, const amg_csr* G, const amg_options* opt,
       Level& L = h->lv[l];
       bool stop = user ? (l >= o.user_nlevels || l + 1 >= o.max_levels)
                        : ((l + 1 >= o.max_levels) || (L.n <= o.min_coarse));
+      // the smoother's node stars and colouring need only A_l's pattern and
+      // G_l: a second host thread builds them while this one does the
+      // coarsening (both are sequential passes)
+      std::future<LevelInts> stars_f;
+      if (!stop)
+        stars_f = std::async(std::launch::async, [&L]() {
+          LevelInts s;
+          stars_and_colours(L.Apat, L.G, s);
+          return s;
+        });
       if (!stop && user) {
         load_user_interp(h.get(), L, o.user_P[l], l, st);
       } else if (!stop) {
@@ -1599,7 +1610,13 @@ amg_status amg_setup(const amg_csr* A, const amg_csr* G, const amg_options* opt,
         if (l == 0 && L.n > 8192) fail(AMG_ERR_COARSEN, "no coarse variables on the finest level");
         break;
       }
-      stars_and_colours(L.Apat, L.G, L.ints);
+      {
+        LevelInts s = stars_f.get();
+        L.ints.star_ptr = std::move(s.star_ptr);
+        L.ints.star_dofs = std::move(s.star_dofs);
+        L.ints.star_color = std::move(s.star_color);
+        L.ints.ncolors = s.ncolors;
+      }
       build_smoother(h.get(), L, st);
       clk.mark(st, "smoother stars + colours", l);
       factor_smoother(h.get(), L, l, st);
