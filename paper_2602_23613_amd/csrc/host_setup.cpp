@@ -344,6 +344,53 @@ Pattern nodal_graph_coarse(const Pattern& Sf, const std::vector<int32_t>& fine_o
 // largest measure (smallest id on ties) becomes C, its undecided
 // neighbours F; undecided neighbours of new F nodes gain one.  Buckets of
 // min-heaps with lazy deletion give exactly that selection order.
+namespace {
+
+// Sets of node ids, one per measure value, as two-level bitmaps: insert and
+// erase in O(1), the smallest id of a set by scanning the set's summary words
+// from a lower bound kept per set.  Replaces a heap per measure with lazy
+// deletion (the same selection: largest measure, then smallest id).
+struct MeasureSets {
+  int64_t words = 0, sums = 0;
+  std::vector<uint64_t> bits;     // per set: `words` words over the ids
+  std::vector<uint64_t> sum;      // per set: bit w set iff bits word w is nonzero
+  std::vector<int64_t> count;     // ids per set
+  std::vector<int64_t> hint;      // per set: no nonzero summary word below this one
+  MeasureSets(int64_t n, int nsets) {
+    words = (n + 63) / 64;
+    sums = (words + 63) / 64;
+    bits.assign((size_t)nsets * words, 0);
+    sum.assign((size_t)nsets * sums, 0);
+    count.assign(nsets, 0);
+    hint.assign(nsets, sums);
+  }
+  void insert(int s, int64_t i) {
+    const int64_t w = i >> 6;
+    uint64_t& b = bits[(size_t)s * words + w];
+    if (b == 0) sum[(size_t)s * sums + (w >> 6)] |= uint64_t(1) << (w & 63);
+    b |= uint64_t(1) << (i & 63);
+    ++count[s];
+    hint[s] = std::min(hint[s], w >> 6);
+  }
+  void erase(int s, int64_t i) {
+    const int64_t w = i >> 6;
+    uint64_t& b = bits[(size_t)s * words + w];
+    b &= ~(uint64_t(1) << (i & 63));
+    if (b == 0) sum[(size_t)s * sums + (w >> 6)] &= ~(uint64_t(1) << (w & 63));
+    --count[s];
+  }
+  int64_t smallest(int s) {
+    const uint64_t* sm = &sum[(size_t)s * sums];
+    int64_t k = hint[s];
+    while (sm[k] == 0) ++k;   // count[s] > 0: some summary word is nonzero
+    hint[s] = k;
+    const int64_t w = (k << 6) + __builtin_ctzll(sm[k]);
+    return (w << 6) + __builtin_ctzll(bits[(size_t)s * words + w]);
+  }
+};
+
+}  // namespace
+
 std::vector<int8_t> rs_first_pass(const Pattern& S, const std::vector<int32_t>& c_ini,
                                   const std::vector<int32_t>& f_ini) {
   const int8_t U = 0, C = 1, F = 2;
@@ -354,8 +401,8 @@ std::vector<int8_t> rs_first_pass(const Pattern& S, const std::vector<int32_t>& 
   std::vector<int32_t> lam(n, 0);
   int64_t maxdeg = 0;
   for (int64_t i = 0; i < n; ++i) maxdeg = std::max<int64_t>(maxdeg, S.ptr[i + 1] - S.ptr[i]);
-  using MinHeap = std::priority_queue<int32_t, std::vector<int32_t>, std::greater<int32_t>>;
-  std::vector<MinHeap> bucket(2 * maxdeg + 2);
+  // the measure |N_U| + 2 |N_F| of an undecided node never exceeds 2 deg
+  MeasureSets sets(n, (int)(2 * maxdeg + 2));
   int64_t top = -1;
   for (int64_t i = 0; i < n; ++i) {
     if (st[i] != U) continue;
@@ -365,24 +412,24 @@ std::vector<int8_t> rs_first_pass(const Pattern& S, const std::vector<int32_t>& 
       l += (s == U) ? 1 : (s == F ? 2 : 0);
     }
     lam[i] = l;
-    bucket[l].push((int32_t)i);
+    sets.insert(l, i);
     top = std::max<int64_t>(top, l);
   }
   std::vector<int32_t> newf;
   while (top >= 0) {
-    if (bucket[top].empty()) {
+    if (sets.count[top] == 0) {
       --top;
       continue;
     }
-    int32_t i = bucket[top].top();
-    bucket[top].pop();
-    if (st[i] != U || lam[i] != top) continue;
+    const int32_t i = (int32_t)sets.smallest((int)top);
+    sets.erase((int)top, i);
     st[i] = C;
     newf.clear();
     for (int64_t t = S.ptr[i]; t < S.ptr[i + 1]; ++t) {
       int32_t j = S.idx[t];
       if (st[j] == U) {
         st[j] = F;
+        sets.erase(lam[j], j);
         newf.push_back(j);
       }
     }
@@ -390,8 +437,9 @@ std::vector<int8_t> rs_first_pass(const Pattern& S, const std::vector<int32_t>& 
       for (int64_t t = S.ptr[j]; t < S.ptr[j + 1]; ++t) {
         int32_t m = S.idx[t];
         if (st[m] == U) {
+          sets.erase(lam[m], m);
           ++lam[m];
-          bucket[lam[m]].push(m);
+          sets.insert(lam[m], m);
           if (lam[m] > top) top = lam[m];
         }
       }

@@ -202,9 +202,10 @@ struct ChunkRegs {
   T v[U];
 };
 
+// everything of a chunk but its (column, value) pairs
 template <class T, int LPR, int WGS, int U>
-__device__ __forceinline__ void chunk_load(bool act, int c, int tid, const SmootherArgs<T>& D,
-                                           ChunkRegs<T, LPR, WGS, U>& R) {
+__device__ __forceinline__ void chunk_load_head(bool act, int c, int tid, const SmootherArgs<T>& D,
+                                                ChunkRegs<T, LPR, WGS, U>& R) {
   constexpr int FPT = ChunkRegs<T, LPR, WGS, U>::FPT;
   R.blk0 = R.nblk = R.r0 = R.nrows = R.nf = 0;
   R.f0 = 0;
@@ -239,6 +240,13 @@ __device__ __forceinline__ void chunk_load(bool act, int c, int tid, const Smoot
     const int t = tid + k * WGS;
     R.fv[k] = t < R.nf ? D.binv[R.f0 + t] : T(0);
   }
+}
+
+// the first U (column, value) pairs of every lane of the chunk's rows
+template <class T, int LPR, int WGS, int U>
+__device__ __forceinline__ void chunk_load_pairs(int tid, const SmootherArgs<T>& D,
+                                                 ChunkRegs<T, LPR, WGS, U>& R) {
+  const int lane = tid % LPR;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int64_t q = R.q0 + lane + (int64_t)u * LPR;
@@ -246,6 +254,13 @@ __device__ __forceinline__ void chunk_load(bool act, int c, int tid, const Smoot
     R.c[u] = in ? D.scol[q] : -1;
     R.v[u] = in ? D.sval[q] : T(0);
   }
+}
+
+template <class T, int LPR, int WGS, int U>
+__device__ __forceinline__ void chunk_load(bool act, int c, int tid, const SmootherArgs<T>& D,
+                                           ChunkRegs<T, LPR, WGS, U>& R) {
+  chunk_load_head<T, LPR, WGS, U>(act, c, tid, D, R);
+  chunk_load_pairs<T, LPR, WGS, U>(tid, D, R);
 }
 
 // Accesses of x.  COH: x is written by other workgroups while the kernel
@@ -1614,13 +1629,23 @@ void ext_blocks(int64_t b0, int64_t nb, const int64_t* bptr, const int32_t* bdof
                      wide, flag, Wl, accepted, dsq);
 }
 
-// Patch extension: one workgroup per column c of P.  The column's patch S
-// (m <= patch_max interior DoFs, ascending) gives the dense SPD system
+// Patch extension: one 256-thread workgroup per column c of P.  The column's
+// patch S (m <= mmax interior DoFs, ascending) gives the dense SPD system
 // A_SS x = -A_S,ext r_c, where r_c holds the column's two exterior values
-// (the signs of its R row).  Thread i gathers row S[i] of A: the lower-
-// triangle entries of A_SS into a packed LDS matrix (row i at i(i+1)/2) and
-// the two exterior couplings.  Right-looking Cholesky in LDS, forward and
-// back substitution, then x goes to P's entries of the column (patch_dst).
+// (the signs of its R row).
+//  * gather: the entries of the patch's rows of A are spread over all
+//    threads (a row-length prefix in LDS maps a flat index to (row, entry));
+//    lower-triangle entries of A_SS go to a packed LDS matrix (row i at
+//    i(i+1)/2), the two exterior couplings of each row to two LDS vectors;
+//  * Cholesky in blocks of 16 columns: the diagonal block by 16 lanes of
+//    wavefront 0 with shuffles (no barrier), the panel below it one row per
+//    thread, the trailing update spread over all threads by (row, column);
+//  * forward and back substitution in the same blocks;
+// about 7 barriers per 16 columns.  x goes to P's entries of the column.
+constexpr int EXT_NB = 16;
+
+__device__ __forceinline__ int tri_off(int i) { return i * (i + 1) / 2; }
+
 __global__ __launch_bounds__(256) void k_ext_patch(
     const int64_t* __restrict__ pptr, const int32_t* __restrict__ pdofs,
     const int64_t* __restrict__ pdst, const int32_t* __restrict__ rd1,
@@ -1631,87 +1656,225 @@ __global__ __launch_bounds__(256) void k_ext_patch(
   extern __shared__ unsigned char lds_raw[];
   double* L = (double*)lds_raw;                             // packed lower triangle
   double* y = L + (size_t)mmax * (mmax + 1) / 2;            // right-hand side, then x
-  int32_t* dofs = (int32_t*)(y + mmax);
+  double* e1v = y + mmax;                                   // A(S_i, ext1)
+  double* e2v = e1v + mmax;                                 // A(S_i, ext2)
+  int64_t* rstart = (int64_t*)(e2v + mmax);                 // first A entry of each row
+  int32_t* pre = (int32_t*)(rstart + mmax);                 // row-length prefix (m + 1)
+  int32_t* dofs = pre + mmax + 1;
   const int64_t c = blockIdx.x;
   const int64_t p0 = pptr[c];
   const int m = (int)(pptr[c + 1] - p0);
   if (m == 0) return;   // the whole workgroup: nothing to extend
   const int tid = threadIdx.x;
-  const int32_t e1 = rd1[c], e2 = rd2[c];
+  const int lane = tid & 63, wave = tid >> 6;
+  const int32_t x1 = rd1[c], x2 = rd2[c];
   const double s1 = (double)rs1[c], s2 = (double)rs2[c];
-  for (int t = tid; t < m; t += 256) dofs[t] = pdofs[p0 + t];
+  int32_t mylen[3] = {0, 0, 0};
+  // rows 3 lane .. 3 lane + 2 of wavefront 0 (m <= 192)
+  if (wave == 0) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int i = 3 * lane + k;
+      if (i < m) {
+        const int32_t r = pdofs[p0 + i];
+        dofs[i] = r;
+        const int64_t a = Aptr[r];
+        rstart[i] = a;
+        mylen[k] = (int32_t)(Aptr[r + 1] - a);
+      }
+    }
+    // exclusive prefix of the row lengths over the wavefront
+    int32_t tot = mylen[0] + mylen[1] + mylen[2];
+    int32_t inc = tot;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t o = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += o;
+    }
+    int32_t run = inc - tot;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int i = 3 * lane + k;
+      if (i < m) pre[i] = run;
+      run += mylen[k];
+    }
+    if (lane == 63) pre[m] = inc;
+  }
   const int tri = m * (m + 1) / 2;
   for (int t = tid; t < tri; t += 256) L[t] = 0.0;
+  for (int t = tid; t < m; t += 256) e1v[t] = e2v[t] = 0.0;
   __syncthreads();
-  for (int i = tid; i < m; i += 256) {
-    const int32_t r = dofs[i];
-    double a1 = 0.0, a2 = 0.0;
-    double* Li = L + i * (i + 1) / 2;
-    for (int64_t q = Aptr[r]; q < Aptr[r + 1]; ++q) {
-      const int32_t j = Acol[q];
-      if (j == e1) {
-        a1 = Aval[q];
-      } else if (j == e2) {
-        a2 = Aval[q];
-      } else if (j <= r) {
-        const int pos = lower_bound_i32(dofs, i + 1, j);
-        if (pos <= i && dofs[pos] == j) Li[pos] = Aval[q];
-      }
+  const int E = pre[m];
+  for (int e = tid; e < E; e += 256) {
+    // row of flat entry e: the last i with pre[i] <= e
+    int lo = 0, hi = m;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pre[mid] <= e) lo = mid; else hi = mid;
     }
-    // two terms with exact +-1 factors: the sum does not depend on the order
-    y[i] = -(a1 * s1 + a2 * s2);
+    const int i = lo;
+    const int64_t q = rstart[i] + (e - pre[i]);
+    const int32_t j = Acol[q];
+    const double a = Aval[q];
+    if (j == x1) {
+      e1v[i] = a;
+    } else if (j == x2) {
+      e2v[i] = a;
+    } else if (j <= dofs[i]) {
+      const int pos = lower_bound_i32(dofs, i + 1, j);
+      if (pos <= i && dofs[pos] == j) L[tri_off(i) + pos] = a;
+    }
   }
   __syncthreads();
-  for (int k = 0; k < m; ++k) {
-    double* Lk = L + k * (k + 1) / 2;
-    if (tid == 0) {
-      double d = Lk[k];
-      if (!(d > 0.0)) {
-        atomicExch(flag, 1);
-        d = 1.0;
+  // two terms with exact +-1 factors: the sum does not depend on the order
+  for (int i = tid; i < m; i += 256) y[i] = -(e1v[i] * s1 + e2v[i] * s2);
+  // ---- blocked Cholesky ----
+  for (int kb = 0; kb < m; kb += EXT_NB) {
+    const int nb = min(EXT_NB, m - kb);
+    if (wave == 0) {
+      // lane r < nb holds row kb + r of the diagonal block
+      double d[EXT_NB];
+#pragma unroll
+      for (int t = 0; t < EXT_NB; ++t)
+        d[t] = (lane < nb && t <= lane && t < nb) ? L[tri_off(kb + lane) + kb + t] : (t == lane ? 1.0 : 0.0);
+#pragma unroll
+      for (int cc = 0; cc < EXT_NB; ++cc) {
+        if (lane == cc) {
+          double v = d[cc];
+          if (cc < nb && !(v > 0.0)) {
+            atomicExch(flag, 1);
+            v = 1.0;
+          }
+          d[cc] = sqrt(v);
+        }
+        const double piv = __shfl(d[cc], cc, 64);
+        if (lane > cc) d[cc] /= piv;
+#pragma unroll
+        for (int jj = cc + 1; jj < EXT_NB; ++jj) {
+          const double ljc = __shfl(d[cc], jj, 64);
+          if (lane >= jj) d[jj] -= d[cc] * ljc;
+        }
       }
-      Lk[k] = sqrt(d);
+      if (lane < nb) {
+#pragma unroll
+        for (int t = 0; t < EXT_NB; ++t)
+          if (t <= lane) L[tri_off(kb + lane) + kb + t] = d[t];
+      }
     }
     __syncthreads();
-    const double dk = Lk[k];
-    for (int i = k + 1 + tid; i < m; i += 256) L[i * (i + 1) / 2 + k] /= dk;
+    const int r0 = kb + nb;
+    // panel: rows i >= r0, columns kb .. kb + nb: x = a L_D^{-T}
+    for (int i = r0 + tid; i < m; i += 256) {
+      double* Li = L + tri_off(i) + kb;
+      double xv[EXT_NB];
+#pragma unroll
+      for (int cc = 0; cc < EXT_NB; ++cc) {
+        if (cc < nb) {
+          double v = Li[cc];
+          const double* Lc = L + tri_off(kb + cc) + kb;
+#pragma unroll
+          for (int t = 0; t < cc; ++t) v -= xv[t] * Lc[t];
+          xv[cc] = v / Lc[cc];
+        } else {
+          xv[cc] = 0.0;
+        }
+      }
+#pragma unroll
+      for (int cc = 0; cc < EXT_NB; ++cc)
+        if (cc < nb) Li[cc] = xv[cc];
+    }
     __syncthreads();
-    // trailing update of rows i > k, columns k < j <= i; several threads per
-    // row once fewer than 256 rows remain
-    const int nr = m - k - 1;
-    if (nr > 0) {
-      const int tpr = max(1, 256 / nr);
-      const int rstep = 256 / tpr;
-      for (int rr = tid / tpr; rr < nr; rr += rstep) {
-        const int i = k + 1 + rr;
-        double* Li = L + i * (i + 1) / 2;
-        const double lik = Li[k];
-        for (int j = k + 1 + tid % tpr; j <= i; j += tpr) Li[j] -= lik * L[j * (j + 1) / 2 + k];
+    // trailing update: L(i, j) -= sum_t L(i, kb + t) L(j, kb + t), r0 <= j <= i < m,
+    // the (i, j) pairs numbered row by row and dealt to threads in turn
+    const int R = m - r0;
+    if (R > 0) {
+      const int T = R * (R + 1) / 2;
+      int e = tid;
+      // (i, j) of flat index e: i the largest with i(i+1)/2 <= e
+      int ii = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+      while (tri_off(ii + 1) <= e) ++ii;
+      while (tri_off(ii) > e) --ii;
+      int jj = e - tri_off(ii);
+      for (; e < T; e += 256) {
+        const double* Li = L + tri_off(r0 + ii) + kb;
+        const double* Lj = L + tri_off(r0 + jj) + kb;
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < EXT_NB; ++t)
+          if (t < nb) acc += Li[t] * Lj[t];
+        L[tri_off(r0 + ii) + r0 + jj] -= acc;
+        jj += 256;
+        while (jj > ii && ii < R) {
+          jj -= ii + 1;
+          ++ii;
+        }
       }
     }
     __syncthreads();
   }
-  // L z = y, then L^T x = z (in y)
-  for (int k = 0; k < m; ++k) {
-    if (tid == 0) y[k] /= L[k * (k + 1) / 2 + k];
+  // ---- L z = y, then L^T x = z (in y), in the same blocks ----
+  for (int kb = 0; kb < m; kb += EXT_NB) {
+    const int nb = min(EXT_NB, m - kb);
+    if (wave == 0) {
+      double lr[EXT_NB];
+#pragma unroll
+      for (int t = 0; t < EXT_NB; ++t)
+        lr[t] = (lane < nb && t <= lane) ? L[tri_off(kb + lane) + kb + t] : 1.0;
+      double yr = lane < nb ? y[kb + lane] : 0.0;
+#pragma unroll
+      for (int cc = 0; cc < EXT_NB; ++cc) {
+        if (lane == cc) yr /= lr[cc];
+        const double zc = __shfl(yr, cc, 64);
+        if (lane > cc) yr -= lr[cc] * zc;
+      }
+      if (lane < nb) y[kb + lane] = yr;
+    }
     __syncthreads();
-    const double zk = y[k];
-    for (int i = k + 1 + tid; i < m; i += 256) y[i] -= L[i * (i + 1) / 2 + k] * zk;
+    for (int i = kb + nb + tid; i < m; i += 256) {
+      const double* Li = L + tri_off(i) + kb;
+      double v = y[i];
+#pragma unroll
+      for (int t = 0; t < EXT_NB; ++t)
+        if (t < nb) v -= Li[t] * y[kb + t];
+      y[i] = v;
+    }
     __syncthreads();
   }
-  for (int k = m - 1; k >= 0; --k) {
-    const double* Lk = L + k * (k + 1) / 2;
-    if (tid == 0) y[k] /= Lk[k];
+  const int nblk = (m + EXT_NB - 1) / EXT_NB;
+  for (int bi = nblk - 1; bi >= 0; --bi) {
+    const int kb = bi * EXT_NB;
+    const int nb = min(EXT_NB, m - kb);
+    if (wave == 0) {
+      // lane r holds x_{kb+r} and column kb + r of the block: lc[t] = L(kb + t, kb + r)
+      double lc[EXT_NB];
+#pragma unroll
+      for (int t = 0; t < EXT_NB; ++t)
+        lc[t] = (lane < nb && t >= lane && t < nb) ? L[tri_off(kb + t) + kb + lane] : 1.0;
+      double xr = lane < nb ? y[kb + lane] : 0.0;
+#pragma unroll
+      for (int cc = EXT_NB - 1; cc >= 0; --cc) {
+        if (lane == cc) xr /= lc[cc];
+        const double xc = __shfl(xr, cc, 64);
+        if (lane < cc) xr -= lc[cc] * xc;
+      }
+      if (lane < nb) y[kb + lane] = xr;
+    }
     __syncthreads();
-    const double xk = y[k];
-    for (int i = tid; i < k; i += 256) y[i] -= Lk[i] * xk;
+    for (int i = tid; i < kb; i += 256) {
+      double v = y[i];
+#pragma unroll
+      for (int t = 0; t < EXT_NB; ++t)
+        if (t < nb) v -= L[tri_off(kb + t) + i] * y[kb + t];
+      y[i] = v;
+    }
     __syncthreads();
   }
   for (int t = tid; t < m; t += 256) Pval[pdst[p0 + t]] = y[t];
 }
 
 size_t ext_patch_lds(int mmax) {
-  return sizeof(double) * ((size_t)mmax * (mmax + 1) / 2 + (size_t)mmax) + sizeof(int32_t) * (size_t)mmax;
+  return sizeof(double) * ((size_t)mmax * (mmax + 1) / 2 + 3 * (size_t)mmax) +
+         sizeof(int64_t) * (size_t)mmax + sizeof(int32_t) * (2 * (size_t)mmax + 1);
 }
 
 void ext_patches(int64_t nc, const int64_t* pptr, const int32_t* pdofs, const int64_t* pdst,
