@@ -12,6 +12,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/amg.h"
@@ -398,12 +399,24 @@ int sweep_mode_for(int64_t n, int64_t nnz, int64_t ns, int64_t nrows, int ncolou
   const bool dense_any = !(dense_env && dense_env[0] == '0') && dense_sweep_ok<double>((int)n, maxs);
   const bool panel_ok = panel_sweep_ok((int)std::min<int64_t>(n, INT32_MAX), maxs);
   int mode = SWEEP_COLOUR;
-  if (ncolours >= 16)
-    mode = (panel_ok && (nnz > 4096 * n || 2 * ns <= 3 * (int64_t)ncolours ||
-                         nrows <= 60 * (int64_t)ncolours))
-               ? SWEEP_PANEL
-               : SWEEP_PIPE;
-  else if (nnz <= 200000) mode = SWEEP_ONE;
+  if (ncolours >= 16) {
+    // one launch per colour while a colour holds 1,024 to 16,383 star rows:
+    // enough rows to fill the device per launch, few enough that the
+    // pipelined form's ticket and counter traffic does not pay (measured at
+    // 128^3: 1,824 rows per colour 0.71 ms per sweep against 1.22 ms
+    // pipelined; 26,300 rows 2.48 ms against 2.00 ms; 140 rows 0.76 against
+    // 0.56 ms)
+    const int64_t per = nrows / std::max(ncolours, 1);
+    if (panel_ok && (nnz > 4096 * n || 2 * ns <= 3 * (int64_t)ncolours ||
+                     nrows <= 60 * (int64_t)ncolours))
+      mode = SWEEP_PANEL;
+    else if (per >= 1024 && per < 16384)
+      mode = SWEEP_COLOUR;
+    else
+      mode = SWEEP_PIPE;
+  } else if (nnz <= 200000) {
+    mode = SWEEP_ONE;
+  }
   if (const char* e = std::getenv("HCURL_AMG_SWEEP")) {
     const std::string f(e);
     if (f == "colour") mode = SWEEP_COLOUR;
@@ -634,17 +647,9 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
       const int32_t d = sb_dofs[r];
       srow_ptr[r + 1] = srow_ptr[r] + (L.Apat.ptr[d + 1] - L.Apat.ptr[d]);
     }
-    std::vector<int32_t> scol(std::max<int64_t>(srow_ptr[nr], 1));
-    parallel_for(nr, [&](int64_t rb, int64_t re) {
-      for (int64_t r = rb; r < re; ++r) {
-        const int32_t d = sb_dofs[r];
-        std::copy(L.Apat.idx.begin() + L.Apat.ptr[d], L.Apat.idx.begin() + L.Apat.ptr[d + 1],
-                  scol.begin() + srow_ptr[r]);
-      }
-    });
     L.srow_nnz = srow_ptr[nr];
     L.srow_ptr = h->pool.upload(srow_ptr, st);
-    L.scol = h->pool.upload(scol, st);
+    L.scol = h->pool.get<int32_t>(std::max<int64_t>(L.srow_nnz, 1));   // gathered below
     L.sval = h->pool.get<double>(std::max<int64_t>(L.srow_nnz, 1));
   }
   L.chunk_blk = h->pool.upload(chunk_blk, st);
@@ -691,6 +696,8 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
     L.Acm = h->pool.get<double>((size_t)L.n * L.n);
   L.sb_ptr = h->pool.upload(sb_ptr, st);
   L.sb_dofs = h->pool.upload(sb_dofs, st);
+  // the column ids of the star-ordered row copy, gathered on the device
+  star_cols(sb_ptr[ns], L.sb_dofs, L.A_ptr, L.A_col, L.srow_ptr, L.scol, st);
   L.ssign = h->pool.upload(ssign, st);
   L.fac_off = h->pool.upload(fac_off, st);
   L.fac_total = fac_off[ns];
@@ -775,23 +782,51 @@ void build_interp_structs(amg_hier* h, Level& L, hipStream_t st) {
 // P^T pattern and the permutation P entry -> P^T entry, from the host copy of
 // P's (possibly truncated) pattern
 void build_transpose(amg_hier* h, Level& L, hipStream_t st) {
-  int64_t n = L.n, nc = L.nc, nnz = L.p_nnz;
-  std::vector<int64_t> tptr(nc + 1, 0), perm(nnz);
-  std::vector<int32_t> tcol(nnz);
-  for (int64_t q = 0; q < nnz; ++q) tptr[L.p_col_h[q] + 1]++;
-  for (int64_t c = 0; c < nc; ++c) tptr[c + 1] += tptr[c];
-  std::vector<int64_t> pos(tptr.begin(), tptr.end() - 1);
-  for (int64_t e = 0; e < n; ++e)
-    for (int64_t q = L.p_ptr_h[e]; q < L.p_ptr_h[e + 1]; ++q) {
-      int64_t d = pos[L.p_col_h[q]]++;
-      tcol[d] = (int32_t)e;
-      perm[q] = d;
+  const int64_t n = L.n, nc = L.nc, nnz = L.p_nnz;
+  // parallel transpose: thread t takes rows [e0(t), e1(t)) of P and counts
+  // its entries per column; a column's entries from thread t follow those of
+  // threads < t, so P^T's rows come out in ascending P-row order
+  const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), n / 4096));
+  const int64_t chunk = (n + nt - 1) / nt;
+  std::vector<std::vector<int64_t>> cnt(nt);
+  auto run = [&](const std::function<void(int)>& body) {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) th.emplace_back(body, t);
+    for (auto& x : th) x.join();
+  };
+  run([&](int t) {
+    cnt[t].assign(nc, 0);
+    const int64_t e0 = std::min(n, t * chunk), e1 = std::min(n, e0 + chunk);
+    for (int64_t q = L.p_ptr_h[e0]; q < L.p_ptr_h[e1]; ++q) ++cnt[t][L.p_col_h[q]];
+  });
+  std::vector<int64_t> tptr(nc + 1, 0);
+  for (int64_t c = 0; c < nc; ++c) {
+    int64_t acc = tptr[c];
+    for (int t = 0; t < nt; ++t) {
+      const int64_t k = cnt[t][c];
+      cnt[t][c] = acc;
+      acc += k;
     }
+    tptr[c + 1] = acc;
+  }
+  std::vector<int64_t> perm(nnz);
+  std::vector<int32_t> tcol(nnz);
+  run([&](int t) {
+    const int64_t e0 = std::min(n, t * chunk), e1 = std::min(n, e0 + chunk);
+    for (int64_t e = e0; e < e1; ++e)
+      for (int64_t q = L.p_ptr_h[e]; q < L.p_ptr_h[e + 1]; ++q) {
+        const int64_t d = cnt[t][L.p_col_h[q]]++;
+        tcol[d] = (int32_t)e;
+        perm[q] = d;
+      }
+  });
   L.PT_ptr = h->pool.upload(tptr, st);
   L.PT_col = h->pool.upload(tcol, st);
   L.PT_perm = h->pool.upload(perm, st);
   L.PT_val = h->pool.get<double>(std::max<int64_t>(nnz, 1));
   L.lpr_PT = lpr_for(nc, nnz);
+  // the uploads read tcol and perm before they go out of scope
+  HIPC(hipStreamSynchronize(st));
 }
 
 // Optional sparsification (not in the paper): drop interior-row entries of

@@ -2,6 +2,8 @@
 #include "host_setup.hpp"
 
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -172,23 +174,38 @@ bool validate_pattern(int64_t n, int64_t m, const int64_t* ptr, const int32_t* i
     err = {-3, "CSR row pointer does not start at 0"};
     return false;
   }
-  for (int64_t i = 0; i < n; ++i) {
-    if (ptr[i + 1] < ptr[i]) {
-      err = {-3, "CSR row pointers decrease at row " + std::to_string(i)};
-      return false;
-    }
-    for (int64_t t = ptr[i]; t < ptr[i + 1]; ++t) {
-      if (idx[t] < 0 || idx[t] >= m) {
-        err = {-3, "CSR column out of range in row " + std::to_string(i)};
-        return false;
+  // rows checked in parallel; the first bad row (and its kind) is reported
+  std::atomic<int64_t> bad_row(n);
+  std::vector<int8_t> kind(n > 0 ? 1 : 0, 0);
+  std::mutex mu;
+  parallel_for(n, [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi && i < bad_row.load(std::memory_order_relaxed); ++i) {
+      int8_t k = 0;
+      if (ptr[i + 1] < ptr[i]) {
+        k = 1;
+      } else {
+        for (int64_t t = ptr[i]; t < ptr[i + 1] && !k; ++t) {
+          if (idx[t] < 0 || idx[t] >= m) k = 2;
+          else if (t > ptr[i] && idx[t] <= idx[t - 1]) k = 3;
+        }
       }
-      if (t > ptr[i] && idx[t] <= idx[t - 1]) {
-        err = {-3, "CSR columns unsorted or duplicated in row " + std::to_string(i)};
-        return false;
+      if (k) {
+        std::lock_guard<std::mutex> g(mu);
+        if (i < bad_row.load()) {
+          bad_row.store(i);
+          kind[0] = k;
+        }
+        return;
       }
     }
-  }
-  return true;
+  });
+  const int64_t i = bad_row.load();
+  if (i == n) return true;
+  const char* what = kind[0] == 1 ? "CSR row pointers decrease at row "
+                     : kind[0] == 2 ? "CSR column out of range in row "
+                                    : "CSR columns unsorted or duplicated in row ";
+  err = {-3, what + std::to_string(i)};
+  return false;
 }
 
 bool incidence_from_csr(int64_t n, int64_t m, const int64_t* ptr, const int32_t* idx,

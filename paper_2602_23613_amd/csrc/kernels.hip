@@ -526,6 +526,23 @@ __global__ void k_star_rows(int64_t nrows, const int32_t* __restrict__ sb_dofs,
   const int64_t s0 = srow_ptr[r], len = srow_ptr[r + 1] - s0;
   for (int64_t q = lane; q < len; q += 32) sval[s0 + q] = Aval[a0 + q];
 }
+// the column ids of the same copy (once per pattern)
+__global__ void k_star_cols(int64_t nrows, const int32_t* __restrict__ sb_dofs,
+                            const int64_t* __restrict__ Aptr, const int32_t* __restrict__ Acol,
+                            const int64_t* __restrict__ srow_ptr, int32_t* __restrict__ scol) {
+  const int64_t r = (int64_t)blockIdx.x * 8 + threadIdx.x / 32;
+  const int lane = threadIdx.x % 32;
+  if (r >= nrows) return;
+  const int64_t a0 = Aptr[sb_dofs[r]];
+  const int64_t s0 = srow_ptr[r], len = srow_ptr[r + 1] - s0;
+  for (int64_t q = lane; q < len; q += 32) scol[s0 + q] = Acol[a0 + q];
+}
+void star_cols(int64_t nrows, const int32_t* sb_dofs, const int64_t* Aptr, const int32_t* Acol,
+               const int64_t* srow_ptr, int32_t* scol, hipStream_t st) {
+  if (nrows > 0)
+    hipLaunchKernelGGL(k_star_cols, dim3((unsigned)((nrows + 7) / 8)), dim3(256), 0, st, nrows,
+                       sb_dofs, Aptr, Acol, srow_ptr, scol);
+}
 void star_rows(int64_t nrows, const int32_t* sb_dofs, const int64_t* Aptr, const double* Aval,
                const int64_t* srow_ptr, double* sval, hipStream_t st) {
   if (nrows > 0)

@@ -116,6 +116,8 @@ template <class T>
 void schwarz_sweep_small(const SmootherDev<T>& S, int backward, const T* b, T* x, hipStream_t st);
 template <class T>
 void schwarz_pipe(const SmootherDev<T>& S, int backward, const T* b, T* x, hipStream_t st);
+void star_cols(int64_t nrows, const int32_t* sb_dofs, const int64_t* Aptr, const int32_t* Acol,
+               const int64_t* srow_ptr, int32_t* scol, hipStream_t st);
 void star_rows(int64_t nrows, const int32_t* sb_dofs, const int64_t* Aptr, const double* Aval,
                const int64_t* srow_ptr, double* sval, hipStream_t st);
 bool panel_sweep_ok(int n, int max_block);
