@@ -550,6 +550,7 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
     wg = 1024;
     lpr = 8;
     while (lpr < 256 && avg_row > 16.0 * lpr && 1024 / (2 * lpr) >= std::max(maxs, 1)) lpr *= 2;
+    if (const char* e = std::getenv("HCURL_AMG_PIPE_LPR")) lpr = std::max(8, std::min(256, std::atoi(e)));
     while (1024 / lpr < std::max(maxs, 1)) lpr /= 2;
   } else {
     while (wg / lpr < std::max(maxs, 1) && wg < 1024) wg *= 2;
