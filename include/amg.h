@@ -207,8 +207,8 @@ void amg_default_options(amg_options *opt);
    (Sections 3-4): per level, augmentG (Algorithm 1), the nodal C/F
    splitting (Algorithm 2), the matching of length-two paths and R, S_I
    (Algorithm 3), G_c = R G I_C (eq. (Gc)), P by local harmonic extension
-   (eq. (sparseP); in 3D the blocks of A_II follow the depth-ordered reading
-   when graph(A_II) has large components), A_c = P^T A P (Section 1), and the
+   (eq. (sparseP): block solves of A_II, or per-column patch solves with
+   ext_mode AMG_EXT_PATCH), A_c = P^T A P (Section 1), and the
    node-star Schwarz smoother with its l1 diagonal (Section 5); coarsening
    stops as in Section 5 (20 levels, 32 DoFs).  The integer phase runs on the
    host, every floating-point step on the GPU.  A and G are borrowed for the

@@ -163,3 +163,36 @@ def test_patch_pcg_matches_oracle(name):
     floor = 64 * EPS * np.linalg.norm(abs(p.A) @ np.abs(uu)) / np.linalg.norm(p.f)
     assert st["true_relres"] <= max(2e-8, floor)
     H.close()
+
+
+def test_patch_numeric_resetup_matches_fresh_setup():
+    """amg_resetup_numeric in the patch form (new coefficient field, same
+    pattern: the patches and every integer result are reused) gives the
+    same V-cycle bits as a fresh setup on the new field, and repeated
+    V-cycles are bitwise equal."""
+    d = dev()
+    p1 = gen.make_problem("hex", 10, alpha=lambda m: fields.subdomain_log_uniform(m, 5, 21))
+    p2 = gen.make_problem("hex", 10, alpha=lambda m: fields.subdomain_log_uniform(m, 5, 22))
+    H = amglib.Hierarchy(p1.A, p1.G, **OPTS)
+    H.resetup(p2.A)
+    H2 = amglib.Hierarchy(p2.A, p2.G, **OPTS)
+    r = torch.tensor(np.random.default_rng(3).standard_normal(p1.A.shape[0]), device=d)
+    z1, z2, z3 = torch.zeros_like(r), torch.zeros_like(r), torch.zeros_like(r)
+    H.vcycle(r, z1)
+    H2.vcycle(r, z2)
+    H2.vcycle(r, z3)
+    torch.cuda.synchronize()
+    assert torch.equal(z1, z2)
+    assert torch.equal(z2, z3)
+    H.close()
+    H2.close()
+
+
+def test_patch_mode_rejects_the_learned_setup():
+    """The network predicts block solves: the patch form refuses to train it."""
+    dev()
+    p, _ = case("hex8_iso")
+    H = amglib.Hierarchy(p.A, p.G, **OPTS)
+    with pytest.raises(amglib.AmgError):
+        H.mlp_train(epochs=1, batch=64)
+    H.close()

@@ -160,3 +160,13 @@ def test_patch_sets_bit_exact(kind, size, cap):
     assert np.array_equal(d["patch_ptr"], ptr)
     assert np.array_equal(d["patch_dofs"], np.concatenate(ps))
     assert max(len(x) for x in ps) <= cap
+
+
+def test_patch_options_are_checked():
+    """Patch sizes beyond what the kernel's LDS holds, or no hops, are
+    refused before any work (AMG_ERR_ARG)."""
+    p = gen.make_problem("hex", 4, beta=1.0)
+    for bad in (dict(patch_cap=193), dict(patch_cap=0), dict(patch_hops=0), dict(patch_hops=9)):
+        with pytest.raises(amglib.AmgError) as e:
+            amglib.level0_integers(p.A, p.G, ext_mode="patch", **bad)
+        assert e.value.status == -1, bad
