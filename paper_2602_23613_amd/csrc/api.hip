@@ -720,6 +720,7 @@ void factor_smoother(amg_hier* h, Level& L, int level, hipStream_t st) {
     panel_slices(L.ngroups, L.n, L.gdof, L.Acm, L.gslc, L.gcf, L.gcb, st);
   star_rows((int64_t)L.ints.star_dofs.size(), L.sb_dofs, L.A_ptr, L.A_val, L.srow_ptr, L.sval, st);
   star_chol(L.nstars, L.sb_ptr, L.sb_dofs, L.fac_off, L.A_dev<double>(), L.fac, h->d_flag, st);
+  HIPC(hipGetLastError());
   check_flag(h, st, AMG_ERR_NOT_SPD, "smoother block Cholesky: non-positive pivot on level " +
                                          std::to_string(level));
   star_inv((int64_t)L.ints.star_dofs.size(), L.row_blk, L.sb_ptr, L.fac_off, L.fac, L.binv, st);
@@ -873,6 +874,7 @@ void compute_interp(amg_hier* h, Level& L, int level, hipStream_t st, bool learn
                L.P_col, L.P_val, S.smax, S.cmax, L.p_row_max, h->d_flag, st, learned ? h->fW : nullptr,
                learned ? h->facc : nullptr, learned ? h->fdsq : nullptr);
   }
+  HIPC(hipGetLastError());
   check_flag(h, st, AMG_ERR_NOT_SPD,
              "local harmonic extension: non-positive pivot in A_BB on level " + std::to_string(level));
 }
@@ -928,6 +930,7 @@ int64_t mm_symbolic(amg_hier* h, int64_t nrows, int64_t ncols, const CsrPat& X, 
                     int32_t*& d_wide, int64_t& nwide, const std::string& what, hipStream_t st) {
   int64_t* d_cnt = h->pool.get<int64_t>(nrows);
   mm_count(nrows, X, Y, d_cnt, h->d_flag, st);
+  HIPC(hipGetLastError());
   std::vector<int64_t> cnt(nrows);
   HIPC(hipMemcpyAsync(cnt.data(), d_cnt, nrows * sizeof(int64_t), hipMemcpyDeviceToHost, st));
   HIPC(hipStreamSynchronize(st));
@@ -958,6 +961,7 @@ int64_t mm_symbolic(amg_hier* h, int64_t nrows, int64_t ncols, const CsrPat& X, 
   d_ccol = h->pool.get<int32_t>(std::max<int64_t>(cptr[nrows], 1));
   mm_fill(nrows, X, Y, d_cptr, d_ccol, h->d_flag, st);
   mm_fill_wide((int64_t)hw.size(), d_hw, X, Y, ncols, d_cptr, d_ccol, st);
+  HIPC(hipGetLastError());
   check_flag(h, st, AMG_ERR_LIMIT, what + ": column fill overflow");
   nwide = (int64_t)nw.size();
   d_wide = nw.empty() ? nullptr : h->pool.upload(nw, st);
@@ -996,6 +1000,7 @@ void galerkin_numeric(amg_hier* h, Level& L, Level& C, hipStream_t st) {
   mm_vals(L.nc, PT, L.PT_val, AP, L.AP_val, C.A_ptr, C.A_col, C.A_val, L.rap_mmax, st);
   mm_vals_wide(L.rap_nwide, L.rap_wide, PT, L.PT_val, AP, L.AP_val, L.nc, C.A_ptr, C.A_col, C.A_val,
                st);
+  HIPC(hipGetLastError());
 }
 
 void coarsest_factor(amg_hier* h, Level& L, hipStream_t st) {

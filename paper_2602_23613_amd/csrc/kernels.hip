@@ -69,13 +69,34 @@ __device__ __forceinline__ int lower_bound_i32(const int32_t* a, int n, int32_t 
 
 template <class T> void fill(int64_t n, T v, T* x, hipStream_t st);
 
+// A dispatch counts its work-items in 32 bits.  Launches whose workgroup
+// count grows with the rows (one workgroup per row, block or column) go out
+// in batches of at most MAX_WG_PER_LAUNCH workgroups (2^30 work-items at 256
+// threads), each told the id of its first workgroup.  HCURL_AMG_MAX_WG
+// lowers the batch size, so that small problems exercise the batching.
+constexpr int64_t MAX_WG_PER_LAUNCH = int64_t(1) << 22;
+static int64_t wg_per_launch() {
+  static const int64_t v = [] {
+    int64_t w = MAX_WG_PER_LAUNCH;
+    if (const char* e = std::getenv("HCURL_AMG_MAX_WG"))
+      w = std::max<int64_t>(1, std::min<int64_t>(w, std::atoll(e)));
+    return w;
+  }();
+  return v;
+}
+template <class F>
+static void in_batches(int64_t nwg, F launch) {
+  const int64_t step = wg_per_launch();
+  for (int64_t w0 = 0; w0 < nwg; w0 += step) launch(w0, (unsigned)std::min(step, nwg - w0));
+}
+
 // ---------------------------------------------------------------------------
 // SpMV family
 // ---------------------------------------------------------------------------
 enum { EPI_Y = 0, EPI_RES = 1, EPI_JAC = 2, EPI_ADD = 3, EPI_DOT = 4 };
 
 template <class T, int LPR, int EPI>
-__global__ __launch_bounds__(256) void k_spmv(int64_t n, const int64_t* __restrict__ ptr,
+__global__ __launch_bounds__(256) void k_spmv(int64_t wg0, int64_t n, const int64_t* __restrict__ ptr,
                                               const int32_t* __restrict__ col,
                                               const T* __restrict__ val, const T* __restrict__ x,
                                               const T* __restrict__ b, const T* __restrict__ dinv,
@@ -83,7 +104,8 @@ __global__ __launch_bounds__(256) void k_spmv(int64_t n, const int64_t* __restri
   constexpr int RPB = 256 / LPR;
   const int lane = threadIdx.x % LPR;
   const int grp = threadIdx.x / LPR;
-  const int64_t row = (int64_t)blockIdx.x * RPB + grp;
+  const int64_t wg = wg0 + blockIdx.x;
+  const int64_t row = wg * RPB + grp;
   T s = 0;
   if (row < n) s = row_dot<LPR, T>(ptr[row], ptr[row + 1], lane, col, val, x);
   s = group_sum<LPR>(s);
@@ -106,7 +128,7 @@ __global__ __launch_bounds__(256) void k_spmv(int64_t n, const int64_t* __restri
       if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
       __syncthreads();
     }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) partial[wg] = red[0];
   }
 }
 
@@ -117,8 +139,10 @@ static void spmv_lpr(int lpr, hipStream_t st, int64_t n, const int64_t* ptr, con
 #define LAUNCH_SPMV(L)                                                                        \
   {                                                                                           \
     int64_t grid = (n + (256 / L) - 1) / (256 / L);                                           \
-    hipLaunchKernelGGL((k_spmv<T, L, EPI>), dim3((unsigned)grid), dim3(256), 0, st, n, ptr, col, \
-                       val, x, b, dinv, y, partial);                                          \
+    in_batches(grid, [&](int64_t w0, unsigned g) {                                            \
+      hipLaunchKernelGGL((k_spmv<T, L, EPI>), dim3(g), dim3(256), 0, st, w0, n, ptr, col, val, \
+                         x, b, dinv, y, partial);                                             \
+    });                                                                                       \
   }
   switch (lpr) {
     case 4: LAUNCH_SPMV(4); break;
@@ -488,7 +512,9 @@ void schwarz_colour(const SmootherDev<T>& S, int colour, const T* b, T* x, hipSt
   const SmootherArgs<T> D = S;
 #define LAUNCH_SW(L, W)                                                                          \
   if (S.lpr == L && S.wg == W) {                                                                 \
-    hipLaunchKernelGGL((k_schwarz<T, L, W>), dim3(c1 - c0), dim3(W), 0, st, D, c0, b, x);         \
+    in_batches(c1 - c0, [&](int64_t w0, unsigned g) {                                            \
+      hipLaunchKernelGGL((k_schwarz<T, L, W>), dim3(g), dim3(W), 0, st, D, (int)(c0 + w0), b, x); \
+    });                                                                                          \
     return;                                                                                      \
   }
   SCHWARZ_SHAPES(LAUNCH_SW)
@@ -519,34 +545,34 @@ void schwarz_pipe(const SmootherDev<T>& S, int backward, const T* b, T* x, hipSt
 __global__ void k_star_rows(int64_t nrows, const int32_t* __restrict__ sb_dofs,
                             const int64_t* __restrict__ Aptr, const double* __restrict__ Aval,
                             const int64_t* __restrict__ srow_ptr, double* __restrict__ sval) {
-  const int64_t r = (int64_t)blockIdx.x * 8 + threadIdx.x / 32;
   const int lane = threadIdx.x % 32;
-  if (r >= nrows) return;
-  const int64_t a0 = Aptr[sb_dofs[r]];
-  const int64_t s0 = srow_ptr[r], len = srow_ptr[r + 1] - s0;
-  for (int64_t q = lane; q < len; q += 32) sval[s0 + q] = Aval[a0 + q];
+  for (int64_t r = (int64_t)blockIdx.x * 8 + threadIdx.x / 32; r < nrows; r += (int64_t)gridDim.x * 8) {
+    const int64_t a0 = Aptr[sb_dofs[r]];
+    const int64_t s0 = srow_ptr[r], len = srow_ptr[r + 1] - s0;
+    for (int64_t q = lane; q < len; q += 32) sval[s0 + q] = Aval[a0 + q];
+  }
 }
 // the column ids of the same copy (once per pattern)
 __global__ void k_star_cols(int64_t nrows, const int32_t* __restrict__ sb_dofs,
                             const int64_t* __restrict__ Aptr, const int32_t* __restrict__ Acol,
                             const int64_t* __restrict__ srow_ptr, int32_t* __restrict__ scol) {
-  const int64_t r = (int64_t)blockIdx.x * 8 + threadIdx.x / 32;
   const int lane = threadIdx.x % 32;
-  if (r >= nrows) return;
-  const int64_t a0 = Aptr[sb_dofs[r]];
-  const int64_t s0 = srow_ptr[r], len = srow_ptr[r + 1] - s0;
-  for (int64_t q = lane; q < len; q += 32) scol[s0 + q] = Acol[a0 + q];
+  for (int64_t r = (int64_t)blockIdx.x * 8 + threadIdx.x / 32; r < nrows; r += (int64_t)gridDim.x * 8) {
+    const int64_t a0 = Aptr[sb_dofs[r]];
+    const int64_t s0 = srow_ptr[r], len = srow_ptr[r + 1] - s0;
+    for (int64_t q = lane; q < len; q += 32) scol[s0 + q] = Acol[a0 + q];
+  }
 }
 void star_cols(int64_t nrows, const int32_t* sb_dofs, const int64_t* Aptr, const int32_t* Acol,
                const int64_t* srow_ptr, int32_t* scol, hipStream_t st) {
   if (nrows > 0)
-    hipLaunchKernelGGL(k_star_cols, dim3((unsigned)((nrows + 7) / 8)), dim3(256), 0, st, nrows,
+    hipLaunchKernelGGL(k_star_cols, dim3((unsigned)std::min<int64_t>((nrows + 7) / 8, MAX_WG_PER_LAUNCH)), dim3(256), 0, st, nrows,
                        sb_dofs, Aptr, Acol, srow_ptr, scol);
 }
 void star_rows(int64_t nrows, const int32_t* sb_dofs, const int64_t* Aptr, const double* Aval,
                const int64_t* srow_ptr, double* sval, hipStream_t st) {
   if (nrows > 0)
-    hipLaunchKernelGGL(k_star_rows, dim3((unsigned)((nrows + 7) / 8)), dim3(256), 0, st, nrows,
+    hipLaunchKernelGGL(k_star_rows, dim3((unsigned)std::min<int64_t>((nrows + 7) / 8, MAX_WG_PER_LAUNCH)), dim3(256), 0, st, nrows,
                        sb_dofs, Aptr, Aval, srow_ptr, sval);
 }
 
@@ -1641,9 +1667,11 @@ void ext_blocks(int64_t b0, int64_t nb, const int64_t* bptr, const int32_t* bdof
   // to keep 64 lanes busy (HCURL_AMG_EXT_WIDE=0/1 forces either way)
   int wide = prow_max > 64 ? 1 : 0;
   if (const char* e = std::getenv("HCURL_AMG_EXT_WIDE")) wide = e[0] == '1' ? 1 : 0;
-  hipLaunchKernelGGL(k_ext_block, dim3((unsigned)nb, (unsigned)ntiles), dim3(64), lds, st, b0, bptr,
-                     bdofs, dof_stage, stage, A.ptr, A.col, A.val, Pptr, Pcol, Pval, smax, ctile,
-                     wide, flag, Wl, accepted, dsq);
+  in_batches(nb, [&](int64_t w0, unsigned g) {
+    hipLaunchKernelGGL(k_ext_block, dim3(g, (unsigned)ntiles), dim3(64), lds, st, b0 + w0, bptr, bdofs,
+                       dof_stage, stage, A.ptr, A.col, A.val, Pptr, Pcol, Pval, smax, ctile, wide,
+                       flag, Wl, accepted, dsq);
+  });
 }
 
 // Patch extension: one 256-thread workgroup per column c of P.  The column's
@@ -1669,7 +1697,7 @@ __global__ __launch_bounds__(256) void k_ext_patch(
     const int32_t* __restrict__ rd2, const int8_t* __restrict__ rs1,
     const int8_t* __restrict__ rs2, const int64_t* __restrict__ Aptr,
     const int32_t* __restrict__ Acol, const double* __restrict__ Aval, double* __restrict__ Pval,
-    int mmax, int* __restrict__ flag) {
+    int mmax, int* __restrict__ flag, int64_t cfirst) {
   extern __shared__ unsigned char lds_raw[];
   double* L = (double*)lds_raw;                             // packed lower triangle
   double* y = L + (size_t)mmax * (mmax + 1) / 2;            // right-hand side, then x
@@ -1678,7 +1706,7 @@ __global__ __launch_bounds__(256) void k_ext_patch(
   int64_t* rstart = (int64_t*)(e2v + mmax);                 // first A entry of each row
   int32_t* pre = (int32_t*)(rstart + mmax);                 // row-length prefix (m + 1)
   int32_t* dofs = pre + mmax + 1;
-  const int64_t c = blockIdx.x;
+  const int64_t c = cfirst + blockIdx.x;
   const int64_t p0 = pptr[c];
   const int m = (int)(pptr[c + 1] - p0);
   if (m == 0) return;   // the whole workgroup: nothing to extend
@@ -1898,8 +1926,10 @@ void ext_patches(int64_t nc, const int64_t* pptr, const int32_t* pdofs, const in
                  const int32_t* rd1, const int32_t* rd2, const int8_t* rs1, const int8_t* rs2,
                  const CsrDev<double>& A, double* Pval, int mmax, int* flag, hipStream_t st) {
   if (nc <= 0 || mmax <= 0) return;
-  hipLaunchKernelGGL(k_ext_patch, dim3((unsigned)nc), dim3(256), ext_patch_lds(mmax), st, pptr,
-                     pdofs, pdst, rd1, rd2, rs1, rs2, A.ptr, A.col, A.val, Pval, mmax, flag);
+  in_batches(nc, [&](int64_t c0, unsigned g) {
+    hipLaunchKernelGGL(k_ext_patch, dim3(g), dim3(256), ext_patch_lds(mmax), st, pptr, pdofs, pdst,
+                       rd1, rd2, rs1, rs2, A.ptr, A.col, A.val, Pval, mmax, flag, c0);
+  });
 }
 
 // x_i = a pseudo-random value in [-1, 1) from a counter-based hash (SplitMix64)
@@ -1985,11 +2015,11 @@ __global__ __launch_bounds__(256) void k_mm_count(int64_t nrows, const int64_t* 
                                                   const int64_t* __restrict__ Yptr,
                                                   const int32_t* __restrict__ Ycol,
                                                   int64_t* __restrict__ cnt,
-                                                  int* __restrict__ overflow, int wide_at) {
+                                                  int* __restrict__ overflow, int wide_at, int64_t r0) {
   __shared__ int32_t hash[HCAP];
   __shared__ int count;
   __shared__ int full;
-  const int64_t i = blockIdx.x;
+  const int64_t i = r0 + blockIdx.x;
   for (int t = threadIdx.x; t < HCAP; t += blockDim.x) hash[t] = -1;
   if (threadIdx.x == 0) {
     count = 0;
@@ -2010,12 +2040,12 @@ __global__ __launch_bounds__(256) void k_mm_fill(int64_t nrows, const int64_t* _
                                                  const int32_t* __restrict__ Ycol,
                                                  const int64_t* __restrict__ Cptr,
                                                  int32_t* __restrict__ Ccol,
-                                                 int* __restrict__ overflow, int wide_at) {
+                                                 int* __restrict__ overflow, int wide_at, int64_t r0) {
   __shared__ int32_t hash[HCAP];
   __shared__ int count;
   __shared__ int nfill;
   __shared__ int full;
-  const int64_t i = blockIdx.x;
+  const int64_t i = r0 + blockIdx.x;
   if (Cptr[i + 1] - Cptr[i] > wide_at) return;   // wide row: k_mm_fill_wide
   for (int t = threadIdx.x; t < HCAP; t += blockDim.x) hash[t] = -1;
   if (threadIdx.x == 0) {
@@ -2072,11 +2102,11 @@ __global__ __launch_bounds__(64) void k_mm_vals(
     const double* __restrict__ Xval, const int64_t* __restrict__ Yptr,
     const int32_t* __restrict__ Ycol, const double* __restrict__ Yval,
     const int64_t* __restrict__ Cptr, const int32_t* __restrict__ Ccol, double* __restrict__ Cval,
-    int mmax) {
+    int mmax, int64_t r0) {
   extern __shared__ unsigned char lds_raw[];
   double* acc = (double*)lds_raw;          // mmax
   int32_t* cols = (int32_t*)(acc + mmax);  // mmax
-  const int64_t i = blockIdx.x;
+  const int64_t i = r0 + blockIdx.x;
   const int64_t o = Cptr[i];
   const int m = (int)(Cptr[i + 1] - o);
   if (m > mmax) return;   // wide row: k_mm_vals_wide
@@ -2264,23 +2294,29 @@ int mm_wide_at() {
 }
 void mm_count(int64_t nrows, const CsrPat& X, const CsrPat& Y, int64_t* cnt, int* overflow,
               hipStream_t st) {
-  if (nrows > 0)
-    hipLaunchKernelGGL(k_mm_count, dim3((unsigned)nrows), dim3(256), 0, st, nrows, X.ptr, X.col,
-                       Y.ptr, Y.col, cnt, overflow, mm_wide_at());
+  const int wide_at = mm_wide_at();
+  in_batches(nrows, [&](int64_t r0, unsigned g) {
+    hipLaunchKernelGGL(k_mm_count, dim3(g), dim3(256), 0, st, nrows, X.ptr, X.col, Y.ptr, Y.col, cnt,
+                       overflow, wide_at, r0);
+  });
 }
 void mm_fill(int64_t nrows, const CsrPat& X, const CsrPat& Y, const int64_t* Cptr, int32_t* Ccol,
              int* overflow, hipStream_t st) {
-  if (nrows > 0)
-    hipLaunchKernelGGL(k_mm_fill, dim3((unsigned)nrows), dim3(256), 0, st, nrows, X.ptr, X.col,
-                       Y.ptr, Y.col, Cptr, Ccol, overflow, mm_wide_at());
+  const int wide_at = mm_wide_at();
+  in_batches(nrows, [&](int64_t r0, unsigned g) {
+    hipLaunchKernelGGL(k_mm_fill, dim3(g), dim3(256), 0, st, nrows, X.ptr, X.col, Y.ptr, Y.col, Cptr,
+                       Ccol, overflow, wide_at, r0);
+  });
 }
 void mm_vals(int64_t nrows, const CsrPat& X, const double* Xval, const CsrPat& Y,
              const double* Yval, const int64_t* Cptr, const int32_t* Ccol, double* Cval, int mmax,
              hipStream_t st) {
   if (nrows <= 0) return;
   size_t lds = (size_t)std::max(mmax, 1) * (sizeof(double) + sizeof(int32_t));
-  hipLaunchKernelGGL(k_mm_vals, dim3((unsigned)nrows), dim3(64), lds, st, nrows, X.ptr, X.col,
-                     Xval, Y.ptr, Y.col, Yval, Cptr, Ccol, Cval, mmax);
+  in_batches(nrows, [&](int64_t r0, unsigned g) {
+    hipLaunchKernelGGL(k_mm_vals, dim3(g), dim3(64), lds, st, nrows, X.ptr, X.col, Xval, Y.ptr, Y.col,
+                       Yval, Cptr, Ccol, Cval, mmax, r0);
+  });
 }
 int mm_hash_cap() { return HCAP; }
 
