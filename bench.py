@@ -199,7 +199,7 @@ def one_step(amg, Ad, Gd, f, torch, prec, maxit, p_trunc=0.0, ext=None):
                       replacements=st["replacements"])
 
 
-SWEEP_KERNEL = {"colour": "k_schwarz<double,{lanes},256>", "pipe": "k_schwarz_pipe<double,{lanes}>",
+SWEEP_KERNEL = {"colour": "k_schwarz<double,{lanes},256>", "pipe": "k_schwarz_pipe<double,{lanes},{pairs}>",
                 "panel": "k_schwarz_panel<double>", "one": "k_schwarz_sweep1<double,...>",
                 "dense": "k_dense_sweep"}
 
@@ -242,7 +242,8 @@ def time_kernels(amg, H, f, torch, reps=20):
     sb = sweep_bytes(li, w)
     form = li["sweep_form"]
     launches = li["ncolors"] if form == "colour" else 1
-    kernel = SWEEP_KERNEL.get(form, form).format(lanes=li["sweep_lanes"]).replace("double", "double" if w == 8 else "float")
+    kernel = SWEEP_KERNEL.get(form, form).format(lanes=li["sweep_lanes"], pairs=li["sweep_pairs"])
+    kernel = kernel.replace("double", "double" if w == 8 else "float")
     return dict(vcycle_ms=vc_ms, vcycle_GBs=vb / (vc_ms * 1e-3) / 1e9, vcycle_bytes=vb,
                 per_level_sweep_ms=per_level, dominant_level=dom, dominant_form=form,
                 dominant_kernel=kernel, dominant_share=4 * per_level[dom] / vc_ms,

@@ -177,6 +177,8 @@ typedef struct {
   int sweep_lanes;         /* lanes per row of the row forms (0 for the dense and panel forms) */
   int prec;                /* 64 or 32: value type of this level's V-cycle work */
   double grad_ratio;       /* rho_l of fp32_rho_tol (computed on every level but the coarsest) */
+  int sweep_pairs;         /* pipelined form: (column, value) pairs per lane loaded before a
+                              chunk waits for the colour before it (0 for the other forms) */
 } amg_level_info;
 
 /* Integer results of one level's setup, for bit-exact comparison.  All

@@ -186,7 +186,7 @@ class Hierarchy:
                      exact_blocks=bool(x.exact_blocks), star_rows=x.star_rows,
                      star_row_nnz=x.star_row_nnz, fac_entries=x.fac_entries,
                      sweep_form=SWEEP_FORMS[x.sweep_form], sweep_lanes=x.sweep_lanes,
-                     prec=x.prec, grad_ratio=x.grad_ratio)
+                     prec=x.prec, grad_ratio=x.grad_ratio, sweep_pairs=x.sweep_pairs)
                 for x in arr[:nl.value]]
 
     def sweep(self, level, b, x, backward=False, stream=None):

@@ -75,7 +75,7 @@ class amg_level_info(C.Structure):
                 ("nblocks", C.c_int64), ("ncolors", C.c_int), ("exact_blocks", C.c_int),
                 ("star_rows", C.c_int64), ("star_row_nnz", C.c_int64), ("fac_entries", C.c_int64),
                 ("sweep_form", C.c_int), ("sweep_lanes", C.c_int), ("prec", C.c_int),
-                ("grad_ratio", C.c_double)]
+                ("grad_ratio", C.c_double), ("sweep_pairs", C.c_int)]
 
 
 class amg_int_export(C.Structure):

@@ -167,6 +167,7 @@ struct Level {
   int sweep_mode = SWEEP_COLOUR;
   int wg_S = 256;
   int pipe_grid = 0;
+  int pipe_u = 8;
   int32_t* sweep_sync = nullptr;   // pipelined sweep: ticket + per-colour counters
   int32_t* chunk_blk = nullptr;
   int32_t* ck_row0 = nullptr;
@@ -242,7 +243,7 @@ struct Level {
     }
     s.row_blk = row_blk;
     s.sync = sweep_sync; s.err = err; s.spin_max = spin_max;
-    s.mode = sweep_mode; s.wg = wg_S; s.lpr = lpr_S; s.pipe_grid = pipe_grid;
+    s.mode = sweep_mode; s.wg = wg_S; s.lpr = lpr_S; s.pipe_grid = pipe_grid; s.pipe_u = pipe_u;
     s.n = (int)n;
     s.pn.n = (int)n;
     s.pn.ngroups = ngroups;
@@ -545,11 +546,16 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
   int lpr = L.lpr_A;
   int wg = 256;
   if (L.sweep_mode == SWEEP_PIPE) {
-    // one chunk per 1024-thread workgroup; rows of about 8-16 entries per lane
+    // one chunk per 1024-thread workgroup.  Every lane loads its first 16
+    // (column, value) pairs before the chunk waits for the colour before it
+    // (8 at 8 lanes per row), so the fewest lanes whose 16 pairs hold an
+    // average row (up to 17 entries per lane) give the most rows per chunk
+    // with the whole row in flight: at 128^3, level 1 (266 entries per row)
+    // sweeps in 1.74 ms at 16 lanes against 1.98 ms at 32 lanes with 8 pairs
     const double avg_row = L.n > 0 ? (double)L.nnz / (double)L.n : 0.0;
     wg = 1024;
     lpr = 8;
-    while (lpr < 256 && avg_row > 16.0 * lpr && 1024 / (2 * lpr) >= std::max(maxs, 1)) lpr *= 2;
+    while (lpr < 256 && avg_row > 17.0 * lpr && 1024 / (2 * lpr) >= std::max(maxs, 1)) lpr *= 2;
     if (const char* e = std::getenv("HCURL_AMG_PIPE_LPR")) lpr = std::max(8, std::min(256, std::atoi(e)));
     while (1024 / lpr < std::max(maxs, 1)) lpr /= 2;
   } else {
@@ -564,6 +570,11 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
     fail(AMG_ERR_LIMIT, "no smoother launch shape for this level");
   L.lpr_S = lpr;
   L.wg_S = wg;
+  // pairs per lane loaded before a pipelined chunk waits: 16 from 16 lanes
+  // per row on, 8 at 8 lanes (HCURL_AMG_PIPE_U=8 selects 8 at 16 and 32)
+  L.pipe_u = lpr >= 16 ? 16 : 8;
+  if (const char* e = std::getenv("HCURL_AMG_PIPE_U"))
+    if (std::atoi(e) == 8 && (lpr == 16 || lpr == 32)) L.pipe_u = 8;
   const int rpb = wg / lpr;
   // blocks in (colour, id) order
   std::vector<int64_t> order(ns);
@@ -2034,6 +2045,7 @@ amg_status amg_hier_info(const amg_hier* h, amg_level_info* lv, int cap, int* nl
       lv[l].fac_entries = L.coarsest ? 0 : L.fac_total;
       lv[l].sweep_form = L.coarsest ? 0 : L.sweep_mode;
       lv[l].sweep_lanes = (L.coarsest || L.sweep_mode == SWEEP_DENSE || L.sweep_mode == SWEEP_PANEL) ? 0 : L.lpr_S;
+      lv[l].sweep_pairs = (!L.coarsest && L.sweep_mode == SWEEP_PIPE) ? L.pipe_u : 0;
       lv[l].prec = L.prec;
       lv[l].grad_ratio = L.grad_ratio;
     }

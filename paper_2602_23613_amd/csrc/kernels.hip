@@ -433,10 +433,9 @@ __global__ __launch_bounds__(1024) void k_schwarz_sweep1(SmootherArgs<T> D, int 
 // sets *err and gives up (the sweep result is then wrong and the caller
 // reports the error), and once *err is set no wait blocks, so the grid always
 // drains.  The caller zeroes sync before each sweep.
-template <class T, int LPR>
+template <class T, int LPR, int U>
 __global__ __launch_bounds__(1024) void k_schwarz_pipe(SmootherArgs<T> D, int backward,
                                                        const T* b, T* x) {
-  constexpr int U = unroll_for<LPR>();
   __shared__ ChunkLds<T, LPR, 1024> S;
   __shared__ int ticket[2];
   int* sync = D.sync;
@@ -531,13 +530,14 @@ void schwarz_pipe(const SmootherDev<T>& S, int backward, const T* b, T* x, hipSt
   const int nsync = SYNC_STRIDE * (S.ncolours + 1);
   hipLaunchKernelGGL(k_zero_i32, dim3((nsync + 255) / 256), dim3(256), 0, st, nsync, S.sync);
   const SmootherArgs<T> D = S;
-#define LAUNCH_PIPE(L)                                                                           \
-  if (S.lpr == L) {                                                                              \
-    hipLaunchKernelGGL((k_schwarz_pipe<T, L>), dim3(S.pipe_grid), dim3(1024), 0, st, D, backward, \
-                       b, x);                                                                    \
+#define LAUNCH_PIPE(L, U)                                                                        \
+  if (S.lpr == L && S.pipe_u == U) {                                                             \
+    hipLaunchKernelGGL((k_schwarz_pipe<T, L, U>), dim3(S.pipe_grid), dim3(1024), 0, st, D,        \
+                       backward, b, x);                                                          \
     return;                                                                                      \
   }
-  LAUNCH_PIPE(8) LAUNCH_PIPE(16) LAUNCH_PIPE(32) LAUNCH_PIPE(64) LAUNCH_PIPE(128) LAUNCH_PIPE(256)
+  LAUNCH_PIPE(8, 8) LAUNCH_PIPE(16, 8) LAUNCH_PIPE(32, 8) LAUNCH_PIPE(16, 16) LAUNCH_PIPE(32, 16)
+  LAUNCH_PIPE(64, 16) LAUNCH_PIPE(128, 16) LAUNCH_PIPE(256, 16)
 #undef LAUNCH_PIPE
 }
 

@@ -87,6 +87,7 @@ struct SmootherDev : SmootherArgs<T> {
   int wg = 256;                         // threads per chunk (rows per chunk = wg / lpr)
   int lpr = 8;
   int pipe_grid = 0;                    // workgroups of the pipelined sweep
+  int pipe_u = 8;                       // (column, value) pairs per lane loaded before the wait
   // dense level (nnz = n^2, one block per colour): the sweep keeps r and x in
   // LDS and updates r from a column-major dense copy of A
   int n = 0;

@@ -575,6 +575,39 @@ def _hex32_case():
     return _hex32["p"], _hex32["Ho"]
 
 
+@pytest.mark.parametrize("lpr", [8, 16, 32, 64])
+def test_pipe_lane_shapes_agree(lpr):
+    """The pipelined form at each lane count (HCURL_AMG_PIPE_LPR forces it
+    on every level): 8 lanes load 8 (column, value) pairs per lane before a
+    chunk waits, 16 and more lanes 16 pairs, and 16 lanes give 64 rows per
+    chunk.  Forward, backward, forward sweeps of every level against the
+    oracle's colour sweep from the same b."""
+    d = dev()
+    p, Ho = _hex32_case()
+    mats = amg._cast(Ho, np.float64)
+    tol = max(1e-10, 16 * kappas(Ho)[1] * EPS)
+    rng = np.random.default_rng(34)
+    H = _with_env({"HCURL_AMG_SWEEP": "pipe", "HCURL_AMG_DENSE_SWEEP": "0",
+                   "HCURL_AMG_PIPE_LPR": str(lpr)}, lambda: amglib.Hierarchy(p.A, p.G))
+    info = H.info()
+    assert all(lv["sweep_form"] == "pipe" for lv in info[:-1]), [lv["sweep_form"] for lv in info]
+    for lvl in range(len(info) - 1):
+        b = rng.standard_normal(info[lvl]["n"])
+        bt = torch.tensor(b, device=d)
+        xt = torch.zeros_like(bt)
+        for bw in (False, True, False):
+            H.sweep(lvl, bt, xt, backward=bw)
+        H.check()
+        nc = Ho.levels[lvl].smoother.ncolors
+        xo = np.zeros_like(b)
+        for order in (range(nc), range(nc - 1, -1, -1), range(nc)):
+            xo = amg._schwarz(mats[lvl], xo, b, list(order))
+        err = np.linalg.norm(xt.cpu().numpy() - xo) / np.linalg.norm(xo)
+        print(f"pipe, {lpr} lanes per row, level {lvl}: rel err vs oracle {err:.2e} (tol {tol:.1e})")
+        assert err <= tol, (lpr, lvl)
+    H.close()
+
+
 @pytest.mark.parametrize("form", ["lds", "global"])
 def test_dense_level_sweep_matches_oracle(form):
     """Level 2 of a 32^3 jump problem (1,176 rows, 68% dense, 343 blocks in
