@@ -559,6 +559,7 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
     if (const char* e = std::getenv("HCURL_AMG_PIPE_LPR")) lpr = std::max(8, std::min(256, std::atoi(e)));
     while (1024 / lpr < std::max(maxs, 1)) lpr /= 2;
   } else {
+    if (const char* e = std::getenv("HCURL_AMG_COLOUR_LPR")) lpr = std::max(4, std::min(64, std::atoi(e)));
     while (wg / lpr < std::max(maxs, 1) && wg < 1024) wg *= 2;
     while (wg / lpr < std::max(maxs, 1) && lpr > 4) lpr /= 2;
     if (wg > 256 && lpr < 16) {   // wide workgroups only pay off with wide rows
