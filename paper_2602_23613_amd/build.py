@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhcurlamg.so")
-SOURCES = ["csrc/host_setup.cpp", "csrc/kernels.hip", "csrc/mlp.hip", "csrc/api.hip"]
+SOURCES = ["csrc/host_setup.cpp", "csrc/kernels.hip", "csrc/transpose.hip", "csrc/mlp.hip", "csrc/api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          # no packed FP32 instructions in device code

@@ -141,7 +141,6 @@ struct Level {
   // patch extension: per-column interior supports, their P entries, R rows
   int64_t* patch_ptr = nullptr;
   int32_t* patch_dofs = nullptr;
-  int64_t* patch_dst = nullptr;
   int32_t* r_d1 = nullptr;
   int32_t* r_d2 = nullptr;
   int8_t* r_sg1 = nullptr;
@@ -760,7 +759,6 @@ void build_interp_structs(amg_hier* h, Level& L, hipStream_t st) {
     if (I.patch_max > PATCH_CAP_MAX) fail(AMG_ERR_LIMIT, "patch larger than the kernel's LDS holds");
     L.patch_ptr = h->pool.upload(I.patch_ptr, st);
     L.patch_dofs = h->pool.upload(I.patch_dofs, st);
-    L.patch_dst = h->pool.upload(I.patch_dst, st);
     L.r_d1 = h->pool.upload(I.r_dof1, st);
     L.r_d2 = h->pool.upload(I.r_dof2, st);
     L.r_sg1 = h->pool.upload(I.r_s1, st);
@@ -797,6 +795,16 @@ void build_interp_structs(amg_hier* h, Level& L, hipStream_t st) {
 // P's (possibly truncated) pattern
 void build_transpose(amg_hier* h, Level& L, hipStream_t st) {
   const int64_t n = L.n, nc = L.nc, nnz = L.p_nnz;
+  L.PT_val = h->pool.get<double>(std::max<int64_t>(nnz, 1));
+  L.lpr_PT = lpr_for(nc, nnz);
+  if (nnz < (int64_t)INT32_MAX && nc < (int64_t)INT32_MAX) {
+    // on the device from P's uploaded pattern (a stable sort by column)
+    L.PT_ptr = h->pool.get<int64_t>(nc + 1);
+    L.PT_col = h->pool.get<int32_t>(std::max<int64_t>(nnz, 1));
+    L.PT_perm = h->pool.get<int64_t>(std::max<int64_t>(nnz, 1));
+    HIPC(transpose_pattern(n, nc, nnz, L.P_ptr, L.P_col, L.PT_ptr, L.PT_col, L.PT_perm, st));
+    return;
+  }
   // parallel transpose: thread t takes rows [e0(t), e1(t)) of P and counts
   // its entries per column; a column's entries from thread t follow those of
   // threads < t, so P^T's rows come out in ascending P-row order
@@ -837,8 +845,6 @@ void build_transpose(amg_hier* h, Level& L, hipStream_t st) {
   L.PT_ptr = h->pool.upload(tptr, st);
   L.PT_col = h->pool.upload(tcol, st);
   L.PT_perm = h->pool.upload(perm, st);
-  L.PT_val = h->pool.get<double>(std::max<int64_t>(nnz, 1));
-  L.lpr_PT = lpr_for(nc, nnz);
   // the uploads read tcol and perm before they go out of scope
   HIPC(hipStreamSynchronize(st));
 }
@@ -878,8 +884,8 @@ void truncate_interp(amg_hier* h, Level& L, double tau, hipStream_t st) {
 void compute_interp(amg_hier* h, Level& L, int level, hipStream_t st, bool learned = false) {
   sign_to_val(L.p_nnz, L.P_sign, L.P_val, st);   // untruncated pattern (p_trunc = 0 here)
   if (L.ints.patch)
-    ext_patches(L.nc, L.patch_ptr, L.patch_dofs, L.patch_dst, L.r_d1, L.r_d2, L.r_sg1, L.r_sg2,
-                L.A_dev<double>(), L.P_val, L.ints.patch_max, h->d_flag, st);
+    ext_patches(L.nc, L.patch_ptr, L.patch_dofs, L.P_ptr, L.P_col, L.r_d1, L.r_d2, L.r_sg1,
+                L.r_sg2, L.A_dev<double>(), L.P_val, L.ints.patch_max, h->d_flag, st);
   for (size_t s = 0; s < L.stages.size(); ++s) {
     const Stage& S = L.stages[s];
     ext_blocks(S.b0, S.nb, L.blk_ptr, L.blk_dofs, L.dof_stage, (int)s, L.A_dev<double>(), L.P_ptr,
@@ -1467,18 +1473,31 @@ void level0_host(const amg_csr* A, const amg_csr* G, Level0Host& out, std::vecto
   std::vector<int64_t> gptr;
   std::vector<int32_t> gcol;
   std::vector<double> gval;
+  const char* ve = std::getenv("HCURL_AMG_VERBOSE");
+  const bool steps = ve && std::atoi(ve) >= 2;
+  auto t0 = std::chrono::steady_clock::now();
+  auto mark = [&](const char* what) {
+    if (!steps) return;
+    auto t1 = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[amg]   host %-34s %.3f s\n", what, std::chrono::duration<double>(t1 - t0).count());
+    t0 = t1;
+  };
   host_csr(A, out.Apat.ptr, out.Apat.idx, Aval);
   out.Apat.n = out.Apat.m = A->nrows;
+  mark("A to the host");
   HostError err;
   if (!validate_pattern(A->nrows, A->ncols, out.Apat.ptr.data(), out.Apat.idx.data(), err))
     fail((amg_status)err.code, "A: " + err.msg);
+  mark("A pattern checked");
   host_csr(G, gptr, gcol, &gval);
   if (!incidence_from_csr(G->nrows, G->ncols, gptr.data(), gcol.data(), gval.data(), out.G, err))
     fail((amg_status)err.code, err.msg);
+  mark("G to the host and checked");
   Incidence Gt;
   std::vector<int32_t> B;
   augment_g(out.G, Gt, B);
   out.S = nodal_graph_level0(out.Apat, Gt);
+  mark("nodal graph of level 0");
 }
 
 void fill_export(const LevelInts& I, amg_int_export* o) {
@@ -1617,8 +1636,18 @@ amg_status amg_setup(const amg_csr* A, const amg_csr* G, const amg_options* opt,
       L.S = std::move(l0.S);
       L.n = A->nrows;
       L.nnz = A->nnz;
-      L.A_ptr = h->pool.upload(L.Apat.ptr, st);
-      L.A_col = h->pool.upload(L.Apat.idx, st);
+      if (A->on_device) {
+        // the pattern checked on the host is the caller's device copy: copy it
+        // on the device instead of uploading the host copy again
+        L.A_ptr = h->pool.get<int64_t>(L.n + 1);
+        L.A_col = h->pool.get<int32_t>(std::max<int64_t>(L.nnz, 1));
+        HIPC(hipMemcpyAsync(L.A_ptr, A->rowptr, (L.n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+        if (L.nnz > 0)
+          HIPC(hipMemcpyAsync(L.A_col, A->colidx, L.nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+      } else {
+        L.A_ptr = h->pool.upload(L.Apat.ptr, st);
+        L.A_col = h->pool.upload(L.Apat.idx, st);
+      }
       L.A_val = h->pool.get<double>(L.nnz);
       if (A->on_device) {
         HIPC(hipMemcpyAsync(L.A_val, A->val, L.nnz * sizeof(double), hipMemcpyDeviceToDevice, st));

@@ -744,59 +744,137 @@ void extension_and_pattern(const Pattern& A, const Incidence& Gt, const EdgeGrap
 // the coupled DoFs join in order of count (largest first, ties to the smaller
 // id) until S_c holds `cap` DoFs.  Replaces the block pattern of P: interior
 // row i holds the columns c with i in S_c (ascending), exterior rows keep
-// their R^T entry; patch_dst maps every (c, i) to its entry of P.
+// their R^T entry.
+
+// Open-addressing map from DoF ids to small counts for the candidates of one
+// round; a generation number clears it in O(1).
+struct CandMap {
+  std::vector<int32_t> key, val;
+  std::vector<uint32_t> gen;
+  uint32_t g = 0, mask = 0;
+  void reset(int64_t most) {
+    size_t cap = 64;
+    while ((int64_t)cap < 2 * most) cap <<= 1;
+    if (cap > key.size()) {
+      key.assign(cap, 0);
+      val.assign(cap, 0);
+      gen.assign(cap, 0);
+      g = 0;
+    }
+    mask = (uint32_t)(key.size() - 1);
+    if (++g == 0) {
+      std::fill(gen.begin(), gen.end(), 0u);
+      g = 1;
+    }
+  }
+  uint32_t slot(int32_t k) const {
+    uint32_t h = ((uint32_t)k * 2654435761u) & mask;
+    while (gen[h] == g && key[h] != k) h = (h + 1) & mask;
+    return h;
+  }
+  bool has(int32_t k) const { return gen[slot(k)] == g; }
+  // count one more coupling of k; true if k is new this round
+  bool bump(int32_t k) {
+    const uint32_t h = slot(k);
+    if (gen[h] != g) {
+      gen[h] = g;
+      key[h] = k;
+      val[h] = 1;
+      return true;
+    }
+    ++val[h];
+    return false;
+  }
+  int32_t count(int32_t k) const { return val[slot(k)]; }
+};
+
 void patch_extension_pattern(const Pattern& A, int hops, int cap, LevelInts& L) {
   StepClock clk;
   const int64_t n = A.n;
   const int64_t nc = (int64_t)L.r_dof1.size();
   std::vector<char> isint(n, 0);
   for (int32_t e : L.interior) isint[e] = 1;
-  std::vector<std::vector<int32_t>> sets(nc);
-  parallel_for(nc, [&](int64_t lo, int64_t hi) {
-    std::vector<int64_t> stamp(n, -1);
-    std::vector<int32_t> cnt(n, 0);
-    std::vector<char> in(n, 0);
-    std::vector<int32_t> S, snap, cand;
-    int64_t tag = lo * (int64_t)(hops + 1);
-    for (int64_t c = lo; c < hi; ++c) {
+  // every thread takes one contiguous range of columns and lists their
+  // supports in one flat vector; the ranges are then copied into place
+  const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), nc / 4096));
+  const int64_t chunk = (nc + nt - 1) / std::max(nt, 1);
+  auto run_threads = [&](const std::function<void(int)>& body) {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) th.emplace_back(body, t);
+    for (auto& x : th) x.join();
+  };
+  std::vector<std::vector<int32_t>> flat(nt);
+  L.patch_ptr.assign(nc + 1, 0);
+  run_threads([&](int t) {
+    const int64_t c0 = std::min(nc, t * chunk), c1 = std::min(nc, c0 + chunk);
+    CandMap cand_map, in_s;
+    std::vector<int32_t> S, snap, cand, tie;
+    std::vector<int32_t> hist;
+    auto& out = flat[t];
+    for (int64_t c = c0; c < c1; ++c) {
       S.clear();
+      in_s.reset(cap);
       const int32_t ext[2] = {L.r_dof1[c], L.r_dof2[c]};
-      for (int h = 0; h < hops && (int64_t)S.size() < (int64_t)cap; ++h, ++tag) {
+      for (int h = 0; h < hops && (int64_t)S.size() < (int64_t)cap; ++h) {
         snap.assign(ext, ext + 2);
         snap.insert(snap.end(), S.begin(), S.end());
+        int64_t most = 0;
+        for (int32_t e : snap) most += A.ptr[e + 1] - A.ptr[e];
+        cand_map.reset(std::min<int64_t>(most, n));
         cand.clear();
         for (int32_t e : snap)
           for (int64_t q = A.ptr[e]; q < A.ptr[e + 1]; ++q) {
             const int32_t j = A.idx[q];
-            if (!isint[j] || in[j]) continue;
-            if (stamp[j] != tag) { stamp[j] = tag; cnt[j] = 0; cand.push_back(j); }
-            ++cnt[j];
+            if (!isint[j] || in_s.has(j)) continue;
+            if (cand_map.bump(j)) cand.push_back(j);
           }
-        std::sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) {
-          return cnt[a] != cnt[b] ? cnt[a] > cnt[b] : a < b;
-        });
         const int64_t room = std::max<int64_t>(0, (int64_t)cap - (int64_t)S.size());
-        for (int64_t t = 0; t < (int64_t)cand.size() && t < room; ++t) {
-          S.push_back(cand[t]);
-          in[cand[t]] = 1;
+        auto take = [&](int32_t j) {
+          S.push_back(j);
+          in_s.bump(j);
+        };
+        if ((int64_t)cand.size() <= room) {
+          for (int32_t j : cand) take(j);
+          continue;
         }
+        // the first `room` candidates in (count descending, id ascending)
+        // order: every candidate above the threshold count, then the
+        // smallest ids of the threshold count
+        int32_t cmax = 0;
+        for (int32_t j : cand) cmax = std::max(cmax, cand_map.count(j));
+        hist.assign(cmax + 2, 0);
+        for (int32_t j : cand) ++hist[cand_map.count(j)];
+        int32_t thr = cmax;
+        int64_t above = 0;
+        while (above + hist[thr] < room) above += hist[thr--];
+        tie.clear();
+        for (int32_t j : cand) {
+          const int32_t k = cand_map.count(j);
+          if (k > thr) take(j);
+          else if (k == thr) tie.push_back(j);
+        }
+        const int64_t rest = room - above;
+        std::nth_element(tie.begin(), tie.begin() + (rest - 1), tie.end());
+        for (int64_t q = 0; q < rest; ++q) take(tie[q]);
       }
-      for (int32_t j : S) in[j] = 0;
       std::sort(S.begin(), S.end());
-      sets[c] = S;
+      out.insert(out.end(), S.begin(), S.end());
+      L.patch_ptr[c + 1] = (int64_t)S.size();
     }
   });
   clk.mark("patch supports");
   L.patch = true;
-  L.patch_ptr.assign(nc + 1, 0);
   L.patch_max = 0;
   for (int64_t c = 0; c < nc; ++c) {
-    L.patch_ptr[c + 1] = L.patch_ptr[c] + (int64_t)sets[c].size();
-    L.patch_max = std::max<int>(L.patch_max, (int)sets[c].size());
+    L.patch_max = std::max<int>(L.patch_max, (int)L.patch_ptr[c + 1]);
+    L.patch_ptr[c + 1] += L.patch_ptr[c];
   }
   L.patch_dofs.resize(L.patch_ptr[nc]);
-  for (int64_t c = 0; c < nc; ++c)
-    std::copy(sets[c].begin(), sets[c].end(), L.patch_dofs.begin() + L.patch_ptr[c]);
+  run_threads([&](int t) {
+    const int64_t c0 = std::min(nc, t * chunk);
+    std::copy(flat[t].begin(), flat[t].end(), L.patch_dofs.begin() + L.patch_ptr[c0]);
+    std::vector<int32_t>().swap(flat[t]);
+  });
   // P's pattern: exterior rows one entry, interior rows one per patch holding
   // them, in ascending column order.  A parallel transpose of the patch lists:
   // thread t takes columns [c0(t), c1(t)) and counts its entries per row; a
@@ -805,14 +883,7 @@ void patch_extension_pattern(const Pattern& A, int hops, int cap, LevelInts& L) 
   Pattern& P = L.p;
   P.n = n;
   P.m = nc;
-  const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), nc / 4096));
-  const int64_t chunk = (nc + nt - 1) / std::max(nt, 1);
   std::vector<std::vector<int32_t>> cnt(nt);
-  auto run_threads = [&](const std::function<void(int)>& body) {
-    std::vector<std::thread> th;
-    for (int t = 0; t < nt; ++t) th.emplace_back(body, t);
-    for (auto& x : th) x.join();
-  };
   run_threads([&](int t) {
     cnt[t].assign(n, 0);
     const int64_t c0 = std::min(nc, t * chunk), c1 = std::min(nc, c0 + chunk);
@@ -837,7 +908,7 @@ void patch_extension_pattern(const Pattern& A, int hops, int cap, LevelInts& L) 
       }
     }
   });
-  P.idx.assign(P.ptr[n], 0);
+  P.idx.resize(P.ptr[n]);
   L.p_ext_sign.assign(P.ptr[n], 0);
   for (int64_t c = 0; c < nc; ++c) {
     P.idx[P.ptr[L.r_dof1[c]]] = (int32_t)c;
@@ -845,15 +916,12 @@ void patch_extension_pattern(const Pattern& A, int hops, int cap, LevelInts& L) 
     P.idx[P.ptr[L.r_dof2[c]]] = (int32_t)c;
     L.p_ext_sign[P.ptr[L.r_dof2[c]]] = L.r_s2[c];
   }
-  L.patch_dst.resize(L.patch_dofs.size());
   run_threads([&](int t) {
     const int64_t c0 = std::min(nc, t * chunk), c1 = std::min(nc, c0 + chunk);
     for (int64_t c = c0; c < c1; ++c)
       for (int64_t q = L.patch_ptr[c]; q < L.patch_ptr[c + 1]; ++q) {
         const int32_t j = L.patch_dofs[q];
-        const int64_t d = P.ptr[j] + cnt[t][j]++;
-        P.idx[d] = (int32_t)c;
-        L.patch_dst[q] = d;
+        P.idx[P.ptr[j] + cnt[t][j]++] = (int32_t)c;
       }
   });
   clk.mark("P pattern from the patches");
@@ -973,7 +1041,6 @@ bool setup_level_integers(const Pattern& A, const Incidence& G, const Pattern& S
   L.patch = false;
   L.patch_ptr.clear();
   L.patch_dofs.clear();
-  L.patch_dst.clear();
   L.patch_max = 0;
   if (ext.ext_mode == 1) {
     // no blocks of A_II: every interior DoF is extended through the patches

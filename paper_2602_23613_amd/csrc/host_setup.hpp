@@ -66,11 +66,10 @@ struct LevelInts {
   std::vector<int32_t> dof_stage;         // -1 exterior, else depth stage index of the DoF's block
   std::vector<int64_t> stage_ptr;         // blocks of each depth stage: [stage_ptr[s], stage_ptr[s+1])
   // patch extension (ext_mode 1): interior support of every column of P
-  // (ascending DoFs) and, per patch entry, its position in P's entries
+  // (ascending DoFs)
   bool patch = false;
   std::vector<int64_t> patch_ptr;
   std::vector<int32_t> patch_dofs;
-  std::vector<int64_t> patch_dst;
   int patch_max = 0;
 };
 

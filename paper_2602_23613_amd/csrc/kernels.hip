@@ -1693,7 +1693,7 @@ __device__ __forceinline__ int tri_off(int i) { return i * (i + 1) / 2; }
 
 __global__ __launch_bounds__(256) void k_ext_patch(
     const int64_t* __restrict__ pptr, const int32_t* __restrict__ pdofs,
-    const int64_t* __restrict__ pdst, const int32_t* __restrict__ rd1,
+    const int64_t* __restrict__ Pptr, const int32_t* __restrict__ Pcol, const int32_t* __restrict__ rd1,
     const int32_t* __restrict__ rd2, const int8_t* __restrict__ rs1,
     const int8_t* __restrict__ rs2, const int64_t* __restrict__ Aptr,
     const int32_t* __restrict__ Acol, const double* __restrict__ Aval, double* __restrict__ Pval,
@@ -1914,7 +1914,16 @@ __global__ __launch_bounds__(256) void k_ext_patch(
     }
     __syncthreads();
   }
-  for (int t = tid; t < m; t += 256) Pval[pdst[p0 + t]] = y[t];
+  // x_i goes to P(S_i, c): row S_i of P lists its columns in ascending order
+  for (int t = tid; t < m; t += 256) {
+    const int64_t r0 = Pptr[dofs[t]];
+    int lo = 0, hi = (int)(Pptr[dofs[t] + 1] - r0);
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (Pcol[r0 + mid] < (int32_t)c) lo = mid + 1; else hi = mid;
+    }
+    Pval[r0 + lo] = y[t];
+  }
 }
 
 size_t ext_patch_lds(int mmax) {
@@ -1922,13 +1931,14 @@ size_t ext_patch_lds(int mmax) {
          sizeof(int64_t) * (size_t)mmax + sizeof(int32_t) * (2 * (size_t)mmax + 1);
 }
 
-void ext_patches(int64_t nc, const int64_t* pptr, const int32_t* pdofs, const int64_t* pdst,
-                 const int32_t* rd1, const int32_t* rd2, const int8_t* rs1, const int8_t* rs2,
-                 const CsrDev<double>& A, double* Pval, int mmax, int* flag, hipStream_t st) {
+void ext_patches(int64_t nc, const int64_t* pptr, const int32_t* pdofs, const int64_t* Pptr,
+                 const int32_t* Pcol, const int32_t* rd1, const int32_t* rd2, const int8_t* rs1,
+                 const int8_t* rs2, const CsrDev<double>& A, double* Pval, int mmax, int* flag,
+                 hipStream_t st) {
   if (nc <= 0 || mmax <= 0) return;
   in_batches(nc, [&](int64_t c0, unsigned g) {
-    hipLaunchKernelGGL(k_ext_patch, dim3(g), dim3(256), ext_patch_lds(mmax), st, pptr, pdofs, pdst,
-                       rd1, rd2, rs1, rs2, A.ptr, A.col, A.val, Pval, mmax, flag, c0);
+    hipLaunchKernelGGL(k_ext_patch, dim3(g), dim3(256), ext_patch_lds(mmax), st, pptr, pdofs, Pptr,
+                       Pcol, rd1, rd2, rs1, rs2, A.ptr, A.col, A.val, Pval, mmax, flag, c0);
   });
 }
 
@@ -1985,13 +1995,14 @@ constexpr int HCAP = 8192;   // LDS hash slots of the symbolic passes (32 KiB)
 // insert the columns of row i of X Y into an LDS hash; the 256 threads take
 // the entries of X's row in turn and walk the matching rows of Y
 __device__ void mm_insert(int64_t i, const int64_t* Xptr, const int32_t* Xcol, const int64_t* Yptr,
-                          const int32_t* Ycol, int32_t* hash, int* count, int* overflow) {
+                          const int32_t* Ycol, int32_t* hash, int tsize, int* count, int* overflow) {
+  const uint32_t mask = (uint32_t)tsize - 1u;
   for (int64_t t = Xptr[i] + threadIdx.x; t < Xptr[i + 1]; t += blockDim.x) {
     const int32_t k = Xcol[t];
     for (int64_t u = Yptr[k]; u < Yptr[k + 1]; ++u) {
       if (*(volatile int*)overflow) return;   // the row goes to the wide passes anyway
       const int32_t J = Ycol[u];
-      uint32_t h = ((uint32_t)J * 2654435761u) & (HCAP - 1);
+      uint32_t h = ((uint32_t)J * 2654435761u) & mask;
       int probes = 0;
       while (true) {
         int32_t old = atomicCAS(&hash[h], -1, J);
@@ -2000,14 +2011,36 @@ __device__ void mm_insert(int64_t i, const int64_t* Xptr, const int32_t* Xcol, c
           break;
         }
         if (old == J) break;
-        h = (h + 1) & (HCAP - 1);
-        if (++probes >= HCAP) {
+        h = (h + 1) & mask;
+        if (++probes >= tsize) {
           atomicExch(overflow, 1);
           break;
         }
       }
     }
   }
+}
+
+// Hash slots for row i: the sum of the lengths of the Y rows that X's row
+// touches bounds its distinct columns; the table takes the power of two at
+// or above twice that bound (at least 64, at most HCAP), so that a short row
+// does not clear and scan all HCAP slots.  Every thread of the block returns
+// the same size.
+__device__ int mm_table_size(int64_t i, const int64_t* Xptr, const int32_t* Xcol,
+                             const int64_t* Yptr, int* red) {
+  if (threadIdx.x == 0) *red = 0;
+  __syncthreads();
+  int64_t u = 0;
+  for (int64_t t = Xptr[i] + threadIdx.x; t < Xptr[i + 1]; t += blockDim.x) {
+    const int32_t k = Xcol[t];
+    u += Yptr[k + 1] - Yptr[k];
+  }
+  if (u > 0) atomicAdd(red, (int)(u < HCAP ? u : HCAP));
+  __syncthreads();
+  const int bound = *red;
+  int tsize = 64;
+  while (tsize < HCAP && tsize < 2 * bound) tsize <<= 1;
+  return tsize;
 }
 
 __global__ __launch_bounds__(256) void k_mm_count(int64_t nrows, const int64_t* __restrict__ Xptr,
@@ -2019,14 +2052,16 @@ __global__ __launch_bounds__(256) void k_mm_count(int64_t nrows, const int64_t* 
   __shared__ int32_t hash[HCAP];
   __shared__ int count;
   __shared__ int full;
+  __shared__ int red;
   const int64_t i = r0 + blockIdx.x;
-  for (int t = threadIdx.x; t < HCAP; t += blockDim.x) hash[t] = -1;
+  const int tsize = mm_table_size(i, Xptr, Xcol, Yptr, &red);
+  for (int t = threadIdx.x; t < tsize; t += blockDim.x) hash[t] = -1;
   if (threadIdx.x == 0) {
     count = 0;
     full = 0;
   }
   __syncthreads();
-  mm_insert(i, Xptr, Xcol, Yptr, Ycol, hash, &count, &full);
+  mm_insert(i, Xptr, Xcol, Yptr, Ycol, hash, tsize, &count, &full);
   __syncthreads();
   // a row too wide for the hash passes (more than wide_at <= HCAP / 2
   // columns) is marked -1 and counted again by k_mm_count_wide
@@ -2045,28 +2080,31 @@ __global__ __launch_bounds__(256) void k_mm_fill(int64_t nrows, const int64_t* _
   __shared__ int count;
   __shared__ int nfill;
   __shared__ int full;
+  __shared__ int red;
   const int64_t i = r0 + blockIdx.x;
   if (Cptr[i + 1] - Cptr[i] > wide_at) return;   // wide row: k_mm_fill_wide
-  for (int t = threadIdx.x; t < HCAP; t += blockDim.x) hash[t] = -1;
+  const int tsize = mm_table_size(i, Xptr, Xcol, Yptr, &red);
+  for (int t = threadIdx.x; t < tsize; t += blockDim.x) hash[t] = -1;
   if (threadIdx.x == 0) {
     count = 0;
     nfill = 0;
     full = 0;
   }
   __syncthreads();
-  mm_insert(i, Xptr, Xcol, Yptr, Ycol, hash, &count, &full);
+  mm_insert(i, Xptr, Xcol, Yptr, Ycol, hash, tsize, &count, &full);
   __syncthreads();
   if (full) {   // cannot happen: the row was counted to fit
     if (threadIdx.x == 0) atomicExch(overflow, 1);
     return;
   }
   // gather the keys into registers, then compact them to the front
+  // (m <= tsize / 2, so the sort's padded length P2 stays inside the table)
   int32_t keys[HCAP / 256];
   int nk = 0;
-  for (int t = threadIdx.x; t < HCAP; t += blockDim.x)
+  for (int t = threadIdx.x; t < tsize; t += blockDim.x)
     if (hash[t] >= 0) keys[nk++] = hash[t];
   __syncthreads();
-  for (int t = threadIdx.x; t < HCAP; t += blockDim.x) hash[t] = 0x7fffffff;
+  for (int t = threadIdx.x; t < tsize; t += blockDim.x) hash[t] = 0x7fffffff;
   __syncthreads();
   for (int t = 0; t < nk; ++t) hash[atomicAdd(&nfill, 1)] = keys[t];
   __syncthreads();

@@ -181,9 +181,16 @@ int red_grid();
 
 // patch extension: one workgroup per column of P (patch of at most mmax DoFs)
 size_t ext_patch_lds(int mmax);
-void ext_patches(int64_t nc, const int64_t* pptr, const int32_t* pdofs, const int64_t* pdst,
-                 const int32_t* rd1, const int32_t* rd2, const int8_t* rs1, const int8_t* rs2,
-                 const CsrDev<double>& A, double* Pval, int mmax, int* flag, hipStream_t st);
+// P^T's pattern on the device (transpose.hip): row pointers tptr (nc + 1),
+// column ids tcol (nnz) and perm[q] = position of P's entry q in P^T.
+// Needs nnz and nc below 2^31; returns the first HIP error.
+hipError_t transpose_pattern(int64_t n, int64_t nc, int64_t nnz, const int64_t* ptr,
+                             const int32_t* col, int64_t* tptr, int32_t* tcol, int64_t* perm,
+                             hipStream_t st);
+void ext_patches(int64_t nc, const int64_t* pptr, const int32_t* pdofs, const int64_t* Pptr,
+                 const int32_t* Pcol, const int32_t* rd1, const int32_t* rd2, const int8_t* rs1,
+                 const int8_t* rs2, const CsrDev<double>& A, double* Pval, int mmax, int* flag,
+                 hipStream_t st);
 size_t ext_block_lds(int smax, int ctile);
 int ext_block_tile(int smax);
 void ext_blocks(int64_t b0, int64_t nb, const int64_t* bptr, const int32_t* bdofs,

@@ -145,7 +145,7 @@ def test_noalloc_spmv_dot_rejects_sizes_beyond_its_scratch():
     assert b"static scratch" in lib.amg_last_error()
 
 
-@pytest.mark.parametrize("kind,size,cap", [("hex", 6, 128), ("hex", 6, 16), ("tri", 4, 128),
+@pytest.mark.parametrize("kind,size,cap", [("hex", 6, 128), ("hex", 6, 16), ("hex", 8, 40), ("tri", 4, 128),
                                            ("tet", 4, 64)])
 def test_patch_sets_bit_exact(kind, size, cap):
     """The patch extension's per-column interior supports (integer graph work
