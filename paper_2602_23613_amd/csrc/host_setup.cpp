@@ -264,41 +264,51 @@ void augment_g(const Incidence& G, Incidence& Gt, std::vector<int32_t>& B) {
 // coupled in A to some edge at v.
 Pattern nodal_graph_level0(const Pattern& A, const Incidence& Gt) {
   Pattern N2R = node_to_rows(Gt);
-  int64_t nn = Gt.m;
-  auto visit = [&](int64_t u, std::vector<int64_t>& stamp, std::vector<int32_t>& out) {
-    out.clear();
-    for (int64_t t = N2R.ptr[u]; t < N2R.ptr[u + 1]; ++t) {
-      int32_t e = N2R.idx[t];
-      for (int64_t q = A.ptr[e]; q < A.ptr[e + 1]; ++q) {
-        int32_t j = A.idx[q];
-        int32_t nodes[2] = {Gt.a[j], Gt.b[j]};
-        for (int32_t v : nodes) {
-          if (v < 0 || v == u || stamp[v] == u) continue;
-          stamp[v] = u;
-          out.push_back(v);
-        }
-      }
-    }
-    std::sort(out.begin(), out.end());
-  };
-  std::vector<std::vector<int32_t>> rows(nn);
-  parallel_for(nn, [&](int64_t b, int64_t e) {
-    std::vector<int64_t> stamp(nn, -1);
-    std::vector<int32_t> out;
-    for (int64_t u = b; u < e; ++u) {
-      visit(u, stamp, out);
-      rows[u] = out;
-    }
-  });
+  const int64_t nn = Gt.m;
+  // every thread lists the sorted neighbours of one contiguous range of
+  // nodes in a flat vector; the lists are then copied into place
+  const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), nn / 4096));
+  const int64_t chunk = (nn + nt - 1) / nt;
+  std::vector<std::vector<int32_t>> flat(nt);
   Pattern S;
   S.n = S.m = nn;
   S.ptr.assign(nn + 1, 0);
-  for (int64_t u = 0; u < nn; ++u) S.ptr[u + 1] = S.ptr[u] + (int64_t)rows[u].size();
+  auto run_threads = [&](const std::function<void(int)>& body) {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) th.emplace_back(body, t);
+    for (auto& x : th) x.join();
+  };
+  run_threads([&](int t) {
+    const int64_t b = std::min(nn, t * chunk), e = std::min(nn, b + chunk);
+    std::vector<int32_t> stamp(nn, -1);
+    std::vector<int32_t> out;
+    auto& dst = flat[t];
+    for (int64_t u = b; u < e; ++u) {
+      out.clear();
+      for (int64_t k = N2R.ptr[u]; k < N2R.ptr[u + 1]; ++k) {
+        const int32_t r = N2R.idx[k];
+        for (int64_t q = A.ptr[r]; q < A.ptr[r + 1]; ++q) {
+          const int32_t j = A.idx[q];
+          const int32_t nodes[2] = {Gt.a[j], Gt.b[j]};
+          for (int32_t v : nodes) {
+            if (v < 0 || v == u || stamp[v] == (int32_t)u) continue;
+            stamp[v] = (int32_t)u;
+            out.push_back(v);
+          }
+        }
+      }
+      std::sort(out.begin(), out.end());
+      dst.insert(dst.end(), out.begin(), out.end());
+      S.ptr[u + 1] = (int64_t)out.size();
+    }
+  });
+  for (int64_t u = 0; u < nn; ++u) S.ptr[u + 1] += S.ptr[u];
   S.idx.resize(S.ptr[nn]);
-  for (int64_t u = 0; u < nn; ++u) {
-    std::copy(rows[u].begin(), rows[u].end(), S.idx.begin() + S.ptr[u]);
-    std::vector<int32_t>().swap(rows[u]);
-  }
+  run_threads([&](int t) {
+    const int64_t b = std::min(nn, t * chunk);
+    std::copy(flat[t].begin(), flat[t].end(), S.idx.begin() + S.ptr[b]);
+    std::vector<int32_t>().swap(flat[t]);
+  });
   return S;
 }
 
@@ -891,13 +901,9 @@ void patch_extension_pattern(const Pattern& A, int hops, int cap, LevelInts& L) 
   });
   std::vector<char> ext(n, 0);
   for (int64_t c = 0; c < nc; ++c) ext[L.r_dof1[c]] = ext[L.r_dof2[c]] = 1;
+  // per-thread start of each row's run (relative to the row) in place of the
+  // counts, and the row lengths; then the row pointers
   P.ptr.assign(n + 1, 0);
-  for (int64_t e = 0; e < n; ++e) {
-    int64_t len = ext[e];
-    for (int t = 0; t < nt; ++t) len += cnt[t][e];
-    P.ptr[e + 1] = P.ptr[e] + len;
-  }
-  // per-thread start of each row's run (relative to the row), in place of the counts
   parallel_for(n, [&](int64_t lo, int64_t hi) {
     for (int64_t e = lo; e < hi; ++e) {
       int32_t acc = ext[e];
@@ -906,8 +912,10 @@ void patch_extension_pattern(const Pattern& A, int hops, int cap, LevelInts& L) 
         cnt[t][e] = acc;
         acc += c;
       }
+      P.ptr[e + 1] = acc;
     }
   });
+  for (int64_t e = 0; e < n; ++e) P.ptr[e + 1] += P.ptr[e];
   P.idx.resize(P.ptr[n]);
   L.p_ext_sign.assign(P.ptr[n], 0);
   for (int64_t c = 0; c < nc; ++c) {
