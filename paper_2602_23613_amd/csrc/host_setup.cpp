@@ -953,7 +953,15 @@ void stars_and_colours(const Pattern& A, const Incidence& G, LevelInts& L) {
   }
   int64_t ns = (int64_t)L.star_ptr.size() - 1;
   L.star_color.assign(ns, -1);
-  std::vector<int64_t> stamp(A.n, -1);
+  // the (at most two) stars holding each DoF, -1 for none
+  std::vector<int32_t> dstar(2 * A.n, -1);
+  parallel_for(A.n, [&](int64_t lo, int64_t hi) {
+    for (int64_t d = lo; d < hi; ++d) {
+      if (G.a[d] >= 0) dstar[2 * d] = star_of_node[G.a[d]];
+      if (G.b[d] >= 0) dstar[2 * d + 1] = star_of_node[G.b[d]];
+    }
+  });
+  std::vector<int32_t> stamp(A.n, -1);
   std::vector<int64_t> cstamp(64, -1);
   int ncol = 0;
   for (int64_t b = 0; b < ns; ++b) {
@@ -962,12 +970,10 @@ void stars_and_colours(const Pattern& A, const Incidence& G, LevelInts& L) {
       int32_t e = L.star_dofs[t];
       for (int64_t q = A.ptr[e]; q <= A.ptr[e + 1]; ++q) {
         int32_t d = (q == A.ptr[e + 1]) ? e : A.idx[q];
-        if (stamp[d] == b) continue;
-        stamp[d] = b;
-        int32_t nodes[2] = {G.a[d], G.b[d]};
-        for (int32_t v : nodes) {
-          if (v < 0) continue;
-          int32_t c = star_of_node[v];
+        if (stamp[d] == (int32_t)b) continue;
+        stamp[d] = (int32_t)b;
+        for (int k = 0; k < 2; ++k) {
+          const int32_t c = dstar[2 * (int64_t)d + k];
           if (c >= 0 && c < b) {
             int col = L.star_color[c];
             if (col >= (int)cstamp.size()) cstamp.resize(col + 1, -1);
