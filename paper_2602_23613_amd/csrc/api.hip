@@ -1699,8 +1699,9 @@ amg_status amg_setup(const amg_csr* A, const amg_csr* G, const amg_options* opt,
         L.ints.star_color = std::move(s.star_color);
         L.ints.ncolors = s.ncolors;
       }
+      clk.mark(st, "smoother stars + colours (wait)", l);
       build_smoother(h.get(), L, st);
-      clk.mark(st, "smoother stars + colours", l);
+      clk.mark(st, "smoother chunks and row copy", l);
       factor_smoother(h.get(), L, l, st);
       clk.mark(st, "smoother factors + l1 (GPU)", l);
       if (!user) {

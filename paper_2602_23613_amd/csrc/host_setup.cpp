@@ -961,31 +961,60 @@ void stars_and_colours(const Pattern& A, const Incidence& G, LevelInts& L) {
       if (G.b[d] >= 0) dstar[2 * d + 1] = star_of_node[G.b[d]];
     }
   });
-  std::vector<int32_t> stamp(A.n, -1);
+  // the earlier stars (smaller index) that share a DoF with, or are
+  // A-coupled to, each star: listed in parallel, one contiguous range of
+  // stars per thread
+  const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), ns / 4096));
+  const int64_t chunk = (ns + nt - 1) / std::max(nt, 1);
+  std::vector<std::vector<int32_t>> flat(nt);
+  std::vector<int64_t> nb_ptr(ns + 1, 0);
+  {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+      th.emplace_back([&, t]() {
+        const int64_t b0 = std::min(ns, t * chunk), b1 = std::min(ns, b0 + chunk);
+        std::vector<int32_t> sstamp(ns, -1);
+        auto& out = flat[t];
+        for (int64_t b = b0; b < b1; ++b) {
+          const size_t before = out.size();
+          for (int64_t t2 = L.star_ptr[b]; t2 < L.star_ptr[b + 1]; ++t2) {
+            const int32_t e = L.star_dofs[t2];
+            for (int64_t q = A.ptr[e]; q <= A.ptr[e + 1]; ++q) {
+              const int32_t d = (q == A.ptr[e + 1]) ? e : A.idx[q];
+              for (int k = 0; k < 2; ++k) {
+                const int32_t c = dstar[2 * (int64_t)d + k];
+                if (c >= 0 && c < b && sstamp[c] != (int32_t)b) {
+                  sstamp[c] = (int32_t)b;
+                  out.push_back(c);
+                }
+              }
+            }
+          }
+          nb_ptr[b + 1] = (int64_t)(out.size() - before);
+        }
+      });
+    for (auto& x : th) x.join();
+  }
+  for (int64_t b = 0; b < ns; ++b) nb_ptr[b + 1] += nb_ptr[b];
+  // greedy colouring in star order: the smallest colour no earlier
+  // neighbour has
   std::vector<int64_t> cstamp(64, -1);
   int ncol = 0;
-  for (int64_t b = 0; b < ns; ++b) {
-    // colours of earlier blocks that share a DoF with, or are A-coupled to, block b
-    for (int64_t t = L.star_ptr[b]; t < L.star_ptr[b + 1]; ++t) {
-      int32_t e = L.star_dofs[t];
-      for (int64_t q = A.ptr[e]; q <= A.ptr[e + 1]; ++q) {
-        int32_t d = (q == A.ptr[e + 1]) ? e : A.idx[q];
-        if (stamp[d] == (int32_t)b) continue;
-        stamp[d] = (int32_t)b;
-        for (int k = 0; k < 2; ++k) {
-          const int32_t c = dstar[2 * (int64_t)d + k];
-          if (c >= 0 && c < b) {
-            int col = L.star_color[c];
-            if (col >= (int)cstamp.size()) cstamp.resize(col + 1, -1);
-            cstamp[col] = b;
-          }
-        }
+  for (int t = 0; t < nt; ++t) {
+    const int64_t b0 = std::min(ns, t * chunk), b1 = std::min(ns, b0 + chunk);
+    const std::vector<int32_t>& nb = flat[t];
+    for (int64_t b = b0; b < b1; ++b) {
+      for (int64_t q = nb_ptr[b]; q < nb_ptr[b + 1]; ++q) {
+        const int col = L.star_color[nb[q - nb_ptr[b0]]];
+        if (col >= (int)cstamp.size()) cstamp.resize(col + 1, -1);
+        cstamp[col] = b;
       }
+      int col = 0;
+      while (col < (int)cstamp.size() && cstamp[col] == b) ++col;
+      L.star_color[b] = col;
+      ncol = std::max(ncol, col + 1);
     }
-    int col = 0;
-    while (col < (int)cstamp.size() && cstamp[col] == b) ++col;
-    L.star_color[b] = col;
-    ncol = std::max(ncol, col + 1);
+    std::vector<int32_t>().swap(flat[t]);
   }
   L.ncolors = ncol;
 }
