@@ -21,7 +21,8 @@
  *   - Every function returns amg_status; 0 (AMG_OK) is success.  On a
  *     negative status the caller's buffers are left untouched and
  *     amg_last_error() returns a message naming the level and the cause.
- *   - CSR inputs are borrowed for the duration of the call only: column
+ *   - CSR inputs are borrowed for the duration of the call only (except a
+ *     device A under amg_options.borrow_a): column
  *     indices sorted and unique within each row, int64 row pointers, int32
  *     column indices, FP64 values.  `on_device` = 1 means the three arrays
  *     are HIP device pointers, 0 means host pointers.
@@ -142,6 +143,13 @@ typedef struct {
   int ext_mode;
   int patch_hops;          /* default 2 */
   int patch_cap;           /* default 128 */
+  /* 0 (default): the hierarchy keeps its own device copy of A.  1, with a
+     device A (on_device = 1): the hierarchy reads the caller's rowptr, colidx
+     and val in place and copies nothing; the caller keeps them allocated and
+     unchanged until amg_destroy, or until an amg_resetup_numeric whose A (also
+     on the device, same pattern) is then borrowed in its place.  A host A is
+     copied whatever this says. */
+  int borrow_a;
 } amg_options;
 
 enum { AMG_EXT_BLOCKS = 0, AMG_EXT_PATCH = 1 };
@@ -214,7 +222,8 @@ void amg_default_options(amg_options *opt);
    node-star Schwarz smoother with its l1 diagonal (Section 5); coarsening
    stops as in Section 5 (20 levels, 32 DoFs).  The integer phase runs on the
    host, every floating-point step on the GPU.  A and G are borrowed for the
-   call; everything kept is copied.  On success *out owns a new handle; on
+   call; everything kept is copied (with borrow_a = 1, a device A is read in
+   place for the life of the handle instead).  On success *out owns a new handle; on
    failure *out is NULL and nothing is left allocated. */
 amg_status amg_setup(const amg_csr *A, const amg_csr *G, const amg_options *opt,
                      void *stream, amg_hier **out);
@@ -222,7 +231,10 @@ amg_status amg_setup(const amg_csr *A, const amg_csr *G, const amg_options *opt,
 /* Recompute every floating-point part of the hierarchy (P, A_c, smoother
    factors, l1 diagonals, coarsest factor) for a new A with exactly the
    pattern of the one given to amg_setup (e.g. a new coefficient field on the
-   same mesh); the integer setup is reused unchanged. */
+   same mesh); the integer setup is reused unchanged.  A handle set up with
+   borrow_a = 1 borrows this A in place of the earlier one (it must be a
+   device A: a host A returns AMG_ERR_ARG).  A different pattern returns
+   AMG_ERR_CSR, a different size AMG_ERR_SHAPE, before anything changes. */
 amg_status amg_resetup_numeric(amg_hier *h, const amg_csr *A, void *stream);
 
 /* z = B r: one V(1,1) cycle with zero initial guess (Section 1, eq. (tl)

@@ -44,11 +44,12 @@ def _csr_arg(M, keep):
 
 def _options(keep, interp="alg", max_levels=20, min_coarse=32, vcycle_prec=64, ext_block_max=64,
              stall_ratio=0.9, p_trunc=0.0, ref=None, schwarz="adjoint", seed=None, user=None,
-             fp32_rho_tol=None, ext_mode="blocks", patch_hops=2, patch_cap=128):
+             fp32_rho_tol=None, ext_mode="blocks", patch_hops=2, patch_cap=128, borrow_a=False):
     o = _lib.default_options()
     o.ext_mode = {"blocks": _lib.AMG_EXT_BLOCKS, "patch": _lib.AMG_EXT_PATCH}[ext_mode]
     o.patch_hops = patch_hops
     o.patch_cap = patch_cap
+    o.borrow_a = 1 if borrow_a else 0
     o.interp = {"alg": _lib.AMG_INTERP_ALG, "ref": _lib.AMG_INTERP_REF,
                 "user": _lib.AMG_INTERP_USER}[interp]
     o.max_levels = max_levels
@@ -123,6 +124,10 @@ class Hierarchy:
         self._h = h
         self.prec = opts.get("vcycle_prec", 64)
         self.n = A[3] if isinstance(A, tuple) else A.shape[0]
+        # borrow_a with device tensors: the library reads them in place, so
+        # the hierarchy holds them until a re-setup borrows another A
+        self._borrow = bool(opts.get("borrow_a")) and isinstance(A, tuple)
+        self._a_ref = A if self._borrow else None
         # level sizes never change after setup (a numeric re-setup keeps them)
         self._sizes = [li["n"] for li in self.info()]
 
@@ -141,6 +146,8 @@ class Hierarchy:
         keep = []
         a = _csr_arg(A, keep)
         _lib.check(load().amg_resetup_numeric(self._h, C.byref(a), _stream(stream)))
+        if self._borrow:
+            self._a_ref = A
 
     def vcycle(self, r, z, stream=None):
         """z = B r (device float64 tensors), asynchronous on the stream."""

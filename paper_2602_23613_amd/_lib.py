@@ -60,7 +60,8 @@ class amg_options(C.Structure):
                 ("schwarz_mode", C.c_int), ("seed", C.c_uint64),
                 ("user_nlevels", C.c_int), ("user_P", C.POINTER(amg_csr)),
                 ("user_G", C.POINTER(amg_csr)), ("fp32_rho_tol", C.c_double),
-                ("ext_mode", C.c_int), ("patch_hops", C.c_int), ("patch_cap", C.c_int)]
+                ("ext_mode", C.c_int), ("patch_hops", C.c_int), ("patch_cap", C.c_int),
+                ("borrow_a", C.c_int)]
 
 
 class amg_solve_stats(C.Structure):

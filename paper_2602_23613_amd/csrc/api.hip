@@ -279,6 +279,7 @@ struct amg_hier {
   int* d_sweep_err = nullptr;   // set by a pipelined smoother sweep whose wait gave up
   int spin_max = 1 << 20;       // polls before such a wait gives up
   int cu_count = 256;
+  bool a_borrowed = false;      // level 0 reads the caller's A in place (amg_options.borrow_a)
   double* d_sc = nullptr;       // CG scalars
   double* d_partial = nullptr;  // reduction partials
   int64_t partial_cap = 0;
@@ -1636,7 +1637,12 @@ amg_status amg_setup(const amg_csr* A, const amg_csr* G, const amg_options* opt,
       L.S = std::move(l0.S);
       L.n = A->nrows;
       L.nnz = A->nnz;
-      if (A->on_device) {
+      h->a_borrowed = o.borrow_a != 0 && A->on_device;
+      if (h->a_borrowed) {
+        // the caller's arrays, read in place (checked on the host above)
+        L.A_ptr = const_cast<int64_t*>(A->rowptr);
+        L.A_col = const_cast<int32_t*>(A->colidx);
+      } else if (A->on_device) {
         // the pattern checked on the host is the caller's device copy: copy it
         // on the device instead of uploading the host copy again
         L.A_ptr = h->pool.get<int64_t>(L.n + 1);
@@ -1648,10 +1654,13 @@ amg_status amg_setup(const amg_csr* A, const amg_csr* G, const amg_options* opt,
         L.A_ptr = h->pool.upload(L.Apat.ptr, st);
         L.A_col = h->pool.upload(L.Apat.idx, st);
       }
-      L.A_val = h->pool.get<double>(L.nnz);
-      if (A->on_device) {
+      if (h->a_borrowed) {
+        L.A_val = const_cast<double*>(A->val);
+      } else if (A->on_device) {
+        L.A_val = h->pool.get<double>(L.nnz);
         HIPC(hipMemcpyAsync(L.A_val, A->val, L.nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
       } else {
+        L.A_val = h->pool.get<double>(L.nnz);
         HIPC(hipMemcpyAsync(L.A_val, aval.data(), L.nnz * sizeof(double), hipMemcpyHostToDevice, st));
       }
       L.lpr_A = lpr_for(L.n, L.nnz);
@@ -1756,7 +1765,18 @@ amg_status amg_resetup_numeric(amg_hier* h, const amg_csr* A, void* stream) {
     // any value is copied, so a rejected call leaves the hierarchy as it was
     host_csr(A, ptr, col, nullptr);
     if (ptr != L0.Apat.ptr || col != L0.Apat.idx) fail(AMG_ERR_CSR, "A's pattern differs from the setup's");
-    if (A->on_device) {
+    if (h->a_borrowed) {
+      if (!A->on_device) fail(AMG_ERR_ARG, "a hierarchy that borrows A needs a device A here too");
+      if (A->val != L0.A_val || A->rowptr != L0.A_ptr || A->colidx != L0.A_col) {
+        // the captured V-cycles hold the old arrays' addresses
+        HIPC(hipStreamSynchronize(st));
+        for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+        h->graphs.clear();
+      }
+      L0.A_ptr = const_cast<int64_t*>(A->rowptr);
+      L0.A_col = const_cast<int32_t*>(A->colidx);
+      L0.A_val = const_cast<double*>(A->val);
+    } else if (A->on_device) {
       HIPC(hipMemcpyAsync(L0.A_val, A->val, L0.nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
     } else {
       HIPC(hipMemcpyAsync(L0.A_val, A->val, L0.nnz * sizeof(double), hipMemcpyHostToDevice, st));

@@ -90,6 +90,36 @@ def _check_extension(A, P, ints, rng, nsample=48):
     return worst
 
 
+def _check_patch_extension(A, P, ints, rng, nsample=64):
+    """Patch form: column c of P is R^T e_c on its two exterior DoFs and
+    X_c = -A_SS^{-1} A_S,ext (R^T e_c) on its patch S (recomputed densely)."""
+    A = A.tocsr()
+    Pc = P.tocsc()
+    pp = np.asarray(ints["patch_ptr"])
+    pd = np.asarray(ints["patch_dofs"])
+    d1, d2 = np.asarray(ints["r_dof1"]), np.asarray(ints["r_dof2"])
+    s1, s2 = np.asarray(ints["r_s1"]), np.asarray(ints["r_s2"])
+    nc = int(ints["nc"])
+    worst = 0.0
+    for c in rng.choice(nc, size=min(nsample, nc), replace=False):
+        col = Pc[:, c]
+        got = dict(zip(col.indices.tolist(), col.data.tolist()))
+        assert got[int(d1[c])] == s1[c] and got[int(d2[c])] == s2[c]
+        S = pd[pp[c]:pp[c + 1]]
+        assert set(got) == set(S.tolist()) | {int(d1[c]), int(d2[c])}
+        if len(S) == 0:
+            continue
+        rhs = A[S][:, [int(d1[c]), int(d2[c])]].toarray() @ np.array([s1[c], s2[c]], dtype=np.float64)
+        Ass = A[S][:, S].toarray()
+        X = -np.linalg.solve(Ass, rhs)
+        G = np.array([got[int(j)] for j in S])
+        err = np.abs(G - X).max() / max(np.abs(X).max(), 1e-300)
+        tol = max(1e-13, 8 * np.linalg.cond(Ass) * EPS)
+        assert err <= tol, (int(c), err, tol)
+        worst = max(worst, err / tol)
+    return worst
+
+
 def _check_galerkin(A, P, A1, rng, nsample=300):
     Pc = P.tocsc()
     absA = abs(A)
@@ -108,17 +138,21 @@ def _check_galerkin(A, P, A1, rng, nsample=300):
     return worst
 
 
-def _fullsize(N):
+def _fullsize(N, ext_mode="blocks"):
     d = dev()
     rng = np.random.default_rng(N)
     p = _workload(N)
-    H = amglib.Hierarchy(_device_csr(p.A, d), _device_csr(p.G, d))
+    print(f"hex {N}^3, {ext_mode} extension", flush=True)
+    H = amglib.Hierarchy(_device_csr(p.A, d), _device_csr(p.G, d), ext_mode=ext_mode)
     info = H.info()
     print("levels", [(l["n"], l["nnz"]) for l in info])
     A0, P0 = H.level(0)
     assert (A0 != p.A).nnz == 0
     ints = H.integers(0)
-    we = _check_extension(A0, P0, ints, rng)
+    if ext_mode == "patch":
+        we = _check_patch_extension(A0, P0, ints, rng)
+    else:
+        we = _check_extension(A0, P0, ints, rng)
     A1, _ = H.level(1)
     wg = _check_galerkin(A0, P0, A1, rng)
     print(f"extension worst err/tol {we:.2e}; Galerkin worst err/bound {wg:.2e}")
@@ -156,3 +190,9 @@ def test_full_size_64():
 
 def test_full_size_128():
     _fullsize(128)
+
+
+def test_full_size_128_patch():
+    """The 128^3 workload in the configuration of the bench.py headline
+    (patch extension, device-resident A and G)."""
+    _fullsize(128, "patch")
