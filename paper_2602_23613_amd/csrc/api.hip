@@ -49,6 +49,25 @@ struct PhaseClock {
   }
 };
 
+// HCURL_AMG_VERBOSE=2: the steps inside a phase (stream synchronised at each)
+struct StepTimer {
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  bool on = false;
+  StepTimer() {
+    const char* e = std::getenv("HCURL_AMG_VERBOSE");
+    on = e && std::atoi(e) >= 2;
+  }
+  void mark(hipStream_t st, const std::string& what) {
+    if (!on) return;
+    (void)hipStreamSynchronize(st);
+    auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[amg]   %-40s %8.3f s\n", what.c_str(),
+                 std::chrono::duration<double>(now - t).count());
+    std::fflush(stderr);
+    t = now;
+  }
+};
+
 struct Fail {
   amg_status code;
   std::string msg;
@@ -74,8 +93,84 @@ int lpr_for(int64_t n, int64_t nnz) {
 }
 
 // Device allocations owned by a hierarchy.
+// Large copies between pageable host memory and the device go through two
+// pinned 32 MiB buffers: the host fills (or drains) one while the DMA engine
+// moves the other.  Pageable copies run at a few GB/s on these hosts; copies
+// below 4 MiB stay plain.
+struct Staging {
+  static constexpr size_t CAP = size_t(32) << 20;
+  static constexpr size_t SMALL = size_t(4) << 20;
+  char* buf[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool pending[2] = {false, false};   // an upload may still read buf[b]
+  void init() {
+    if (buf[0]) return;
+    for (int b = 0; b < 2; ++b) {
+      HIPC(hipHostMalloc((void**)&buf[b], CAP, hipHostMallocDefault));
+      HIPC(hipEventCreateWithFlags(&ev[b], hipEventDisableTiming));
+    }
+  }
+  void drain(int b) {
+    if (pending[b]) {
+      HIPC(hipEventSynchronize(ev[b]));
+      pending[b] = false;
+    }
+  }
+  void h2d(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (bytes < SMALL) {
+      HIPC(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+      return;
+    }
+    init();
+    for (size_t off = 0, k = 0; off < bytes; off += CAP, ++k) {
+      const int b = (int)(k & 1);
+      const size_t len = std::min(CAP, bytes - off);
+      drain(b);
+      std::memcpy(buf[b], (const char*)src + off, len);
+      HIPC(hipMemcpyAsync((char*)dst + off, buf[b], len, hipMemcpyHostToDevice, st));
+      HIPC(hipEventRecord(ev[b], st));
+      pending[b] = true;
+    }
+  }
+  // returns once dst holds the bytes
+  void d2h(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (bytes < SMALL) {
+      HIPC(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+      HIPC(hipStreamSynchronize(st));
+      return;
+    }
+    init();
+    const size_t n = (bytes + CAP - 1) / CAP;
+    auto issue = [&](size_t k) {
+      const int b = (int)(k & 1);
+      drain(b);
+      const size_t off = k * CAP, len = std::min(CAP, bytes - off);
+      HIPC(hipMemcpyAsync(buf[b], (const char*)src + off, len, hipMemcpyDeviceToHost, st));
+      HIPC(hipEventRecord(ev[b], st));
+    };
+    issue(0);
+    for (size_t k = 0; k < n; ++k) {
+      if (k + 1 < n) issue(k + 1);
+      const int b = (int)(k & 1);
+      HIPC(hipEventSynchronize(ev[b]));
+      const size_t off = k * CAP, len = std::min(CAP, bytes - off);
+      std::memcpy((char*)dst + off, buf[b], len);
+    }
+  }
+  ~Staging() {
+    for (int b = 0; b < 2; ++b) {
+      if (ev[b]) {
+        (void)hipEventSynchronize(ev[b]);
+        (void)hipEventDestroy(ev[b]);
+      }
+      if (buf[b]) (void)hipHostFree(buf[b]);
+    }
+  }
+};
+
 struct Pool {
   std::vector<void*> ptrs;
+  Staging stage;
   template <class T>
   T* get(size_t n) {
     if (n == 0) n = 1;
@@ -87,7 +182,7 @@ struct Pool {
   template <class T>
   T* upload(const std::vector<T>& v, hipStream_t st) {
     T* d = get<T>(v.size());
-    if (!v.empty()) HIPC(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    if (!v.empty()) stage.h2d(d, v.data(), v.size() * sizeof(T), st);
     return d;
   }
   ~Pool() {
@@ -350,11 +445,16 @@ void check_sweep_err(amg_hier* h, hipStream_t st) {
 }
 
 // Host copies of a CSR (pattern, and values if wanted).
+// (sg: pinned staging for device arrays; NULL copies them directly)
 void host_csr(const amg_csr* M, std::vector<int64_t>& ptr, std::vector<int32_t>& col,
-              std::vector<double>* val) {
+              std::vector<double>* val, Staging* sg = nullptr) {
+  auto d2h = [&](void* dst, const void* src, size_t bytes) {
+    if (sg) sg->d2h(dst, src, bytes, nullptr);
+    else HIPC(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+  };
   ptr.resize(M->nrows + 1);
   if (M->on_device) {
-    HIPC(hipMemcpy(ptr.data(), M->rowptr, ptr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+    d2h(ptr.data(), M->rowptr, ptr.size() * sizeof(int64_t));
   } else {
     std::memcpy(ptr.data(), M->rowptr, ptr.size() * sizeof(int64_t));
   }
@@ -363,8 +463,8 @@ void host_csr(const amg_csr* M, std::vector<int64_t>& ptr, std::vector<int32_t>&
   col.resize(nnz);
   if (val) val->resize(nnz);
   if (M->on_device) {
-    HIPC(hipMemcpy(col.data(), M->colidx, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
-    if (val) HIPC(hipMemcpy(val->data(), M->val, nnz * sizeof(double), hipMemcpyDeviceToHost));
+    d2h(col.data(), M->colidx, nnz * sizeof(int32_t));
+    if (val) d2h(val->data(), M->val, nnz * sizeof(double));
   } else {
     std::memcpy(col.data(), M->colidx, nnz * sizeof(int32_t));
     if (val) std::memcpy(val->data(), M->val, nnz * sizeof(double));
@@ -947,12 +1047,13 @@ constexpr int64_t MM_LDS_ROW = 65536 / (sizeof(double) + sizeof(int32_t));
 int64_t mm_symbolic(amg_hier* h, int64_t nrows, int64_t ncols, const CsrPat& X, const CsrPat& Y,
                     std::vector<int64_t>& cptr, int64_t*& d_cptr, int32_t*& d_ccol,
                     int32_t*& d_wide, int64_t& nwide, const std::string& what, hipStream_t st) {
+  StepTimer tm;
   int64_t* d_cnt = h->pool.get<int64_t>(nrows);
   mm_count(nrows, X, Y, d_cnt, h->d_flag, st);
   HIPC(hipGetLastError());
+  tm.mark(st, what + ": count");
   std::vector<int64_t> cnt(nrows);
-  HIPC(hipMemcpyAsync(cnt.data(), d_cnt, nrows * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  HIPC(hipStreamSynchronize(st));
+  h->pool.stage.d2h(cnt.data(), d_cnt, nrows * sizeof(int64_t), st);
   std::vector<int32_t> hw;   // rows too wide for the hash passes
   for (int64_t i = 0; i < nrows; ++i)
     if (cnt[i] < 0) hw.push_back((int32_t)i);
@@ -976,8 +1077,10 @@ int64_t mm_symbolic(amg_hier* h, int64_t nrows, int64_t ncols, const CsrPat& X, 
     mmax = std::max(mmax, cnt[i]);
     if (cnt[i] > lds_row) nw.push_back((int32_t)i);
   }
+  tm.mark(st, what + ": counts to host, scan");
   d_cptr = h->pool.upload(cptr, st);
   d_ccol = h->pool.get<int32_t>(std::max<int64_t>(cptr[nrows], 1));
+  tm.mark(st, what + ": row pointers up, columns allocated");
   mm_fill(nrows, X, Y, d_cptr, d_ccol, h->d_flag, st);
   mm_fill_wide((int64_t)hw.size(), d_hw, X, Y, ncols, d_cptr, d_ccol, st);
   HIPC(hipGetLastError());
@@ -985,6 +1088,7 @@ int64_t mm_symbolic(amg_hier* h, int64_t nrows, int64_t ncols, const CsrPat& X, 
   nwide = (int64_t)nw.size();
   d_wide = nw.empty() ? nullptr : h->pool.upload(nw, st);
   HIPC(hipStreamSynchronize(st));
+  tm.mark(st, what + ": fill");
   return std::min(mmax, lds_row);
 }
 
@@ -996,7 +1100,9 @@ void galerkin_symbolic(amg_hier* h, Level& L, Level& C, int level, hipStream_t s
   L.ap_mmax = (int)mm_symbolic(h, n, nc, A, P, apptr, L.AP_ptr, L.AP_col, L.ap_wide, L.ap_nwide,
                                "A P" + lv, st);
   L.ap_nnz = apptr[n];
+  StepTimer tm;
   L.AP_val = h->pool.get<double>(std::max<int64_t>(L.ap_nnz, 1));
+  tm.mark(st, "A P values allocated (" + std::to_string(L.ap_nnz) + " entries)");
   CsrPat AP{L.AP_ptr, L.AP_col};
   std::vector<int64_t> cptr;
   L.rap_mmax = (int)mm_symbolic(h, nc, nc, PT, AP, cptr, C.A_ptr, C.A_col, L.rap_wide,
@@ -1007,9 +1113,10 @@ void galerkin_symbolic(amg_hier* h, Level& L, Level& C, int level, hipStream_t s
   C.lpr_A = lpr_for(C.n, C.nnz);
   C.Apat.n = C.Apat.m = nc;
   C.Apat.ptr = cptr;
+  tm.mark(st, "P^T (A P) symbolic");
   C.Apat.idx.resize(C.nnz);
-  HIPC(hipMemcpyAsync(C.Apat.idx.data(), C.A_col, C.nnz * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  HIPC(hipStreamSynchronize(st));
+  h->pool.stage.d2h(C.Apat.idx.data(), C.A_col, C.nnz * sizeof(int32_t), st);
+  tm.mark(st, "A_c pattern to the host");
 }
 
 void galerkin_numeric(amg_hier* h, Level& L, Level& C, hipStream_t st) {
@@ -1465,7 +1572,8 @@ struct Level0Host {
   Pattern S;
 };
 
-void level0_host(const amg_csr* A, const amg_csr* G, Level0Host& out, std::vector<double>* Aval) {
+void level0_host(const amg_csr* A, const amg_csr* G, Level0Host& out, std::vector<double>* Aval,
+                 Staging* sg = nullptr) {
   validate_csr_arg(A, "A");
   validate_csr_arg(G, "G");
   if (A->nrows != A->ncols) fail(AMG_ERR_SHAPE, "A is not square");
@@ -1483,14 +1591,14 @@ void level0_host(const amg_csr* A, const amg_csr* G, Level0Host& out, std::vecto
     std::fprintf(stderr, "[amg]   host %-34s %.3f s\n", what, std::chrono::duration<double>(t1 - t0).count());
     t0 = t1;
   };
-  host_csr(A, out.Apat.ptr, out.Apat.idx, Aval);
+  host_csr(A, out.Apat.ptr, out.Apat.idx, Aval, sg);
   out.Apat.n = out.Apat.m = A->nrows;
   mark("A to the host");
   HostError err;
   if (!validate_pattern(A->nrows, A->ncols, out.Apat.ptr.data(), out.Apat.idx.data(), err))
     fail((amg_status)err.code, "A: " + err.msg);
   mark("A pattern checked");
-  host_csr(G, gptr, gcol, &gval);
+  host_csr(G, gptr, gcol, &gval, sg);
   if (!incidence_from_csr(G->nrows, G->ncols, gptr.data(), gcol.data(), gval.data(), out.G, err))
     fail((amg_status)err.code, err.msg);
   mark("G to the host and checked");
@@ -1627,7 +1735,7 @@ amg_status amg_setup(const amg_csr* A, const amg_csr* G, const amg_options* opt,
     PhaseClock clk;
     Level0Host l0;
     std::vector<double> aval;
-    level0_host(A, G, l0, A->on_device ? nullptr : &aval);
+    level0_host(A, G, l0, A->on_device ? nullptr : &aval, &h->pool.stage);
     clk.mark(st, "input copy + nodal graph", 0);
     h->lv.emplace_back();
     {
@@ -1763,7 +1871,7 @@ amg_status amg_resetup_numeric(amg_hier* h, const amg_csr* A, void* stream) {
     std::vector<int32_t> col;
     // the pattern must be the one given to amg_setup; it is checked before
     // any value is copied, so a rejected call leaves the hierarchy as it was
-    host_csr(A, ptr, col, nullptr);
+    host_csr(A, ptr, col, nullptr, &h->pool.stage);
     if (ptr != L0.Apat.ptr || col != L0.Apat.idx) fail(AMG_ERR_CSR, "A's pattern differs from the setup's");
     if (h->a_borrowed) {
       if (!A->on_device) fail(AMG_ERR_ARG, "a hierarchy that borrows A needs a device A here too");
