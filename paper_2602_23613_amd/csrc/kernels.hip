@@ -1688,6 +1688,7 @@ void ext_blocks(int64_t b0, int64_t nb, const int64_t* bptr, const int32_t* bdof
 //  * forward and back substitution in the same blocks;
 // about 7 barriers per 16 columns.  x goes to P's entries of the column.
 constexpr int EXT_NB = 16;
+constexpr int EXT_GATHER = 4;   // entries of A per thread with their loads in flight together
 
 __device__ __forceinline__ int tri_off(int i) { return i * (i + 1) / 2; }
 
@@ -1704,7 +1705,8 @@ __global__ __launch_bounds__(256) void k_ext_patch(
   double* e1v = y + mmax;                                   // A(S_i, ext1)
   double* e2v = e1v + mmax;                                 // A(S_i, ext2)
   int64_t* rstart = (int64_t*)(e2v + mmax);                 // first A entry of each row
-  int32_t* pre = (int32_t*)(rstart + mmax);                 // row-length prefix (m + 1)
+  double* rdiag = (double*)(rstart + mmax);                 // 1 / L(i, i)
+  int32_t* pre = (int32_t*)(rdiag + mmax);                  // row-length prefix (m + 1)
   int32_t* dofs = pre + mmax + 1;
   const int64_t c = cfirst + blockIdx.x;
   const int64_t p0 = pptr[c];
@@ -1750,24 +1752,46 @@ __global__ __launch_bounds__(256) void k_ext_patch(
   for (int t = tid; t < m; t += 256) e1v[t] = e2v[t] = 0.0;
   __syncthreads();
   const int E = pre[m];
-  for (int e = tid; e < E; e += 256) {
-    // row of flat entry e: the last i with pre[i] <= e
-    int lo = 0, hi = m;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (pre[mid] <= e) lo = mid; else hi = mid;
+  // EXT_GATHER flat entries per thread and round, their loads issued together
+  for (int e0 = tid; e0 < E; e0 += 256 * EXT_GATHER) {
+    int ri[EXT_GATHER];
+    int32_t jv[EXT_GATHER];
+    double av[EXT_GATHER];
+#pragma unroll
+    for (int u = 0; u < EXT_GATHER; ++u) {
+      const int e = e0 + u * 256;
+      ri[u] = -1;
+      if (e < E) {
+        // row of flat entry e: the last i with pre[i] <= e
+        int lo = 0, hi = m;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (pre[mid] <= e) lo = mid; else hi = mid;
+        }
+        ri[u] = lo;
+      }
     }
-    const int i = lo;
-    const int64_t q = rstart[i] + (e - pre[i]);
-    const int32_t j = Acol[q];
-    const double a = Aval[q];
-    if (j == x1) {
-      e1v[i] = a;
-    } else if (j == x2) {
-      e2v[i] = a;
-    } else if (j <= dofs[i]) {
-      const int pos = lower_bound_i32(dofs, i + 1, j);
-      if (pos <= i && dofs[pos] == j) L[tri_off(i) + pos] = a;
+#pragma unroll
+    for (int u = 0; u < EXT_GATHER; ++u) {
+      if (ri[u] >= 0) {
+        const int64_t q = rstart[ri[u]] + (e0 + u * 256 - pre[ri[u]]);
+        jv[u] = Acol[q];
+        av[u] = Aval[q];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < EXT_GATHER; ++u) {
+      const int i = ri[u];
+      if (i < 0) continue;
+      const int32_t j = jv[u];
+      if (j == x1) {
+        e1v[i] = av[u];
+      } else if (j == x2) {
+        e2v[i] = av[u];
+      } else if (j <= dofs[i]) {
+        const int pos = lower_bound_i32(dofs, i + 1, j);
+        if (pos <= i && dofs[pos] == j) L[tri_off(i) + pos] = av[u];
+      }
     }
   }
   __syncthreads();
@@ -1804,6 +1828,7 @@ __global__ __launch_bounds__(256) void k_ext_patch(
 #pragma unroll
         for (int t = 0; t < EXT_NB; ++t)
           if (t <= lane) L[tri_off(kb + lane) + kb + t] = d[t];
+        rdiag[kb + lane] = 1.0 / d[lane];
       }
     }
     __syncthreads();
@@ -1819,7 +1844,7 @@ __global__ __launch_bounds__(256) void k_ext_patch(
           const double* Lc = L + tri_off(kb + cc) + kb;
 #pragma unroll
           for (int t = 0; t < cc; ++t) v -= xv[t] * Lc[t];
-          xv[cc] = v / Lc[cc];
+          xv[cc] = v * rdiag[kb + cc];
         } else {
           xv[cc] = 0.0;
         }
@@ -1866,9 +1891,10 @@ __global__ __launch_bounds__(256) void k_ext_patch(
       for (int t = 0; t < EXT_NB; ++t)
         lr[t] = (lane < nb && t <= lane) ? L[tri_off(kb + lane) + kb + t] : 1.0;
       double yr = lane < nb ? y[kb + lane] : 0.0;
+      const double rd = lane < nb ? rdiag[kb + lane] : 1.0;
 #pragma unroll
       for (int cc = 0; cc < EXT_NB; ++cc) {
-        if (lane == cc) yr /= lr[cc];
+        if (lane == cc) yr *= rd;
         const double zc = __shfl(yr, cc, 64);
         if (lane > cc) yr -= lr[cc] * zc;
       }
@@ -1896,9 +1922,10 @@ __global__ __launch_bounds__(256) void k_ext_patch(
       for (int t = 0; t < EXT_NB; ++t)
         lc[t] = (lane < nb && t >= lane && t < nb) ? L[tri_off(kb + t) + kb + lane] : 1.0;
       double xr = lane < nb ? y[kb + lane] : 0.0;
+      const double rd = lane < nb ? rdiag[kb + lane] : 1.0;
 #pragma unroll
       for (int cc = EXT_NB - 1; cc >= 0; --cc) {
-        if (lane == cc) xr /= lc[cc];
+        if (lane == cc) xr *= rd;
         const double xc = __shfl(xr, cc, 64);
         if (lane < cc) xr -= lc[cc] * xc;
       }
@@ -1927,7 +1954,7 @@ __global__ __launch_bounds__(256) void k_ext_patch(
 }
 
 size_t ext_patch_lds(int mmax) {
-  return sizeof(double) * ((size_t)mmax * (mmax + 1) / 2 + 3 * (size_t)mmax) +
+  return sizeof(double) * ((size_t)mmax * (mmax + 1) / 2 + 4 * (size_t)mmax) +
          sizeof(int64_t) * (size_t)mmax + sizeof(int32_t) * (2 * (size_t)mmax + 1);
 }
 
