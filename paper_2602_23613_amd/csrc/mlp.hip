@@ -1,7 +1,7 @@
 // Learned-setup surrogate network (gfx950): a 64 -> 128 -> 128 -> 64 MLP that
 // maps a normalised extension block D^{-1/2} A_BB D^{-1/2} (size <= 8) to its
 // inverse, trained on the exact local solves of the harmonic extension
-// (eq. (sparseP)).  Matrix products use MFMA (v_mfma_f32_16x16x16_bf16, BF16
+// (eq. (sparseP)).  Matrix products use MFMA (v_mfma_f32_16x16x32_bf16, BF16
 // operands, FP32 accumulation); master weights and Adam state are FP32.  At
 // inference the prediction is refined in FP64 by Newton-Schulz steps and
 // accepted only if ||Ahat W - I||_F <= tol; otherwise the exact solve is used.
@@ -12,6 +12,7 @@
 namespace hamg {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
@@ -30,9 +31,11 @@ static unsigned grid1(int64_t n, int bs = 256) {
 // ---------------------------------------------------------------------------
 // C[M x N] (+)= sum_k A(m, k) B(k, n), BF16 operands with arbitrary strides,
 // FP32 accumulation.  One wavefront per 16 x 16 tile of C; M, N, K multiples
-// of 16.  Operand layout of v_mfma_f32_16x16x16_bf16: lane l holds
-// A(l % 16, 4 (l / 16) + t) and B(4 (l / 16) + t, l % 16), t = 0..3; the
-// result holds C(4 (l / 16) + t, l % 16).
+// of 16.  K goes in steps of 32 through gfx950's v_mfma_f32_16x16x32_bf16
+// (lane l holds A(l % 16, 8 (l / 16) + t) and B(8 (l / 16) + t, l % 16),
+// t = 0..7), a last step of 16 through v_mfma_f32_16x16x16_bf16 (lane l
+// holds A(l % 16, 4 (l / 16) + t) and B(4 (l / 16) + t, l % 16), t = 0..3);
+// both leave C(4 (l / 16) + t, l % 16) in lane l, t = 0..3.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const uint16_t* __restrict__ A,
                                                    int64_t lda_m, int64_t lda_k,
@@ -44,11 +47,21 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const ui
   const int64_t tile = (int64_t)blockIdx.x * (blockDim.x / 64) + wave;
   const int64_t tm = tile / tiles_n, tn = tile % tiles_n;
   if (tm * 16 >= M) return;   // whole wavefront leaves together
-  const int i = lane % 16, kq = 4 * (lane / 16);
+  const int i = lane % 16, kq = 4 * (lane / 16), kq8 = 8 * (lane / 16);
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
   const uint16_t* Ap = A + (tm * 16 + i) * lda_m;
   const uint16_t* Bp = B + (tn * 16 + i) * ldb_n;
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  int k0 = 0;
+  for (; k0 + 32 <= K; k0 += 32) {
+    bf16x8 a, b;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      a[t] = __builtin_bit_cast(__bf16, Ap[(int64_t)(k0 + kq8 + t) * lda_k]);
+      b[t] = __builtin_bit_cast(__bf16, Bp[(int64_t)(k0 + kq8 + t) * ldb_k]);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+  }
+  if (k0 < K) {   // K = 16 (mod 32)
     bf16x4 a, b;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
