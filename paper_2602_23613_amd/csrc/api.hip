@@ -265,6 +265,8 @@ struct Level {
   int32_t* sweep_sync = nullptr;   // pipelined sweep: ticket + per-colour counters
   int32_t* chunk_blk = nullptr;
   int32_t* ck_row0 = nullptr;
+  int64_t* ck_q = nullptr;
+  int4* ck_row = nullptr;
   int64_t* ck_fac0 = nullptr;
   int64_t srow_nnz = 0;
   int64_t* srow_ptr = nullptr;     // the smoother's copy of A's rows in star order
@@ -326,6 +328,7 @@ struct Level {
     s.chunk_colour = chunk_colour; s.chunk_blk = chunk_blk;
     s.sb_ptr = sb_ptr; s.sb_dofs = sb_dofs; s.fac_off = fac_off;
     s.ck_row0 = ck_row0; s.ck_fac0 = ck_fac0; s.srow_ptr = srow_ptr; s.scol = scol;
+    s.ck_q = ck_q; s.ck_row = ck_row;
     if constexpr (std::is_same<T, double>::value) {
       s.fac = fac;
       s.binv = binv;
@@ -762,6 +765,7 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
     }
     L.srow_nnz = srow_ptr[nr];
     L.srow_ptr = h->pool.upload(srow_ptr, st);
+
     L.scol = h->pool.get<int32_t>(std::max<int64_t>(L.srow_nnz, 1));   // gathered below
     L.sval = h->pool.get<double>(std::max<int64_t>(L.srow_nnz, 1));
   }
@@ -823,6 +827,14 @@ void build_smoother(amg_hier* h, Level& L, hipStream_t st) {
     L.row_blk = h->pool.upload(row_blk, st);
   }
   L.dinv = h->pool.get<double>(L.n);
+  // per chunk, padded to rpb row slots: entry ranges and {DoF, block start
+  // in the chunk, block size, factor offset in the chunk}, built on the
+  // device from the arrays above
+  L.ck_q = h->pool.get<int64_t>((size_t)nchunks * (rpb + 1));
+  L.ck_row = reinterpret_cast<int4*>(h->pool.get<int32_t>((size_t)nchunks * rpb * 4));
+  chunk_tables(nchunks, rpb, L.ck_row0, L.ck_fac0, L.srow_ptr, L.sb_dofs, L.row_blk, L.sb_ptr,
+               L.fac_off, L.ck_q, L.ck_row, st);
+  HIPC(hipGetLastError());
 }
 
 void factor_smoother(amg_hier* h, Level& L, int level, hipStream_t st) {

@@ -231,33 +231,30 @@ template <class T, int LPR, int WGS, int U>
 __device__ __forceinline__ void chunk_load_head(bool act, int c, int tid, const SmootherArgs<T>& D,
                                                 ChunkRegs<T, LPR, WGS, U>& R) {
   constexpr int FPT = ChunkRegs<T, LPR, WGS, U>::FPT;
+  constexpr int RPB = WGS / LPR;
   R.blk0 = R.nblk = R.r0 = R.nrows = R.nf = 0;
   R.f0 = 0;
+  const int grp = tid / LPR, lane = tid % LPR;
+  R.q0 = R.q1 = 0;
+  R.rdof = R.mydof = 0;
+  R.bp = R.bs = R.bfo = 0;
   if (act) {
-    R.blk0 = D.chunk_blk[c];
-    R.nblk = D.chunk_blk[c + 1] - R.blk0;
+    // everything below is indexed by the chunk and the thread alone
     R.r0 = D.ck_row0[c];
     R.nrows = D.ck_row0[c + 1] - R.r0;
     R.f0 = D.ck_fac0[c];
     R.nf = (int)(D.ck_fac0[c + 1] - R.f0);
-  }
-  const int grp = tid / LPR, lane = tid % LPR;
-  R.q0 = R.q1 = 0;
-  R.rdof = R.mydof = 0;
-  if (grp < R.nrows) {
-    const int64_t r = (int64_t)R.r0 + grp;
-    R.q0 = D.srow_ptr[r];
-    R.q1 = D.srow_ptr[r + 1];
-    if (lane == 0) R.rdof = D.sb_dofs[r];
-  }
-  R.bp = R.bs = R.bfo = 0;
-  if (tid < R.nrows) {
-    R.mydof = D.sb_dofs[R.r0 + tid];
-    const int rb = D.row_blk[R.r0 + tid];
-    const int64_t p0 = D.sb_ptr[rb];
-    R.bp = (int)(p0 - R.r0);
-    R.bs = (int)(D.sb_ptr[rb + 1] - p0);
-    R.bfo = (int)(D.fac_off[rb] - R.f0);
+    const int64_t* cq = D.ck_q + (int64_t)c * (RPB + 1);
+    R.q0 = cq[grp];
+    R.q1 = cq[grp + 1];
+    if (lane == 0) R.rdof = D.ck_row[(int64_t)c * RPB + grp].x;
+    if (tid < RPB) {
+      const int4 info = D.ck_row[(int64_t)c * RPB + tid];
+      R.mydof = info.x;
+      R.bp = info.y;
+      R.bs = info.z;
+      R.bfo = info.w;
+    }
   }
 #pragma unroll
   for (int k = 0; k < FPT; ++k) {
@@ -539,6 +536,46 @@ void schwarz_pipe(const SmootherDev<T>& S, int backward, const T* b, T* x, hipSt
   LAUNCH_PIPE(8, 8) LAUNCH_PIPE(16, 8) LAUNCH_PIPE(32, 8) LAUNCH_PIPE(16, 16) LAUNCH_PIPE(32, 16)
   LAUNCH_PIPE(64, 16) LAUNCH_PIPE(128, 16) LAUNCH_PIPE(256, 16)
 #undef LAUNCH_PIPE
+}
+
+static unsigned grid_for(int64_t n);
+
+// slot i of chunk c is star row r0 + i (r0 = ck_row0[c]) while that is below
+// the next chunk's first row; the entry range of a slot past the rows is empty
+__global__ void k_chunk_tables(int64_t nchunks, int rpb, const int32_t* __restrict__ ck_row0,
+                               const int64_t* __restrict__ ck_fac0, const int64_t* __restrict__ srow_ptr,
+                               const int32_t* __restrict__ sb_dofs, const int32_t* __restrict__ row_blk,
+                               const int64_t* __restrict__ sb_ptr, const int64_t* __restrict__ fac_off,
+                               int64_t* __restrict__ ck_q, int4* __restrict__ ck_row) {
+  const int64_t total = nchunks * (int64_t)(rpb + 1);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = t / (rpb + 1);
+    const int i = (int)(t % (rpb + 1));
+    const int64_t r0 = ck_row0[c], r1 = ck_row0[c + 1];
+    const int64_t r = r0 + i;
+    ck_q[t] = srow_ptr[r < r1 ? r : r1];
+    if (i < rpb) {
+      int4 info = make_int4(0, 0, 0, 0);
+      if (r < r1) {
+        const int32_t b = row_blk[r];
+        info.x = sb_dofs[r];
+        info.y = (int)(sb_ptr[b] - r0);
+        info.z = (int)(sb_ptr[b + 1] - sb_ptr[b]);
+        info.w = (int)(fac_off[b] - ck_fac0[c]);
+      }
+      ck_row[c * rpb + i] = info;
+    }
+  }
+}
+void chunk_tables(int64_t nchunks, int rpb, const int32_t* ck_row0, const int64_t* ck_fac0,
+                  const int64_t* srow_ptr, const int32_t* sb_dofs, const int32_t* row_blk,
+                  const int64_t* sb_ptr, const int64_t* fac_off, int64_t* ck_q, int4* ck_row,
+                  hipStream_t st) {
+  if (nchunks > 0)
+    hipLaunchKernelGGL(k_chunk_tables, dim3(grid_for(nchunks * (int64_t)(rpb + 1))), dim3(256), 0, st,
+                       nchunks, rpb, ck_row0, ck_fac0, srow_ptr, sb_dofs, row_blk, sb_ptr, fac_off, ck_q,
+                       ck_row);
 }
 
 // values of the smoother's row copy: star row r is row sb_dofs[r] of A

@@ -43,6 +43,13 @@ struct SmootherArgs {
   const T* binv = nullptr;                // symmetric inverses, packed like fac (row forms)
   const int32_t* row_blk = nullptr;       // block of each star row
   const int32_t* ck_row0 = nullptr;       // first star row of each chunk (+ sentinel)
+  // per chunk, padded to WGS / LPR row slots: the row copy's entry range of
+  // every slot (rpb + 1 offsets; slots past the chunk's rows are empty) and
+  // every slot's {DoF, block start in the chunk, block size, factor offset
+  // in the chunk}, so that a chunk reaches its rows' entries and blocks in
+  // one dependent load
+  const int64_t* ck_q = nullptr;
+  const int4* ck_row = nullptr;
   const int64_t* ck_fac0 = nullptr;       // first factor entry of each chunk (+ sentinel)
   const int64_t* srow_ptr = nullptr;      // the smoother's copy of A's rows in star order
   const int32_t* scol = nullptr;
@@ -181,6 +188,13 @@ int red_grid();
 
 // patch extension: one workgroup per column of P (patch of at most mmax DoFs)
 size_t ext_patch_lds(int mmax);
+// The padded per-chunk tables of SmootherArgs (ck_q, ck_row) from the
+// smoother's star-order arrays: one thread per (chunk, row slot).
+void chunk_tables(int64_t nchunks, int rpb, const int32_t* ck_row0, const int64_t* ck_fac0,
+                  const int64_t* srow_ptr, const int32_t* sb_dofs, const int32_t* row_blk,
+                  const int64_t* sb_ptr, const int64_t* fac_off, int64_t* ck_q, int4* ck_row,
+                  hipStream_t st);
+
 // P^T's pattern on the device (transpose.hip): row pointers tptr (nc + 1),
 // column ids tcol (nnz) and perm[q] = position of P's entry q in P^T.
 // Needs nnz and nc below 2^31; returns the first HIP error.
