@@ -2425,7 +2425,6 @@ int mm_hash_cap() { return HCAP; }
 // ---------------------------------------------------------------------------
 // setup: smoother factors and l1 diagonal
 // ---------------------------------------------------------------------------
-constexpr int MAXS = 32;
 
 // one thread per block: gather the lower triangle of A_BB, factor, store packed
 __global__ void k_star_chol(int64_t nb, const int64_t* __restrict__ sb_ptr,
