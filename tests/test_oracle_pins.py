@@ -810,3 +810,80 @@ def test_patch_extension_two_grid_factor_against_exact_extension():
     ex = _two_grid_factor(Hb, Pex, p.A)
     print(f"two-grid factor: exact {ex:.3f}, patch {rp:.3f}, depth-ordered blocks {r9:.3f}")
     assert ex <= rp + 1e-9 and rp < r9
+
+
+# ----------------------------------------------------------------------------
+# 3D localisations in their unbounded limits: eq. (sparseP) with the global
+# A_II^{-1}, computed densely
+# ----------------------------------------------------------------------------
+def _dense_ideal(p, lv):
+    n = p.A.shape[0]
+    Rt = amg.r_transpose(lv.rr, n).toarray()
+    Ad = p.A.toarray()
+    I = lv.interior
+    Pd = Rt.copy()
+    Pd[I] = Rt[I] - np.linalg.solve(Ad[np.ix_(I, I)], Ad[I] @ Rt)
+    return Pd
+
+
+@pytest.mark.parametrize("N", [6, 8])
+def test_block_extension_is_exact_in_3d_when_the_block_bound_admits_components(N):
+    """3D: graph(A_II) is one connected component; with a block bound above
+    |I| that component is the one block and P is eq. (sparseP) exactly, the
+    dense formula with the global A_II^{-1}."""
+    p = gen.make_problem("hex", N, beta=1.0, alpha=lambda m: fields.subdomain_log_uniform(m, 2, 5))
+    H = oracle.setup(p.A, p.G, max_levels=2, ext_block_max=10 ** 6)
+    lv = H.levels[0]
+    assert lv.exact_blocks and len(lv.blocks) == 1
+    Pd = _dense_ideal(p, lv)
+    assert np.abs(lv.P.toarray() - Pd).max() <= 1e-10 * np.abs(Pd).max()
+
+
+def test_patch_extension_is_exact_in_3d_without_cap_and_with_enough_hops():
+    """3D, hex 6^3 with jumps: with no cap and one hop more than the diameter
+    of graph(A_II) (measured here by BFS), every patch is the whole interior
+    set (graph(A_II) is connected), and the per-column least-energy extension
+    is column c of eq. (sparseP) with the global A_II^{-1}."""
+    p = gen.make_problem("hex", 6, beta=1.0, alpha=lambda m: fields.subdomain_log_uniform(m, 2, 5))
+    H0 = oracle.setup(p.A, p.G, max_levels=2)
+    I = H0.levels[0].interior
+    AII = abs(p.A.tocsr()[I][:, I]) > 0
+    diam = shortest_path(AII, unweighted=True, directed=False).max()
+    assert np.isfinite(diam)
+    H = oracle.setup(p.A, p.G, max_levels=2, ext_mode="patch", patch_hops=int(diam) + 1,
+                     patch_cap=10 ** 6)
+    lv = H.levels[0]
+    assert all(np.array_equal(S, np.sort(I)) for S in lv.patches)
+    Pd = _dense_ideal(p, lv)
+    assert np.abs(lv.P.toarray() - Pd).max() <= 1e-10 * np.abs(Pd).max()
+
+
+@pytest.mark.parametrize("alpha", ["iso", "jump"])
+def test_depth_ordered_blocks_are_harmonic_given_the_shallower_rows(alpha):
+    """The 3D block form (bound 64, so A_II is split): for every block B of
+    depth d, P restricted to the exterior rows, the rows of blocks of depth
+    below d and B's own rows is A-harmonic on B; the couplings of B to the
+    other blocks of depth >= d are exactly what the localisation drops.
+    Blocks partition the interior set, depths are nondecreasing along the
+    processing order and P keeps R^T on the exterior."""
+    al = 1.0 if alpha == "iso" else (lambda m: fields.subdomain_log_uniform(m, 2, 5))
+    p = gen.make_problem("hex", 6, beta=1.0, alpha=al)
+    H = oracle.setup(p.A, p.G, max_levels=2)
+    lv = H.levels[0]
+    assert not lv.exact_blocks
+    n = p.A.shape[0]
+    allb = np.concatenate(lv.blocks)
+    assert np.array_equal(np.sort(allb), np.sort(lv.interior))
+    Pd = lv.P.toarray()
+    Ad = p.A.toarray()
+    Rt = amg.r_transpose(lv.rr, n).toarray()
+    ext = np.setdiff1d(np.arange(n), lv.interior)
+    assert np.array_equal(Pd[ext], Rt[ext])
+    depths = np.asarray(lv.depths)
+    for b, B in enumerate(lv.blocks):
+        keep = np.concatenate([ext] + [lv.blocks[k] for k in range(len(lv.blocks))
+                                       if depths[k] < depths[b]] + [B])
+        res = Ad[np.ix_(B, keep)] @ Pd[keep]
+        scale = (abs(Ad[np.ix_(B, keep)]) @ abs(Pd[keep])).max()
+        assert np.abs(res).max() <= 1e-12 * max(scale, 1e-300)
+    assert len(set(depths.tolist())) > 1
