@@ -680,6 +680,92 @@ def test_fp32_form_keeps_fp64_where_the_near_kernel_needs_it():
     assert np.linalg.norm(p.f - p.A @ x) > 1e-6 * np.linalg.norm(p.f)
 
 
+@pytest.mark.parametrize("N,lo,hi", [(8, 2, 4), (8, 8, 2), (12, 8, 2)])
+def test_gradient_ratio_bounds_the_fp32_storage_error_of_gradient_energies(N, lo, hi):
+    """Rounding A_l to FP32 moves each entry by at most eps_32/2 of itself, so
+    the energy (G^T A G)_vv of a hat-function gradient moves by at most
+    eps_32/2 * (|G|^T |A| |G|)_vv, i.e. by at most eps_32/2 * rho_l of itself.
+    The FP32 form's choice of level types rests on that bound: it must hold
+    for the actual rounding on every level, and on the finest level (rho ~
+    alpha / (beta h^2)) the actual worst change comes within a factor 10 of
+    it, so rho measures the real loss and not a loose upper bound."""
+    p = gen.make_problem("hex", N, beta=1.0, alpha=lambda m: fields.subdomain_log_uniform(m, lo, hi))
+    H = oracle.setup(p.A, p.G)
+    eps = float(np.finfo(np.float32).eps)
+    for l, lv in enumerate(H.levels[:-1]):
+        A, G = sp.csr_matrix(lv.A), sp.csr_matrix(lv.G)
+        rho = amg.gradient_ratio(A, G)
+        den = (G.T @ A @ G).diagonal()
+        moved = (G.T @ (A.astype(np.float32).astype(np.float64) - A) @ G).diagonal()
+        ok = den > 0
+        worst = float(np.max(np.abs(moved[ok]) / den[ok]))
+        assert worst <= 0.5 * eps * rho * (1 + 1e-9), (l, worst, rho)
+        if l == 0:
+            assert worst >= 0.05 * eps * rho, (worst, rho)
+            assert rho > 1e6
+
+
+@pytest.mark.parametrize("N,lo,hi", [(8, 2, 4), (10, 8, 2)])
+def test_flexible_cg_equals_cg_for_a_fixed_symmetric_preconditioner(N, lo, hi):
+    """The FP32 form runs CG with the Polak-Ribiere beta (r_k - r_{k-1})^T z_k
+    / r_{k-1}^T z_{k-1}.  With a fixed SPD preconditioner (the FP64 V-cycle)
+    CG keeps r_{k-1}^T z_k = 0, so that beta is the standard one in exact
+    arithmetic: the residual histories agree to rounding over the first
+    iterations, the iteration counts agree and so do the solutions."""
+    p = gen.make_problem("hex", N, beta=1.0, alpha=lambda m: fields.subdomain_log_uniform(m, lo, hi),
+                         f=lambda n: fields.rhs_uniform(n, 5))
+    H = oracle.setup(p.A, p.G)
+    xs, its, hs = oracle.pcg(H, p.A, p.f, flexible=False)
+    xf, itf, hf = oracle.pcg(H, p.A, p.f, flexible=True)
+    assert its == itf
+    hs, hf = np.array(hs[:10]), np.array(hf[:10])
+    assert np.abs(hs - hf).max() <= 1e-7 * hs.max()
+    assert np.linalg.norm(xs - xf) <= 1e-8 * np.linalg.norm(xs)
+
+
+def test_flexible_cg_orthogonalises_against_the_last_direction(monkeypatch):
+    """With a preconditioner that changes every iteration (here z = D_k r with
+    a new random positive diagonal D_k each call) the Polak-Ribiere beta is
+    the flexible CG of Notay (2000): it makes each new direction A-orthogonal
+    to the previous one, beta_k = -z_k^T A p_{k-1} / p_{k-1}^T A p_{k-1}
+    (substitute r_k - r_{k-1} = -alpha A p_{k-1}).  The iterates of the
+    oracle's CG must equal those of that explicit form, written out here;
+    the standard beta (which assumes r_{k-1}^T z_k = 0) must not."""
+    p = gen.make_problem("hex", 4, beta=1.0, alpha=lambda m: fields.subdomain_log_uniform(m, 2, 3),
+                         f=lambda n: fields.rhs_uniform(n, 9))
+    H = oracle.setup(p.A, p.G)
+    A = sp.csr_matrix(p.A)
+    n = A.shape[0]
+    K = 8
+    rng = np.random.default_rng(4)
+    D = [np.exp(rng.uniform(-1.5, 1.5, n)) for _ in range(K + 2)]
+    calls = {"k": 0}
+
+    def varying(H_, r, dtype=np.float64, level=0):
+        z = D[calls["k"]] * np.asarray(r, dtype=np.float64)
+        calls["k"] += 1
+        return z
+
+    x = np.zeros(n)
+    r = p.f.copy()
+    z = D[0] * r
+    d = z.copy()
+    for k in range(K):
+        q = A @ d
+        a = (r @ z) / (d @ q)
+        x = x + a * d
+        r = r - a * q
+        z = D[k + 1] * r
+        d = z - ((z @ q) / (d @ q)) * d
+    monkeypatch.setattr(amg, "vcycle", varying)
+    xf, itf, _ = amg.pcg(H, A, p.f, rtol=1e-30, maxit=K, flexible=True)
+    calls["k"] = 0
+    xs, its, _ = amg.pcg(H, A, p.f, rtol=1e-30, maxit=K, flexible=False)
+    assert itf == its == K
+    assert np.linalg.norm(xf - x) <= 1e-10 * np.linalg.norm(x)
+    assert np.linalg.norm(xs - x) > 1e-3 * np.linalg.norm(x)
+
+
 # ----------------------------------------------------------------------------
 # the 3D extension reading (case 2 of the block construction) against the
 # exact interior harmonic extension: measured, not a pin of the paper
