@@ -31,10 +31,40 @@ def _stream(stream):
     return None
 
 
+def _check_csr_arrays(rp, ci, va, nrows, name="A"):
+    """What the C ABI assumes of a CSR triple it gets as raw pointers: row
+    pointers int64 with nrows + 1 entries, column ids int32, values float64
+    with as many entries as column ids, all contiguous, and either all three
+    host numpy arrays or all three CUDA tensors on one device.  A library
+    that borrows A keeps reading these arrays, so a wrong type or length
+    would make its kernels read past them."""
+    if all(isinstance(a, np.ndarray) for a in (rp, ci, va)):
+        kinds = [(a.dtype, a.flags.c_contiguous, a.size) for a in (rp, ci, va)]
+        want = (np.dtype(np.int64), np.dtype(np.int32), np.dtype(np.float64))
+    else:
+        import torch
+        if not all(isinstance(a, torch.Tensor) and a.is_cuda for a in (rp, ci, va)):
+            raise TypeError(f"{name}: rowptr, colidx and val must be all numpy arrays or all CUDA tensors")
+        if len({a.device for a in (rp, ci, va)}) != 1:
+            raise ValueError(f"{name}: rowptr, colidx and val are on different devices")
+        kinds = [(a.dtype, a.is_contiguous(), a.numel()) for a in (rp, ci, va)]
+        want = (torch.int64, torch.int32, torch.float64)
+    for (dt, contig, _), w, part in zip(kinds, want, ("rowptr", "colidx", "val")):
+        if dt != w:
+            raise TypeError(f"{name}.{part} must be {w}, got {dt}")
+        if not contig:
+            raise ValueError(f"{name}.{part} must be contiguous")
+    if kinds[0][2] != nrows + 1:
+        raise ValueError(f"{name}.rowptr has {kinds[0][2]} entries, expected nrows + 1 = {nrows + 1}")
+    if kinds[1][2] != kinds[2][2]:
+        raise ValueError(f"{name}: colidx has {kinds[1][2]} entries and val {kinds[2][2]}")
+
+
 def _csr_arg(M, keep):
     """amg_csr for a scipy matrix (host) or a (rowptr, colidx, val, nrows, ncols) tuple of tensors."""
     if isinstance(M, tuple):
         rp, ci, va, nr, nc = M
+        _check_csr_arrays(rp, ci, va, nr)
         keep.extend([rp, ci, va])
         return _lib.make_csr(rp, ci, va, nr, nc)
     rp, ci, va = _lib.host_csr(M)
@@ -317,6 +347,9 @@ def level0_integers(A, G, **opts):
 def spmv(rowptr, colidx, val, x, y, stream=None):
     """y = A x with the library's CSR kernel (all device tensors)."""
     n = rowptr.shape[0] - 1
+    _check_csr_arrays(rowptr, colidx, val, n)
+    _vec(x, x.numel(), "x")
+    _vec(y, n, "y")
     a = _lib.make_csr(rowptr, colidx, val, n, x.shape[0])
     _lib.check(load().amg_spmv(C.byref(a), x.data_ptr(), y.data_ptr(), _stream(stream)))
 
@@ -326,6 +359,7 @@ def spmv_dot(rowptr, colidx, val, x, y, dot, stream=None, noalloc=False):
     entry).  noalloc=False: amg_spmv_dot (synchronizes the stream);
     noalloc=True: amg_spmv_dot_noalloc (static scratch, asynchronous)."""
     n = rowptr.shape[0] - 1
+    _check_csr_arrays(rowptr, colidx, val, n)
     _vec(x, n, "x")
     _vec(y, n, "y")
     _vec(dot, 1, "dot")

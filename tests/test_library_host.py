@@ -122,6 +122,43 @@ def test_unsorted_csr_is_rejected():
     assert e.value.status == -3
 
 
+def test_csr_tuples_are_checked_before_their_pointers_are_passed():
+    """A CSR tuple reaches the C ABI as three raw pointers, so the binding
+    checks what the library assumes of them: int64 row pointers with
+    nrows + 1 entries, int32 column ids, float64 values as many as the
+    column ids, contiguous, all host arrays or all CUDA tensors.  Host
+    tuples go through the host-only integer setup; every bad variant is
+    refused before any library call."""
+    p = gen.make_problem("hex", 3)
+    A = p.A.tocsr()
+    rp = A.indptr.astype(np.int64)
+    ci = A.indices.astype(np.int32)
+    va = A.data.astype(np.float64)
+    n = A.shape[0]
+    G = p.G.tocsr()
+    Gt = (G.indptr.astype(np.int64), G.indices.astype(np.int32), G.data.astype(np.float64),
+          G.shape[0], G.shape[1])
+    ref = amglib.level0_integers(A, G)
+    got = amglib.level0_integers((rp, ci, va, n, n), Gt)
+    assert sorted(ref) == sorted(got)
+    assert all(np.array_equal(np.asarray(ref[k]), np.asarray(got[k])) for k in ref)
+    bad = [
+        ((rp.astype(np.int32), ci, va, n, n), TypeError),
+        ((rp, ci.astype(np.int64), va, n, n), TypeError),
+        ((rp, ci, va.astype(np.float32), n, n), TypeError),
+        ((rp[:-1], ci, va, n, n), ValueError),
+        ((rp, ci, va[:-1], n, n), ValueError),
+        ((rp, ci, np.repeat(va, 2)[::2], n, n), ValueError),
+    ]
+    for tup, err in bad:
+        with pytest.raises(err):
+            amglib.level0_integers(tup, Gt)
+    torch = pytest.importorskip("torch")
+    cpu = (torch.from_numpy(rp), torch.from_numpy(ci), torch.from_numpy(va), n, n)
+    with pytest.raises(TypeError):
+        amglib.level0_integers(cpu, Gt)
+
+
 def test_noalloc_spmv_dot_rejects_sizes_beyond_its_scratch():
     """The allocation-free SpMV-with-dot checks its partial-sum count against
     the static scratch before any HIP call: a 20M-row descriptor (mean row
