@@ -474,6 +474,27 @@ def test_galerkin_symmetric_positive_definite():
         assert np.linalg.eigvalsh(0.5 * (A + A.T)).min() > 0
 
 
+@pytest.mark.parametrize("kind,size,alpha", [("hex", 6, "jump"), ("tri", 4, "stripes")])
+def test_l1_jacobi_diagonal_bounds_a(kind, size, alpha):
+    """Section 5's l1-Jacobi divides by D_ii = sum_j |a_ij|.  D - A is then
+    diagonally dominant with a non-negative diagonal, hence positive
+    semi-definite (Gershgorin), so every eigenvalue of D^{-1} A lies in
+    (0, 1] and the l1 step never increases the A-norm of the error.  The
+    plain Jacobi diagonal diag(A) would put the largest one near 3 on
+    these Nedelec matrices, so the pin tells the two apart."""
+    import scipy.linalg as sl
+    al = (lambda m: fields.subdomain_log_uniform(m, 2, 5)) if alpha == "jump" else \
+        (lambda m: fields.stripes_2d(m))
+    p = gen.make_problem(kind, size, beta=1.0, alpha=al)
+    H = oracle.setup(p.A, p.G)
+    assert H.nlevels >= 2
+    for lv in H.levels[:-1]:
+        A = lv.A.toarray()
+        ev = sl.eigh(A, np.diag(lv.smoother.l1), eigvals_only=True)
+        assert ev.min() > 0 and ev.max() <= 1 + 1e-12
+        assert sl.eigh(A, np.diag(np.diag(A)), eigvals_only=True).max() > 2
+
+
 def test_colouring_makes_colour_blocks_uncoupled():
     p, H = _small_hier()
     for lv in H.levels:
