@@ -495,6 +495,38 @@ def test_l1_jacobi_diagonal_bounds_a(kind, size, alpha):
         assert sl.eigh(A, np.diag(np.diag(A)), eigvals_only=True).max() > 2
 
 
+@pytest.mark.parametrize("kind,size", [("hex", 6), ("tri", 4)])
+def test_schwarz_colour_step_zeroes_the_residual_on_its_blocks(kind, size):
+    """Section 5's multiplicative Schwarz solves each node-star block exactly:
+    the blocks are the supports of the columns of G_l, and after one colour's
+    step from any x the residual b - A x vanishes on every block of that
+    colour (the blocks of a colour share no DoF and no entry of A, so one
+    block's correction leaves the others' residuals alone)."""
+    p = gen.make_problem(kind, size, beta=1.0, alpha=lambda m: fields.subdomain_log_uniform(m, 2, 6)
+                         if kind == "hex" else 1.0)
+    H = oracle.setup(p.A, p.G)
+    mats = amg._cast(H, np.float64)
+    rng = np.random.default_rng(11)
+    for l, lv in enumerate(H.levels[:-1]):
+        G = sp.csc_matrix(lv.G)
+        supports = [G.indices[G.indptr[v]:G.indptr[v + 1]] for v in range(G.shape[1])]
+        stars = sorted(tuple(sorted(int(i) for i in sup)) for sup in supports if len(sup))
+        assert sorted(tuple(int(i) for i in b) for b in lv.smoother.blocks) == stars
+        A = sp.csr_matrix(lv.A)
+        n = A.shape[0]
+        for c in range(min(lv.smoother.ncolors, 4)):
+            x = rng.standard_normal(n)
+            b = rng.standard_normal(n)
+            y = amg._schwarz(mats[l], x.copy(), b, [c])
+            r = b - A @ y
+            dofs = np.concatenate([blk for blk, col in zip(lv.smoother.blocks, lv.smoother.color)
+                                   if col == c])
+            scale = (abs(A) @ abs(y) + abs(b))[dofs].max()
+            assert np.abs(r[dofs]).max() <= 1e-12 * scale
+            others = np.setdiff1d(np.arange(n), dofs)
+            assert np.array_equal(y[others], x[others])
+
+
 def test_colouring_makes_colour_blocks_uncoupled():
     p, H = _small_hier()
     for lv in H.levels:
